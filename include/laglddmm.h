@@ -1,0 +1,241 @@
+/*
+ * laglddmm.h - C ABI of the MI355X (gfx950) Lagrangian Gauss-Newton-Krylov
+ * registration hot path.
+ *
+ * The library implements, on one GPU, the operations of Mang & Ruthotto,
+ * "A Lagrangian Gauss-Newton-Krylov solver for mass- and intensity-
+ * preserving diffeomorphic image registration" (SIAM J. Sci. Comput. 2017):
+ * RK4 characteristics of a stationary or time-dependent velocity
+ * (Algorithm 1), the transport solve (eq. rhoEndIR) and the particle push-
+ * forward (eq. rhoEndOMT), the Jacobian products of the final state with
+ * respect to the velocity (Sec. 3.2), the Gauss-Newton Hessian matvec
+ * (Sec. 3.2) and the spectral preconditioner (Sec. 3.2, PCG paragraph).
+ *
+ * Conventions (all calls):
+ *  - Grids are cell-centred and periodic on the box [0, extent_0) x ... ;
+ *    sizes are given x first; unused axes (dim = 2) have size 1.
+ *  - All arrays are float32, contiguous, x fastest:
+ *      image-shaped   : [m_z][m_y][m_x]                       (n_points floats)
+ *      velocity-shaped: [nt_nodes][dim][m_z][m_y][m_x]       (n_unknowns floats)
+ *                       component 0 is the x component
+ *      phi            : [dim][n_points], the displacement of each
+ *                       characteristic's end point from its start cell centre
+ *                       (not wrapped; periodic wrap happens inside
+ *                       interpolation).
+ *  - Every pointer argument except the plan and `stream` is a DEVICE pointer
+ *    unless stated otherwise.  The caller allocates and owns every buffer;
+ *    the plan owns only its workspace.  Outputs must not alias inputs.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    asynchronous on that stream and allocates nothing, except
+ *    lag_plan_create, lag_pcg and lag_gn_solve, which are documented below.
+ *  - A plan is used by one stream at a time (it owns scratch buffers).
+ *  - Return value: LAG_OK (0) or one of the LAG_E* codes; no exception ever
+ *    crosses the ABI.  lag_strerror() names a code.  After LAG_EHIP the HIP
+ *    error string is available from lag_last_hip_error().
+ */
+#ifndef LAGLDDMM_H
+#define LAGLDDMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LAG_OK = 0,
+    LAG_EINVAL = 1,        /* bad argument: null pointer, bad size/model/dir  */
+    LAG_EUNSUPPORTED = 2,  /* valid request this build does not implement     */
+    LAG_EHIP = 3,          /* a HIP runtime call or kernel launch failed      */
+    LAG_ENOMEM = 4,        /* device allocation failed (allocating calls only)*/
+    LAG_EBREAKDOWN = 5,    /* PCG met p^T H p <= 0                            */
+    LAG_ELINESEARCH = 6    /* Armijo line search found no acceptable step     */
+};
+
+enum { LAG_TRANSPORT = 0, LAG_CONTINUITY = 1 };   /* eq. transport / eq. continuity */
+enum { LAG_DIFFUSION = 0, LAG_CURVATURE = 1 };    /* H1 / H2 seminorm regulariser (Sec. 2.1) */
+
+/* One registration problem.  The discrete velocity has
+ * n_unknowns = nt_nodes * dim * prod(vel_m) entries (Sec. 3: n = (n_t+1) d m^d),
+ * stored at the velocity-grid cell centres and, when nt_nodes > 1, at the
+ * time nodes t_j = j / (nt_nodes - 1).  Characteristics start at every image
+ * cell centre (n_points = prod(img_m)). */
+typedef struct lag_problem {
+    int32_t dim;          /* 2 or 3                                            */
+    int32_t img_m[3];     /* image cells per axis (x, y, z); >= 1              */
+    int32_t vel_m[3];     /* velocity cells per axis; >= 2 on used axes        */
+    double  extent[3];    /* domain edge lengths, > 0                          */
+    int32_t nt_nodes;     /* 1 = stationary velocity, else n_t + 1 >= 2        */
+    int32_t model;        /* LAG_TRANSPORT or LAG_CONTINUITY                   */
+    int32_t reg;          /* LAG_DIFFUSION or LAG_CURVATURE                    */
+    int32_t nsteps;       /* N >= 1 RK4 steps over the unit time interval      */
+    double  alpha;        /* regularisation weight, >= 0                       */
+    double  gamma;        /* Hessian shift gamma I (Sec. 3.2), >= 0            */
+} lag_problem;
+
+typedef struct lag_plan_s* lag_plan;
+
+/* ---- host-only helpers (no GPU needed) -------------------------------- */
+
+/* Validate a problem description.  Host only; touches no device. */
+int lag_problem_check(const lag_problem* prob);
+
+/* Sizes of a valid problem: characteristics (= image cells) and unknowns.
+ * Host pointers; either output may be NULL. */
+int lag_problem_sizes(const lag_problem* prob, int64_t* n_points, int64_t* n_unknowns);
+
+const char* lag_strerror(int status);
+
+/* Text of the last HIP error seen by this library in the calling thread
+ * (empty string if none).  The returned pointer stays valid until the next
+ * library call in that thread. */
+const char* lag_last_hip_error(void);
+
+/* ---- plans ------------------------------------------------------------- */
+
+/* Create a plan for `prob` on the current HIP device: validates the problem,
+ * allocates the workspace (packed velocity copies, RK4 stage-time tables,
+ * FFT twiddles, scratch) and uploads host-computed tables.  This is the
+ * allocating call; it synchronises the device.  *out receives the plan. */
+int lag_plan_create(const lag_problem* prob, lag_plan* out);
+
+/* Release a plan and its workspace (synchronises the device).  NULL is OK. */
+int lag_plan_destroy(lag_plan plan);
+
+/* Copy of the plan's problem (host pointer). */
+int lag_plan_problem(lag_plan plan, lag_problem* out);
+
+/* ---- the hot path ------------------------------------------------------- */
+
+/* Characteristics by RK4 with N equal steps (Algorithm 1 without the
+ * derivative; classical fourth stage at y + dt*v3).  dir = -1 traces from
+ * t = 1 back to t = 0, giving y(v, x_c, 1, 0) (transport); dir = +1 traces
+ * from 0 to 1, giving y(v, x_c, 0, 1) (continuity).
+ * v: velocity-shaped.  phi: [dim][n_points] output displacements. */
+int lag_trace(lag_plan plan, const float* v, int32_t dir, float* phi, void* stream);
+
+/* Transport solve u1(x_c) = T(y(v, x_c, 1, 0)) (eq. rhoEndIR): periodic
+ * (bi/tri)linear interpolation of the image T at x_c + phi.
+ * T, u: image-shaped; phi: [dim][n_points]. */
+int lag_transport(lag_plan plan, const float* T, const float* phi, float* u, void* stream);
+
+/* Particle push-forward u1 = F(y(v, x_c, 0, 1)) T (eq. rhoEndOMT) with hat
+ * width equal to the image cell size, i.e. F is the transpose of linear
+ * interpolation at the end points x_c + phi (mass preserving by
+ * construction).  Deterministic: particles are binned by cell and every
+ * cell sums its contributions in a fixed order (no float atomics).
+ * T, u: image-shaped; phi: [dim][n_points]. */
+int lag_pushforward(lag_plan plan, const float* T, const float* phi, float* u, void* stream);
+
+/* Jacobian-vector product Jdv = (d_v u1) dv of the plan's model (Sec. 3.2,
+ * derivative of u1; Algorithm 1's derivative recursion applied to dv).
+ * v, dv: velocity-shaped; T, Jdv: image-shaped.  For the transport model
+ * Jdv[i] = grad T(y_i) . (d_v y_i) dv; for continuity
+ * Jdv = sum_j T_j grad_y F(y_j) (d_v y_j) dv (deterministic binned sum). */
+int lag_jvp(lag_plan plan, const float* v, const float* T, const float* dv,
+            float* Jdv, void* stream);
+
+/* Vector-Jacobian product JTw = (d_v u1)^T w (the data part of the gradient,
+ * Sec. 3.2).  v, JTw: velocity-shaped; T, w: image-shaped.  Characteristics
+ * are recomputed, never stored (memory independent of N).  The velocity-
+ * grid sum uses float atomics, so the last bits may vary between runs. */
+int lag_vjp(lag_plan plan, const float* v, const float* T, const float* w,
+            float* JTw, void* stream);
+
+/* Gauss-Newton Hessian matvec (Sec. 3.2):
+ *   Hp = h^d J^T (W (J p)) + alpha h_v^d sum_j w_j A p_j + gamma p,
+ * h^d = image cell volume, h_v^d = velocity cell volume, w_j the
+ * trapezoidal time weights of the velocity nodes (1 if stationary),
+ * A = -Laplace_h (diffusion) or Laplace_h^2 (curvature), periodic.
+ * wvox: image-shaped voxel weights W, or NULL for W = 1.
+ * v, p, Hp: velocity-shaped; T image-shaped.  Transport: one fused pass per
+ * characteristic; continuity: J p on the image grid, then J^T. */
+int gn_hessmat(lag_plan plan, const float* v, const float* T, const float* wvox,
+               const float* p, float* Hp, void* stream);
+
+/* Spectral preconditioner (Sec. 3.2, PCG paragraph): per velocity component
+ * and time node j, z = F^-1[ F(r) / mu_j(k) ] with
+ * mu_j(k) = alpha h_v^d w_j lambda_A(k) + gamma, the symbol of the
+ * regulariser block of H on the periodic grid (DFT, hand-written radix-2/3/5
+ * FFT).  If mu_j(0) = 0 (gamma = 0) the constant mode is divided by the
+ * smallest nonzero mu_j instead (pseudo-inverse made SPD).
+ * r, z: velocity-shaped.  Supported sizes: every vel_m[a] whose prime
+ * factors are 2, 3 and 5 and which is <= 1024 (else LAG_EUNSUPPORTED at
+ * plan creation... reported by this call). */
+int spectral_precond_apply(lag_plan plan, const float* r, float* z, void* stream);
+
+/* ---- compositions used by the Gauss-Newton driver ----------------------- */
+
+/* Regulariser part of H: out = alpha h_v^d w_j A p_j + gamma p. */
+int lag_reg_apply(lag_plan plan, const float* p, float* out, void* stream);
+
+/* Objective J(v) = D + alpha S (eq. discOpti, eq. SSD, Sec. 2.1).
+ * u (image-shaped, may be NULL) receives u1(v); out3 (device, 3 doubles)
+ * receives {J, D, S}. */
+int lag_objective(lag_plan plan, const float* v, const float* T, const float* R,
+                  float* u, double* out3, void* stream);
+
+/* Gradient g = J^T (h^d (u1 - R)) + alpha h_v^d w_j A v (Sec. 3.2) and the
+ * objective (out3 as in lag_objective; may be NULL). */
+int lag_gradient(lag_plan plan, const float* v, const float* T, const float* R,
+                 float* g, double* out3, void* stream);
+
+/* Dot product of two n-vectors with float64 accumulation, deterministic
+ * order; result written to out (device, 1 double). n <= 2^31. */
+int lag_dot(lag_plan plan, int64_t n, const float* x, const float* y, double* out,
+            void* stream);
+
+typedef struct lag_pcg_info {
+    int32_t iters;        /* PCG iterations taken                           */
+    int32_t matvecs;      /* gn_hessmat calls                               */
+    int32_t breakdown;    /* 1 if p^T H p <= 0 stopped the iteration        */
+    double  relres;       /* final |r| / |b|                                */
+} lag_pcg_info;
+
+/* Preconditioned CG for H(v) x = b (Sec. 3.2, eq. solveGN), x0 = 0,
+ * stopping when |r|_2 <= tol |b|_2 or after maxit iterations.  H is
+ * gn_hessmat with voxel weights wvox (NULL = 1); the preconditioner is
+ * spectral_precond_apply.  Runs on `stream` and synchronises it once per
+ * iteration to read the residual (host-side control flow).  info: host
+ * pointer, may be NULL.  Returns LAG_EBREAKDOWN if p^T H p <= 0 (x then
+ * holds the last iterate). */
+int lag_pcg(lag_plan plan, const float* v, const float* T, const float* wvox,
+            const float* b, float* x, double tol, int32_t maxit,
+            lag_pcg_info* info, void* stream);
+
+typedef struct lag_gn_options {
+    double  gtol;           /* stop when |g| <= gtol |g(v=0)|   (1e-2)        */
+    int32_t max_gn;         /* Gauss-Newton iteration cap         (50)        */
+    double  pcg_tol;        /* PCG relative residual               (0.1)      */
+    int32_t pcg_maxit;      /* PCG iteration cap                   (50)       */
+    double  armijo_c1;      /* sufficient decrease constant        (1e-4)     */
+    int32_t max_halvings;   /* line-search step halvings           (10)       */
+} lag_gn_options;
+
+typedef struct lag_gn_info {
+    int32_t iters;          /* Gauss-Newton iterations (search directions)    */
+    int32_t pcg_iters;      /* total PCG iterations                           */
+    int32_t matvecs;        /* total gn_hessmat calls                          */
+    int32_t converged;      /* 1 if the gradient tolerance was met            */
+    double  J0, J;          /* objective at the start and at the end          */
+    double  g0, gnorm;      /* |g(v=0)| and final |g|                         */
+} lag_gn_info;
+
+/* Default options (host pointer). */
+void lag_gn_default_options(lag_gn_options* opt);
+
+/* Inexact Gauss-Newton-Krylov solve of min_v J(v) (Sec. 3.2): search
+ * direction from lag_pcg, Armijo backtracking by halving.  v is the start
+ * value on entry and the solution on exit (velocity-shaped, device).
+ * opt: host pointer or NULL for defaults; info: host pointer or NULL.
+ * Synchronises `stream` to read scalars.  Returns LAG_ELINESEARCH if the
+ * line search fails (v then holds the last accepted iterate). */
+int lag_gn_solve(lag_plan plan, const float* T, const float* R, float* v,
+                 const lag_gn_options* opt, lag_gn_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAGLDDMM_H */

@@ -1,0 +1,20 @@
+"""MI355X-native Lagrangian Gauss-Newton-Krylov registration hot path.
+
+The computation lives in ``liblaglddmm.so`` (hand-written HIP for gfx950,
+built by ``paper_1703_04446_amd.build``); this package is a thin ctypes
+binding with the C-ABI's function names.  Importing the package does not
+touch the GPU; the library is loaded on first use and a missing library is
+an error.
+"""
+
+from ._lib import (  # noqa: F401
+    LAG_OK, LAG_EINVAL, LAG_EUNSUPPORTED, LAG_EHIP, LAG_ENOMEM, LAG_EBREAKDOWN, LAG_ELINESEARCH,
+    LAG_TRANSPORT, LAG_CONTINUITY, LAG_DIFFUSION, LAG_CURVATURE,
+    LagProblem, LagError, Plan, make_problem, load, header_symbols, strerror,
+    lag_problem_check, lag_problem_sizes, lag_plan_create, lag_plan_destroy,
+    lag_trace, lag_transport, lag_pushforward, lag_jvp, lag_vjp, gn_hessmat,
+    spectral_precond_apply, lag_reg_apply, lag_objective, lag_gradient, lag_dot,
+    lag_pcg, lag_gn_default_options, lag_gn_solve,
+)
+
+LIB_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__), "liblaglddmm.so")

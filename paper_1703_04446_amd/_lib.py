@@ -1,0 +1,314 @@
+"""ctypes binding of liblaglddmm (argument marshalling only).
+
+Every function here forwards to the C-ABI entry point of the same name in
+``include/laglddmm.h``; the work runs in the HIP kernels of the library.
+Tensors must be float32, contiguous and on the current HIP device; the call
+is enqueued on torch's current stream.  A missing library is an error: there
+is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblaglddmm.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "laglddmm.h")
+
+LAG_OK, LAG_EINVAL, LAG_EUNSUPPORTED, LAG_EHIP, LAG_ENOMEM, LAG_EBREAKDOWN, LAG_ELINESEARCH = range(7)
+LAG_TRANSPORT, LAG_CONTINUITY = 0, 1
+LAG_DIFFUSION, LAG_CURVATURE = 0, 1
+
+
+class LagProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("img_m", ctypes.c_int32 * 3),
+        ("vel_m", ctypes.c_int32 * 3),
+        ("extent", ctypes.c_double * 3),
+        ("nt_nodes", ctypes.c_int32),
+        ("model", ctypes.c_int32),
+        ("reg", ctypes.c_int32),
+        ("nsteps", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+    ]
+
+
+class LagPcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("matvecs", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+
+class LagGnOptions(ctypes.Structure):
+    _fields_ = [("gtol", ctypes.c_double), ("max_gn", ctypes.c_int32),
+                ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int32),
+                ("armijo_c1", ctypes.c_double), ("max_halvings", ctypes.c_int32)]
+
+
+class LagGnInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
+                ("matvecs", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("J0", ctypes.c_double), ("J", ctypes.c_double),
+                ("g0", ctypes.c_double), ("gnorm", ctypes.c_double)]
+
+
+class LagError(RuntimeError):
+    def __init__(self, name, status, detail=""):
+        self.status = status
+        msg = f"{name} failed: {strerror(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "lag_problem_check": (_I, [ctypes.POINTER(LagProblem)]),
+    "lag_problem_sizes": (_I, [ctypes.POINTER(LagProblem), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_int64)]),
+    "lag_strerror": (ctypes.c_char_p, [_I]),
+    "lag_last_hip_error": (ctypes.c_char_p, []),
+    "lag_plan_create": (_I, [ctypes.POINTER(LagProblem), ctypes.POINTER(_P)]),
+    "lag_plan_destroy": (_I, [_P]),
+    "lag_plan_problem": (_I, [_P, ctypes.POINTER(LagProblem)]),
+    "lag_trace": (_I, [_P, _P, ctypes.c_int32, _P, _P]),
+    "lag_transport": (_I, [_P, _P, _P, _P, _P]),
+    "lag_pushforward": (_I, [_P, _P, _P, _P, _P]),
+    "lag_jvp": (_I, [_P, _P, _P, _P, _P, _P]),
+    "lag_vjp": (_I, [_P, _P, _P, _P, _P, _P]),
+    "gn_hessmat": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "spectral_precond_apply": (_I, [_P, _P, _P, _P]),
+    "lag_reg_apply": (_I, [_P, _P, _P, _P]),
+    "lag_objective": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "lag_gradient": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "lag_dot": (_I, [_P, ctypes.c_int64, _P, _P, _P, _P]),
+    "lag_pcg": (_I, [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int32,
+                     ctypes.POINTER(LagPcgInfo), _P]),
+    "lag_gn_default_options": (None, [ctypes.POINTER(LagGnOptions)]),
+    "lag_gn_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(LagGnOptions),
+                          ctypes.POINTER(LagGnInfo), _P]),
+}
+
+
+def header_symbols(path=HEADER):
+    """Names of the functions ``include/laglddmm.h`` declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def load(path=LIB_PATH):
+    """Load the shared library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"liblaglddmm.so not built at {path}; run paper_1703_04446_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(status):
+    return load().lag_strerror(int(status)).decode()
+
+
+def _check(name, status):
+    if status != LAG_OK:
+        detail = ""
+        if status == LAG_EHIP:
+            detail = load().lag_last_hip_error().decode()
+        raise LagError(name, status, detail)
+
+
+def make_problem(dim, img_m, vel_m, nt_nodes=1, model="transport", reg="diffusion", nsteps=5,
+                 alpha=1e-2, gamma=0.0, extent=(1.0, 1.0, 1.0)):
+    """Fill a ``lag_problem`` (sizes x first; unused axes become 1)."""
+    p = LagProblem()
+    p.dim = dim
+    for a in range(3):
+        p.img_m[a] = int(img_m[a]) if a < dim else 1
+        p.vel_m[a] = int(vel_m[a]) if a < dim else 1
+        p.extent[a] = float(extent[a]) if a < len(extent) else 1.0
+    p.nt_nodes = nt_nodes
+    p.model = {"transport": LAG_TRANSPORT, "continuity": LAG_CONTINUITY}[model] if isinstance(model, str) else model
+    p.reg = {"diffusion": LAG_DIFFUSION, "curvature": LAG_CURVATURE}[reg] if isinstance(reg, str) else reg
+    p.nsteps = nsteps
+    p.alpha = alpha
+    p.gamma = gamma
+    return p
+
+
+def lag_problem_check(prob):
+    return load().lag_problem_check(ctypes.byref(prob))
+
+
+def lag_problem_sizes(prob):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check("lag_problem_sizes", load().lag_problem_sizes(ctypes.byref(prob), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+# ---------------------------------------------------------------------------
+# device-side helpers (torch is used for memory and streams only)
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, n=None, name="tensor"):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.dtype not in (torch.float32, torch.float64) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous float tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Owns a ``lag_plan``; sizes are read from the problem."""
+
+    def __init__(self, prob: LagProblem):
+        self.prob = prob
+        self.n_points, self.n_unknowns = lag_problem_sizes(prob)
+        h = ctypes.c_void_p()
+        _check("lag_plan_create", load().lag_plan_create(ctypes.byref(prob), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().lag_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def lag_plan_create(prob):
+    return Plan(prob)
+
+
+def lag_plan_destroy(plan):
+    plan.close()
+
+
+def lag_trace(plan, v, direction, phi):
+    _check("lag_trace", load().lag_trace(plan.handle, _ptr(v, plan.n_unknowns, "v"), int(direction),
+                                         _ptr(phi, plan.prob.dim * plan.n_points, "phi"), _stream()))
+
+
+def lag_transport(plan, T, phi, u):
+    _check("lag_transport", load().lag_transport(plan.handle, _ptr(T, plan.n_points, "T"),
+                                                 _ptr(phi, plan.prob.dim * plan.n_points, "phi"),
+                                                 _ptr(u, plan.n_points, "u"), _stream()))
+
+
+def lag_pushforward(plan, T, phi, u):
+    _check("lag_pushforward", load().lag_pushforward(plan.handle, _ptr(T, plan.n_points, "T"),
+                                                     _ptr(phi, plan.prob.dim * plan.n_points, "phi"),
+                                                     _ptr(u, plan.n_points, "u"), _stream()))
+
+
+def lag_jvp(plan, v, T, dv, Jdv):
+    _check("lag_jvp", load().lag_jvp(plan.handle, _ptr(v, plan.n_unknowns, "v"), _ptr(T, plan.n_points, "T"),
+                                     _ptr(dv, plan.n_unknowns, "dv"), _ptr(Jdv, plan.n_points, "Jdv"), _stream()))
+
+
+def lag_vjp(plan, v, T, w, JTw):
+    _check("lag_vjp", load().lag_vjp(plan.handle, _ptr(v, plan.n_unknowns, "v"), _ptr(T, plan.n_points, "T"),
+                                     _ptr(w, plan.n_points, "w"), _ptr(JTw, plan.n_unknowns, "JTw"), _stream()))
+
+
+def gn_hessmat(plan, v, T, wvox, p, Hp):
+    _check("gn_hessmat", load().gn_hessmat(plan.handle, _ptr(v, plan.n_unknowns, "v"),
+                                           _ptr(T, plan.n_points, "T"), _ptr(wvox, plan.n_points, "wvox"),
+                                           _ptr(p, plan.n_unknowns, "p"), _ptr(Hp, plan.n_unknowns, "Hp"),
+                                           _stream()))
+
+
+def spectral_precond_apply(plan, r, z):
+    _check("spectral_precond_apply", load().spectral_precond_apply(
+        plan.handle, _ptr(r, plan.n_unknowns, "r"), _ptr(z, plan.n_unknowns, "z"), _stream()))
+
+
+def lag_reg_apply(plan, p, out):
+    _check("lag_reg_apply", load().lag_reg_apply(plan.handle, _ptr(p, plan.n_unknowns, "p"),
+                                                 _ptr(out, plan.n_unknowns, "out"), _stream()))
+
+
+def lag_objective(plan, v, T, R, u, out3):
+    _check("lag_objective", load().lag_objective(plan.handle, _ptr(v, plan.n_unknowns, "v"),
+                                                 _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
+                                                 _ptr(u, plan.n_points, "u"), _ptr(out3, 3, "out3"), _stream()))
+
+
+def lag_gradient(plan, v, T, R, g, out3):
+    _check("lag_gradient", load().lag_gradient(plan.handle, _ptr(v, plan.n_unknowns, "v"),
+                                               _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
+                                               _ptr(g, plan.n_unknowns, "g"), _ptr(out3, 3, "out3"), _stream()))
+
+
+def lag_dot(plan, x, y, out):
+    n = x.numel()
+    _check("lag_dot", load().lag_dot(plan.handle, n, _ptr(x, n, "x"), _ptr(y, n, "y"), _ptr(out, 1, "out"),
+                                     _stream()))
+
+
+def lag_pcg(plan, v, T, wvox, b, x, tol=0.1, maxit=50):
+    info = LagPcgInfo()
+    st = load().lag_pcg(plan.handle, _ptr(v, plan.n_unknowns, "v"), _ptr(T, plan.n_points, "T"),
+                        _ptr(wvox, plan.n_points, "wvox"), _ptr(b, plan.n_unknowns, "b"),
+                        _ptr(x, plan.n_unknowns, "x"), float(tol), int(maxit), ctypes.byref(info), _stream())
+    if st not in (LAG_OK, LAG_EBREAKDOWN):
+        _check("lag_pcg", st)
+    return {"iters": info.iters, "matvecs": info.matvecs, "breakdown": bool(info.breakdown),
+            "relres": info.relres, "status": st}
+
+
+def lag_gn_default_options():
+    o = LagGnOptions()
+    load().lag_gn_default_options(ctypes.byref(o))
+    return o
+
+
+def lag_gn_solve(plan, T, R, v, options=None):
+    o = options if options is not None else lag_gn_default_options()
+    info = LagGnInfo()
+    st = load().lag_gn_solve(plan.handle, _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
+                             _ptr(v, plan.n_unknowns, "v"), ctypes.byref(o), ctypes.byref(info), _stream())
+    if st not in (LAG_OK, LAG_ELINESEARCH):
+        _check("lag_gn_solve", st)
+    return {"iters": info.iters, "pcg_iters": info.pcg_iters, "matvecs": info.matvecs,
+            "converged": bool(info.converged), "J0": info.J0, "J": info.J, "g0": info.g0,
+            "gnorm": info.gnorm, "status": st}
+
+
+def problem_arrays_to_device(*arrays):
+    """float32 contiguous device copies of NumPy arrays (test/bench helper)."""
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda() for a in arrays]

@@ -1,0 +1,574 @@
+// C ABI of liblaglddmm: argument validation, plan management, the hot-path
+// entry points and the native PCG / Gauss-Newton driver.
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lag_internal.hpp"
+
+namespace lag {
+
+static thread_local std::string g_hip_error;
+
+int set_hip_error(hipError_t e) {
+  g_hip_error = hipGetErrorString(e);
+  return LAG_EHIP;
+}
+
+int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, hipStream_t s);
+int launch_pcg_p(long long n, float* p, const float* z, double* sc, hipStream_t s);
+int launch_scale_mul(long long n, float c, const float* a, const float* w, float* out, hipStream_t s);
+int launch_axpby(long long n, float a, const float* x, float b, const float* y, float* out, hipStream_t s);
+
+// Lanes of one wave sit on a 4x4x4 (3-D) or 8x8 (2-D) lattice.
+static void choose_bricks(lag_plan P) {
+  const int D = P->geo.dim;
+  lag::Bricks& B = P->bricks;
+  const int lane[3] = {D == 3 ? 4 : 8, D == 3 ? 4 : 8, D == 3 ? 4 : 1};
+  const int target[3] = {16, 16, D == 3 ? 8 : 1};
+  const size_t budget = 64 * 1024;
+  int halo = D == 3 ? 3 : 4;
+  int nreg[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a < D) {
+      double r = (double)P->prob.img_m[a] / P->prob.vel_m[a];
+      B.stride[a] = std::max(1, (int)lround(r));
+    } else {
+      B.stride[a] = 1;
+    }
+    B.rdim[a] = lane[a] * B.stride[a];
+    nreg[a] = a < D ? std::max(1, target[a] / B.rdim[a]) : 1;
+  }
+  for (;;) {
+    int tvol = 1;
+    for (int a = 0; a < 3; ++a) {
+      B.bdim[a] = nreg[a] * B.rdim[a];
+      if (a < D) {
+        double ext = ceil((B.bdim[a] - 1) * P->geo.ratio[a]);
+        B.tdim[a] = (int)ext + 3 + 2 * halo;
+      } else {
+        B.tdim[a] = 1;
+      }
+      tvol *= B.tdim[a];
+    }
+    size_t bytes = sizeof(float) * (size_t)P->fields * tvol;
+    if (bytes <= budget) {
+      B.tvol = tvol;
+      break;
+    }
+    int amax = 0;
+    for (int a = 1; a < D; ++a)
+      if (nreg[a] > nreg[amax]) amax = a;
+    if (nreg[amax] > 1) {
+      nreg[amax] = (nreg[amax] + 1) / 2;
+    } else if (halo > 1) {
+      --halo;
+    } else {
+      B.tvol = tvol;  // smallest possible tile; exceeds the budget only for huge node counts
+      break;
+    }
+  }
+  B.halo = halo;
+  B.nbricks = 1;
+  for (int a = 0; a < 3; ++a) {
+    B.nreg[a] = nreg[a];
+    B.nb[a] = a < D ? (P->prob.img_m[a] + B.bdim[a] - 1) / B.bdim[a] : 1;
+    B.nbricks *= B.nb[a];
+  }
+}
+
+static void free_plan(lag_plan P) {
+  if (!P) return;
+  void* ptrs[] = {P->pack_v, P->pack_p, P->st_j0[0], P->st_j0[1], P->st_th[0], P->st_th[1], P->reg_scale,
+                  P->img_a, P->img_b, P->phi, P->bin_count, P->bin_start, P->bin_cursor, P->bin_items,
+                  P->part_base, P->part_vals, P->scan_blocks, P->red_partial, P->scalars, P->fft_buf,
+                  P->fft_tw[0], P->fft_tw[1], P->fft_tw[2], P->fft_lam[0], P->fft_lam[1], P->fft_lam[2],
+                  P->fft_mu1, P->flags};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < 10; ++i)
+    if (P->vec[i]) (void)hipFree(P->vec[i]);
+  delete P;
+}
+
+}  // namespace lag
+
+using namespace lag;
+
+#define LAG_CHECK(cond)          \
+  do {                           \
+    if (!(cond)) return LAG_EINVAL; \
+  } while (0)
+
+static inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+extern "C" {
+
+const char* lag_strerror(int status) {
+  switch (status) {
+    case LAG_OK: return "ok";
+    case LAG_EINVAL: return "invalid argument";
+    case LAG_EUNSUPPORTED: return "unsupported problem or size";
+    case LAG_EHIP: return "HIP runtime error";
+    case LAG_ENOMEM: return "device allocation failed";
+    case LAG_EBREAKDOWN: return "PCG breakdown (p^T H p <= 0)";
+    case LAG_ELINESEARCH: return "Armijo line search failed";
+    default: return "unknown status";
+  }
+}
+
+const char* lag_last_hip_error(void) { return g_hip_error.c_str(); }
+
+int lag_problem_check(const lag_problem* p) {
+  LAG_CHECK(p);
+  LAG_CHECK(p->dim == 2 || p->dim == 3);
+  long long np = 1, nv = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (a < p->dim) {
+      LAG_CHECK(p->img_m[a] >= 2 && p->img_m[a] <= (1 << 20));
+      LAG_CHECK(p->vel_m[a] >= 2 && p->vel_m[a] <= (1 << 20));
+      LAG_CHECK(p->extent[a] > 0.0 && isfinite(p->extent[a]));
+      np *= p->img_m[a];
+      nv *= p->vel_m[a];
+    } else {
+      LAG_CHECK(p->img_m[a] == 1 && p->vel_m[a] == 1);
+    }
+  }
+  LAG_CHECK(p->nt_nodes >= 1 && p->nt_nodes <= 64);
+  LAG_CHECK(p->model == LAG_TRANSPORT || p->model == LAG_CONTINUITY);
+  LAG_CHECK(p->reg == LAG_DIFFUSION || p->reg == LAG_CURVATURE);
+  LAG_CHECK(p->nsteps >= 1 && p->nsteps <= (1 << 16));
+  LAG_CHECK(p->alpha >= 0.0 && isfinite(p->alpha));
+  LAG_CHECK(p->gamma >= 0.0 && isfinite(p->gamma));
+  LAG_CHECK(np <= 0x7fffffffLL);
+  LAG_CHECK(nv * p->nt_nodes * p->dim <= 0x7fffffffLL);
+  return LAG_OK;
+}
+
+int lag_problem_sizes(const lag_problem* p, int64_t* n_points, int64_t* n_unknowns) {
+  int rc = lag_problem_check(p);
+  if (rc) return rc;
+  int64_t np = 1, nv = 1;
+  for (int a = 0; a < p->dim; ++a) {
+    np *= p->img_m[a];
+    nv *= p->vel_m[a];
+  }
+  if (n_points) *n_points = np;
+  if (n_unknowns) *n_unknowns = nv * p->dim * p->nt_nodes;
+  return LAG_OK;
+}
+
+#define ALLOC(ptr, bytes)                                         \
+  do {                                                            \
+    if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess) {       \
+      (void)hipGetLastError();                                    \
+      lag::free_plan(P);                                          \
+      return LAG_ENOMEM;                                          \
+    }                                                             \
+  } while (0)
+
+#define HIPC(call)                                                \
+  do {                                                            \
+    hipError_t _e = (call);                                       \
+    if (_e != hipSuccess) {                                       \
+      lag::free_plan(P);                                          \
+      return lag::set_hip_error(_e);                              \
+    }                                                             \
+  } while (0)
+
+int lag_plan_create(const lag_problem* prob, lag_plan* out) {
+  LAG_CHECK(out);
+  *out = nullptr;
+  int rc = lag_problem_check(prob);
+  if (rc) return rc;
+  lag_plan P = new lag_plan_s();
+  P->prob = *prob;
+  HIPC(hipGetDevice(&P->device));
+  const int D = prob->dim;
+  Geo& g = P->geo;
+  g.dim = D;
+  g.nodes = prob->nt_nodes;
+  g.nsteps = prob->nsteps;
+  g.np = 1;
+  g.nv = 1;
+  double cell = 1.0, cellv = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    g.mi[a] = a < D ? prob->img_m[a] : 1;
+    g.mv[a] = a < D ? prob->vel_m[a] : 1;
+    double L = a < D ? prob->extent[a] : 1.0;
+    g.inv_hi[a] = (float)(g.mi[a] / L);
+    g.inv_hv[a] = (float)(g.mv[a] / L);
+    g.ratio[a] = (double)g.mv[a] / (double)g.mi[a];
+    if (a < D) {
+      g.np *= g.mi[a];
+      g.nv *= g.mv[a];
+      cell *= L / g.mi[a];
+      cellv *= L / g.mv[a];
+    }
+  }
+  g.cell_img = (float)cell;
+  P->fields = g.nodes * D;
+  P->n_unknowns = (long long)P->fields * g.nv;
+  choose_bricks(P);
+
+  // time-node quadrature weights (trapezoid; 1 for a stationary field)
+  const int nt = g.nodes - 1;
+  for (int j = 0; j < g.nodes; ++j)
+    P->node_w[j] = nt == 0 ? 1.0 : ((j == 0 || j == nt) ? 0.5 / nt : 1.0 / nt);
+  std::vector<float> scale(2 * g.nodes);
+  for (int j = 0; j < g.nodes; ++j) {
+    scale[j] = (float)(prob->alpha * cellv * P->node_w[j]);
+    scale[g.nodes + j] = (float)(cellv * P->node_w[j]);
+  }
+  ALLOC(P->reg_scale, sizeof(float) * 2 * g.nodes);
+  HIPC(hipMemcpy(P->reg_scale, scale.data(), sizeof(float) * 2 * g.nodes, hipMemcpyHostToDevice));
+
+  // RK4 stage tables (Algorithm 1: stage times t_k, t_k + dt/2, t_k + dt/2, t_k + dt)
+  const int N = prob->nsteps;
+  for (int k2 = 0; k2 < 2; ++k2) {
+    const int dir = k2 == 0 ? -1 : 1;
+    const double dt = (double)dir / N;
+    const double t0 = dir > 0 ? 0.0 : 1.0;
+    std::vector<int> j0(4 * N);
+    std::vector<float> th(4 * N);
+    const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int k = 0; k < N; ++k) {
+      const double tk = t0 + k * dt;
+      for (int s = 0; s < 4; ++s) {
+        double t = tk + cst[s] * dt;
+        int jj = 0;
+        double theta = 0.0;
+        if (nt > 0) {
+          jj = std::min((int)floor(t * nt), nt - 1);
+          jj = std::max(jj, 0);
+          theta = t * nt - jj;
+        }
+        j0[4 * k + s] = jj;
+        th[4 * k + s] = (float)theta;
+      }
+    }
+    ALLOC(P->st_j0[k2], sizeof(int) * 4 * N);
+    ALLOC(P->st_th[k2], sizeof(float) * 4 * N);
+    HIPC(hipMemcpy(P->st_j0[k2], j0.data(), sizeof(int) * 4 * N, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(P->st_th[k2], th.data(), sizeof(float) * 4 * N, hipMemcpyHostToDevice));
+  }
+
+  const size_t vec = D == 3 ? sizeof(float4) : sizeof(float2);
+  ALLOC(P->pack_v, vec * g.nv * g.nodes);
+  ALLOC(P->pack_p, vec * g.nv * g.nodes);
+  ALLOC(P->img_a, sizeof(float) * g.np);
+  ALLOC(P->img_b, sizeof(float) * g.np);
+  ALLOC(P->phi, sizeof(float) * g.np * D);
+  ALLOC(P->bin_count, sizeof(int) * (g.np + 1));
+  ALLOC(P->bin_start, sizeof(int) * (g.np + 1));
+  ALLOC(P->bin_cursor, sizeof(int) * g.np);
+  ALLOC(P->bin_items, sizeof(int) * g.np);
+  ALLOC(P->part_base, sizeof(int) * g.np);
+  ALLOC(P->part_vals, sizeof(float) * g.np * (1 << D));
+  ALLOC(P->scan_blocks, sizeof(int) * ((g.np + 1023) / 1024 + 2));
+  ALLOC(P->red_partial, sizeof(double) * kRedBlocks);
+  ALLOC(P->scalars, sizeof(double) * 32);
+  HIPC(hipMemset(P->scalars, 0, sizeof(double) * 32));
+  for (int i = 0; i < 10; ++i) ALLOC(P->vec[i], sizeof(float) * P->n_unknowns);
+  ALLOC(P->flags, sizeof(int) * 4);
+  HIPC(hipMemset(P->flags, 0, sizeof(int) * 4));
+  rc = precond_setup(P);
+  if (rc) {
+    lag::free_plan(P);
+    return rc;
+  }
+  HIPC(hipDeviceSynchronize());
+  *out = P;
+  return LAG_OK;
+}
+
+int lag_plan_destroy(lag_plan plan) {
+  if (!plan) return LAG_OK;
+  (void)hipDeviceSynchronize();
+  lag::free_plan(plan);
+  return LAG_OK;
+}
+
+int lag_plan_problem(lag_plan plan, lag_problem* out) {
+  LAG_CHECK(plan && out);
+  *out = plan->prob;
+  return LAG_OK;
+}
+
+int lag_trace(lag_plan P, const float* v, int32_t dir, float* phi, void* stream) {
+  LAG_CHECK(P && v && phi && (dir == 1 || dir == -1));
+  int rc = launch_pack(P, v, P->pack_v, S(stream));
+  if (rc) return rc;
+  return launch_trace(P, P->pack_v, dir, phi, S(stream));
+}
+
+int lag_transport(lag_plan P, const float* T, const float* phi, float* u, void* stream) {
+  LAG_CHECK(P && T && phi && u);
+  return launch_transport(P, T, phi, u, S(stream));
+}
+
+int lag_pushforward(lag_plan P, const float* T, const float* phi, float* u, void* stream) {
+  LAG_CHECK(P && T && phi && u);
+  return launch_pushforward(P, T, phi, u, S(stream));
+}
+
+int lag_jvp(lag_plan P, const float* v, const float* T, const float* dv, float* Jdv, void* stream) {
+  LAG_CHECK(P && v && T && dv && Jdv);
+  int rc = launch_pack(P, v, P->pack_v, S(stream));
+  if (rc) return rc;
+  if ((rc = launch_pack(P, dv, P->pack_p, S(stream)))) return rc;
+  return launch_jvp(P, P->pack_v, P->pack_p, T, Jdv, S(stream));
+}
+
+int lag_vjp(lag_plan P, const float* v, const float* T, const float* w, float* JTw, void* stream) {
+  LAG_CHECK(P && v && T && w && JTw);
+  int rc = launch_pack(P, v, P->pack_v, S(stream));
+  if (rc) return rc;
+  return launch_vjp(P, P->pack_v, T, w, JTw, S(stream));
+}
+
+int gn_hessmat(lag_plan P, const float* v, const float* T, const float* wvox, const float* p, float* Hp,
+               void* stream) {
+  LAG_CHECK(P && v && T && p && Hp);
+  hipStream_t s = S(stream);
+  int rc = launch_pack(P, v, P->pack_v, s);
+  if (rc) return rc;
+  if ((rc = launch_pack(P, p, P->pack_p, s))) return rc;
+  if (P->prob.model == LAG_TRANSPORT) {
+    if ((rc = launch_fill(Hp, P->n_unknowns, 0.f, s))) return rc;
+    if ((rc = launch_hess_transport(P, P->pack_v, P->pack_p, T, wvox, Hp, s))) return rc;
+  } else {
+    // J p on the image grid, weight by h^d W, then J^T
+    if ((rc = launch_jvp(P, P->pack_v, P->pack_p, T, P->img_a, s))) return rc;
+    if ((rc = launch_scale_mul(P->geo.np, P->geo.cell_img, P->img_a, wvox, P->img_b, s))) return rc;
+    if ((rc = launch_vjp(P, P->pack_v, T, P->img_b, Hp, s))) return rc;
+  }
+  return launch_reg(P, p, Hp, /*accumulate=*/1, /*gamma=*/1, 1.f, s);
+}
+
+int spectral_precond_apply(lag_plan P, const float* r, float* z, void* stream) {
+  LAG_CHECK(P && r && z);
+  return launch_precond(P, r, z, S(stream));
+}
+
+int lag_reg_apply(lag_plan P, const float* p, float* out, void* stream) {
+  LAG_CHECK(P && p && out);
+  return launch_reg(P, p, out, 0, 1, 1.f, S(stream));
+}
+
+int lag_dot(lag_plan P, int64_t n, const float* x, const float* y, double* out, void* stream) {
+  LAG_CHECK(P && x && y && out && n >= 0 && n <= 0x7fffffffLL);
+  return launch_dot(P, n, x, y, out, S(stream));
+}
+
+}  // extern "C"
+
+namespace lag {
+__global__ void k_halve(double* x) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *x *= 0.5;
+}
+__global__ void k_set(double* x, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *x = v;
+}
+}  // namespace lag
+
+extern "C" {
+
+static int objective_full(lag_plan P, const float* v, const float* T, const float* R, float* u, float* wres,
+                          double* out3, hipStream_t s) {
+  const int dir = P->prob.model == LAG_TRANSPORT ? -1 : 1;
+  int rc = launch_pack(P, v, P->pack_v, s);
+  if (rc) return rc;
+  if ((rc = launch_trace(P, P->pack_v, dir, P->phi, s))) return rc;
+  float* uu = u ? u : P->img_a;
+  if (P->prob.model == LAG_TRANSPORT) rc = launch_transport(P, T, P->phi, uu, s);
+  else rc = launch_pushforward(P, T, P->phi, uu, s);
+  if (rc) return rc;
+  if ((rc = launch_ssd(P, uu, R, wres, P->geo.cell_img, out3 + 1, s))) return rc;
+  float* tmp = P->vec[9];
+  if ((rc = launch_reg(P, v, tmp, 0, 0, 0.f, s))) return rc;
+  if ((rc = launch_dot(P, P->n_unknowns, v, tmp, out3 + 2, s))) return rc;
+  hipLaunchKernelGGL(lag::k_halve, dim3(1), dim3(64), 0, s, out3 + 2);
+  LAG_LAUNCH_CHECK();
+  return launch_combine_J(out3, P->prob.alpha, s);
+}
+
+int lag_objective(lag_plan P, const float* v, const float* T, const float* R, float* u, double* out3,
+                  void* stream) {
+  LAG_CHECK(P && v && T && R);
+  return objective_full(P, v, T, R, u, nullptr, out3 ? out3 : P->scalars + 8, S(stream));
+}
+
+int lag_gradient(lag_plan P, const float* v, const float* T, const float* R, float* g, double* out3,
+                 void* stream) {
+  LAG_CHECK(P && v && T && R && g);
+  hipStream_t s = S(stream);
+  int rc = objective_full(P, v, T, R, nullptr, P->img_b, out3 ? out3 : P->scalars + 8, s);
+  if (rc) return rc;
+  // pack_v still holds v
+  if ((rc = launch_vjp(P, P->pack_v, T, P->img_b, g, s))) return rc;
+  return launch_reg(P, v, g, 1, 0, 1.f, s);
+}
+
+// ---- PCG / Gauss-Newton ------------------------------------------------------
+
+static int read_scalars(lag_plan P, double* host, int off, int cnt, hipStream_t s) {
+  LAG_HIP(hipMemcpyAsync(host, P->scalars + off, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  return LAG_OK;
+}
+
+int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const float* b, float* x, double tol,
+            int32_t maxit, lag_pcg_info* info, void* stream) {
+  LAG_CHECK(P && v && T && b && x && maxit >= 0 && tol >= 0.0);
+  hipStream_t s = S(stream);
+  const long long n = P->n_unknowns;
+  float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
+  double* sc = P->scalars;  // [0] rz, [1] pHp, [2] rz_new, [3] rr, [4] breakdown, [5] bb
+  lag_pcg_info loc = {0, 0, 0, 0.0};
+  int rc;
+  if ((rc = launch_fill(x, n, 0.f, s))) return rc;
+  if ((rc = launch_axpby(n, 1.f, b, 0.f, nullptr, r, s))) return rc;
+  if ((rc = launch_dot(P, n, b, b, sc + 5, s))) return rc;
+  double h[6];
+  if ((rc = read_scalars(P, h, 0, 6, s))) return rc;
+  const double nb = sqrt(h[5]);
+  if (nb == 0.0) {
+    if (info) *info = loc;
+    return LAG_OK;
+  }
+  if ((rc = launch_precond(P, r, z, s))) return rc;
+  if ((rc = launch_dot(P, n, r, z, sc + 0, s))) return rc;
+  if ((rc = launch_axpby(n, 1.f, z, 0.f, nullptr, p, s))) return rc;
+  double rr = h[5];
+  int status = LAG_OK;
+  // clear the breakdown flag
+  hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 4, 0.0);
+  LAG_LAUNCH_CHECK();
+  for (int it = 0; it < maxit; ++it) {
+    if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
+    if ((rc = read_scalars(P, h, 0, 5, s))) return rc;
+    rr = h[3];
+    if (h[4] != 0.0) {
+      status = LAG_EBREAKDOWN;
+      loc.breakdown = 1;
+      break;
+    }
+    if (sqrt(rr) <= tol * nb) break;
+    if ((rc = gn_hessmat(P, v, T, wvox, p, Hp, stream))) return rc;
+    loc.matvecs++;
+    if ((rc = launch_dot(P, n, p, Hp, sc + 1, s))) return rc;
+    if ((rc = launch_pcg_xr(n, x, r, p, Hp, sc, s))) return rc;
+    if ((rc = launch_precond(P, r, z, s))) return rc;
+    if ((rc = launch_dot(P, n, r, z, sc + 2, s))) return rc;
+    if ((rc = launch_pcg_p(n, p, z, sc, s))) return rc;
+    loc.iters = it + 1;
+  }
+  if (status == LAG_OK) {
+    if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
+    if ((rc = read_scalars(P, h, 0, 5, s))) return rc;
+    rr = h[3];
+    if (h[4] != 0.0) {
+      status = LAG_EBREAKDOWN;
+      loc.breakdown = 1;
+      if (loc.iters > 0) loc.iters--;
+    }
+  }
+  loc.relres = sqrt(rr) / nb;
+  if (info) *info = loc;
+  return status;
+}
+
+void lag_gn_default_options(lag_gn_options* o) {
+  if (!o) return;
+  o->gtol = 1e-2;
+  o->max_gn = 50;
+  o->pcg_tol = 0.1;
+  o->pcg_maxit = 50;
+  o->armijo_c1 = 1e-4;
+  o->max_halvings = 10;
+}
+
+int lag_gn_solve(lag_plan P, const float* T, const float* R, float* v, const lag_gn_options* opt,
+                 lag_gn_info* info, void* stream) {
+  LAG_CHECK(P && T && R && v);
+  lag_gn_options o;
+  lag_gn_default_options(&o);
+  if (opt) o = *opt;
+  LAG_CHECK(o.max_gn >= 0 && o.pcg_maxit >= 0 && o.max_halvings >= 0 && o.gtol >= 0.0);
+  hipStream_t s = S(stream);
+  const long long n = P->n_unknowns;
+  float *g = P->vec[0], *rhs = P->vec[1], *dv = P->vec[2], *vt = P->vec[7], *zero = P->vec[8];
+  double* sc = P->scalars;
+  double h[16];
+  lag_gn_info loc;
+  memset(&loc, 0, sizeof(loc));
+  int rc;
+  // reference gradient norm at v = 0
+  if ((rc = launch_fill(zero, n, 0.f, s))) return rc;
+  if ((rc = lag_gradient(P, zero, T, R, g, sc + 8, stream))) return rc;
+  if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+  if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
+  loc.g0 = sqrt(h[3]);
+  int status = LAG_OK;
+  for (int it = 0; it < o.max_gn; ++it) {
+    if ((rc = lag_gradient(P, v, T, R, g, sc + 8, stream))) return rc;
+    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
+    const double J = h[0];
+    const double gn = sqrt(h[3]);
+    if (it == 0) loc.J0 = J;
+    loc.J = J;
+    loc.gnorm = gn;
+    if (gn <= o.gtol * loc.g0) {
+      loc.converged = 1;
+      break;
+    }
+    if ((rc = launch_axpby(n, -1.f, g, 0.f, nullptr, rhs, s))) return rc;
+    lag_pcg_info pi;
+    rc = lag_pcg(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
+    if (rc != LAG_OK && rc != LAG_EBREAKDOWN) return rc;
+    loc.pcg_iters += pi.iters;
+    loc.matvecs += pi.matvecs;
+    if ((rc = launch_dot(P, n, g, dv, sc + 12, s))) return rc;
+    if ((rc = read_scalars(P, h + 4, 12, 1, s))) return rc;
+    const double slope = h[4];
+    double mu = 1.0;
+    bool accepted = false;
+    for (int k = 0; k <= o.max_halvings; ++k) {
+      if ((rc = launch_axpby(n, 1.f, v, (float)mu, dv, vt, s))) return rc;
+      if ((rc = objective_full(P, vt, T, R, nullptr, nullptr, sc + 13, s))) return rc;
+      if ((rc = read_scalars(P, h + 5, 13, 1, s))) return rc;
+      if (h[5] <= J + o.armijo_c1 * mu * slope) {
+        accepted = true;
+        break;
+      }
+      mu *= 0.5;
+    }
+    loc.iters = it + 1;
+    if (!accepted) {
+      status = LAG_ELINESEARCH;
+      break;
+    }
+    if ((rc = launch_axpby(n, 1.f, vt, 0.f, nullptr, v, s))) return rc;
+    loc.J = h[5];
+  }
+  if (status == LAG_OK && !loc.converged && o.max_gn > 0) {
+    // report the gradient at the final iterate
+    if ((rc = lag_gradient(P, v, T, R, g, sc + 8, stream))) return rc;
+    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
+    loc.J = h[0];
+    loc.gnorm = sqrt(h[3]);
+    loc.converged = loc.gnorm <= o.gtol * loc.g0;
+  }
+  if (info) *info = loc;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Reductions and vector updates for the Gauss-Newton-Krylov driver.
+//
+// Inner products and the SSD distance (eq. SSD) accumulate in float64 with a
+// fixed grid and a fixed reduction tree, so their results do not depend on
+// scheduling.  PCG scalars stay on the device: the update kernels read
+// alpha = (r.z)/(p.Hp) and beta = (r.z)_new/(r.z)_old from device memory.
+
+#include "lag_internal.hpp"
+
+namespace lag {
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_dot_partial(const float* __restrict__ x, const float* __restrict__ y,
+                                                         long long n, double* __restrict__ part) {
+  __shared__ double sh[kBlock];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    s += (double)x[i] * (double)y[i];
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// SSD partials; also writes wres = scale * (u - R) when wres != null
+__global__ void __launch_bounds__(kBlock) k_ssd_partial(const float* __restrict__ u, const float* __restrict__ R,
+                                                         float* __restrict__ wres, float scale, long long n,
+                                                         double* __restrict__ part) {
+  __shared__ double sh[kBlock];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    float r = u[i] - R[i];
+    s += (double)r * (double)r;
+    if (wres) wres[i] = scale * r;
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__ part, int nparts, double scale,
+                                                       double* __restrict__ dst) {
+  __shared__ double sh[kBlock];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) *dst = scale * t;
+}
+
+static int reduce_launch(long long n, unsigned& blocks) {
+  long long b = (n + kBlock - 1) / kBlock;
+  if (b > kRedBlocks) b = kRedBlocks;
+  if (b < 1) b = 1;
+  blocks = (unsigned)b;
+  return 0;
+}
+
+int launch_dot(lag_plan P, long long n, const float* x, const float* y, double* dst, hipStream_t s) {
+  unsigned blocks;
+  reduce_launch(n, blocks);
+  hipLaunchKernelGGL(k_dot_partial, dim3(blocks), dim3(kBlock), 0, s, x, y, n, P->red_partial);
+  LAG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, P->red_partial, (int)blocks, 1.0, dst);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float scale, double* dst, hipStream_t s) {
+  unsigned blocks;
+  const long long n = P->geo.np;
+  reduce_launch(n, blocks);
+  hipLaunchKernelGGL(k_ssd_partial, dim3(blocks), dim3(kBlock), 0, s, u, R, wres, scale, n, P->red_partial);
+  LAG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, P->red_partial, (int)blocks,
+                     0.5 * (double)P->geo.cell_img, dst);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+__global__ void __launch_bounds__(kBlock) k_axpy(long long n, float a, const float* __restrict__ x,
+                                                  float* __restrict__ y) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fmaf(a, x[i], y[i]);
+}
+
+int launch_axpy(long long n, float a, const float* x, float* y, hipStream_t s) {
+  if (n <= 0) return LAG_OK;
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, a, x, y);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+__global__ void k_combine_J(double* s3, double alpha) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) s3[0] = s3[1] + alpha * s3[2];
+}
+
+int launch_combine_J(double* s3, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine_J, dim3(1), dim3(64), 0, s, s3, alpha);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+// ---- PCG updates with device scalars --------------------------------------
+// sc[0] = r.z (current), sc[1] = p.Hp, sc[2] = r.z (new), sc[3] = r.r,
+// sc[4] = breakdown flag (p.Hp <= 0)
+
+__global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restrict__ x, float* __restrict__ r,
+                                                    const float* __restrict__ p, const float* __restrict__ Hp,
+                                                    double* __restrict__ sc) {
+  const double pHp = sc[1];
+  const bool ok = pHp > 0.0;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && !ok) sc[4] = 1.0;
+  if (!ok || i >= n) return;
+  const float a = (float)(sc[0] / pHp);
+  x[i] = fmaf(a, p[i], x[i]);
+  r[i] = fmaf(-a, Hp[i], r[i]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_pcg_p(long long n, float* __restrict__ p, const float* __restrict__ z,
+                                                   const double* __restrict__ sc) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float beta = (float)(sc[2] / sc[0]);
+  p[i] = fmaf(beta, p[i], z[i]);
+}
+
+__global__ void k_pcg_roll(double* sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = sc[2];
+}
+
+int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_xr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, x, r, p, Hp, sc);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_pcg_p(long long n, float* p, const float* z, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_p, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, p, z, sc);
+  LAG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_pcg_roll, dim3(1), dim3(64), 0, s, sc);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale_mul(long long n, float c, const float* __restrict__ a,
+                                                       const float* __restrict__ w, float* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float v = c * a[i];
+  if (w) v *= w[i];
+  out[i] = v;
+}
+
+int launch_scale_mul(long long n, float c, const float* a, const float* w, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_mul, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, c, a, w, out);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy_axpby(long long n, float a, const float* __restrict__ x, float b,
+                                                        const float* __restrict__ y, float* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + (y ? b * y[i] : 0.f);
+}
+
+int launch_axpby(long long n, float a, const float* x, float b, const float* y, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_axpby, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, a, x, b, y,
+                     out);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+}  // namespace lag

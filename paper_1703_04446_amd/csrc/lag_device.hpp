@@ -1,0 +1,318 @@
+// Device-side building blocks shared by the laglddmm kernels (gfx950).
+//
+// Geometry: periodic cell-centred grids.  A characteristic is identified by
+// its start image cell (integer multi-index) and carries its displacement
+// phi from that cell centre.  Its fractional cell coordinate on a grid with
+// m_G cells per axis is s = (i + 1/2) m_G/m_img - 1/2 + phi m_G/L; the
+// integer part of the constant term is kept as an int and only the small
+// fractional remainder is added to phi m_G/L in float32, so cell selection
+// loses no precision to large absolute coordinates.
+//
+// Interpolation (Sec. 3.1): trilinear (bilinear) in space per velocity
+// component, linear in time between velocity nodes.  Velocities are packed
+// per node as float4 {vx, vy, vz, 0} (3-D) or float2 {vx, vy} (2-D) so one
+// corner of one sample is one vector load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lag {
+
+constexpr int kBlock = 256;        // threads per block for point kernels
+constexpr int kXcds = 8;           // MI355X: 8 XCDs, blocks dispatched round-robin
+
+template <int D> struct VecT;
+template <> struct VecT<2> { using T = float2; };
+template <> struct VecT<3> { using T = float4; };
+
+// Launch-time geometry of one problem (passed by value).
+struct Geo {
+  int dim;
+  int nodes;
+  int nsteps;
+  int mi[3];            // image cells per axis (unused axes 1)
+  int mv[3];            // velocity cells per axis
+  float inv_hi[3];      // m_img / L
+  float inv_hv[3];      // m_vel / L
+  double ratio[3];      // m_vel / m_img
+  long long np;         // image cells = characteristics
+  long long nv;         // velocity cells per field
+  float cell_img;       // image cell volume h^d
+};
+
+// Per-call RK4 stage-time table: for stage q = 4k + s the lower node j0 and
+// the weight theta of node j0 + 1 (linear interpolation in time).
+struct Stages {
+  const int* j0;
+  const float* th;
+  float dt;
+};
+
+// Brick decomposition used by kernels that accumulate into the velocity
+// grid through an LDS tile.
+struct Bricks {
+  int bdim[3];        // brick size in image cells
+  int nb[3];          // bricks per axis
+  int nbricks;        // total
+  int stride[3];      // lane stride in image cells (about m_img / m_vel)
+  int rdim[3];        // wave region = (4 or 8) * stride per axis
+  int nreg[3];        // regions per brick per axis
+  int tdim[3];        // LDS tile size in velocity cells
+  int halo;           // tile margin in velocity cells
+  int tvol;           // tdim product
+};
+
+__device__ __forceinline__ int wrapi(int c, int m) {
+  if ((unsigned)c < (unsigned)m) return c;
+  int r = c % m;
+  return r < 0 ? r + m : r;
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// XCD-aware block remap: consecutive logical blocks land on the same XCD so
+// each XCD's L2 sees a compact part of the grid.  Launch kXcds*ceil(n/kXcds)
+// blocks; returns -1 for the padding blocks.
+__device__ __forceinline__ long long xcd_block(long long nlogical) {
+  long long b = blockIdx.x;
+  long long per = (nlogical + kXcds - 1) / kXcds;
+  long long id = (b % kXcds) * per + b / kXcds;
+  return id < nlogical ? id : -1;
+}
+
+template <int D>
+struct Start {
+  int i[D];          // image cell multi-index
+  int cv[D];         // integer part of the start coordinate on the velocity grid
+  float fv[D];       // fractional part (exact for power-of-two ratios)
+};
+
+template <int D>
+__device__ __forceinline__ void make_start(const Geo& g, long long p, Start<D>& S) {
+  long long r = p;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S.i[a] = (int)(r % g.mi[a]);
+    r /= g.mi[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    double s = ((double)S.i[a] + 0.5) * g.ratio[a] - 0.5;
+    double fl = floor(s);
+    S.cv[a] = (int)fl;
+    S.fv[a] = (float)(s - fl);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void make_start_idx(const Geo& g, const int idx[D], Start<D>& S) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S.i[a] = idx[a];
+    double s = ((double)idx[a] + 0.5) * g.ratio[a] - 0.5;
+    double fl = floor(s);
+    S.cv[a] = (int)fl;
+    S.fv[a] = (float)(s - fl);
+  }
+}
+
+template <int D> struct Loc { int c[D]; float f[D]; };
+
+// Point on the velocity grid.
+template <int D>
+__device__ __forceinline__ void locate_v(const Geo& g, const Start<D>& S, const float phi[D], Loc<D>& L) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float t = fmaf(phi[a], g.inv_hv[a], S.fv[a]);
+    float fl = floorf(t);
+    L.c[a] = S.cv[a] + (int)fl;
+    L.f[a] = t - fl;
+  }
+}
+
+// Point on the image grid (start coordinate is the integer cell itself).
+template <int D>
+__device__ __forceinline__ void locate_i(const Geo& g, const Start<D>& S, const float phi[D], Loc<D>& L) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float t = phi[a] * g.inv_hi[a];
+    float fl = floorf(t);
+    L.c[a] = S.i[a] + (int)fl;
+    L.f[a] = t - fl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vector field sampling: value and (optionally) spatial Jacobian G[c][a] =
+// d v_c / d y_a of the trilinear interpolant.  One-sided on grid lines
+// (the floor-selected cell), consistent with the oracle.
+template <bool GRAD>
+__device__ __forceinline__ void sample_vec(const float4* __restrict__ f, const Geo& g, const Loc<3>& L,
+                                           float val[3], float G[3][3]) {
+  const int mx = g.mv[0], my = g.mv[1], mz = g.mv[2];
+  int x0 = wrapi(L.c[0], mx), y0 = wrapi(L.c[1], my), z0 = wrapi(L.c[2], mz);
+  int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
+  int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
+  int z1 = (z0 + 1 == mz) ? 0 : z0 + 1;
+  int r00 = (z0 * my + y0) * mx, r01 = (z0 * my + y1) * mx;
+  int r10 = (z1 * my + y0) * mx, r11 = (z1 * my + y1) * mx;
+  float4 a000 = f[r00 + x0], a100 = f[r00 + x1];
+  float4 a010 = f[r01 + x0], a110 = f[r01 + x1];
+  float4 a001 = f[r10 + x0], a101 = f[r10 + x1];
+  float4 a011 = f[r11 + x0], a111 = f[r11 + x1];
+  const float fx = L.f[0], fy = L.f[1], fz = L.f[2];
+#define LAG_COMP(c, FLD)                                                         \
+  {                                                                             \
+    float e00 = lerpf(a000.FLD, a100.FLD, fx), e10 = lerpf(a010.FLD, a110.FLD, fx); \
+    float e01 = lerpf(a001.FLD, a101.FLD, fx), e11 = lerpf(a011.FLD, a111.FLD, fx); \
+    float g0 = lerpf(e00, e10, fy), g1 = lerpf(e01, e11, fy);                   \
+    val[c] = lerpf(g0, g1, fz);                                                 \
+    if (GRAD) {                                                                 \
+      G[c][2] = (g1 - g0) * g.inv_hv[2];                                        \
+      G[c][1] = lerpf(e10 - e00, e11 - e01, fz) * g.inv_hv[1];                  \
+      float d0 = lerpf(a100.FLD - a000.FLD, a110.FLD - a010.FLD, fy);           \
+      float d1 = lerpf(a101.FLD - a001.FLD, a111.FLD - a011.FLD, fy);           \
+      G[c][0] = lerpf(d0, d1, fz) * g.inv_hv[0];                                \
+    }                                                                           \
+  }
+  LAG_COMP(0, x)
+  LAG_COMP(1, y)
+  LAG_COMP(2, z)
+#undef LAG_COMP
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void sample_vec(const float2* __restrict__ f, const Geo& g, const Loc<2>& L,
+                                           float val[2], float G[2][2]) {
+  const int mx = g.mv[0], my = g.mv[1];
+  int x0 = wrapi(L.c[0], mx), y0 = wrapi(L.c[1], my);
+  int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
+  int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
+  float2 a00 = f[y0 * mx + x0], a10 = f[y0 * mx + x1];
+  float2 a01 = f[y1 * mx + x0], a11 = f[y1 * mx + x1];
+  const float fx = L.f[0], fy = L.f[1];
+#define LAG_COMP(c, FLD)                                                   \
+  {                                                                       \
+    float e0 = lerpf(a00.FLD, a10.FLD, fx), e1 = lerpf(a01.FLD, a11.FLD, fx); \
+    val[c] = lerpf(e0, e1, fy);                                           \
+    if (GRAD) {                                                           \
+      G[c][1] = (e1 - e0) * g.inv_hv[1];                                  \
+      G[c][0] = lerpf(a10.FLD - a00.FLD, a11.FLD - a01.FLD, fy) * g.inv_hv[0]; \
+    }                                                                     \
+  }
+  LAG_COMP(0, x)
+  LAG_COMP(1, y)
+#undef LAG_COMP
+}
+
+// Velocity (and Jacobian) at stage q of the current sweep: stationary fields
+// have one node; otherwise blend nodes j0 and j0+1 with weight theta.
+template <int D, bool NS, bool GRAD>
+__device__ __forceinline__ void sample_vel(const typename VecT<D>::T* __restrict__ f, const Geo& g,
+                                           const Stages& st, int q, const Loc<D>& L,
+                                           float val[D], float G[D][D]) {
+  if (!NS) {
+    sample_vec<GRAD>(f, g, L, val, G);
+  } else {
+    int j0 = st.j0[q];
+    float th = st.th[q];
+    float v0[D], v1[D], G0[D][D], G1[D][D];
+    sample_vec<GRAD>(f + (long long)j0 * g.nv, g, L, v0, G0);
+    sample_vec<GRAD>(f + (long long)(j0 + 1) * g.nv, g, L, v1, G1);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      val[c] = lerpf(v0[c], v1[c], th);
+      if (GRAD) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) G[c][a] = lerpf(G0[c][a], G1[c][a], th);
+      }
+    }
+  }
+}
+
+// Scalar image sampling: value and gradient of the (bi/tri)linear interpolant.
+template <int D, bool VAL, bool GRAD>
+__device__ __forceinline__ void sample_img(const float* __restrict__ T, const Geo& g, const Loc<D>& L,
+                                           float& val, float grad[D]) {
+  if constexpr (D == 3) {
+    const int mx = g.mi[0], my = g.mi[1], mz = g.mi[2];
+    int x0 = wrapi(L.c[0], mx), y0 = wrapi(L.c[1], my), z0 = wrapi(L.c[2], mz);
+    int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
+    int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
+    int z1 = (z0 + 1 == mz) ? 0 : z0 + 1;
+    long long r00 = ((long long)z0 * my + y0) * mx, r01 = ((long long)z0 * my + y1) * mx;
+    long long r10 = ((long long)z1 * my + y0) * mx, r11 = ((long long)z1 * my + y1) * mx;
+    float a000 = T[r00 + x0], a100 = T[r00 + x1], a010 = T[r01 + x0], a110 = T[r01 + x1];
+    float a001 = T[r10 + x0], a101 = T[r10 + x1], a011 = T[r11 + x0], a111 = T[r11 + x1];
+    const float fx = L.f[0], fy = L.f[1], fz = L.f[2];
+    float e00 = lerpf(a000, a100, fx), e10 = lerpf(a010, a110, fx);
+    float e01 = lerpf(a001, a101, fx), e11 = lerpf(a011, a111, fx);
+    float g0 = lerpf(e00, e10, fy), g1 = lerpf(e01, e11, fy);
+    if (VAL) val = lerpf(g0, g1, fz);
+    if (GRAD) {
+      grad[2] = (g1 - g0) * g.inv_hi[2];
+      grad[1] = lerpf(e10 - e00, e11 - e01, fz) * g.inv_hi[1];
+      float d0 = lerpf(a100 - a000, a110 - a010, fy);
+      float d1 = lerpf(a101 - a001, a111 - a011, fy);
+      grad[0] = lerpf(d0, d1, fz) * g.inv_hi[0];
+    }
+  } else {
+    const int mx = g.mi[0], my = g.mi[1];
+    int x0 = wrapi(L.c[0], mx), y0 = wrapi(L.c[1], my);
+    int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
+    int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
+    float a00 = T[(long long)y0 * mx + x0], a10 = T[(long long)y0 * mx + x1];
+    float a01 = T[(long long)y1 * mx + x0], a11 = T[(long long)y1 * mx + x1];
+    const float fx = L.f[0], fy = L.f[1];
+    float e0 = lerpf(a00, a10, fx), e1 = lerpf(a01, a11, fx);
+    if (VAL) val = lerpf(e0, e1, fy);
+    if (GRAD) {
+      grad[1] = (e1 - e0) * g.inv_hi[1];
+      grad[0] = lerpf(a10 - a00, a11 - a01, fy) * g.inv_hi[0];
+    }
+  }
+}
+
+// Corner weights of a linear stencil, corner code bit a = offset along axis a.
+template <int D>
+__device__ __forceinline__ void corner_weights(const Loc<D>& L, float w[1 << D]) {
+#pragma unroll
+  for (int o = 0; o < (1 << D); ++o) {
+    float p = 1.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) p *= ((o >> a) & 1) ? L.f[a] : 1.f - L.f[a];
+    w[o] = p;
+  }
+}
+
+// Derivatives of the corner weights with respect to the physical position.
+template <int D>
+__device__ __forceinline__ void corner_dweights(const Loc<D>& L, const float inv_h[3], float dw[1 << D][D]) {
+#pragma unroll
+  for (int o = 0; o < (1 << D); ++o) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float p = ((o >> a) & 1) ? inv_h[a] : -inv_h[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        if (b != a) p *= ((o >> b) & 1) ? L.f[b] : 1.f - L.f[b];
+      dw[o][a] = p;
+    }
+  }
+}
+
+// Flat index (x fastest) of corner o of the cell at L on a grid of size m.
+template <int D>
+__device__ __forceinline__ long long corner_index(const Loc<D>& L, const int m[3], int o) {
+  long long idx = 0, stride = 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int c = wrapi(L.c[a] + ((o >> a) & 1), m[a]);
+    idx += (long long)c * stride;
+    stride *= m[a];
+  }
+  return idx;
+}
+
+}  // namespace lag

@@ -1,0 +1,100 @@
+// Host-side internals of liblaglddmm: the plan object, status helpers and
+// the launchers each translation unit exports to the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "laglddmm.h"
+#include "lag_device.hpp"
+
+struct lag_plan_s {
+  lag_problem prob;
+  int device = 0;
+  lag::Geo geo{};
+  lag::Bricks bricks{};
+  int fields = 0;              // nodes * dim velocity fields
+  long long n_unknowns = 0;
+
+  // packed copies of velocity-shaped inputs (float2/float4 per node)
+  void* pack_v = nullptr;
+  void* pack_p = nullptr;
+  // RK4 stage tables, [0] for dir = -1 and [1] for dir = +1 (4N entries)
+  int* st_j0[2] = {nullptr, nullptr};
+  float* st_th[2] = {nullptr, nullptr};
+  // time-node weights of the regulariser (host copy and device scale table)
+  double node_w[64];
+  float* reg_scale = nullptr;  // per node: alpha h_v^d w_j
+  // image-sized scratch
+  float* img_a = nullptr;
+  float* img_b = nullptr;
+  float* phi = nullptr;        // dim * np
+  // deterministic binning (continuity)
+  int* bin_count = nullptr;    // np + 1
+  int* bin_start = nullptr;    // np + 1
+  int* bin_cursor = nullptr;   // np
+  int* bin_items = nullptr;    // np
+  int* part_base = nullptr;    // np
+  float* part_vals = nullptr;  // 2^d * np
+  int* scan_blocks = nullptr;  // block sums for the scan
+  // reductions
+  double* red_partial = nullptr;  // kRedBlocks
+  double* scalars = nullptr;      // 16 device scalars
+  // velocity-sized scratch (PCG / GN vectors)
+  float* vec[10] = {nullptr};
+  // spectral preconditioner
+  int fft_ok = 0;
+  float2* fft_buf = nullptr;   // fields * nv complex
+  float2* fft_tw[3] = {nullptr, nullptr, nullptr};
+  float* fft_lam[3] = {nullptr, nullptr, nullptr};
+  float* fft_mu1 = nullptr;    // per node replacement for a zero mode
+  int fft_rad[3][16];
+  int fft_nrad[3];
+  // status flags written by kernels (bit 0: singular RK4 step Jacobian)
+  int* flags = nullptr;
+};
+
+namespace lag {
+
+constexpr int kRedBlocks = 1024;
+
+int set_hip_error(hipError_t e);   // records the message, returns LAG_EHIP
+#define LAG_HIP(call)                                    \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) return ::lag::set_hip_error(_e); \
+  } while (0)
+#define LAG_LAUNCH_CHECK() LAG_HIP(hipGetLastError())
+
+// ---- launchers (each returns a LAG_* status) -----------------------------
+int launch_pack(lag_plan P, const float* v, void* dst, hipStream_t s);
+int launch_fill(float* x, long long n, float val, hipStream_t s);
+int launch_zero_i(int* x, long long n, hipStream_t s);
+// deterministic binned scatter of per-particle corner values (part_base/part_vals)
+int bin_and_gather(lag_plan P, float* out, hipStream_t s);
+int launch_trace(lag_plan P, const void* vpack, int dir, float* phi, hipStream_t s);
+int launch_transport(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s);
+int launch_pushforward(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s);
+int launch_jvp(lag_plan P, const void* vpack, const void* dpack, const float* T, float* out,
+               hipStream_t s);
+// seed: transport -> per-characteristic weights w (image-shaped);
+//       continuity -> image-shaped field w whose interpolant gradient is taken.
+int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, float* out,
+               hipStream_t s);
+int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
+                          const float* wvox, float* out, hipStream_t s);
+int launch_reg(lag_plan P, const float* p, float* out, int accumulate, int with_gamma,
+               float extra_scale, hipStream_t s);
+int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s);
+int precond_setup(lag_plan P);     // host tables + allocations (plan creation)
+
+// reductions: result written to dst (device double)
+int launch_dot(lag_plan P, long long n, const float* x, const float* y, double* dst, hipStream_t s);
+// D = h^d/2 |u - R|^2 -> dst; wres = scale * (u - R) if wres != null
+int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float scale, double* dst,
+               hipStream_t s);
+int launch_axpy(long long n, float a, const float* x, float* y, hipStream_t s);
+int launch_combine_J(double* s3, double alpha, hipStream_t s);
+
+}  // namespace lag

@@ -1,0 +1,870 @@
+// RK4 characteristics, transport, Jacobian products and the fused
+// Gauss-Newton matvec (transport model) for gfx950.
+//
+// Algorithm 1 (RK4 with the derivative recursion) is evaluated per
+// characteristic, one thread per characteristic, in float32 with the
+// position kept as a displacement from the start cell centre.
+//
+// Jacobian-transpose products need the adjoint of the RK4 map.  Instead of
+// storing the trajectory (which would make memory grow with N) the kernels
+// make two forward sweeps:
+//   pass 1: positions, the tangent (for J p) and the flow Jacobian
+//           F = d y_N / d y_0 = M_{N-1} ... M_0, M_k the RK4 step Jacobian;
+//   seed:   ybar_N from the image side, ybar_0 = F^T ybar_N;
+//   pass 2: recompute each step's stages, recover ybar_{k+1} = M_k^{-T}
+//           ybar_k by a d x d solve, form the stage adjoints and scatter
+//           them onto the velocity grid.
+// This is the exact discrete adjoint (up to rounding) with O(1) state per
+// characteristic, the memory property the paper stresses for its forward
+// recursion.  Positions are formed with explicit fmaf so both passes select
+// bit-identical interpolation cells.
+//
+// Velocity-grid accumulation goes through an LDS tile per brick of image
+// cells (float atomics in LDS, then one atomic per touched tile node into
+// global memory); points whose stencil leaves the tile fall back to global
+// atomics, so results never depend on the tile margin.
+
+#include "lag_internal.hpp"
+
+namespace lag {
+
+// ---------------------------------------------------------------------------
+// small dense helpers
+template <int D>
+__device__ __forceinline__ void matmul(const float A[D][D], const float B[D][D], float C[D][D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < D; ++k) s = fmaf(A[i][k], B[k][j], s);
+      C[i][j] = s;
+    }
+}
+
+// Jacobian of one RK4 step, M = I + dt/6 (K1 + 2 K2 + 2 K3 + K4) with
+// K1 = G1, K2 = G2 (I + dt/2 K1), K3 = G3 (I + dt/2 K2), K4 = G4 (I + dt K3).
+template <int D>
+__device__ __forceinline__ void step_jacobian(float dt, const float G1[D][D], const float G2[D][D],
+                                              const float G3[D][D], const float G4[D][D], float M[D][D]) {
+  float A[D][D], K2[D][D], K3[D][D], K4[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) A[i][j] = (i == j ? 1.f : 0.f) + 0.5f * dt * G1[i][j];
+  matmul<D>(G2, A, K2);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) A[i][j] = (i == j ? 1.f : 0.f) + 0.5f * dt * K2[i][j];
+  matmul<D>(G3, A, K3);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) A[i][j] = (i == j ? 1.f : 0.f) + dt * K3[i][j];
+  matmul<D>(G4, A, K4);
+  const float c = dt / 6.f;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      M[i][j] = (i == j ? 1.f : 0.f) + c * (G1[i][j] + 2.f * K2[i][j] + 2.f * K3[i][j] + K4[i][j]);
+}
+
+// Solve M^T x = b; returns false if M is (numerically) singular.
+__device__ __forceinline__ bool solveT(const float M[3][3], const float b[3], float x[3]) {
+  // rows of M^T are the columns of M
+  float a00 = M[0][0], a01 = M[1][0], a02 = M[2][0];
+  float a10 = M[0][1], a11 = M[1][1], a12 = M[2][1];
+  float a20 = M[0][2], a21 = M[1][2], a22 = M[2][2];
+  float c00 = a11 * a22 - a12 * a21, c01 = a12 * a20 - a10 * a22, c02 = a10 * a21 - a11 * a20;
+  float det = a00 * c00 + a01 * c01 + a02 * c02;
+  if (!(fabsf(det) > 1e-20f)) return false;
+  float inv = 1.f / det;
+  float c10 = a02 * a21 - a01 * a22, c11 = a00 * a22 - a02 * a20, c12 = a01 * a20 - a00 * a21;
+  float c20 = a01 * a12 - a02 * a11, c21 = a02 * a10 - a00 * a12, c22 = a00 * a11 - a01 * a10;
+  x[0] = (c00 * b[0] + c10 * b[1] + c20 * b[2]) * inv;
+  x[1] = (c01 * b[0] + c11 * b[1] + c21 * b[2]) * inv;
+  x[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * inv;
+  return true;
+}
+__device__ __forceinline__ bool solveT(const float M[2][2], const float b[2], float x[2]) {
+  float det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  if (!(fabsf(det) > 1e-20f)) return false;
+  float inv = 1.f / det;
+  // M^T = [[M00, M10], [M01, M11]]
+  x[0] = (M[1][1] * b[0] - M[1][0] * b[1]) * inv;
+  x[1] = (-M[0][1] * b[0] + M[0][0] * b[1]) * inv;
+  return true;
+}
+
+// Stage positions and the state update, with explicit fmaf so that every
+// sweep rounds identically.
+template <int D>
+__device__ __forceinline__ void stage_pos(const float phi[D], float c, const float k[D], float P[D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) P[a] = fmaf(c, k[a], phi[a]);
+}
+template <int D>
+__device__ __forceinline__ void rk4_update(float phi[D], float dt, const float k1[D], const float k2[D],
+                                           const float k3[D], const float k4[D]) {
+  const float c = dt * (1.f / 6.f);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float s = fmaf(2.f, k2[a], k1[a]);
+    s = fmaf(2.f, k3[a], s);
+    s = s + k4[a];
+    phi[a] = fmaf(c, s, phi[a]);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void matvec_acc(const float G[D][D], const float x[D], const float e[D], float y[D]) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    float s = e[c];
+#pragma unroll
+    for (int a = 0; a < D; ++a) s = fmaf(G[c][a], x[a], s);
+    y[c] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: positions, optional tangent (direction field dp) and flow Jacobian.
+template <int D, bool NS, bool TAN, bool FJ>
+__device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
+                                             const typename VecT<D>::T* __restrict__ vp,
+                                             const typename VecT<D>::T* __restrict__ dp,
+                                             const Start<D>& S, float phi[D], float dphi[D],
+                                             float F[D][D]) {
+  constexpr bool GR = TAN || FJ;
+  const float dt = st.dt, hdt = 0.5f * dt;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    phi[a] = 0.f;
+    dphi[a] = 0.f;
+#pragma unroll
+    for (int b = 0; b < D; ++b) F[a][b] = (a == b) ? 1.f : 0.f;
+  }
+  for (int k = 0; k < g.nsteps; ++k) {
+    const int q = 4 * k;
+    float k1[D], k2[D], k3[D], k4[D], P[D];
+    float G1[D][D], G2[D][D], G3[D][D], G4[D][D];
+    float e[D], Dk[D], Dsum[D], X[D], dummy[D][D];
+    Loc<D> L;
+    // stage 1 at phi
+    locate_v<D>(g, S, phi, L);
+    sample_vel<D, NS, GR>(vp, g, st, q, L, k1, G1);
+    if (TAN) {
+      sample_vel<D, NS, false>(dp, g, st, q, L, e, dummy);
+      matvec_acc<D>(G1, dphi, e, Dk);
+#pragma unroll
+      for (int a = 0; a < D; ++a) { Dsum[a] = Dk[a]; X[a] = fmaf(hdt, Dk[a], dphi[a]); }
+    }
+    // stage 2 at phi + dt/2 k1
+    stage_pos<D>(phi, hdt, k1, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, NS, GR>(vp, g, st, q + 1, L, k2, G2);
+    if (TAN) {
+      sample_vel<D, NS, false>(dp, g, st, q + 1, L, e, dummy);
+      matvec_acc<D>(G2, X, e, Dk);
+#pragma unroll
+      for (int a = 0; a < D; ++a) { Dsum[a] = fmaf(2.f, Dk[a], Dsum[a]); X[a] = fmaf(hdt, Dk[a], dphi[a]); }
+    }
+    // stage 3 at phi + dt/2 k2
+    stage_pos<D>(phi, hdt, k2, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, NS, GR>(vp, g, st, q + 2, L, k3, G3);
+    if (TAN) {
+      sample_vel<D, NS, false>(dp, g, st, q + 2, L, e, dummy);
+      matvec_acc<D>(G3, X, e, Dk);
+#pragma unroll
+      for (int a = 0; a < D; ++a) { Dsum[a] = fmaf(2.f, Dk[a], Dsum[a]); X[a] = fmaf(dt, Dk[a], dphi[a]); }
+    }
+    // stage 4 at phi + dt k3
+    stage_pos<D>(phi, dt, k3, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, NS, GR>(vp, g, st, q + 3, L, k4, G4);
+    if (TAN) {
+      sample_vel<D, NS, false>(dp, g, st, q + 3, L, e, dummy);
+      matvec_acc<D>(G4, X, e, Dk);
+#pragma unroll
+      for (int a = 0; a < D; ++a) dphi[a] = fmaf(dt * (1.f / 6.f), Dsum[a] + Dk[a], dphi[a]);
+    }
+    if (FJ) {
+      float M[D][D], Fn[D][D];
+      step_jacobian<D>(dt, G1, G2, G3, G4, M);
+      matmul<D>(M, F, Fn);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) F[a][b] = Fn[a][b];
+    }
+    rk4_update<D>(phi, dt, k1, k2, k3, k4);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Velocity-grid accumulator: LDS tile of a brick with global fallback.
+template <int D, bool NS>
+struct TileAcc {
+  float* lds;
+  float* gout;
+  const int* j0;
+  const float* th;
+  int org[3];
+  int td[3];
+  int mv[3];
+  int tvol;
+  long long nv;
+
+  __device__ __forceinline__ void add(const Loc<D>& L, int q, const float kb[D]) const {
+    float w[1 << D];
+    corner_weights<D>(L, w);
+    int jA = 0;
+    float wA = 1.f, wB = 0.f;
+    if (NS) {
+      jA = j0[q];
+      wB = th[q];
+      wA = 1.f - wB;
+    }
+    bool in = true;
+    int t[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      t[a] = L.c[a] - org[a];
+      in = in && (t[a] >= 0) && (t[a] + 1 < td[a]);
+    }
+    if (in) {
+      int base = (t[2] * td[1] + t[1]) * td[0] + t[0];
+#pragma unroll
+      for (int o = 0; o < (1 << D); ++o) {
+        int off = base + (o & 1) + ((o >> 1) & 1) * td[0];
+        if (D == 3) off += ((o >> 2) & 1) * td[0] * td[1];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          float val = w[o] * kb[c];
+          atomicAdd(&lds[(jA * D + c) * tvol + off], wA * val);
+          if (NS) atomicAdd(&lds[((jA + 1) * D + c) * tvol + off], wB * val);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int o = 0; o < (1 << D); ++o) {
+        long long gi = corner_index<D>(L, mv, o);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          float val = w[o] * kb[c];
+          unsafeAtomicAdd(&gout[(long long)(jA * D + c) * nv + gi], wA * val);
+          if (NS) unsafeAtomicAdd(&gout[(long long)((jA + 1) * D + c) * nv + gi], wB * val);
+        }
+      }
+    }
+  }
+};
+
+// pass 2: replay the sweep, recover the step adjoints and scatter them.
+template <int D, bool NS>
+__device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
+                                             const typename VecT<D>::T* __restrict__ vp,
+                                             const Start<D>& S, float ybar[D],
+                                             const TileAcc<D, NS>& acc) {
+  const float dt = st.dt, hdt = 0.5f * dt;
+  float phi[D];
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) phi[a] = 0.f;
+  for (int k = 0; k < g.nsteps; ++k) {
+    const int q = 4 * k;
+    float k1[D], k2[D], k3[D], k4[D], P[D];
+    float G1[D][D], G2[D][D], G3[D][D], G4[D][D];
+    Loc<D> L1, L2, L3, L4;
+    locate_v<D>(g, S, phi, L1);
+    sample_vel<D, NS, true>(vp, g, st, q, L1, k1, G1);
+    stage_pos<D>(phi, hdt, k1, P);
+    locate_v<D>(g, S, P, L2);
+    sample_vel<D, NS, true>(vp, g, st, q + 1, L2, k2, G2);
+    stage_pos<D>(phi, hdt, k2, P);
+    locate_v<D>(g, S, P, L3);
+    sample_vel<D, NS, true>(vp, g, st, q + 2, L3, k3, G3);
+    stage_pos<D>(phi, dt, k3, P);
+    locate_v<D>(g, S, P, L4);
+    sample_vel<D, NS, true>(vp, g, st, q + 3, L4, k4, G4);
+
+    float M[D][D], yn[D];
+    step_jacobian<D>(dt, G1, G2, G3, G4, M);
+    if (!solveT(M, ybar, yn)) {
+      ok = false;
+#pragma unroll
+      for (int a = 0; a < D; ++a) yn[a] = ybar[a];
+    }
+    // adjoints of the stage velocities
+    float kb[D], pb[D];
+    const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb[a] = c6 * yn[a];
+    acc.add(L4, q + 3, kb);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float s = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s = fmaf(G4[c][a], kb[c], s);
+      pb[a] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb[a] = fmaf(dt, pb[a], c3 * yn[a]);
+    acc.add(L3, q + 2, kb);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float s = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s = fmaf(G3[c][a], kb[c], s);
+      pb[a] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb[a] = fmaf(hdt, pb[a], c3 * yn[a]);
+    acc.add(L2, q + 1, kb);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float s = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s = fmaf(G2[c][a], kb[c], s);
+      pb[a] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb[a] = fmaf(hdt, pb[a], c6 * yn[a]);
+    acc.add(L1, q, kb);
+#pragma unroll
+    for (int a = 0; a < D; ++a) ybar[a] = yn[a];
+    rk4_update<D>(phi, dt, k1, k2, k3, k4);
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pack(const float* __restrict__ v, typename VecT<D>::T* __restrict__ out,
+                                                 long long nv, int nodes) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long tot = nv * nodes;
+  if (i >= tot) return;
+  long long j = i / nv, x = i - j * nv;
+  const float* b = v + j * D * nv + x;
+  if constexpr (D == 3) {
+    out[i] = make_float4(b[0], b[nv], b[2 * nv], 0.f);
+  } else {
+    out[i] = make_float2(b[0], b[nv]);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(float* __restrict__ x, long long n, float val) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = val;
+}
+
+template <int D, bool NS>
+__global__ void __launch_bounds__(kBlock) k_trace(Geo g, Stages st, const typename VecT<D>::T* __restrict__ vp,
+                                                  float* __restrict__ phi_out) {
+  long long blk = xcd_block((g.np + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  long long p = blk * kBlock + threadIdx.x;
+  if (p >= g.np) return;
+  Start<D> S;
+  make_start<D>(g, p, S);
+  float phi[D], dphi[D], F[D][D];
+  forward_pass<D, NS, false, false>(g, st, vp, nullptr, S, phi, dphi, F);
+#pragma unroll
+  for (int a = 0; a < D; ++a) phi_out[a * g.np + p] = phi[a];
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_transport(Geo g, const float* __restrict__ T, const float* __restrict__ phi,
+                                                      float* __restrict__ u) {
+  long long blk = xcd_block((g.np + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  long long p = blk * kBlock + threadIdx.x;
+  if (p >= g.np) return;
+  Start<D> S;
+  long long r = p;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S.i[a] = (int)(r % g.mi[a]);
+    r /= g.mi[a];
+  }
+  float ph[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) ph[a] = phi[a * g.np + p];
+  Loc<D> L;
+  locate_i<D>(g, S, ph, L);
+  float val, grad[D];
+  sample_img<D, true, false>(T, g, L, val, grad);
+  u[p] = val;
+}
+
+// transport JVP: Jdv_i = grad T(y_i) . dy_i
+template <int D, bool NS>
+__global__ void __launch_bounds__(kBlock) k_jvp_transport(Geo g, Stages st, const typename VecT<D>::T* __restrict__ vp,
+                                                          const typename VecT<D>::T* __restrict__ dp,
+                                                          const float* __restrict__ T, float* __restrict__ out) {
+  long long blk = xcd_block((g.np + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  long long p = blk * kBlock + threadIdx.x;
+  if (p >= g.np) return;
+  Start<D> S;
+  make_start<D>(g, p, S);
+  float phi[D], dphi[D], F[D][D];
+  forward_pass<D, NS, true, false>(g, st, vp, dp, S, phi, dphi, F);
+  Loc<D> L;
+  locate_i<D>(g, S, phi, L);
+  float val, gT[D];
+  sample_img<D, false, true>(T, g, L, val, gT);
+  float s = 0.f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) s = fmaf(gT[a], dphi[a], s);
+  out[p] = s;
+}
+
+// continuity JVP, first half: per particle, the 2^d corner contributions
+// T_j grad w_o(y_j) . dy_j and the base cell, plus the bin count.
+template <int D, bool NS>
+__global__ void __launch_bounds__(kBlock) k_jvp_cont_prep(Geo g, Stages st, const typename VecT<D>::T* __restrict__ vp,
+                                                          const typename VecT<D>::T* __restrict__ dp,
+                                                          const float* __restrict__ T, int* __restrict__ base,
+                                                          float* __restrict__ vals, int* __restrict__ count) {
+  long long blk = xcd_block((g.np + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  long long p = blk * kBlock + threadIdx.x;
+  if (p >= g.np) return;
+  Start<D> S;
+  make_start<D>(g, p, S);
+  float phi[D], dphi[D], F[D][D];
+  forward_pass<D, NS, true, false>(g, st, vp, dp, S, phi, dphi, F);
+  Loc<D> L;
+  locate_i<D>(g, S, phi, L);
+  float dw[1 << D][D];
+  corner_dweights<D>(L, g.inv_hi, dw);
+  const float m = T[p];
+#pragma unroll
+  for (int o = 0; o < (1 << D); ++o) {
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) s = fmaf(dw[o][a], dphi[a], s);
+    vals[(long long)o * g.np + p] = m * s;
+  }
+  int b = (int)corner_index<D>(L, g.mi, 0);
+  base[p] = b;
+  atomicAdd(&count[b], 1);
+}
+
+// push-forward, first half: corner weights times the particle mass.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_push_prep(Geo g, const float* __restrict__ T, const float* __restrict__ phi,
+                                                      int* __restrict__ base, float* __restrict__ vals,
+                                                      int* __restrict__ count) {
+  long long blk = xcd_block((g.np + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  long long p = blk * kBlock + threadIdx.x;
+  if (p >= g.np) return;
+  Start<D> S;
+  long long r = p;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S.i[a] = (int)(r % g.mi[a]);
+    r /= g.mi[a];
+  }
+  float ph[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) ph[a] = phi[a * g.np + p];
+  Loc<D> L;
+  locate_i<D>(g, S, ph, L);
+  float w[1 << D];
+  corner_weights<D>(L, w);
+  const float m = T[p];
+#pragma unroll
+  for (int o = 0; o < (1 << D); ++o) vals[(long long)o * g.np + p] = m * w[o];
+  int b = (int)corner_index<D>(L, g.mi, 0);
+  base[p] = b;
+  atomicAdd(&count[b], 1);
+}
+
+// ---------------------------------------------------------------------------
+// brick kernels with an LDS accumulation tile
+
+template <int D>
+__device__ __forceinline__ void brick_origin(const Geo& g, const Bricks& B, long long bid, int O[3], int org[3]) {
+  int b0 = (int)(bid % B.nb[0]);
+  int b1 = (int)((bid / B.nb[0]) % B.nb[1]);
+  int b2 = (int)(bid / ((long long)B.nb[0] * B.nb[1]));
+  int bb[3] = {b0, b1, b2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    O[a] = bb[a] * B.bdim[a];
+    if (a < D) {
+      double s = ((double)O[a] + 0.5) * g.ratio[a] - 0.5;
+      org[a] = (int)floor(s) - B.halo;
+    } else {
+      org[a] = 0;
+    }
+  }
+}
+
+// Iterate over the characteristics of a brick.  Each wave takes (region,
+// phase) items; within an item the 64 lanes sit `stride` image cells apart so
+// that they start in distinct velocity cells (few LDS atomic collisions).
+template <int D, class Body>
+__device__ __forceinline__ void for_brick_points(const Geo& g, const Bricks& B, const int O[3], Body body) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int l[3];
+  if (D == 3) {
+    l[0] = lane & 3; l[1] = (lane >> 2) & 3; l[2] = lane >> 4;
+  } else {
+    l[0] = lane & 7; l[1] = lane >> 3; l[2] = 0;
+  }
+  const int P = B.stride[0] * B.stride[1] * B.stride[2];
+  const int nreg = B.nreg[0] * B.nreg[1] * B.nreg[2];
+  for (int w = wave; w < nreg * P; w += nw) {
+    int reg = w / P, ph = w - (w / P) * P;
+    int r0 = reg % B.nreg[0], r1 = (reg / B.nreg[0]) % B.nreg[1], r2 = reg / (B.nreg[0] * B.nreg[1]);
+    int p0 = ph % B.stride[0], p1 = (ph / B.stride[0]) % B.stride[1], p2 = ph / (B.stride[0] * B.stride[1]);
+    int idx[3];
+    idx[0] = O[0] + r0 * B.rdim[0] + l[0] * B.stride[0] + p0;
+    idx[1] = O[1] + r1 * B.rdim[1] + l[1] * B.stride[1] + p1;
+    idx[2] = O[2] + r2 * B.rdim[2] + l[2] * B.stride[2] + p2;
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) in = in && idx[a] < g.mi[a];
+    if (in) body(idx);
+  }
+}
+
+template <int D, bool NS>
+__device__ __forceinline__ void flush_tile(const Geo& g, const TileAcc<D, NS>& acc, int fields) {
+  __syncthreads();
+  const int tot = fields * acc.tvol;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    float val = acc.lds[i];
+    if (val == 0.f) continue;
+    int f = i / acc.tvol, r = i - f * acc.tvol;
+    int t0 = r % acc.td[0], t1 = (r / acc.td[0]) % acc.td[1], t2 = r / (acc.td[0] * acc.td[1]);
+    long long gi = wrapi(acc.org[0] + t0, g.mv[0]) + (long long)g.mv[0] * wrapi(acc.org[1] + t1, g.mv[1]);
+    if (D == 3) gi += (long long)g.mv[0] * g.mv[1] * wrapi(acc.org[2] + t2, g.mv[2]);
+    unsafeAtomicAdd(&acc.gout[(long long)f * acc.nv + gi], val);
+  }
+}
+
+template <int D, bool NS>
+__device__ __forceinline__ TileAcc<D, NS> make_acc(float* lds, float* gout, const Geo& g, const Stages& st,
+                                                   const Bricks& B, const int org[3], int fields) {
+  TileAcc<D, NS> acc;
+  acc.lds = lds;
+  acc.gout = gout;
+  acc.tvol = B.tvol;
+  acc.nv = g.nv;
+  acc.j0 = st.j0;
+  acc.th = st.th;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc.org[a] = org[a];
+    acc.td[a] = B.tdim[a];
+    acc.mv[a] = g.mv[a];
+  }
+  for (int i = threadIdx.x; i < fields * B.tvol; i += blockDim.x) lds[i] = 0.f;
+  __syncthreads();
+  return acc;
+}
+
+// VJP: MODEL 0 = transport (seed w_i grad T(y_i)),
+//      MODEL 1 = continuity (seed T_j grad I(w)(y_j)).
+template <int D, bool NS, int MODEL>
+__global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, const typename VecT<D>::T* __restrict__ vp,
+                                                const float* __restrict__ T, const float* __restrict__ w,
+                                                float* __restrict__ out, int* __restrict__ flags) {
+  extern __shared__ float lds[];
+  long long bid = xcd_block(B.nbricks);
+  if (bid < 0) return;
+  int O[3], org[3];
+  brick_origin<D>(g, B, bid, O, org);
+  const int fields = g.nodes * D;
+  TileAcc<D, NS> acc = make_acc<D, NS>(lds, out, g, st, B, org, fields);
+  bool bad = false;
+  for_brick_points<D>(g, B, O, [&](const int idx[3]) {
+    Start<D> S;
+    make_start_idx<D>(g, idx, S);
+    long long p = idx[0] + (long long)g.mi[0] * idx[1];
+    if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
+    float phi[D], dphi[D], F[D][D];
+    forward_pass<D, NS, false, true>(g, st, vp, nullptr, S, phi, dphi, F);
+    Loc<D> L;
+    locate_i<D>(g, S, phi, L);
+    float yN[D], val;
+    if (MODEL == 0) {
+      float gT[D];
+      sample_img<D, false, true>(T, g, L, val, gT);
+      const float wi = w[p];
+#pragma unroll
+      for (int a = 0; a < D; ++a) yN[a] = wi * gT[a];
+    } else {
+      float gw[D];
+      sample_img<D, false, true>(w, g, L, val, gw);
+      const float m = T[p];
+#pragma unroll
+      for (int a = 0; a < D; ++a) yN[a] = m * gw[a];
+    }
+    bool nz = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) nz = nz || (yN[a] != 0.f);
+    if (!nz) return;
+    float y0[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) s = fmaf(F[a][b], yN[a], s);
+      y0[b] = s;
+    }
+    if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) bad = true;
+  });
+  if (bad) atomicOr(flags, 1);
+  flush_tile<D, NS>(g, acc, fields);
+}
+
+// Fused transport Gauss-Newton data term: out += h^d J^T (W (J p)).
+template <int D, bool NS>
+__global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bricks B,
+                                                           const typename VecT<D>::T* __restrict__ vp,
+                                                           const typename VecT<D>::T* __restrict__ pp,
+                                                           const float* __restrict__ T, const float* __restrict__ wvox,
+                                                           float* __restrict__ out, int* __restrict__ flags) {
+  extern __shared__ float lds[];
+  long long bid = xcd_block(B.nbricks);
+  if (bid < 0) return;
+  int O[3], org[3];
+  brick_origin<D>(g, B, bid, O, org);
+  const int fields = g.nodes * D;
+  TileAcc<D, NS> acc = make_acc<D, NS>(lds, out, g, st, B, org, fields);
+  bool bad = false;
+  for_brick_points<D>(g, B, O, [&](const int idx[3]) {
+    Start<D> S;
+    make_start_idx<D>(g, idx, S);
+    long long p = idx[0] + (long long)g.mi[0] * idx[1];
+    if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
+    float W = wvox ? wvox[p] : 1.f;
+    if (W == 0.f) return;
+    float phi[D], dphi[D], F[D][D];
+    forward_pass<D, NS, true, true>(g, st, vp, pp, S, phi, dphi, F);
+    Loc<D> L;
+    locate_i<D>(g, S, phi, L);
+    float gT[D], val;
+    sample_img<D, false, true>(T, g, L, val, gT);
+    float Jp = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) Jp = fmaf(gT[a], dphi[a], Jp);
+    const float s = g.cell_img * W * Jp;
+    if (s == 0.f) return;
+    float yN[D], y0[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) yN[a] = s * gT[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float t = 0.f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) t = fmaf(F[a][b], yN[a], t);
+      y0[b] = t;
+    }
+    if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) bad = true;
+  });
+  if (bad) atomicOr(flags, 1);
+  flush_tile<D, NS>(g, acc, fields);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline unsigned grid_for(long long nlogical) {
+  long long per = (nlogical + kXcds - 1) / kXcds;
+  return (unsigned)(per * kXcds);
+}
+
+static inline Stages stages_for(lag_plan P, int dir) {
+  Stages st;
+  int k = dir < 0 ? 0 : 1;
+  st.j0 = P->st_j0[k];
+  st.th = P->st_th[k];
+  st.dt = (float)((double)dir / (double)P->prob.nsteps);
+  return st;
+}
+
+static inline int model_dir(lag_plan P) { return P->prob.model == LAG_TRANSPORT ? -1 : 1; }
+
+int launch_pack(lag_plan P, const float* v, void* dst, hipStream_t s) {
+  long long tot = P->geo.nv * P->geo.nodes;
+  unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
+  if (P->geo.dim == 3)
+    hipLaunchKernelGGL(k_pack<3>, dim3(grid), dim3(kBlock), 0, s, v, (float4*)dst, P->geo.nv, P->geo.nodes);
+  else
+    hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(kBlock), 0, s, v, (float2*)dst, P->geo.nv, P->geo.nodes);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_fill(float* x, long long n, float val, hipStream_t s) {
+  if (n <= 0) return LAG_OK;
+  unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, s, x, n, val);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+#define LAG_DISPATCH_DNS(KERNEL, ...)                                              \
+  do {                                                                             \
+    const bool ns_ = P->geo.nodes > 1;                                             \
+    if (P->geo.dim == 3) {                                                         \
+      if (ns_) hipLaunchKernelGGL((KERNEL<3, true>), __VA_ARGS__);                 \
+      else hipLaunchKernelGGL((KERNEL<3, false>), __VA_ARGS__);                    \
+    } else {                                                                       \
+      if (ns_) hipLaunchKernelGGL((KERNEL<2, true>), __VA_ARGS__);                 \
+      else hipLaunchKernelGGL((KERNEL<2, false>), __VA_ARGS__);                    \
+    }                                                                              \
+  } while (0)
+
+int launch_trace(lag_plan P, const void* vpack, int dir, float* phi, hipStream_t s) {
+  Stages st = stages_for(P, dir);
+  unsigned grid = grid_for((P->geo.np + kBlock - 1) / kBlock);
+  if (P->geo.dim == 3) {
+    if (P->geo.nodes > 1)
+      hipLaunchKernelGGL((k_trace<3, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, st, (const float4*)vpack, phi);
+    else
+      hipLaunchKernelGGL((k_trace<3, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, st, (const float4*)vpack, phi);
+  } else {
+    if (P->geo.nodes > 1)
+      hipLaunchKernelGGL((k_trace<2, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, st, (const float2*)vpack, phi);
+    else
+      hipLaunchKernelGGL((k_trace<2, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, st, (const float2*)vpack, phi);
+  }
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_transport(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s) {
+  unsigned grid = grid_for((P->geo.np + kBlock - 1) / kBlock);
+  if (P->geo.dim == 3)
+    hipLaunchKernelGGL(k_transport<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, T, phi, u);
+  else
+    hipLaunchKernelGGL(k_transport<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, T, phi, u);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+
+int launch_pushforward(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s) {
+  int rc = launch_zero_i(P->bin_count, P->geo.np + 1, s);
+  if (rc) return rc;
+  unsigned grid = grid_for((P->geo.np + kBlock - 1) / kBlock);
+  if (P->geo.dim == 3)
+    hipLaunchKernelGGL(k_push_prep<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, T, phi, P->part_base,
+                       P->part_vals, P->bin_count);
+  else
+    hipLaunchKernelGGL(k_push_prep<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, T, phi, P->part_base,
+                       P->part_vals, P->bin_count);
+  LAG_LAUNCH_CHECK();
+  return bin_and_gather(P, u, s);
+}
+
+int launch_jvp(lag_plan P, const void* vpack, const void* dpack, const float* T, float* out, hipStream_t s) {
+  const int dir = model_dir(P);
+  Stages st = stages_for(P, dir);
+  unsigned grid = grid_for((P->geo.np + kBlock - 1) / kBlock);
+  if (P->prob.model == LAG_TRANSPORT) {
+    if (P->geo.dim == 3) {
+      if (P->geo.nodes > 1)
+        hipLaunchKernelGGL((k_jvp_transport<3, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                           (const float4*)vpack, (const float4*)dpack, T, out);
+      else
+        hipLaunchKernelGGL((k_jvp_transport<3, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                           (const float4*)vpack, (const float4*)dpack, T, out);
+    } else {
+      if (P->geo.nodes > 1)
+        hipLaunchKernelGGL((k_jvp_transport<2, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                           (const float2*)vpack, (const float2*)dpack, T, out);
+      else
+        hipLaunchKernelGGL((k_jvp_transport<2, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                           (const float2*)vpack, (const float2*)dpack, T, out);
+    }
+    LAG_LAUNCH_CHECK();
+    return LAG_OK;
+  }
+  int rc = launch_zero_i(P->bin_count, P->geo.np + 1, s);
+  if (rc) return rc;
+  if (P->geo.dim == 3) {
+    if (P->geo.nodes > 1)
+      hipLaunchKernelGGL((k_jvp_cont_prep<3, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                         (const float4*)vpack, (const float4*)dpack, T, P->part_base, P->part_vals, P->bin_count);
+    else
+      hipLaunchKernelGGL((k_jvp_cont_prep<3, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                         (const float4*)vpack, (const float4*)dpack, T, P->part_base, P->part_vals, P->bin_count);
+  } else {
+    if (P->geo.nodes > 1)
+      hipLaunchKernelGGL((k_jvp_cont_prep<2, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                         (const float2*)vpack, (const float2*)dpack, T, P->part_base, P->part_vals, P->bin_count);
+    else
+      hipLaunchKernelGGL((k_jvp_cont_prep<2, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, st,
+                         (const float2*)vpack, (const float2*)dpack, T, P->part_base, P->part_vals, P->bin_count);
+  }
+  LAG_LAUNCH_CHECK();
+  return bin_and_gather(P, out, s);
+}
+
+int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, float* out, hipStream_t s) {
+  int rc = launch_fill(out, P->n_unknowns, 0.f, s);
+  if (rc) return rc;
+  const int dir = model_dir(P);
+  Stages st = stages_for(P, dir);
+  const lag::Bricks& B = P->bricks;
+  unsigned grid = grid_for(B.nbricks);
+  size_t lds = sizeof(float) * (size_t)P->fields * B.tvol;
+  const bool ns = P->geo.nodes > 1;
+  const bool tr = P->prob.model == LAG_TRANSPORT;
+#define LAG_VJP(DD, NSV, MM, VT)                                                                        \
+  hipLaunchKernelGGL((k_vjp<DD, NSV, MM>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B, (const VT*)vpack, T, w, \
+                     out, P->flags)
+  if (P->geo.dim == 3) {
+    if (ns) { if (tr) LAG_VJP(3, true, 0, float4); else LAG_VJP(3, true, 1, float4); }
+    else { if (tr) LAG_VJP(3, false, 0, float4); else LAG_VJP(3, false, 1, float4); }
+  } else {
+    if (ns) { if (tr) LAG_VJP(2, true, 0, float2); else LAG_VJP(2, true, 1, float2); }
+    else { if (tr) LAG_VJP(2, false, 0, float2); else LAG_VJP(2, false, 1, float2); }
+  }
+#undef LAG_VJP
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T, const float* wvox,
+                          float* out, hipStream_t s) {
+  Stages st = stages_for(P, -1);
+  const lag::Bricks& B = P->bricks;
+  unsigned grid = grid_for(B.nbricks);
+  size_t lds = sizeof(float) * (size_t)P->fields * B.tvol;
+  if (P->geo.dim == 3) {
+    if (P->geo.nodes > 1)
+      hipLaunchKernelGGL((k_hess_transport<3, true>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
+                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->flags);
+    else
+      hipLaunchKernelGGL((k_hess_transport<3, false>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
+                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->flags);
+  } else {
+    if (P->geo.nodes > 1)
+      hipLaunchKernelGGL((k_hess_transport<2, true>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
+                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->flags);
+    else
+      hipLaunchKernelGGL((k_hess_transport<2, false>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
+                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->flags);
+  }
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+}  // namespace lag

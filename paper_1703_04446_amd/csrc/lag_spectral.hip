@@ -1,0 +1,450 @@
+// Regulariser stencil and spectral preconditioner (gfx950).
+//
+// Regulariser (Sec. 2.1; derivative and Hessian term in Sec. 3.2): per time
+// node j and component c, out = s_j A p_{j,c} (+ gamma p) with
+// A = -Laplace_h (diffusion) or Laplace_h^2 (curvature) on the periodic
+// velocity grid and s_j a per-node scale (alpha h_v^d w_j).  Differences are
+// formed before scaling so smooth fields lose little to cancellation.
+//
+// Preconditioner (Sec. 3.2, PCG paragraph): the regulariser block of the
+// Gauss-Newton matrix is circulant on the periodic grid, so it is inverted
+// in Fourier space: z = F^-1[F(r) / mu(k)], mu(k) = s_j lambda_A(k) + gamma.
+// The transform is a hand-written Stockham autosort FFT of radix 4/2/3/5
+// performed line by line in LDS; the forward and inverse transforms along
+// the last axis are fused with the division.  Twiddles and eigenvalue tables
+// are computed on the host in double precision at plan creation.
+
+#include <math.h>
+
+#include <vector>
+
+#include "lag_internal.hpp"
+
+namespace lag {
+
+// ---------------------------------------------------------------------------
+// regulariser
+
+template <int D>
+__device__ __forceinline__ float lap_at(const float* __restrict__ f, const int m[3], const float ih2[3],
+                                        int x, int y, int z) {
+  // -Laplace_h f at (x, y, z); arguments already wrapped
+  const float c = f[((long long)z * m[1] + y) * m[0] + x];
+  float s = 0.f;
+  {
+    int xp = x + 1 == m[0] ? 0 : x + 1, xm = x == 0 ? m[0] - 1 : x - 1;
+    float a = f[((long long)z * m[1] + y) * m[0] + xp] - c;
+    float b = f[((long long)z * m[1] + y) * m[0] + xm] - c;
+    s = fmaf(-(a + b), ih2[0], s);
+  }
+  {
+    int yp = y + 1 == m[1] ? 0 : y + 1, ym = y == 0 ? m[1] - 1 : y - 1;
+    float a = f[((long long)z * m[1] + yp) * m[0] + x] - c;
+    float b = f[((long long)z * m[1] + ym) * m[0] + x] - c;
+    s = fmaf(-(a + b), ih2[1], s);
+  }
+  if (D == 3) {
+    int zp = z + 1 == m[2] ? 0 : z + 1, zm = z == 0 ? m[2] - 1 : z - 1;
+    float a = f[((long long)zp * m[1] + y) * m[0] + x] - c;
+    float b = f[((long long)zm * m[1] + y) * m[0] + x] - c;
+    s = fmaf(-(a + b), ih2[2], s);
+  }
+  return s;
+}
+
+template <int D, bool CURV>
+__global__ void __launch_bounds__(kBlock) k_reg(Geo g, const float* __restrict__ p, float* __restrict__ out,
+                                                const float* __restrict__ scale, float gamma, int accumulate,
+                                                float ih2x, float ih2y, float ih2z) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = g.nv * g.nodes * D;
+  if (i >= tot) return;
+  const long long f = i / g.nv;
+  const long long r = i - f * g.nv;
+  const int j = (int)(f / D);
+  const float* fld = p + f * g.nv;
+  const int m[3] = {g.mv[0], g.mv[1], D == 3 ? g.mv[2] : 1};
+  const float ih2[3] = {ih2x, ih2y, ih2z};
+  const int x = (int)(r % m[0]), y = (int)((r / m[0]) % m[1]), z = (int)(r / ((long long)m[0] * m[1]));
+  float a;
+  if (!CURV) {
+    a = lap_at<D>(fld, m, ih2, x, y, z);
+  } else {
+    // (-Laplace)(-Laplace p) by differences of the inner Laplacian
+    const float c = lap_at<D>(fld, m, ih2, x, y, z);
+    float s = 0.f;
+    {
+      int xp = x + 1 == m[0] ? 0 : x + 1, xm = x == 0 ? m[0] - 1 : x - 1;
+      float u = lap_at<D>(fld, m, ih2, xp, y, z) - c, w = lap_at<D>(fld, m, ih2, xm, y, z) - c;
+      s = fmaf(-(u + w), ih2[0], s);
+    }
+    {
+      int yp = y + 1 == m[1] ? 0 : y + 1, ym = y == 0 ? m[1] - 1 : y - 1;
+      float u = lap_at<D>(fld, m, ih2, x, yp, z) - c, w = lap_at<D>(fld, m, ih2, x, ym, z) - c;
+      s = fmaf(-(u + w), ih2[1], s);
+    }
+    if (D == 3) {
+      int zp = z + 1 == m[2] ? 0 : z + 1, zm = z == 0 ? m[2] - 1 : z - 1;
+      float u = lap_at<D>(fld, m, ih2, x, y, zp) - c, w = lap_at<D>(fld, m, ih2, x, y, zm) - c;
+      s = fmaf(-(u + w), ih2[2], s);
+    }
+    a = s;
+  }
+  float val = scale[j] * a;
+  if (gamma != 0.f) val = fmaf(gamma, fld[r], val);
+  if (accumulate) val += out[i];
+  out[i] = val;
+}
+
+int launch_reg(lag_plan P, const float* p, float* out, int accumulate, int with_gamma, float extra_scale,
+               hipStream_t s) {
+  // extra_scale selects the table: 1 -> alpha h_v^d w_j, 0 -> h_v^d w_j
+  const float* scale = P->reg_scale + (extra_scale != 0.f ? 0 : P->geo.nodes);
+  const float gamma = with_gamma ? (float)P->prob.gamma : 0.f;
+  float ih2[3];
+  for (int a = 0; a < 3; ++a) {
+    double h = P->prob.extent[a] / P->prob.vel_m[a];
+    ih2[a] = (float)(1.0 / (h * h));
+  }
+  const long long tot = P->geo.nv * P->fields;
+  unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
+  const bool curv = P->prob.reg == LAG_CURVATURE;
+  if (P->geo.dim == 3) {
+    if (curv)
+      hipLaunchKernelGGL((k_reg<3, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, p, out, scale, gamma, accumulate,
+                         ih2[0], ih2[1], ih2[2]);
+    else
+      hipLaunchKernelGGL((k_reg<3, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, p, out, scale, gamma, accumulate,
+                         ih2[0], ih2[1], ih2[2]);
+  } else {
+    if (curv)
+      hipLaunchKernelGGL((k_reg<2, true>), dim3(grid), dim3(kBlock), 0, s, P->geo, p, out, scale, gamma, accumulate,
+                         ih2[0], ih2[1], ih2[2]);
+    else
+      hipLaunchKernelGGL((k_reg<2, false>), dim3(grid), dim3(kBlock), 0, s, P->geo, p, out, scale, gamma, accumulate,
+                         ih2[0], ih2[1], ih2[2]);
+  }
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FFT
+
+struct FftLine {
+  int n;            // line length
+  int nrad;         // number of radix stages
+  int rad[16];      // radices in application order
+  const float2* tw; // tw[q] = exp(-2 pi i q / n)
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-LDS Stockham FFT of `lines` lines of length n (buffers [lines][n]).
+// Returns the buffer holding the result.  INV selects exp(+2 pi i ...).
+template <bool INV>
+__device__ float2* lds_fft(const FftLine& L, int lines, float2* b0, float2* b1) {
+  const int n = L.n;
+  int Ns = 1;
+  for (int st = 0; st < L.nrad; ++st) {
+    const int R = L.rad[st];
+    const int nb = n / R;
+    const int span = n / (Ns * R);      // twiddle stride
+    const int step = n / R;             // small-DFT root stride
+    for (int b = threadIdx.x; b < lines * nb; b += blockDim.x) {
+      const int line = b / nb, j = b - (b / nb) * nb;
+      const float2* src = b0 + line * n;
+      float2* dst = b1 + line * n;
+      const int k = j % Ns;
+      float2 v[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) {
+        if (r < R) {
+          float2 x = src[j + r * nb];
+          float2 t = L.tw[r * k * span];
+          if (INV) t.y = -t.y;
+          v[r] = r ? cmul(x, t) : x;
+        }
+      }
+      float2 w[5];
+      if (R == 2) {
+        w[0] = make_float2(v[0].x + v[1].x, v[0].y + v[1].y);
+        w[1] = make_float2(v[0].x - v[1].x, v[0].y - v[1].y);
+      } else if (R == 4) {
+        float2 a = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+        float2 bq = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+        float2 c = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+        float2 d = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+        // multiply d by -i (forward) or +i (inverse)
+        float2 dj = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+        w[0] = make_float2(a.x + c.x, a.y + c.y);
+        w[2] = make_float2(a.x - c.x, a.y - c.y);
+        w[1] = make_float2(bq.x + dj.x, bq.y + dj.y);
+        w[3] = make_float2(bq.x - dj.x, bq.y - dj.y);
+      } else {
+        // generic small DFT with roots from the twiddle table
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+          if (s < R) {
+            float2 acc = v[0];
+#pragma unroll
+            for (int r = 1; r < 5; ++r) {
+              if (r < R) {
+                float2 t = L.tw[((r * s) % R) * step];
+                if (INV) t.y = -t.y;
+                float2 m = cmul(v[r], t);
+                acc.x += m.x;
+                acc.y += m.y;
+              }
+            }
+            w[s] = acc;
+          }
+        }
+      }
+      const int d0 = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+        if (r < R) dst[d0 + r * Ns] = w[r];
+    }
+    __syncthreads();
+    float2* t = b0;
+    b0 = b1;
+    b1 = t;
+    Ns *= R;
+  }
+  return b0;
+}
+
+// Spectral symbol of the regulariser block (with the zero-mode rule) times
+// the number of grid points (to normalise the unscaled inverse transform).
+struct Symbol {
+  const float* lam[3];
+  const float* scale;  // per node s_j
+  const float* mu1;    // per node replacement for mu = 0
+  float gamma;
+  int curv;
+  float nv;
+};
+
+// One pass along `axis` for all lines of all fields.
+// MODE 0: forward; 1: inverse; 2: forward, divide by mu, inverse.
+// IN_REAL: read float input (imaginary 0); OUT_REAL: write the real part.
+template <int D, int MODE, bool IN_REAL, bool OUT_REAL>
+__global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, FftLine L, Symbol sym,
+                                                     const void* __restrict__ in, void* __restrict__ out) {
+  extern __shared__ float2 sh[];
+  const int n = L.n;
+  float2* b0 = sh;
+  float2* b1 = sh + lpb * n;
+  const int m0 = g.mv[0], m1 = g.mv[1], m2 = D == 3 ? g.mv[2] : 1;
+  const int fields = g.nodes * D;
+  // group decomposition
+  long long group = blockIdx.x;
+  long long base;           // address of element 0 of line 0
+  long long lstride;        // address step between lines of the group
+  long long estride;        // address step along the line
+  int nlines;               // valid lines in this group
+  int f, c1 = 0, c2 = 0;    // field and coordinates of line 0 (for the symbol)
+  if (axis == 0) {
+    long long rows = (long long)fields * m1 * m2;
+    long long row0 = group * lpb;
+    if (row0 >= rows) return;
+    nlines = (int)min((long long)lpb, rows - row0);
+    base = row0 * m0;
+    lstride = m0;
+    estride = 1;
+    f = 0;
+  } else {
+    int xg = (int)(group % ((m0 + lpb - 1) / lpb));
+    long long rest = group / ((m0 + lpb - 1) / lpb);
+    int other = axis == 1 ? m2 : m1;
+    int o = (int)(rest % other);
+    f = (int)(rest / other);
+    if (f >= fields) return;
+    int x0 = xg * lpb;
+    nlines = min(lpb, m0 - x0);
+    if (axis == 1) {
+      base = (long long)f * g.nv + (long long)o * m0 * m1 + x0;
+      estride = m0;
+      c2 = o;
+    } else {
+      base = (long long)f * g.nv + (long long)o * m0 + x0;
+      estride = (long long)m0 * m1;
+      c1 = o;
+    }
+    lstride = 1;
+    c1 = axis == 1 ? 0 : c1;
+  }
+  // load (lines contiguous in x for axes 1, 2 -> coalesced)
+  for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
+    int i = e / nlines, l = e - (e / nlines) * nlines;
+    long long a = base + (long long)l * lstride + (long long)i * estride;
+    float2 v;
+    if (IN_REAL) v = make_float2(((const float*)in)[a], 0.f);
+    else v = ((const float2*)in)[a];
+    b0[l * n + i] = v;
+  }
+  __syncthreads();
+  float2* res;
+  if (MODE == 1) {
+    res = lds_fft<true>(L, nlines, b0, b1);
+  } else {
+    res = lds_fft<false>(L, nlines, b0, b1);
+  }
+  if (MODE == 2) {
+    // divide by the symbol; the fused axis is the last one
+    float2* other = (res == b0) ? b1 : b0;
+    for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
+      int l = e / n, i = e - (e / n) * n;
+      int kx, ky, kz = 0;
+      if (axis == 0) {
+        // only used when the grid is 1-D along x (not reachable for D >= 2)
+        kx = i; ky = 0;
+      } else if (D == 2) {
+        // axis 1 lines: x varies across lines, y along the line
+        kx = ((int)(group % ((m0 + lpb - 1) / lpb))) * lpb + l;
+        ky = i;
+      } else {
+        kx = ((int)(group % ((m0 + lpb - 1) / lpb))) * lpb + l;
+        ky = c1;
+        kz = i;
+      }
+      float lam = sym.lam[0][kx] + sym.lam[1][ky] + (D == 3 ? sym.lam[2][kz] : 0.f);
+      if (sym.curv) lam = lam * lam;
+      const int j = f / D;
+      float mu = fmaf(sym.scale[j], lam, sym.gamma);
+      if (mu == 0.f) mu = sym.mu1[j];
+      float inv = 1.f / (mu * sym.nv);
+      float2 v = res[e];
+      res[e] = make_float2(v.x * inv, v.y * inv);
+    }
+    __syncthreads();
+    res = lds_fft<true>(L, nlines, res, other);
+  }
+  for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
+    int i = e / nlines, l = e - (e / nlines) * nlines;
+    long long a = base + (long long)l * lstride + (long long)i * estride;
+    float2 v = res[l * n + i];
+    if (OUT_REAL) ((float*)out)[a] = v.x;
+    else ((float2*)out)[a] = v;
+  }
+}
+
+static bool factor_radices(int n, int* rad, int* nrad) {
+  int k = 0;
+  int m = n;
+  while (m % 4 == 0 && k < 16) { rad[k++] = 4; m /= 4; }
+  while (m % 2 == 0 && k < 16) { rad[k++] = 2; m /= 2; }
+  while (m % 3 == 0 && k < 16) { rad[k++] = 3; m /= 3; }
+  while (m % 5 == 0 && k < 16) { rad[k++] = 5; m /= 5; }
+  *nrad = k;
+  return m == 1;
+}
+
+int precond_setup(lag_plan P) {
+  const int D = P->geo.dim;
+  P->fft_ok = 1;
+  for (int a = 0; a < D; ++a) {
+    int n = P->prob.vel_m[a];
+    if (n > 1024 || !factor_radices(n, P->fft_rad[a], &P->fft_nrad[a])) P->fft_ok = 0;
+  }
+  if (!P->fft_ok) return LAG_OK;  // spectral_precond_apply reports LAG_EUNSUPPORTED
+  LAG_HIP(hipMalloc(&P->fft_buf, sizeof(float2) * P->geo.nv * P->fields));
+  for (int a = 0; a < D; ++a) {
+    const int n = P->prob.vel_m[a];
+    std::vector<float2> tw(n);
+    for (int q = 0; q < n; ++q) {
+      double ang = -2.0 * M_PI * (double)q / (double)n;
+      tw[q] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+    LAG_HIP(hipMalloc(&P->fft_tw[a], sizeof(float2) * n));
+    LAG_HIP(hipMemcpy(P->fft_tw[a], tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+    std::vector<float> lam(n);
+    const double h = P->prob.extent[a] / n;
+    for (int k = 0; k < n; ++k) {
+      double sn = sin(M_PI * (double)k / (double)n);
+      lam[k] = (float)(4.0 / (h * h) * sn * sn);
+    }
+    LAG_HIP(hipMalloc(&P->fft_lam[a], sizeof(float) * n));
+    LAG_HIP(hipMemcpy(P->fft_lam[a], lam.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+  }
+  // smallest nonzero eigenvalue of each node's block (replaces a zero mode)
+  double lmin = 1e300;
+  for (int a = 0; a < D; ++a) {
+    const int n = P->prob.vel_m[a];
+    const double h = P->prob.extent[a] / n;
+    double sn = sin(M_PI / (double)n);
+    lmin = fmin(lmin, 4.0 / (h * h) * sn * sn);
+  }
+  if (P->prob.reg == LAG_CURVATURE) lmin = lmin * lmin;
+  std::vector<float> mu1(P->geo.nodes);
+  double hv = 1.0;
+  for (int a = 0; a < D; ++a) hv *= P->prob.extent[a] / P->prob.vel_m[a];
+  for (int j = 0; j < P->geo.nodes; ++j)
+    mu1[j] = (float)(P->prob.alpha * hv * P->node_w[j] * lmin + P->prob.gamma);
+  LAG_HIP(hipMalloc(&P->fft_mu1, sizeof(float) * P->geo.nodes));
+  LAG_HIP(hipMemcpy(P->fft_mu1, mu1.data(), sizeof(float) * P->geo.nodes, hipMemcpyHostToDevice));
+  return LAG_OK;
+}
+
+static int lines_per_block(int n, int axis, int m0) {
+  int lpb = 2048 / n;
+  if (lpb < 1) lpb = 1;
+  if (lpb > 32) lpb = 32;
+  if (axis != 0 && lpb > m0) lpb = m0;
+  return lpb;
+}
+
+template <int D, int MODE, bool IR, bool OR>
+static int fft_pass(lag_plan P, int axis, const void* in, void* out, hipStream_t s) {
+  FftLine L;
+  L.n = P->prob.vel_m[axis];
+  L.nrad = P->fft_nrad[axis];
+  for (int i = 0; i < 16; ++i) L.rad[i] = P->fft_rad[axis][i];
+  L.tw = P->fft_tw[axis];
+  Symbol sym;
+  for (int a = 0; a < 3; ++a) sym.lam[a] = P->fft_lam[a];
+  sym.scale = P->reg_scale;
+  sym.mu1 = P->fft_mu1;
+  sym.gamma = (float)P->prob.gamma;
+  sym.curv = P->prob.reg == LAG_CURVATURE;
+  sym.nv = (float)P->geo.nv;
+  const int m0 = P->prob.vel_m[0], m1 = P->prob.vel_m[1], m2 = D == 3 ? P->prob.vel_m[2] : 1;
+  const int lpb = lines_per_block(L.n, axis, m0);
+  long long groups;
+  if (axis == 0) {
+    long long rows = (long long)P->fields * m1 * m2;
+    groups = (rows + lpb - 1) / lpb;
+  } else {
+    long long xg = (m0 + lpb - 1) / lpb;
+    groups = xg * (axis == 1 ? m2 : m1) * P->fields;
+  }
+  size_t lds = sizeof(float2) * 2 * (size_t)lpb * L.n;
+  hipLaunchKernelGGL((k_fft_axis<D, MODE, IR, OR>), dim3((unsigned)groups), dim3(kBlock), lds, s, P->geo, axis, lpb,
+                     L, sym, in, out);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s) {
+  if (!P->fft_ok) return LAG_EUNSUPPORTED;
+  if (!(P->prob.alpha > 0.0) && !(P->prob.gamma > 0.0)) return LAG_EINVAL;
+  float2* buf = P->fft_buf;
+  int rc;
+  if (P->geo.dim == 3) {
+    if ((rc = fft_pass<3, 0, true, false>(P, 0, r, buf, s))) return rc;
+    if ((rc = fft_pass<3, 0, false, false>(P, 1, buf, buf, s))) return rc;
+    if ((rc = fft_pass<3, 2, false, false>(P, 2, buf, buf, s))) return rc;
+    if ((rc = fft_pass<3, 1, false, false>(P, 1, buf, buf, s))) return rc;
+    if ((rc = fft_pass<3, 1, false, true>(P, 0, buf, z, s))) return rc;
+  } else {
+    if ((rc = fft_pass<2, 0, true, false>(P, 0, r, buf, s))) return rc;
+    if ((rc = fft_pass<2, 2, false, false>(P, 1, buf, buf, s))) return rc;
+    if ((rc = fft_pass<2, 1, false, true>(P, 0, buf, z, s))) return rc;
+  }
+  return LAG_OK;
+}
+
+}  // namespace lag
