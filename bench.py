@@ -1,0 +1,194 @@
+"""Throughput benchmark: Gauss-Newton Hessian matvecs per second at 128^3.
+
+Workload (3-D transport registration): 128^3 Gaussian-blob template
+(24 blobs), stationary 64^3 velocity, RK4 with N = 10, SSD distance,
+diffusion regulariser alpha = 1e-2; the reference image is the template
+transported by a random-Fourier ground-truth velocity (|k| <= 4, max |v| =
+0.05), computed on the GPU.  Inputs are synthetic and resident in HBM before
+timing starts.
+
+One step = one inexact Gauss-Newton iteration at the fixed iterate
+v = v_true / 2 (objective and gradient, a PCG solve of the Gauss-Newton
+system with the spectral preconditioner to relative residual 0.1 (at most 50
+iterations), and an Armijo line search), i.e. one pass over every step of the
+hot path.  value = Hessian matvecs performed in the timed steps / timed
+seconds.
+
+The JSON line also carries:
+  roofline     - the dominant kernel (the Gauss-Newton matvec kernel), timed
+                 with HIP events on its own stream inside the timed region;
+  cpu_baseline - the FP64 NumPy oracle's matvec on a sample of the
+                 characteristics of the same problem, scaled to matvecs/s.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="3d128_transport")
+    ap.add_argument("--cpu-sample", type=int, default=65536,
+                    help="characteristics in the oracle's timed sample (0 = skip the CPU baseline)")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *msg):
+    if not args.quiet:
+        print("[bench]", *msg, file=sys.stderr, flush=True)
+
+
+# algorithmic work of the fused transport matvec kernel per characteristic
+# and RK4 step (3-D, stationary); derivation in the design notes
+FLOP_PER_CHAR_STEP_3D = 2628
+FLOP_PER_CHAR_END_3D = 120
+
+
+def cpu_baseline(w, v, p, nsample):
+    """Oracle matvec on `nsample` characteristics, scaled to the full grid."""
+    import oracle as O
+    P = O.Problem(dim=w.dim, img_m=w.img_m, vel_m=w.vel_m, nodes=w.nodes, model=w.model,
+                  reg=w.reg, nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma)
+    T = w.template().ravel()
+    rng = np.random.default_rng(12345)
+    pts = np.sort(rng.choice(P.n_points, nsample, replace=False))
+    t0 = time.perf_counter()
+    O.hessmat(P, v, T, p, points=pts)
+    dt = time.perf_counter() - t0
+    t_full = dt * P.n_points / nsample
+    return {"value": 1.0 / t_full, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsample} of {P.n_points} characteristics (uniform random, seed 12345); "
+                      f"{dt:.2f} s measured, scaled by {P.n_points / nsample:.1f}; "
+                      f"single-threaded NumPy float64"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1703_04446_amd as L
+    from synthetic import workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    L.load()
+    w = workload(args.workload)
+    log(args, f"workload {w.name}: image {w.img_m}, velocity {w.vel_m}, N={w.nsteps}")
+    T = w.template().ravel().astype(np.float32)
+    vt = w.velocity_true().astype(np.float32)
+    p0 = w.direction(0).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()  # noqa: E731
+    prob = L.make_problem(w.dim, w.img_m, w.vel_m, nt_nodes=w.nodes, model=w.model, reg=w.reg,
+                          nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma)
+    plan = L.Plan(prob)
+    n, nu = plan.n_points, plan.n_unknowns
+    Td, vtd = dev(T), dev(vt)
+    # reference image: the template transported by the ground truth (GPU)
+    phi = torch.empty(w.dim * n, device="cuda")
+    Rd = torch.empty(n, device="cuda")
+    L.lag_trace(plan, vtd, -1 if w.model == "transport" else 1, phi)
+    if w.model == "transport":
+        L.lag_transport(plan, Td, phi, Rd)
+    else:
+        L.lag_pushforward(plan, Td, phi, Rd)
+    v = 0.5 * vtd
+    g = torch.empty(nu, device="cuda")
+    rhs = torch.empty(nu, device="cuda")
+    dv = torch.empty(nu, device="cuda")
+    vtrial = torch.empty(nu, device="cuda")
+    out3 = torch.zeros(3, dtype=torch.float64, device="cuda")
+
+    def gn_iteration():
+        L.lag_gradient(plan, v, Td, Rd, g, out3)
+        J = float(out3[0].item())
+        torch.neg(g, out=rhs)
+        info = L.lag_pcg(plan, v, Td, None, rhs, dv, tol=w.pcg_tol, maxit=w.pcg_maxit)
+        slope = float(torch.dot(g.double(), dv.double()).item())
+        mu, halvings = 1.0, 0
+        while True:
+            torch.add(v, dv, alpha=mu, out=vtrial)
+            L.lag_objective(plan, vtrial, Td, Rd, None, out3)
+            Jt = float(out3[0].item())
+            if Jt <= J + 1e-4 * mu * slope or halvings >= 10:
+                break
+            mu *= 0.5
+            halvings += 1
+        return info, J, Jt, mu
+
+    for i in range(args.warmup):
+        info, J, Jt, mu = gn_iteration()
+        log(args, f"warmup {i}: pcg iters {info['iters']} relres {info['relres']:.3f} "
+                  f"J {J:.4e} -> {Jt:.4e} (mu {mu})")
+    L.lag_profile_enable(plan, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    matvecs = 0
+    iters = []
+    for i in range(args.steps):
+        info, J, Jt, mu = gn_iteration()
+        matvecs += info["matvecs"]
+        iters.append(info["iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, kern_n = L.lag_profile_read(plan)
+    log(args, f"timed {args.steps} steps in {dt:.3f} s, {matvecs} matvecs, pcg iters {iters}; "
+              f"matvec kernel {kern_ms / max(kern_n, 1):.3f} ms avg over {kern_n} launches")
+
+    # roofline of the dominant kernel
+    kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
+    flops = n * (w.nsteps * FLOP_PER_CHAR_STEP_3D + FLOP_PER_CHAR_END_3D)
+    achieved = flops / kern_avg_s / 1e12
+    roof = {"bound": "alu", "kernel": "k_hess_transport<3,false>", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+            "kernel_ms": round(kern_avg_s * 1e3, 4), "launches_timed": kern_n}
+    res = {
+        "metric": "GN Hessian matvecs/s at 128^3",
+        "value": round(matvecs / dt, 3),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "image": list(w.img_m), "velocity": list(w.vel_m),
+                   "nsteps": w.nsteps, "model": w.model, "regularizer": w.reg, "alpha": w.alpha,
+                   "iterate": "v_true/2", "pcg_tol": w.pcg_tol, "pcg_maxit": w.pcg_maxit},
+        "matvecs_per_step": matvecs / args.steps,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    plan.close()
+    if args.cpu_sample > 0:
+        log(args, f"timing the oracle on {args.cpu_sample} characteristics ...")
+        res["cpu_baseline"] = cpu_baseline(w, 0.5 * vt.astype(np.float64), p0.astype(np.float64),
+                                           args.cpu_sample)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -25,9 +25,11 @@
  *  - Every pointer argument except the plan and `stream` is a DEVICE pointer
  *    unless stated otherwise.  The caller allocates and owns every buffer;
  *    the plan owns only its workspace.  Outputs must not alias inputs.
- *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
- *    asynchronous on that stream and allocates nothing, except
- *    lag_plan_create, lag_pcg and lag_gn_solve, which are documented below.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  The hot-path
+ *    calls are asynchronous on that stream and allocate nothing.  Plan
+ *    creation/destruction allocate/free and synchronise the device; the
+ *    profiling reads, lag_pcg and lag_gn_solve synchronise (documented at
+ *    each).
  *  - A plan is used by one stream at a time (it owns scratch buffers).
  *  - Return value: LAG_OK (0) or one of the LAG_E* codes; no exception ever
  *    crosses the ABI.  lag_strerror() names a code.  After LAG_EHIP the HIP
@@ -63,7 +65,7 @@ enum { LAG_DIFFUSION = 0, LAG_CURVATURE = 1 };    /* H1 / H2 seminorm regularise
  * cell centre (n_points = prod(img_m)). */
 typedef struct lag_problem {
     int32_t dim;          /* 2 or 3                                            */
-    int32_t img_m[3];     /* image cells per axis (x, y, z); >= 1              */
+    int32_t img_m[3];     /* image cells per axis (x, y, z); >= 2 on used axes */
     int32_t vel_m[3];     /* velocity cells per axis; >= 2 on used axes        */
     double  extent[3];    /* domain edge lengths, > 0                          */
     int32_t nt_nodes;     /* 1 = stationary velocity, else n_t + 1 >= 2        */
@@ -105,6 +107,16 @@ int lag_plan_destroy(lag_plan plan);
 
 /* Copy of the plan's problem (host pointer). */
 int lag_plan_problem(lag_plan plan, lag_problem* out);
+
+/* Kernel timing for measurement: when enabled, every launch of the
+ * Gauss-Newton matvec's main kernel is bracketed by HIP events recorded on
+ * the stream it runs on (up to 256 launches between reads).  Enabling
+ * creates the events (host call, once per plan).  lag_profile_read
+ * synchronises on the recorded events, returns the summed kernel time in
+ * milliseconds and the number of timed launches (host pointers), and resets
+ * the count. */
+int lag_profile_enable(lag_plan plan, int32_t enable);
+int lag_profile_read(lag_plan plan, double* ms_total, int32_t* launches);
 
 /* ---- the hot path ------------------------------------------------------- */
 
@@ -160,9 +172,9 @@ int gn_hessmat(lag_plan plan, const float* v, const float* T, const float* wvox,
  * regulariser block of H on the periodic grid (DFT, hand-written radix-2/3/5
  * FFT).  If mu_j(0) = 0 (gamma = 0) the constant mode is divided by the
  * smallest nonzero mu_j instead (pseudo-inverse made SPD).
- * r, z: velocity-shaped.  Supported sizes: every vel_m[a] whose prime
- * factors are 2, 3 and 5 and which is <= 1024 (else LAG_EUNSUPPORTED at
- * plan creation... reported by this call). */
+ * r, z: velocity-shaped.  Supported sizes: every vel_m[a] <= 1024 whose
+ * prime factors are 2, 3 and 5; other sizes return LAG_EUNSUPPORTED.
+ * alpha = gamma = 0 (no regulariser block to invert) returns LAG_EINVAL. */
 int spectral_precond_apply(lag_plan plan, const float* r, float* z, void* stream);
 
 /* ---- compositions used by the Gauss-Newton driver ----------------------- */

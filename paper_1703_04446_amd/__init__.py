@@ -14,7 +14,7 @@ from ._lib import (  # noqa: F401
     lag_problem_check, lag_problem_sizes, lag_plan_create, lag_plan_destroy,
     lag_trace, lag_transport, lag_pushforward, lag_jvp, lag_vjp, gn_hessmat,
     spectral_precond_apply, lag_reg_apply, lag_objective, lag_gradient, lag_dot,
-    lag_pcg, lag_gn_default_options, lag_gn_solve,
+    lag_pcg, lag_gn_default_options, lag_gn_solve, lag_profile_enable, lag_profile_read,
 )
 
 LIB_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__), "liblaglddmm.so")

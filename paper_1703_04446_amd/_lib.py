@@ -78,6 +78,8 @@ _SIGS = {
     "lag_plan_create": (_I, [ctypes.POINTER(LagProblem), ctypes.POINTER(_P)]),
     "lag_plan_destroy": (_I, [_P]),
     "lag_plan_problem": (_I, [_P, ctypes.POINTER(LagProblem)]),
+    "lag_profile_enable": (_I, [_P, ctypes.c_int32]),
+    "lag_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "lag_trace": (_I, [_P, _P, ctypes.c_int32, _P, _P]),
     "lag_transport": (_I, [_P, _P, _P, _P, _P]),
     "lag_pushforward": (_I, [_P, _P, _P, _P, _P]),
@@ -215,6 +217,17 @@ def lag_plan_create(prob):
 
 def lag_plan_destroy(plan):
     plan.close()
+
+
+def lag_profile_enable(plan, enable=True):
+    _check("lag_profile_enable", load().lag_profile_enable(plan.handle, int(bool(enable))))
+
+
+def lag_profile_read(plan):
+    """(summed milliseconds, launches) of the timed matvec kernel launches."""
+    ms, n = ctypes.c_double(), ctypes.c_int32()
+    _check("lag_profile_read", load().lag_profile_read(plan.handle, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def lag_trace(plan, v, direction, phi):

@@ -88,11 +88,14 @@ static void free_plan(lag_plan P) {
                   P->img_a, P->img_b, P->phi, P->bin_count, P->bin_start, P->bin_cursor, P->bin_items,
                   P->part_base, P->part_vals, P->scan_blocks, P->red_partial, P->scalars, P->fft_buf,
                   P->fft_tw[0], P->fft_tw[1], P->fft_tw[2], P->fft_lam[0], P->fft_lam[1], P->fft_lam[2],
-                  P->fft_mu1, P->flags};
+                  P->fft_mu1, P->flags, P->tile_part, P->cover_start[0], P->cover_start[1],
+                  P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 10; ++i)
     if (P->vec[i]) (void)hipFree(P->vec[i]);
+  if (P->prof_on)
+    for (int i = 0; i < 2 * 256; ++i) (void)hipEventDestroy(P->prof_ev[i]);
   delete P;
 }
 
@@ -277,6 +280,11 @@ int lag_plan_create(const lag_problem* prob, lag_plan* out) {
   for (int i = 0; i < 10; ++i) ALLOC(P->vec[i], sizeof(float) * P->n_unknowns);
   ALLOC(P->flags, sizeof(int) * 4);
   HIPC(hipMemset(P->flags, 0, sizeof(int) * 4));
+  rc = tiles_setup(P);
+  if (rc) {
+    lag::free_plan(P);
+    return rc;
+  }
   rc = precond_setup(P);
   if (rc) {
     lag::free_plan(P);
@@ -291,6 +299,32 @@ int lag_plan_destroy(lag_plan plan) {
   if (!plan) return LAG_OK;
   (void)hipDeviceSynchronize();
   lag::free_plan(plan);
+  return LAG_OK;
+}
+
+int lag_profile_enable(lag_plan P, int32_t enable) {
+  LAG_CHECK(P);
+  if (enable && !P->prof_on) {
+    for (int i = 0; i < 2 * 256; ++i) LAG_HIP(hipEventCreate(&P->prof_ev[i]));
+    P->prof_on = 1;
+  }
+  P->prof_n = 0;
+  return LAG_OK;
+}
+
+int lag_profile_read(lag_plan P, double* ms_total, int32_t* launches) {
+  LAG_CHECK(P && ms_total && launches);
+  *ms_total = 0.0;
+  *launches = 0;
+  if (!P->prof_on) return LAG_OK;
+  for (int i = 0; i < P->prof_n; ++i) {
+    LAG_HIP(hipEventSynchronize(P->prof_ev[2 * i + 1]));
+    float ms = 0.f;
+    LAG_HIP(hipEventElapsedTime(&ms, P->prof_ev[2 * i], P->prof_ev[2 * i + 1]));
+    *ms_total += ms;
+  }
+  *launches = P->prof_n;
+  P->prof_n = 0;
   return LAG_OK;
 }
 

@@ -51,8 +51,17 @@ struct lag_plan_s {
   float* fft_mu1 = nullptr;    // per node replacement for a zero mode
   int fft_rad[3][16];
   int fft_nrad[3];
+  // per-brick partial velocity tiles and, per axis, the list of (brick,
+  // tile offset) pairs covering each velocity index (fixed-order reduction)
+  float* tile_part = nullptr;
+  int* cover_start[3] = {nullptr, nullptr, nullptr};
+  int2* cover_ent[3] = {nullptr, nullptr, nullptr};
   // status flags written by kernels (bit 0: singular RK4 step Jacobian)
   int* flags = nullptr;
+  // optional HIP-event timing of the dominant Gauss-Newton matvec kernel
+  int prof_on = 0;
+  int prof_n = 0;
+  hipEvent_t prof_ev[2 * 256];
 };
 
 namespace lag {
@@ -84,6 +93,8 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
                hipStream_t s);
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
+int launch_tile_reduce(lag_plan P, float* out, hipStream_t s);
+int tiles_setup(lag_plan P);       // partial-tile buffer + cover tables (plan creation)
 int launch_reg(lag_plan P, const float* p, float* out, int accumulate, int with_gamma,
                float extra_scale, hipStream_t s);
 int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s);
@@ -96,5 +107,16 @@ int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float sc
                hipStream_t s);
 int launch_axpy(long long n, float a, const float* x, float* y, hipStream_t s);
 int launch_combine_J(double* s3, double alpha, hipStream_t s);
+
+// profiling brackets around the dominant matvec kernel (no-ops unless enabled)
+inline void prof_begin(lag_plan P, hipStream_t s) {
+  if (P->prof_on && P->prof_n < 256) (void)hipEventRecord(P->prof_ev[2 * P->prof_n], s);
+}
+inline void prof_end(lag_plan P, hipStream_t s) {
+  if (P->prof_on && P->prof_n < 256) {
+    (void)hipEventRecord(P->prof_ev[2 * P->prof_n + 1], s);
+    ++P->prof_n;
+  }
+}
 
 }  // namespace lag

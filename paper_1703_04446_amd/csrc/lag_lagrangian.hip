@@ -24,6 +24,10 @@
 // global memory); points whose stencil leaves the tile fall back to global
 // atomics, so results never depend on the tile margin.
 
+#include <math.h>
+
+#include <vector>
+
 #include "lag_internal.hpp"
 
 namespace lag {
@@ -262,6 +266,109 @@ struct TileAcc {
       }
     }
   }
+
+  // Add pre-merged corner values a[slot][o][c] of one cell (slot 1 is the
+  // second time node of a time-dependent field).
+  template <int NSLOT>
+  __device__ __forceinline__ void add_block(const int cell[D], int jA, const float a[NSLOT][1 << D][D]) const {
+    bool in = true;
+    int t[3] = {0, 0, 0};
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      t[ax] = cell[ax] - org[ax];
+      in = in && (t[ax] >= 0) && (t[ax] + 1 < td[ax]);
+    }
+    if (in) {
+      int base = (t[2] * td[1] + t[1]) * td[0] + t[0];
+#pragma unroll
+      for (int o = 0; o < (1 << D); ++o) {
+        int off = base + (o & 1) + ((o >> 1) & 1) * td[0];
+        if (D == 3) off += ((o >> 2) & 1) * td[0] * td[1];
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+          for (int c = 0; c < D; ++c) atomicAdd(&lds[((jA + s) * D + c) * tvol + off], a[s][o][c]);
+      }
+    } else {
+      Loc<D> L;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        L.c[ax] = cell[ax];
+        L.f[ax] = 0.f;
+      }
+#pragma unroll
+      for (int o = 0; o < (1 << D); ++o) {
+        long long gi = corner_index<D>(L, mv, o);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+          for (int c = 0; c < D; ++c)
+            unsafeAtomicAdd(&gout[(long long)((jA + s) * D + c) * nv + gi], a[s][o][c]);
+      }
+    }
+  }
+};
+
+// Register accumulator that merges the scatter of consecutive samples
+// falling in the same velocity cell (and time interval); it is flushed to
+// the tile only when the cell changes, which cuts LDS atomics by the number
+// of RK4 stages spent inside one cell.
+template <int D, bool NS>
+struct Merge {
+  static constexpr int NSLOT = NS ? 2 : 1;
+  int cell[D];
+  int j0;
+  bool active;
+  float a[NSLOT][1 << D][D];
+
+  __device__ __forceinline__ void reset() { active = false; }
+
+  __device__ __forceinline__ void flush(const TileAcc<D, NS>& acc) {
+    if (active) acc.template add_block<NSLOT>(cell, j0, a);
+    active = false;
+  }
+
+  __device__ __forceinline__ void add(const TileAcc<D, NS>& acc, const Loc<D>& L, int q, const float kb[D]) {
+    int jA = NS ? acc.j0[q] : 0;
+    float th = NS ? acc.th[q] : 0.f;
+    bool same = active && (jA == j0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) same = same && (L.c[ax] == cell[ax]);
+    if (!same) {
+      flush(acc);
+      active = true;
+      j0 = jA;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) cell[ax] = L.c[ax];
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+        for (int o = 0; o < (1 << D); ++o)
+#pragma unroll
+          for (int c = 0; c < D; ++c) a[s][o][c] = 0.f;
+    }
+    float w[1 << D];
+    corner_weights<D>(L, w);
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o)
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        float val = w[o] * kb[c];
+        if (NS) {
+          a[0][o][c] = fmaf(1.f - th, val, a[0][o][c]);
+          a[1][o][c] = fmaf(th, val, a[1][o][c]);
+        } else {
+          a[0][o][c] += val;
+        }
+      }
+  }
+};
+
+// 3-D time-dependent fields would need 48 merge registers; they scatter
+// every sample directly instead.
+template <int D, bool NS>
+struct UseMerge {
+  static constexpr bool value = !(NS && D == 3);
 };
 
 // pass 2: replay the sweep, recover the step adjoints and scatter them.
@@ -273,6 +380,13 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
   const float dt = st.dt, hdt = 0.5f * dt;
   float phi[D];
   bool ok = true;
+  constexpr bool MERGE = UseMerge<D, NS>::value;
+  Merge<D, NS> mg;
+  mg.reset();
+  auto scat = [&](const Loc<D>& L, int q, const float kb[D]) {
+    if (MERGE) mg.add(acc, L, q, kb);
+    else acc.add(L, q, kb);
+  };
 #pragma unroll
   for (int a = 0; a < D; ++a) phi[a] = 0.f;
   for (int k = 0; k < g.nsteps; ++k) {
@@ -304,7 +418,7 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
     const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
 #pragma unroll
     for (int a = 0; a < D; ++a) kb[a] = c6 * yn[a];
-    acc.add(L4, q + 3, kb);
+    scat(L4, q + 3, kb);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       float s = 0.f;
@@ -314,7 +428,7 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) kb[a] = fmaf(dt, pb[a], c3 * yn[a]);
-    acc.add(L3, q + 2, kb);
+    scat(L3, q + 2, kb);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       float s = 0.f;
@@ -324,7 +438,7 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) kb[a] = fmaf(hdt, pb[a], c3 * yn[a]);
-    acc.add(L2, q + 1, kb);
+    scat(L2, q + 1, kb);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       float s = 0.f;
@@ -334,11 +448,12 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) kb[a] = fmaf(hdt, pb[a], c6 * yn[a]);
-    acc.add(L1, q, kb);
+    scat(L1, q, kb);
 #pragma unroll
     for (int a = 0; a < D; ++a) ybar[a] = yn[a];
     rk4_update<D>(phi, dt, k1, k2, k3, k4);
   }
+  if (MERGE) mg.flush(acc);
   return ok;
 }
 
@@ -540,19 +655,15 @@ __device__ __forceinline__ void for_brick_points(const Geo& g, const Bricks& B, 
   }
 }
 
+// Write the block's tile to its slot of the partial-tile buffer; a separate
+// kernel sums the overlapping tiles per velocity node in a fixed order.
 template <int D, bool NS>
-__device__ __forceinline__ void flush_tile(const Geo& g, const TileAcc<D, NS>& acc, int fields) {
+__device__ __forceinline__ void flush_tile(const TileAcc<D, NS>& acc, int fields, float* __restrict__ part,
+                                           long long bid) {
   __syncthreads();
   const int tot = fields * acc.tvol;
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-    float val = acc.lds[i];
-    if (val == 0.f) continue;
-    int f = i / acc.tvol, r = i - f * acc.tvol;
-    int t0 = r % acc.td[0], t1 = (r / acc.td[0]) % acc.td[1], t2 = r / (acc.td[0] * acc.td[1]);
-    long long gi = wrapi(acc.org[0] + t0, g.mv[0]) + (long long)g.mv[0] * wrapi(acc.org[1] + t1, g.mv[1]);
-    if (D == 3) gi += (long long)g.mv[0] * g.mv[1] * wrapi(acc.org[2] + t2, g.mv[2]);
-    unsafeAtomicAdd(&acc.gout[(long long)f * acc.nv + gi], val);
-  }
+  float* dst = part + bid * (long long)tot;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) dst[i] = acc.lds[i];
 }
 
 template <int D, bool NS>
@@ -581,7 +692,8 @@ __device__ __forceinline__ TileAcc<D, NS> make_acc(float* lds, float* gout, cons
 template <int D, bool NS, int MODEL>
 __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, const typename VecT<D>::T* __restrict__ vp,
                                                 const float* __restrict__ T, const float* __restrict__ w,
-                                                float* __restrict__ out, int* __restrict__ flags) {
+                                                float* __restrict__ out, float* __restrict__ part,
+                                                int* __restrict__ flags) {
   extern __shared__ float lds[];
   long long bid = xcd_block(B.nbricks);
   if (bid < 0) return;
@@ -628,7 +740,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
     if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) bad = true;
   });
   if (bad) atomicOr(flags, 1);
-  flush_tile<D, NS>(g, acc, fields);
+  flush_tile<D, NS>(acc, fields, part, bid);
 }
 
 // Fused transport Gauss-Newton data term: out += h^d J^T (W (J p)).
@@ -637,7 +749,8 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
                                                            const typename VecT<D>::T* __restrict__ vp,
                                                            const typename VecT<D>::T* __restrict__ pp,
                                                            const float* __restrict__ T, const float* __restrict__ wvox,
-                                                           float* __restrict__ out, int* __restrict__ flags) {
+                                                           float* __restrict__ out, float* __restrict__ part,
+                                                           int* __restrict__ flags) {
   extern __shared__ float lds[];
   long long bid = xcd_block(B.nbricks);
   if (bid < 0) return;
@@ -677,7 +790,88 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
     if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) bad = true;
   });
   if (bad) atomicOr(flags, 1);
-  flush_tile<D, NS>(g, acc, fields);
+  flush_tile<D, NS>(acc, fields, part, bid);
+}
+
+// Sum the partial tiles into the velocity-grid output in a fixed order:
+// out[f][node] += sum over covering bricks (z, then y, then x order).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fields, const float* __restrict__ part,
+                                                        const int* __restrict__ cs0, const int2* __restrict__ ce0,
+                                                        const int* __restrict__ cs1, const int2* __restrict__ ce1,
+                                                        const int* __restrict__ cs2, const int2* __restrict__ ce2,
+                                                        float* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nv * fields) return;
+  const long long f = i / g.nv, r = i - f * g.nv;
+  const int X = (int)(r % g.mv[0]);
+  const int Y = (int)((r / g.mv[0]) % g.mv[1]);
+  const int Z = D == 3 ? (int)(r / ((long long)g.mv[0] * g.mv[1])) : 0;
+  const long long tsz = (long long)fields * B.tvol;
+  float sum = 0.f;
+  for (int ez = cs2[Z]; ez < cs2[Z + 1]; ++ez) {
+    const int2 cz = ce2[ez];
+    for (int ey = cs1[Y]; ey < cs1[Y + 1]; ++ey) {
+      const int2 cy = ce1[ey];
+      const int bzy = cy.x + B.nb[1] * cz.x;
+      const int tzy = cy.y + B.tdim[1] * cz.y;
+      for (int ex = cs0[X]; ex < cs0[X + 1]; ++ex) {
+        const int2 cx = ce0[ex];
+        const long long b = cx.x + (long long)B.nb[0] * bzy;
+        const int t = cx.y + B.tdim[0] * tzy;
+        sum += part[b * tsz + f * B.tvol + t];
+      }
+    }
+  }
+  out[i] += sum;
+}
+
+int launch_tile_reduce(lag_plan P, float* out, hipStream_t s) {
+  const long long tot = P->geo.nv * P->fields;
+  unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
+  if (P->geo.dim == 3)
+    hipLaunchKernelGGL(k_tile_reduce<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields, P->tile_part,
+                       P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1], P->cover_start[2],
+                       P->cover_ent[2], out);
+  else
+    hipLaunchKernelGGL(k_tile_reduce<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields, P->tile_part,
+                       P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1], P->cover_start[2],
+                       P->cover_ent[2], out);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int tiles_setup(lag_plan P) {
+  const Geo& g = P->geo;
+  const Bricks& B = P->bricks;
+  LAG_HIP(hipMalloc(&P->tile_part, sizeof(float) * (size_t)B.nbricks * P->fields * B.tvol));
+  for (int a = 0; a < 3; ++a) {
+    const int m = g.mv[a];
+    std::vector<std::vector<int2>> lists(m);
+    for (int b = 0; b < B.nb[a]; ++b) {
+      int org = 0;
+      if (a < g.dim) {
+        double sv = ((double)(b * B.bdim[a]) + 0.5) * g.ratio[a] - 0.5;
+        org = (int)floor(sv) - B.halo;
+      }
+      for (int t = 0; t < B.tdim[a]; ++t) {
+        int X = ((org + t) % m + m) % m;
+        lists[X].push_back(make_int2(b, t));
+      }
+    }
+    std::vector<int> start(m + 1, 0);
+    std::vector<int2> ent;
+    for (int X = 0; X < m; ++X) {
+      start[X] = (int)ent.size();
+      ent.insert(ent.end(), lists[X].begin(), lists[X].end());
+    }
+    start[m] = (int)ent.size();
+    LAG_HIP(hipMalloc(&P->cover_start[a], sizeof(int) * (m + 1)));
+    LAG_HIP(hipMalloc(&P->cover_ent[a], sizeof(int2) * std::max<size_t>(ent.size(), 1)));
+    LAG_HIP(hipMemcpy(P->cover_start[a], start.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice));
+    LAG_HIP(hipMemcpy(P->cover_ent[a], ent.data(), sizeof(int2) * ent.size(), hipMemcpyHostToDevice));
+  }
+  return LAG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -829,7 +1023,7 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
   const bool tr = P->prob.model == LAG_TRANSPORT;
 #define LAG_VJP(DD, NSV, MM, VT)                                                                        \
   hipLaunchKernelGGL((k_vjp<DD, NSV, MM>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B, (const VT*)vpack, T, w, \
-                     out, P->flags)
+                     out, P->tile_part, P->flags)
   if (P->geo.dim == 3) {
     if (ns) { if (tr) LAG_VJP(3, true, 0, float4); else LAG_VJP(3, true, 1, float4); }
     else { if (tr) LAG_VJP(3, false, 0, float4); else LAG_VJP(3, false, 1, float4); }
@@ -839,7 +1033,7 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
   }
 #undef LAG_VJP
   LAG_LAUNCH_CHECK();
-  return LAG_OK;
+  return launch_tile_reduce(P, out, s);
 }
 
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T, const float* wvox,
@@ -848,23 +1042,25 @@ int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, cons
   const lag::Bricks& B = P->bricks;
   unsigned grid = grid_for(B.nbricks);
   size_t lds = sizeof(float) * (size_t)P->fields * B.tvol;
+  prof_begin(P, s);
   if (P->geo.dim == 3) {
     if (P->geo.nodes > 1)
       hipLaunchKernelGGL((k_hess_transport<3, true>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->flags);
+                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->tile_part, P->flags);
     else
       hipLaunchKernelGGL((k_hess_transport<3, false>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->flags);
+                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->tile_part, P->flags);
   } else {
     if (P->geo.nodes > 1)
       hipLaunchKernelGGL((k_hess_transport<2, true>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->flags);
+                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->tile_part, P->flags);
     else
       hipLaunchKernelGGL((k_hess_transport<2, false>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->flags);
+                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->tile_part, P->flags);
   }
+  prof_end(P, s);
   LAG_LAUNCH_CHECK();
-  return LAG_OK;
+  return launch_tile_reduce(P, out, s);
 }
 
 }  // namespace lag
