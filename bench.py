@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--workload", default="3d128_transport")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="characteristics in the oracle's timed sample (0 = skip the CPU baseline)")
+    ap.add_argument("--jac-blocks", type=int, default=8,
+                    help="assembled-Jacobian capacity in cell blocks per characteristic")
+    ap.add_argument("--matrix-free", action="store_true",
+                    help="use the matrix-free Gauss-Newton matvec instead of the assembled Jacobian")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -99,7 +103,8 @@ def main():
     p0 = w.direction(0).astype(np.float32)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()  # noqa: E731
     prob = L.make_problem(w.dim, w.img_m, w.vel_m, nt_nodes=w.nodes, model=w.model, reg=w.reg,
-                          nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma)
+                          nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma,
+                          jac_blocks=0 if args.matrix_free else args.jac_blocks)
     plan = L.Plan(prob)
     n, nu = plan.n_points, plan.n_unknowns
     Td, vtd = dev(T), dev(vt)
@@ -112,42 +117,28 @@ def main():
     else:
         L.lag_pushforward(plan, Td, phi, Rd)
     v = 0.5 * vtd
-    g = torch.empty(nu, device="cuda")
-    rhs = torch.empty(nu, device="cuda")
-    dv = torch.empty(nu, device="cuda")
-    vtrial = torch.empty(nu, device="cuda")
-    out3 = torch.zeros(3, dtype=torch.float64, device="cuda")
+    v_next = torch.empty_like(v)
+    opts = L.lag_gn_default_options()
+    opts.pcg_tol, opts.pcg_maxit = w.pcg_tol, w.pcg_maxit
 
     def gn_iteration():
-        L.lag_gradient(plan, v, Td, Rd, g, out3)
-        J = float(out3[0].item())
-        torch.neg(g, out=rhs)
-        info = L.lag_pcg(plan, v, Td, None, rhs, dv, tol=w.pcg_tol, maxit=w.pcg_maxit)
-        slope = float(torch.dot(g.double(), dv.double()).item())
-        mu, halvings = 1.0, 0
-        while True:
-            torch.add(v, dv, alpha=mu, out=vtrial)
-            L.lag_objective(plan, vtrial, Td, Rd, None, out3)
-            Jt = float(out3[0].item())
-            if Jt <= J + 1e-4 * mu * slope or halvings >= 10:
-                break
-            mu *= 0.5
-            halvings += 1
-        return info, J, Jt, mu
+        return L.lag_gn_step(plan, Td, Rd, v, v_next, opts)
 
     for i in range(args.warmup):
-        info, J, Jt, mu = gn_iteration()
-        log(args, f"warmup {i}: pcg iters {info['iters']} relres {info['relres']:.3f} "
-                  f"J {J:.4e} -> {Jt:.4e} (mu {mu})")
+        info = gn_iteration()
+        log(args, f"warmup {i}: assembled {info['assembled']} pcg iters {info['pcg_iters']} "
+                  f"J {info['J']:.4e} -> {info['J_next']:.4e} (mu {info['mu']})")
     L.lag_profile_enable(plan, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     matvecs = 0
     iters = []
+    assembled = []
     for i in range(args.steps):
-        info, J, Jt, mu = gn_iteration()
+        info = gn_iteration()
         matvecs += info["matvecs"]
-        iters.append(info["iters"])
+        iters.append(info["pcg_iters"])
+        assembled.append(info["assembled"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kern_ms, kern_n = L.lag_profile_read(plan)
@@ -156,12 +147,24 @@ def main():
 
     # roofline of the dominant kernel
     kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
-    flops = n * (w.nsteps * FLOP_PER_CHAR_STEP_3D + FLOP_PER_CHAR_END_3D)
-    achieved = flops / kern_avg_s / 1e12
-    roof = {"bound": "alu", "kernel": "k_hess_transport<3,false>", "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
-            "kernel_ms": round(kern_avg_s * 1e3, 4), "launches_timed": kern_n}
+    if all(assembled):
+        # assembled matvec: algorithmic bytes = stored Jacobian blocks + one
+        # count byte per row slot + p read + Hp written (4 B per unknown each)
+        blocks, kmax_seen, bpb = L.lag_jacobian_info(plan)
+        alg_bytes = blocks * bpb + n + 2 * 4 * nu
+        achieved = alg_bytes / kern_avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": f"k_jac_apply<{w.dim}>", "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": None, "alg_bytes_per_launch": int(alg_bytes), "jac_blocks": int(blocks),
+                "blocks_per_row_max": kmax_seen}
+    else:
+        flops = n * (w.nsteps * FLOP_PER_CHAR_STEP_3D + FLOP_PER_CHAR_END_3D)
+        achieved = flops / kern_avg_s / 1e12
+        roof = {"bound": "alu", "kernel": f"k_hess_transport<{w.dim},false>", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None}
+    roof["kernel_ms"] = round(kern_avg_s * 1e3, 4)
+    roof["launches_timed"] = kern_n
     res = {
         "metric": "GN Hessian matvecs/s at 128^3",
         "value": round(matvecs / dt, 3),
@@ -179,6 +182,7 @@ def main():
                    "nsteps": w.nsteps, "model": w.model, "regularizer": w.reg, "alpha": w.alpha,
                    "iterate": "v_true/2", "pcg_tol": w.pcg_tol, "pcg_maxit": w.pcg_maxit},
         "matvecs_per_step": matvecs / args.steps,
+        "assembled_jacobian": bool(all(assembled)),
         "roofline": roof,
         "cpu_baseline": None,
     }

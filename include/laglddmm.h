@@ -74,6 +74,10 @@ typedef struct lag_problem {
     int32_t nsteps;       /* N >= 1 RK4 steps over the unit time interval      */
     double  alpha;        /* regularisation weight, >= 0                       */
     double  gamma;        /* Hessian shift gamma I (Sec. 3.2), >= 0            */
+    int32_t jac_blocks;   /* capacity of the assembled Jacobian, in velocity-
+                             cell blocks per characteristic (0 = no assembled
+                             Jacobian; used only by the transport model with
+                             a stationary velocity; <= 255)                    */
 } lag_problem;
 
 typedef struct lag_plan_s* lag_plan;
@@ -177,6 +181,38 @@ int gn_hessmat(lag_plan plan, const float* v, const float* T, const float* wvox,
  * alpha = gamma = 0 (no regulariser block to invert) returns LAG_EINVAL. */
 int spectral_precond_apply(lag_plan plan, const float* r, float* z, void* stream);
 
+/* ---- assembled Jacobian (transport model, stationary velocity) ----------
+ * The paper notes that the sparse derivative can be built explicitly to
+ * speed up matrix-vector products (Sec. 1 contributions; Sec. 3.3).  Row i of
+ * J = d u1/d v, grad T(y_i)^T d y_i/d v, is stored as one block of
+ * 2^d x dim values per velocity cell the characteristic's RK4 samples visit
+ * (plan capacity: jac_blocks blocks per characteristic).  Assembly costs
+ * about one lag_vjp; each following product streams the stored blocks. */
+
+/* Assemble J(v) for the plan's template T.  Synchronises `stream`.
+ * *stored (host) is set to 1 if every row fit the plan's capacity (the
+ * assembled calls below may then be used until the next assembly), else 0
+ * (callers use the matrix-free calls).  LAG_EUNSUPPORTED if the plan has no
+ * Jacobian storage (jac_blocks = 0, continuity, or a time-dependent
+ * velocity). */
+int lag_jacobian_assemble(lag_plan plan, const float* v, const float* T, int32_t* stored,
+                          void* stream);
+
+/* Size of the last assembly (host pointers): stored blocks (0 if none is
+ * stored), the largest block count of any characteristic (may exceed the
+ * capacity, which is why an assembly was not stored), and the bytes one
+ * block occupies (values plus packed cell). */
+int lag_jacobian_info(lag_plan plan, int64_t* blocks, int32_t* max_blocks, int32_t* bytes_per_block);
+
+/* gn_hessmat with the assembled J of the last successful assembly:
+ * Hp = h^d J^T (W (J p)) + alpha h_v^d A p + gamma p.  LAG_EINVAL if no
+ * assembly is stored. */
+int gn_hessmat_assembled(lag_plan plan, const float* wvox, const float* p, float* Hp,
+                         void* stream);
+
+/* J^T w with the assembled J (w image-shaped, JTw velocity-shaped). */
+int lag_vjp_assembled(lag_plan plan, const float* w, float* JTw, void* stream);
+
 /* ---- compositions used by the Gauss-Newton driver ----------------------- */
 
 /* Regulariser part of H: out = alpha h_v^d w_j A p_j + gamma p. */
@@ -205,6 +241,11 @@ typedef struct lag_pcg_info {
     double  relres;       /* final |r| / |b|                                */
 } lag_pcg_info;
 
+/* lag_gradient whose data term J^T (h^d res) uses the assembled J; v and T
+ * must be the ones passed to the last successful lag_jacobian_assemble. */
+int lag_gradient_assembled(lag_plan plan, const float* v, const float* T, const float* R,
+                           float* g, double* out3, void* stream);
+
 /* Preconditioned CG for H(v) x = b (Sec. 3.2, eq. solveGN), x0 = 0,
  * stopping when |r|_2 <= tol |b|_2 or after maxit iterations.  H is
  * gn_hessmat with voxel weights wvox (NULL = 1); the preconditioner is
@@ -215,6 +256,10 @@ typedef struct lag_pcg_info {
 int lag_pcg(lag_plan plan, const float* v, const float* T, const float* wvox,
             const float* b, float* x, double tol, int32_t maxit,
             lag_pcg_info* info, void* stream);
+
+/* lag_pcg with the assembled Gauss-Newton operator (gn_hessmat_assembled). */
+int lag_pcg_assembled(lag_plan plan, const float* wvox, const float* b, float* x, double tol,
+                      int32_t maxit, lag_pcg_info* info, void* stream);
 
 typedef struct lag_gn_options {
     double  gtol;           /* stop when |g| <= gtol |g(v=0)|   (1e-2)        */
@@ -237,12 +282,33 @@ typedef struct lag_gn_info {
 /* Default options (host pointer). */
 void lag_gn_default_options(lag_gn_options* opt);
 
+typedef struct lag_gn_step_info {
+    int32_t assembled;      /* 1 if the step used the assembled Jacobian       */
+    int32_t pcg_iters;      /* PCG iterations                                 */
+    int32_t matvecs;        /* Gauss-Newton matvecs                            */
+    int32_t halvings;       /* line-search step halvings                       */
+    int32_t stopped;        /* 1 if |g| <= gstop and no step was taken         */
+    int32_t accepted;       /* 1 if the line search found a step               */
+    double  J, gnorm;       /* objective and gradient norm at v                */
+    double  J_next, mu;     /* objective at v_next and the step length         */
+} lag_gn_step_info;
+
+/* One inexact Gauss-Newton iteration (Sec. 3.2, eq. solveGN): gradient at v,
+ * PCG for H(v) dv = -g (assembled Jacobian when the plan has one and it
+ * fits, else matrix-free), Armijo backtracking, v_next = v + mu dv.  If
+ * |g| <= gstop, no step is taken and v_next = v.  v and v_next are distinct
+ * velocity-shaped device buffers.  Synchronises `stream`.  Returns
+ * LAG_ELINESEARCH if no acceptable step was found (v_next = v). */
+int lag_gn_step(lag_plan plan, const float* T, const float* R, const float* v, float* v_next,
+                const lag_gn_options* opt, double gstop, lag_gn_step_info* info, void* stream);
+
 /* Inexact Gauss-Newton-Krylov solve of min_v J(v) (Sec. 3.2): search
  * direction from lag_pcg, Armijo backtracking by halving.  v is the start
  * value on entry and the solution on exit (velocity-shaped, device).
  * opt: host pointer or NULL for defaults; info: host pointer or NULL.
- * Synchronises `stream` to read scalars.  Returns LAG_ELINESEARCH if the
- * line search fails (v then holds the last accepted iterate). */
+ * Each iteration is lag_gn_step.  Synchronises `stream` to read scalars.
+ * Returns LAG_ELINESEARCH if the line search fails (v then holds the last
+ * accepted iterate). */
 int lag_gn_solve(lag_plan plan, const float* T, const float* R, float* v,
                  const lag_gn_options* opt, lag_gn_info* info, void* stream);
 

@@ -36,6 +36,7 @@ class LagProblem(ctypes.Structure):
         ("nsteps", ctypes.c_int32),
         ("alpha", ctypes.c_double),
         ("gamma", ctypes.c_double),
+        ("jac_blocks", ctypes.c_int32),
     ]
 
 
@@ -48,6 +49,14 @@ class LagGnOptions(ctypes.Structure):
     _fields_ = [("gtol", ctypes.c_double), ("max_gn", ctypes.c_int32),
                 ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int32),
                 ("armijo_c1", ctypes.c_double), ("max_halvings", ctypes.c_int32)]
+
+
+class LagGnStepInfo(ctypes.Structure):
+    _fields_ = [("assembled", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
+                ("matvecs", ctypes.c_int32), ("halvings", ctypes.c_int32),
+                ("stopped", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("J", ctypes.c_double), ("gnorm", ctypes.c_double),
+                ("J_next", ctypes.c_double), ("mu", ctypes.c_double)]
 
 
 class LagGnInfo(ctypes.Structure):
@@ -94,6 +103,16 @@ _SIGS = {
     "lag_pcg": (_I, [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int32,
                      ctypes.POINTER(LagPcgInfo), _P]),
     "lag_gn_default_options": (None, [ctypes.POINTER(LagGnOptions)]),
+    "lag_jacobian_assemble": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
+    "gn_hessmat_assembled": (_I, [_P, _P, _P, _P, _P]),
+    "lag_jacobian_info": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32)]),
+    "lag_vjp_assembled": (_I, [_P, _P, _P, _P]),
+    "lag_gradient_assembled": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "lag_pcg_assembled": (_I, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32,
+                               ctypes.POINTER(LagPcgInfo), _P]),
+    "lag_gn_step": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(LagGnOptions), ctypes.c_double,
+                         ctypes.POINTER(LagGnStepInfo), _P]),
     "lag_gn_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(LagGnOptions),
                           ctypes.POINTER(LagGnInfo), _P]),
 }
@@ -135,8 +154,11 @@ def _check(name, status):
 
 
 def make_problem(dim, img_m, vel_m, nt_nodes=1, model="transport", reg="diffusion", nsteps=5,
-                 alpha=1e-2, gamma=0.0, extent=(1.0, 1.0, 1.0)):
-    """Fill a ``lag_problem`` (sizes x first; unused axes become 1)."""
+                 alpha=1e-2, gamma=0.0, extent=(1.0, 1.0, 1.0), jac_blocks=0):
+    """Fill a ``lag_problem`` (sizes x first; unused axes become 1).
+
+    ``jac_blocks`` > 0 gives the plan storage for an assembled Jacobian
+    (transport model with a stationary velocity only)."""
     p = LagProblem()
     p.dim = dim
     for a in range(3):
@@ -149,6 +171,7 @@ def make_problem(dim, img_m, vel_m, nt_nodes=1, model="transport", reg="diffusio
     p.nsteps = nsteps
     p.alpha = alpha
     p.gamma = gamma
+    p.jac_blocks = jac_blocks
     return p
 
 
@@ -301,6 +324,64 @@ def lag_pcg(plan, v, T, wvox, b, x, tol=0.1, maxit=50):
         _check("lag_pcg", st)
     return {"iters": info.iters, "matvecs": info.matvecs, "breakdown": bool(info.breakdown),
             "relres": info.relres, "status": st}
+
+
+def lag_jacobian_assemble(plan, v, T):
+    """Assemble J(v); returns True if it fit the plan's capacity."""
+    stored = ctypes.c_int32()
+    _check("lag_jacobian_assemble", load().lag_jacobian_assemble(
+        plan.handle, _ptr(v, plan.n_unknowns, "v"), _ptr(T, plan.n_points, "T"), ctypes.byref(stored),
+        _stream()))
+    return bool(stored.value)
+
+
+def lag_jacobian_info(plan):
+    """(stored blocks, largest per-row block count, bytes per block)."""
+    b, m, nb = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check("lag_jacobian_info", load().lag_jacobian_info(plan.handle, ctypes.byref(b), ctypes.byref(m),
+                                                         ctypes.byref(nb)))
+    return b.value, m.value, nb.value
+
+
+def gn_hessmat_assembled(plan, wvox, p, Hp):
+    _check("gn_hessmat_assembled", load().gn_hessmat_assembled(
+        plan.handle, _ptr(wvox, plan.n_points, "wvox"), _ptr(p, plan.n_unknowns, "p"),
+        _ptr(Hp, plan.n_unknowns, "Hp"), _stream()))
+
+
+def lag_vjp_assembled(plan, w, JTw):
+    _check("lag_vjp_assembled", load().lag_vjp_assembled(
+        plan.handle, _ptr(w, plan.n_points, "w"), _ptr(JTw, plan.n_unknowns, "JTw"), _stream()))
+
+
+def lag_gradient_assembled(plan, v, T, R, g, out3):
+    _check("lag_gradient_assembled", load().lag_gradient_assembled(
+        plan.handle, _ptr(v, plan.n_unknowns, "v"), _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
+        _ptr(g, plan.n_unknowns, "g"), _ptr(out3, 3, "out3"), _stream()))
+
+
+def lag_pcg_assembled(plan, wvox, b, x, tol=0.1, maxit=50):
+    info = LagPcgInfo()
+    st = load().lag_pcg_assembled(plan.handle, _ptr(wvox, plan.n_points, "wvox"), _ptr(b, plan.n_unknowns, "b"),
+                                  _ptr(x, plan.n_unknowns, "x"), float(tol), int(maxit), ctypes.byref(info),
+                                  _stream())
+    if st not in (LAG_OK, LAG_EBREAKDOWN):
+        _check("lag_pcg_assembled", st)
+    return {"iters": info.iters, "matvecs": info.matvecs, "breakdown": bool(info.breakdown),
+            "relres": info.relres, "status": st}
+
+
+def lag_gn_step(plan, T, R, v, v_next, options=None, gstop=0.0):
+    o = options if options is not None else lag_gn_default_options()
+    info = LagGnStepInfo()
+    st = load().lag_gn_step(plan.handle, _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
+                            _ptr(v, plan.n_unknowns, "v"), _ptr(v_next, plan.n_unknowns, "v_next"),
+                            ctypes.byref(o), float(gstop), ctypes.byref(info), _stream())
+    if st not in (LAG_OK, LAG_ELINESEARCH):
+        _check("lag_gn_step", st)
+    d = {f: getattr(info, f) for f, _ in LagGnStepInfo._fields_}
+    d["status"] = st
+    return d
 
 
 def lag_gn_default_options():

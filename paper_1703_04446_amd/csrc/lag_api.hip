@@ -89,7 +89,8 @@ static void free_plan(lag_plan P) {
                   P->part_base, P->part_vals, P->scan_blocks, P->red_partial, P->scalars, P->fft_buf,
                   P->fft_tw[0], P->fft_tw[1], P->fft_tw[2], P->fft_lam[0], P->fft_lam[1], P->fft_lam[2],
                   P->fft_mu1, P->flags, P->tile_part, P->cover_start[0], P->cover_start[1],
-                  P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2]};
+                  P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2], P->jac_vals,
+                  P->jac_cell, P->jac_cnt, P->jac_max};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < 10; ++i)
@@ -148,6 +149,7 @@ int lag_problem_check(const lag_problem* p) {
   LAG_CHECK(p->nsteps >= 1 && p->nsteps <= (1 << 16));
   LAG_CHECK(p->alpha >= 0.0 && isfinite(p->alpha));
   LAG_CHECK(p->gamma >= 0.0 && isfinite(p->gamma));
+  LAG_CHECK(p->jac_blocks >= 0 && p->jac_blocks <= 255);
   LAG_CHECK(np <= 0x7fffffffLL);
   LAG_CHECK(nv * p->nt_nodes * p->dim <= 0x7fffffffLL);
   return LAG_OK;
@@ -280,6 +282,16 @@ int lag_plan_create(const lag_problem* prob, lag_plan* out) {
   for (int i = 0; i < 10; ++i) ALLOC(P->vec[i], sizeof(float) * P->n_unknowns);
   ALLOC(P->flags, sizeof(int) * 4);
   HIPC(hipMemset(P->flags, 0, sizeof(int) * 4));
+  if (prob->jac_blocks > 0 && prob->model == LAG_TRANSPORT && g.nodes == 1) {
+    const lag::Bricks& B = P->bricks;
+    P->jac_k = prob->jac_blocks;
+    P->jac_slots = (long long)B.nbricks * B.bdim[0] * B.bdim[1] * B.bdim[2];
+    const int nv4 = D == 3 ? 6 : 2;
+    ALLOC(P->jac_vals, sizeof(float4) * (size_t)P->jac_k * nv4 * P->jac_slots);
+    ALLOC(P->jac_cell, sizeof(int) * (size_t)P->jac_k * P->jac_slots);
+    ALLOC(P->jac_cnt, (size_t)P->jac_slots);
+    ALLOC(P->jac_max, sizeof(int) * 2);
+  }
   rc = tiles_setup(P);
   if (rc) {
     lag::free_plan(P);
@@ -449,6 +461,64 @@ int lag_gradient(lag_plan P, const float* v, const float* T, const float* R, flo
   return launch_reg(P, v, g, 1, 0, 1.f, s);
 }
 
+// ---- assembled Jacobian ------------------------------------------------------
+
+int lag_jacobian_assemble(lag_plan P, const float* v, const float* T, int32_t* stored, void* stream) {
+  LAG_CHECK(P && v && T && stored);
+  *stored = 0;
+  P->jac_ready = 0;
+  if (P->jac_k == 0) return LAG_EUNSUPPORTED;
+  hipStream_t s = S(stream);
+  int rc = launch_pack(P, v, P->pack_v, s);
+  if (rc) return rc;
+  if ((rc = launch_jac_assemble(P, P->pack_v, T, s))) return rc;
+  int mx[2] = {0, 0};
+  LAG_HIP(hipMemcpyAsync(mx, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  P->jac_ready = mx[0] <= P->jac_k;
+  P->jac_blocks_stored = mx[1];
+  P->jac_max_seen = mx[0];
+  *stored = P->jac_ready;
+  return LAG_OK;
+}
+
+int lag_jacobian_info(lag_plan P, int64_t* blocks, int32_t* max_blocks, int32_t* bytes_per_block) {
+  LAG_CHECK(P && blocks && max_blocks && bytes_per_block);
+  *blocks = P->jac_ready ? P->jac_blocks_stored : 0;
+  *max_blocks = P->jac_max_seen;
+  *bytes_per_block = P->geo.dim == 3 ? 6 * 16 + 4 : 2 * 16 + 4;
+  return LAG_OK;
+}
+
+int gn_hessmat_assembled(lag_plan P, const float* wvox, const float* p, float* Hp, void* stream) {
+  LAG_CHECK(P && p && Hp && P->jac_ready);
+  hipStream_t s = S(stream);
+  int rc = launch_pack(P, p, P->pack_p, s);
+  if (rc) return rc;
+  if ((rc = launch_fill(Hp, P->n_unknowns, 0.f, s))) return rc;
+  if ((rc = launch_jac_apply(P, P->pack_p, wvox, nullptr, P->geo.cell_img, Hp, s))) return rc;
+  return launch_reg(P, p, Hp, 1, 1, 1.f, s);
+}
+
+int lag_vjp_assembled(lag_plan P, const float* w, float* JTw, void* stream) {
+  LAG_CHECK(P && w && JTw && P->jac_ready);
+  hipStream_t s = S(stream);
+  int rc = launch_fill(JTw, P->n_unknowns, 0.f, s);
+  if (rc) return rc;
+  return launch_jac_apply(P, P->pack_p, nullptr, w, 1.f, JTw, s);
+}
+
+int lag_gradient_assembled(lag_plan P, const float* v, const float* T, const float* R, float* g, double* out3,
+                           void* stream) {
+  LAG_CHECK(P && v && T && R && g && P->jac_ready);
+  hipStream_t s = S(stream);
+  int rc = objective_full(P, v, T, R, nullptr, P->img_b, out3 ? out3 : P->scalars + 8, s);
+  if (rc) return rc;
+  if ((rc = launch_fill(g, P->n_unknowns, 0.f, s))) return rc;
+  if ((rc = launch_jac_apply(P, P->pack_p, nullptr, P->img_b, 1.f, g, s))) return rc;
+  return launch_reg(P, v, g, 1, 0, 1.f, s);
+}
+
 // ---- PCG / Gauss-Newton ------------------------------------------------------
 
 static int read_scalars(lag_plan P, double* host, int off, int cnt, hipStream_t s) {
@@ -457,10 +527,13 @@ static int read_scalars(lag_plan P, double* host, int off, int cnt, hipStream_t 
   return LAG_OK;
 }
 
-int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const float* b, float* x, double tol,
-            int32_t maxit, lag_pcg_info* info, void* stream) {
-  LAG_CHECK(P && v && T && b && x && maxit >= 0 && tol >= 0.0);
-  hipStream_t s = S(stream);
+}  // extern "C"
+
+// Preconditioned CG with the Gauss-Newton operator `H` (a callable
+// H(p, Hp) -> status); device-side alpha/beta, one host sync per iteration.
+template <class Op>
+static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int32_t maxit, lag_pcg_info* info,
+                    hipStream_t s) {
   const long long n = P->n_unknowns;
   float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
   double* sc = P->scalars;  // [0] rz, [1] pHp, [2] rz_new, [3] rr, [4] breakdown, [5] bb
@@ -469,6 +542,8 @@ int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const
   if ((rc = launch_fill(x, n, 0.f, s))) return rc;
   if ((rc = launch_axpby(n, 1.f, b, 0.f, nullptr, r, s))) return rc;
   if ((rc = launch_dot(P, n, b, b, sc + 5, s))) return rc;
+  hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 4, 0.0);
+  LAG_LAUNCH_CHECK();
   double h[6];
   if ((rc = read_scalars(P, h, 0, 6, s))) return rc;
   const double nb = sqrt(h[5]);
@@ -481,9 +556,6 @@ int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const
   if ((rc = launch_axpby(n, 1.f, z, 0.f, nullptr, p, s))) return rc;
   double rr = h[5];
   int status = LAG_OK;
-  // clear the breakdown flag
-  hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 4, 0.0);
-  LAG_LAUNCH_CHECK();
   for (int it = 0; it < maxit; ++it) {
     if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
     if ((rc = read_scalars(P, h, 0, 5, s))) return rc;
@@ -491,10 +563,11 @@ int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const
     if (h[4] != 0.0) {
       status = LAG_EBREAKDOWN;
       loc.breakdown = 1;
+      if (loc.iters > 0) loc.iters--;
       break;
     }
     if (sqrt(rr) <= tol * nb) break;
-    if ((rc = gn_hessmat(P, v, T, wvox, p, Hp, stream))) return rc;
+    if ((rc = H(p, Hp))) return rc;
     loc.matvecs++;
     if ((rc = launch_dot(P, n, p, Hp, sc + 1, s))) return rc;
     if ((rc = launch_pcg_xr(n, x, r, p, Hp, sc, s))) return rc;
@@ -518,6 +591,22 @@ int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const
   return status;
 }
 
+extern "C" {
+
+int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const float* b, float* x, double tol,
+            int32_t maxit, lag_pcg_info* info, void* stream) {
+  LAG_CHECK(P && v && T && b && x && maxit >= 0 && tol >= 0.0);
+  auto H = [&](const float* p, float* Hp) { return gn_hessmat(P, v, T, wvox, p, Hp, stream); };
+  return pcg_impl(P, H, b, x, tol, maxit, info, S(stream));
+}
+
+int lag_pcg_assembled(lag_plan P, const float* wvox, const float* b, float* x, double tol, int32_t maxit,
+                      lag_pcg_info* info, void* stream) {
+  LAG_CHECK(P && b && x && maxit >= 0 && tol >= 0.0 && P->jac_ready);
+  auto H = [&](const float* p, float* Hp) { return gn_hessmat_assembled(P, wvox, p, Hp, stream); };
+  return pcg_impl(P, H, b, x, tol, maxit, info, S(stream));
+}
+
 void lag_gn_default_options(lag_gn_options* o) {
   if (!o) return;
   o->gtol = 1e-2;
@@ -526,6 +615,72 @@ void lag_gn_default_options(lag_gn_options* o) {
   o->pcg_maxit = 50;
   o->armijo_c1 = 1e-4;
   o->max_halvings = 10;
+}
+
+int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, float* v_next,
+                const lag_gn_options* opt, double gstop, lag_gn_step_info* info, void* stream) {
+  LAG_CHECK(P && T && R && v && v_next && v != v_next);
+  lag_gn_options o;
+  lag_gn_default_options(&o);
+  if (opt) o = *opt;
+  LAG_CHECK(o.pcg_maxit >= 0 && o.max_halvings >= 0);
+  hipStream_t s = S(stream);
+  const long long n = P->n_unknowns;
+  float *g = P->vec[0], *rhs = P->vec[1], *dv = P->vec[2];
+  double* sc = P->scalars;
+  double h[8];
+  lag_gn_step_info loc;
+  memset(&loc, 0, sizeof(loc));
+  int rc;
+  int32_t stored = 0;
+  if (P->jac_k > 0) {
+    if ((rc = lag_jacobian_assemble(P, v, T, &stored, stream))) return rc;
+  }
+  loc.assembled = stored;
+  if (stored) rc = lag_gradient_assembled(P, v, T, R, g, sc + 8, stream);
+  else rc = lag_gradient(P, v, T, R, g, sc + 8, stream);
+  if (rc) return rc;
+  if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+  if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
+  loc.J = h[0];
+  loc.gnorm = sqrt(h[3]);
+  loc.J_next = loc.J;
+  if (loc.gnorm <= gstop) {
+    loc.stopped = 1;
+    if (info) *info = loc;
+    return launch_axpby(n, 1.f, v, 0.f, nullptr, v_next, s);
+  }
+  if ((rc = launch_axpby(n, -1.f, g, 0.f, nullptr, rhs, s))) return rc;
+  lag_pcg_info pi;
+  if (stored) rc = lag_pcg_assembled(P, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
+  else rc = lag_pcg(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
+  if (rc != LAG_OK && rc != LAG_EBREAKDOWN) return rc;
+  loc.pcg_iters = pi.iters;
+  loc.matvecs = pi.matvecs;
+  if ((rc = launch_dot(P, n, g, dv, sc + 12, s))) return rc;
+  if ((rc = read_scalars(P, h + 4, 12, 1, s))) return rc;
+  const double slope = h[4];
+  double mu = 1.0;
+  for (int k = 0; k <= o.max_halvings; ++k) {
+    if ((rc = launch_axpby(n, 1.f, v, (float)mu, dv, v_next, s))) return rc;
+    if ((rc = objective_full(P, v_next, T, R, nullptr, nullptr, sc + 13, s))) return rc;
+    if ((rc = read_scalars(P, h + 5, 13, 1, s))) return rc;
+    if (h[5] <= loc.J + o.armijo_c1 * mu * slope) {
+      loc.accepted = 1;
+      loc.J_next = h[5];
+      loc.mu = mu;
+      break;
+    }
+    loc.halvings = k + 1;
+    mu *= 0.5;
+  }
+  if (!loc.accepted) {
+    if (info) *info = loc;
+    if ((rc = launch_axpby(n, 1.f, v, 0.f, nullptr, v_next, s))) return rc;
+    return LAG_ELINESEARCH;
+  }
+  if (info) *info = loc;
+  return LAG_OK;
 }
 
 int lag_gn_solve(lag_plan P, const float* T, const float* R, float* v, const lag_gn_options* opt,
@@ -537,9 +692,9 @@ int lag_gn_solve(lag_plan P, const float* T, const float* R, float* v, const lag
   LAG_CHECK(o.max_gn >= 0 && o.pcg_maxit >= 0 && o.max_halvings >= 0 && o.gtol >= 0.0);
   hipStream_t s = S(stream);
   const long long n = P->n_unknowns;
-  float *g = P->vec[0], *rhs = P->vec[1], *dv = P->vec[2], *vt = P->vec[7], *zero = P->vec[8];
+  float *g = P->vec[0], *vn = P->vec[7], *zero = P->vec[8];
   double* sc = P->scalars;
-  double h[16];
+  double h[8];
   lag_gn_info loc;
   memset(&loc, 0, sizeof(loc));
   int rc;
@@ -549,57 +704,30 @@ int lag_gn_solve(lag_plan P, const float* T, const float* R, float* v, const lag
   if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
   if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
   loc.g0 = sqrt(h[3]);
+  const double gstop = o.gtol * loc.g0;
   int status = LAG_OK;
-  for (int it = 0; it < o.max_gn; ++it) {
-    if ((rc = lag_gradient(P, v, T, R, g, sc + 8, stream))) return rc;
-    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
-    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
-    const double J = h[0];
-    const double gn = sqrt(h[3]);
-    if (it == 0) loc.J0 = J;
-    loc.J = J;
-    loc.gnorm = gn;
-    if (gn <= o.gtol * loc.g0) {
-      loc.converged = 1;
+  for (int it = 0; it <= o.max_gn; ++it) {
+    lag_gn_step_info si;
+    // the last pass only evaluates the gradient (gstop = +inf)
+    const double stop_here = it == o.max_gn ? 1e300 : gstop;
+    rc = lag_gn_step(P, T, R, v, vn, &o, stop_here, &si, stream);
+    if (rc != LAG_OK && rc != LAG_ELINESEARCH) return rc;
+    if (it == 0) loc.J0 = si.J;
+    loc.J = si.J;
+    loc.gnorm = si.gnorm;
+    if (si.stopped) {
+      loc.converged = si.gnorm <= gstop;
       break;
     }
-    if ((rc = launch_axpby(n, -1.f, g, 0.f, nullptr, rhs, s))) return rc;
-    lag_pcg_info pi;
-    rc = lag_pcg(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
-    if (rc != LAG_OK && rc != LAG_EBREAKDOWN) return rc;
-    loc.pcg_iters += pi.iters;
-    loc.matvecs += pi.matvecs;
-    if ((rc = launch_dot(P, n, g, dv, sc + 12, s))) return rc;
-    if ((rc = read_scalars(P, h + 4, 12, 1, s))) return rc;
-    const double slope = h[4];
-    double mu = 1.0;
-    bool accepted = false;
-    for (int k = 0; k <= o.max_halvings; ++k) {
-      if ((rc = launch_axpby(n, 1.f, v, (float)mu, dv, vt, s))) return rc;
-      if ((rc = objective_full(P, vt, T, R, nullptr, nullptr, sc + 13, s))) return rc;
-      if ((rc = read_scalars(P, h + 5, 13, 1, s))) return rc;
-      if (h[5] <= J + o.armijo_c1 * mu * slope) {
-        accepted = true;
-        break;
-      }
-      mu *= 0.5;
-    }
     loc.iters = it + 1;
-    if (!accepted) {
+    loc.pcg_iters += si.pcg_iters;
+    loc.matvecs += si.matvecs;
+    if (rc == LAG_ELINESEARCH) {
       status = LAG_ELINESEARCH;
       break;
     }
-    if ((rc = launch_axpby(n, 1.f, vt, 0.f, nullptr, v, s))) return rc;
-    loc.J = h[5];
-  }
-  if (status == LAG_OK && !loc.converged && o.max_gn > 0) {
-    // report the gradient at the final iterate
-    if ((rc = lag_gradient(P, v, T, R, g, sc + 8, stream))) return rc;
-    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
-    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
-    loc.J = h[0];
-    loc.gnorm = sqrt(h[3]);
-    loc.converged = loc.gnorm <= o.gtol * loc.g0;
+    if ((rc = launch_axpby(n, 1.f, vn, 0.f, nullptr, v, s))) return rc;
+    loc.J = si.J_next;
   }
   if (info) *info = loc;
   return status;

@@ -51,6 +51,17 @@ struct lag_plan_s {
   float* fft_mu1 = nullptr;    // per node replacement for a zero mode
   int fft_rad[3][16];
   int fft_nrad[3];
+  // assembled Jacobian (transport, stationary): capacity jac_k blocks per
+  // characteristic slot; jac_ready once a complete assembly is stored
+  int jac_k = 0;
+  long long jac_slots = 0;
+  float4* jac_vals = nullptr;
+  int* jac_cell = nullptr;
+  unsigned char* jac_cnt = nullptr;
+  int* jac_max = nullptr;
+  int jac_ready = 0;
+  long long jac_blocks_stored = 0;
+  int jac_max_seen = 0;
   // per-brick partial velocity tiles and, per axis, the list of (brick,
   // tile offset) pairs covering each velocity index (fixed-order reduction)
   float* tile_part = nullptr;
@@ -94,6 +105,9 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
 int launch_tile_reduce(lag_plan P, float* out, hipStream_t s);
+int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, hipStream_t s);
+int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
+                     hipStream_t s);
 int tiles_setup(lag_plan P);       // partial-tile buffer + cover tables (plan creation)
 int launch_reg(lag_plan P, const float* p, float* out, int accumulate, int with_gamma,
                float extra_scale, hipStream_t s);

@@ -323,14 +323,16 @@ struct Merge {
 
   __device__ __forceinline__ void reset() { active = false; }
 
-  __device__ __forceinline__ void flush(const TileAcc<D, NS>& acc) {
+  template <class Acc>
+  __device__ __forceinline__ void flush(Acc& acc) {
     if (active) acc.template add_block<NSLOT>(cell, j0, a);
     active = false;
   }
 
-  __device__ __forceinline__ void add(const TileAcc<D, NS>& acc, const Loc<D>& L, int q, const float kb[D]) {
-    int jA = NS ? acc.j0[q] : 0;
-    float th = NS ? acc.th[q] : 0.f;
+  template <class Acc>
+  __device__ __forceinline__ void add(Acc& acc, const Stages& st, const Loc<D>& L, int q, const float kb[D]) {
+    int jA = NS ? st.j0[q] : 0;
+    float th = NS ? st.th[q] : 0.f;
     bool same = active && (jA == j0);
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) same = same && (L.c[ax] == cell[ax]);
@@ -372,11 +374,14 @@ struct UseMerge {
 };
 
 // pass 2: replay the sweep, recover the step adjoints and scatter them.
-template <int D, bool NS>
+// The four stage adjoints of a step are formed last-to-first (each depends
+// on the next) and then scattered first-to-last, so that consecutive
+// scatters move monotonically along the characteristic and the register
+// merge sees each crossed cell once.
+template <int D, bool NS, class Acc>
 __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
                                              const typename VecT<D>::T* __restrict__ vp,
-                                             const Start<D>& S, float ybar[D],
-                                             const TileAcc<D, NS>& acc) {
+                                             const Start<D>& S, float ybar[D], Acc& acc) {
   const float dt = st.dt, hdt = 0.5f * dt;
   float phi[D];
   bool ok = true;
@@ -384,7 +389,7 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
   Merge<D, NS> mg;
   mg.reset();
   auto scat = [&](const Loc<D>& L, int q, const float kb[D]) {
-    if (MERGE) mg.add(acc, L, q, kb);
+    if constexpr (MERGE) mg.add(acc, st, L, q, kb);
     else acc.add(L, q, kb);
   };
 #pragma unroll
@@ -413,47 +418,47 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
 #pragma unroll
       for (int a = 0; a < D; ++a) yn[a] = ybar[a];
     }
-    // adjoints of the stage velocities
-    float kb[D], pb[D];
+    // adjoints of the stage velocities, last stage first
+    float kb1[D], kb2[D], kb3[D], kb4[D], pb[D];
     const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
 #pragma unroll
-    for (int a = 0; a < D; ++a) kb[a] = c6 * yn[a];
-    scat(L4, q + 3, kb);
+    for (int a = 0; a < D; ++a) kb4[a] = c6 * yn[a];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      float s = 0.f;
+      float t = 0.f;
 #pragma unroll
-      for (int c = 0; c < D; ++c) s = fmaf(G4[c][a], kb[c], s);
-      pb[a] = s;
+      for (int c = 0; c < D; ++c) t = fmaf(G4[c][a], kb4[c], t);
+      pb[a] = t;
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) kb[a] = fmaf(dt, pb[a], c3 * yn[a]);
-    scat(L3, q + 2, kb);
+    for (int a = 0; a < D; ++a) kb3[a] = fmaf(dt, pb[a], c3 * yn[a]);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      float s = 0.f;
+      float t = 0.f;
 #pragma unroll
-      for (int c = 0; c < D; ++c) s = fmaf(G3[c][a], kb[c], s);
-      pb[a] = s;
+      for (int c = 0; c < D; ++c) t = fmaf(G3[c][a], kb3[c], t);
+      pb[a] = t;
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) kb[a] = fmaf(hdt, pb[a], c3 * yn[a]);
-    scat(L2, q + 1, kb);
+    for (int a = 0; a < D; ++a) kb2[a] = fmaf(hdt, pb[a], c3 * yn[a]);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      float s = 0.f;
+      float t = 0.f;
 #pragma unroll
-      for (int c = 0; c < D; ++c) s = fmaf(G2[c][a], kb[c], s);
-      pb[a] = s;
+      for (int c = 0; c < D; ++c) t = fmaf(G2[c][a], kb2[c], t);
+      pb[a] = t;
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) kb[a] = fmaf(hdt, pb[a], c6 * yn[a]);
-    scat(L1, q, kb);
+    for (int a = 0; a < D; ++a) kb1[a] = fmaf(hdt, pb[a], c6 * yn[a]);
+    scat(L1, q, kb1);
+    scat(L2, q + 1, kb2);
+    scat(L3, q + 2, kb3);
+    scat(L4, q + 3, kb4);
 #pragma unroll
     for (int a = 0; a < D; ++a) ybar[a] = yn[a];
     rk4_update<D>(phi, dt, k1, k2, k3, k4);
   }
-  if (MERGE) mg.flush(acc);
+  if constexpr (MERGE) mg.flush(acc);
   return ok;
 }
 
@@ -793,6 +798,256 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
   flush_tile<D, NS>(acc, fields, part, bid);
 }
 
+// ---------------------------------------------------------------------------
+// Assembled Jacobian (transport model, stationary velocity).
+//
+// Row i of J = d u1 / d v is grad T(y_i)^T d y_i / d v; by the adjoint
+// replay above it is a sum over RK4 samples of corner-weight x stage-adjoint
+// products, which the register merge already groups into one block of
+// 2^d x d values per velocity cell the characteristic crosses.  Storing
+// those blocks (cell + values) once per Gauss-Newton iteration turns every
+// following matvec into a stream over J: s_i = h^d W_i J_i p, then
+// s_i J_i^T scattered through the LDS tile.  Blocks are stored in the
+// brick-processing order (slot = brick, wave item, lane) so each wave reads
+// its 64 rows with coalesced loads.  A cell is stored as three 10-bit
+// offsets from the brick's tile origin.
+
+template <int D>
+struct JacLayout {
+  static constexpr int NV = (1 << D) * D;      // values per block
+  static constexpr int NV4 = (NV + 3) / 4;     // float4 per block
+};
+
+template <int D>
+struct JacWriter {
+  float4* __restrict__ vals;   // [k][NV4][nslots]
+  int* __restrict__ cells;     // [k][nslots]
+  long long nslots;
+  long long slot;
+  int kmax;
+  int count;
+  int org[3];
+
+  template <int NSLOT>
+  __device__ __forceinline__ void add_block(const int cell[D], int /*jA*/, const float a[NSLOT][1 << D][D]) {
+    if (count < kmax) {
+      int packed = 0;
+      bool fits = true;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        int t = cell[ax] - org[ax] + 512;
+        fits = fits && t >= 0 && t < 1024;
+        packed |= (t & 1023) << (10 * ax);
+      }
+      if (!fits) {
+        count = kmax;  // cannot be stored: report an overflow
+      } else {
+        cells[(long long)count * nslots + slot] = packed;
+        const float* f = &a[0][0][0];
+#pragma unroll
+        for (int j = 0; j < JacLayout<D>::NV4; ++j)
+          vals[((long long)count * JacLayout<D>::NV4 + j) * nslots + slot] =
+              make_float4(f[4 * j], f[4 * j + 1], f[4 * j + 2], f[4 * j + 3]);
+      }
+    }
+    ++count;
+  }
+};
+
+// Visit every slot of a brick (including slots outside the image, flagged).
+template <int D, class Body>
+__device__ __forceinline__ void for_brick_slots(const Geo& g, const Bricks& B, const int O[3], Body body) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int l[3];
+  if (D == 3) {
+    l[0] = lane & 3; l[1] = (lane >> 2) & 3; l[2] = lane >> 4;
+  } else {
+    l[0] = lane & 7; l[1] = lane >> 3; l[2] = 0;
+  }
+  const int P = B.stride[0] * B.stride[1] * B.stride[2];
+  const int nreg = B.nreg[0] * B.nreg[1] * B.nreg[2];
+  for (int w = wave; w < nreg * P; w += nw) {
+    int reg = w / P, ph = w - (w / P) * P;
+    int r0 = reg % B.nreg[0], r1 = (reg / B.nreg[0]) % B.nreg[1], r2 = reg / (B.nreg[0] * B.nreg[1]);
+    int p0 = ph % B.stride[0], p1 = (ph / B.stride[0]) % B.stride[1], p2 = ph / (B.stride[0] * B.stride[1]);
+    int idx[3];
+    idx[0] = O[0] + r0 * B.rdim[0] + l[0] * B.stride[0] + p0;
+    idx[1] = O[1] + r1 * B.rdim[1] + l[1] * B.stride[1] + p1;
+    idx[2] = O[2] + r2 * B.rdim[2] + l[2] * B.stride[2] + p2;
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) in = in && idx[a] < g.mi[a];
+    body(idx, w * 64 + lane, in);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Bricks B,
+                                                         const typename VecT<D>::T* __restrict__ vp,
+                                                         const float* __restrict__ T, float4* __restrict__ vals,
+                                                         int* __restrict__ cells, unsigned char* __restrict__ cnt,
+                                                         long long nslots, int kmax, int* __restrict__ maxcount,
+                                                         int* __restrict__ flags) {
+  long long bid = xcd_block(B.nbricks);
+  if (bid < 0) return;
+  int O[3], org[3];
+  brick_origin<D>(g, B, bid, O, org);
+  const long long base = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2];
+  int mymax = 0, mysum = 0;
+  bool bad = false;
+  for_brick_slots<D>(g, B, O, [&](const int idx[3], int local, bool in) {
+    const long long slot = base + local;
+    if (!in) {
+      cnt[slot] = 0;
+      return;
+    }
+    Start<D> S;
+    make_start_idx<D>(g, idx, S);
+    float phi[D], dphi[D], F[D][D];
+    forward_pass<D, false, false, true>(g, st, vp, nullptr, S, phi, dphi, F);
+    Loc<D> L;
+    locate_i<D>(g, S, phi, L);
+    float gT[D], val;
+    sample_img<D, false, true>(T, g, L, val, gT);
+    bool nz = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) nz = nz || (gT[a] != 0.f);
+    if (!nz) {
+      cnt[slot] = 0;
+      return;
+    }
+    float y0[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float t = 0.f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) t = fmaf(F[a][b], gT[a], t);
+      y0[b] = t;
+    }
+    JacWriter<D> jw;
+    jw.vals = vals;
+    jw.cells = cells;
+    jw.nslots = nslots;
+    jw.slot = slot;
+    jw.kmax = kmax;
+    jw.count = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jw.org[a] = org[a];
+    if (!adjoint_pass<D, false>(g, st, vp, S, y0, jw)) bad = true;
+    cnt[slot] = (unsigned char)min(jw.count, 255);
+    mymax = max(mymax, jw.count);
+    mysum += min(jw.count, kmax);
+  });
+  if (mymax > 0) atomicMax(maxcount, mymax);
+  if (mysum > 0) atomicAdd(maxcount + 1, mysum);
+  if (bad) atomicOr(flags, 1);
+}
+
+// Corner values of one stored block: dot with p (gather) or scale.
+template <int D>
+__device__ __forceinline__ void jac_block_cell(int packed, const int org[3], int cell[D]) {
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) cell[ax] = org[ax] + ((packed >> (10 * ax)) & 1023) - 512;
+}
+
+template <int D>
+__device__ __forceinline__ float jac_block_dot(const Geo& g, const int cell[D], const float* f,
+                                               const typename VecT<D>::T* __restrict__ pp) {
+  float s = 0.f;
+  if constexpr (D == 3) {
+    const int mx = g.mv[0], my = g.mv[1], mz = g.mv[2];
+    int x0 = wrapi(cell[0], mx), y0 = wrapi(cell[1], my), z0 = wrapi(cell[2], mz);
+    int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
+    int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
+    int z1 = (z0 + 1 == mz) ? 0 : z0 + 1;
+    const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      float4 q = pp[((long long)zs[(o >> 2) & 1] * my + ys[(o >> 1) & 1]) * mx + xs[o & 1]];
+      s = fmaf(f[3 * o], q.x, s);
+      s = fmaf(f[3 * o + 1], q.y, s);
+      s = fmaf(f[3 * o + 2], q.z, s);
+    }
+  } else {
+    const int mx = g.mv[0], my = g.mv[1];
+    int x0 = wrapi(cell[0], mx), y0 = wrapi(cell[1], my);
+    int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
+    int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
+    const int xs[2] = {x0, x1}, ys[2] = {y0, y1};
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      float2 q = pp[(long long)ys[(o >> 1) & 1] * mx + xs[o & 1]];
+      s = fmaf(f[2 * o], q.x, s);
+      s = fmaf(f[2 * o + 1], q.y, s);
+    }
+  }
+  return s;
+}
+
+// Apply the stored Jacobian: with wseed == null, s_i = scale W_i J_i p
+// (Gauss-Newton data term); otherwise s_i = scale wseed_i (transpose
+// product J^T w).  Then scatter s_i J_i^T into the brick's tile.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const float4* __restrict__ vals,
+                                                      const int* __restrict__ cells,
+                                                      const unsigned char* __restrict__ cnt, long long nslots,
+                                                      const typename VecT<D>::T* __restrict__ pp,
+                                                      const float* __restrict__ wvox, const float* __restrict__ wseed,
+                                                      float scale, float* __restrict__ out, float* __restrict__ part) {
+  extern __shared__ float lds[];
+  long long bid = xcd_block(B.nbricks);
+  if (bid < 0) return;
+  int O[3], org[3];
+  brick_origin<D>(g, B, bid, O, org);
+  Stages none;
+  none.j0 = nullptr;
+  none.th = nullptr;
+  none.dt = 0.f;
+  TileAcc<D, false> acc = make_acc<D, false>(lds, out, g, none, B, org, D);
+  const long long base = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2];
+  constexpr int NV4 = JacLayout<D>::NV4;
+  for_brick_slots<D>(g, B, O, [&](const int idx[3], int local, bool in) {
+    if (!in) return;
+    const long long slot = base + local;
+    const int n = cnt[slot];
+    if (n == 0) return;
+    long long p = idx[0] + (long long)g.mi[0] * idx[1];
+    if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
+    float s;
+    if (wseed) {
+      s = scale * wseed[p];
+    } else {
+      s = 0.f;
+      for (int k = 0; k < n; ++k) {
+        int cell[D];
+        jac_block_cell<D>(cells[(long long)k * nslots + slot], org, cell);
+        float f[4 * NV4];
+#pragma unroll
+        for (int j = 0; j < NV4; ++j) {
+          float4 q = vals[((long long)k * NV4 + j) * nslots + slot];
+          f[4 * j] = q.x; f[4 * j + 1] = q.y; f[4 * j + 2] = q.z; f[4 * j + 3] = q.w;
+        }
+        s += jac_block_dot<D>(g, cell, f, pp);
+      }
+      s *= scale * (wvox ? wvox[p] : 1.f);
+    }
+    if (s == 0.f) return;
+    for (int k = 0; k < n; ++k) {
+      int cell[D];
+      jac_block_cell<D>(cells[(long long)k * nslots + slot], org, cell);
+      float a[1][1 << D][D];
+      float* f = &a[0][0][0];
+#pragma unroll
+      for (int j = 0; j < NV4; ++j) {
+        float4 q = vals[((long long)k * NV4 + j) * nslots + slot];
+        f[4 * j] = s * q.x; f[4 * j + 1] = s * q.y; f[4 * j + 2] = s * q.z; f[4 * j + 3] = s * q.w;
+      }
+      acc.template add_block<1>(cell, 0, a);
+    }
+  });
+  flush_tile<D, false>(acc, D, part, bid);
+}
+
 // Sum the partial tiles into the velocity-grid output in a fixed order:
 // out[f][node] += sum over covering bricks (z, then y, then x order).
 template <int D>
@@ -1059,6 +1314,39 @@ int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, cons
                          (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->tile_part, P->flags);
   }
   prof_end(P, s);
+  LAG_LAUNCH_CHECK();
+  return launch_tile_reduce(P, out, s);
+}
+
+int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, hipStream_t s) {
+  Stages st = stages_for(P, -1);
+  const lag::Bricks& B = P->bricks;
+  unsigned grid = grid_for(B.nbricks);
+  int rc = launch_zero_i(P->jac_max, 2, s);
+  if (rc) return rc;
+  if (P->geo.dim == 3)
+    hipLaunchKernelGGL(k_jac_assemble<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, st, B, (const float4*)vpack, T,
+                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags);
+  else
+    hipLaunchKernelGGL(k_jac_assemble<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, st, B, (const float2*)vpack, T,
+                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
+                     hipStream_t s) {
+  const lag::Bricks& B = P->bricks;
+  unsigned grid = grid_for(B.nbricks);
+  size_t lds = sizeof(float) * (size_t)P->geo.dim * B.tvol;
+  if (!wseed) prof_begin(P, s);
+  if (P->geo.dim == 3)
+    hipLaunchKernelGGL(k_jac_apply<3>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
+                       P->jac_cnt, P->jac_slots, (const float4*)ppack, wvox, wseed, scale, out, P->tile_part);
+  else
+    hipLaunchKernelGGL(k_jac_apply<2>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
+                       P->jac_cnt, P->jac_slots, (const float2*)ppack, wvox, wseed, scale, out, P->tile_part);
+  if (!wseed) prof_end(P, s);
   LAG_LAUNCH_CHECK();
   return launch_tile_reduce(P, out, s);
 }

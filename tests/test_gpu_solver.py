@@ -1,0 +1,185 @@
+"""Assembled-Jacobian products, PCG and Gauss-Newton on the GPU.
+
+The assembled path must agree with the matrix-free kernels and with the
+oracle to the same 1e-5 relative bar; the solver is checked iterate-wise
+(the problem is non-convex and PCG inexact, so iterates are not unique): at
+the GPU's iterates the oracle's objective matches the GPU's, the objective
+decreases monotonically and the gradient tolerance is reached.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from cases import SMALL_CASES, Case, gpu_problem, oracle_problem, relerr
+from test_gpu_parity import MASK_CELLS, Dev, f32
+
+pytestmark = pytest.mark.gpu
+
+ASSEMBLY_CASES = [
+    SMALL_CASES[0],
+    Case("2d_transport_ragged_stat", 2, (45, 36), (15, 18), nsteps=6, amplitude=0.08, gamma=1e-3,
+         reg="curvature", alpha=1e-3, seed=7150),
+    SMALL_CASES[4],
+    SMALL_CASES[7],
+]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1703_04446_amd as _L
+    _L.load()
+    return _L
+
+
+def assembled_plan(L, case, k=16):
+    import paper_1703_04446_amd as _L
+    prob = gpu_problem(case)
+    prob.jac_blocks = k
+    return _L.Plan(prob)
+
+
+@pytest.mark.parametrize("case", ASSEMBLY_CASES, ids=[c.name for c in ASSEMBLY_CASES])
+def test_assembled_products(case, torch, L):
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    plan = assembled_plan(L, case)
+    n, nu = plan.n_points, plan.n_unknowns
+    T, v = f32(case.template()), f32(case.velocity())
+    p, w = f32(case.direction(5)), f32(case.image_field(5))
+    assert L.lag_jacobian_assemble(plan, dev.put(v), dev.put(T))
+    _, margin = O.jvp(OP, v, T, np.zeros(OP.vel_shape), return_margin=True)
+    keep = margin >= MASK_CELLS
+    W = f32(keep * np.random.default_rng(case.seed + 1).uniform(0.5, 1.5, n))
+    # Hessian: assembled vs matrix-free vs oracle
+    Ha, Hm = dev.empty(nu), dev.empty(nu)
+    L.gn_hessmat_assembled(plan, dev.put(W), dev.put(p), Ha)
+    L.gn_hessmat(plan, dev.put(v), dev.put(T), dev.put(W), dev.put(p), Hm)
+    Ho = O.hessmat(OP, v, T, p, wvox=W)
+    ea, em = relerr(dev.get(Ha), Ho), relerr(dev.get(Ha), dev.get(Hm))
+    # data term alone
+    cD = case.with_(alpha=0.0, gamma=0.0)
+    planD = assembled_plan(L, cD)
+    assert L.lag_jacobian_assemble(planD, dev.put(v), dev.put(T))
+    HD = dev.empty(nu)
+    L.gn_hessmat_assembled(planD, dev.put(W), dev.put(p), HD)
+    eD = relerr(dev.get(HD), O.hessmat(oracle_problem(cD), v, T, p, wvox=W))
+    # transpose product
+    JTw = dev.empty(nu)
+    L.lag_vjp_assembled(plan, dev.put(w * keep), JTw)
+    eT = relerr(dev.get(JTw), O.vjp(OP, v, T, w * keep))
+    # gradient: assembled vs matrix-free on the same GPU inputs
+    vt = f32(case.velocity(seed_off=2))
+    R = f32(O.objective(OP, vt, T, np.zeros(n))["u"])
+    out3 = torch.zeros(3, dtype=torch.float64, device="cuda")
+    ga, gm = dev.empty(nu), dev.empty(nu)
+    L.lag_gradient_assembled(plan, dev.put(v), dev.put(T), dev.put(R), ga, out3)
+    L.lag_gradient(plan, dev.put(v), dev.put(T), dev.put(R), gm, out3)
+    eg = relerr(dev.get(ga), dev.get(gm))
+    print(case.name, f"hess/oracle {ea:.2e} hess/matfree {em:.2e} data {eD:.2e} vjp {eT:.2e} grad {eg:.2e}",
+          flush=True)
+    assert ea < 1e-5 and em < 1e-5 and eD < 1e-5 and eT < 1e-5 and eg < 1e-5
+    planD.close()
+    plan.close()
+
+
+def test_assembly_overflow_reported(torch, L):
+    """A capacity of one block per characteristic cannot hold rows that cross
+    cells: the assembly reports it and the assembled calls refuse to run."""
+    case = SMALL_CASES[0]
+    dev = Dev(torch)
+    plan = assembled_plan(L, case, k=1)
+    T, v = f32(case.template()), f32(case.velocity(scale=4.0))
+    assert not L.lag_jacobian_assemble(plan, dev.put(v), dev.put(T))
+    with pytest.raises(L.LagError):
+        L.gn_hessmat_assembled(plan, None, dev.put(f32(case.direction(0))), dev.empty(plan.n_unknowns))
+
+
+def test_no_jacobian_storage_for_continuity(torch, L):
+    case = SMALL_CASES[2]
+    dev = Dev(torch)
+    plan = assembled_plan(L, case, k=8)
+    with pytest.raises(L.LagError) as e:
+        L.lag_jacobian_assemble(plan, dev.put(f32(case.velocity())), dev.put(f32(case.template())))
+    assert e.value.status == L.LAG_EUNSUPPORTED
+
+
+def test_pcg_assembled_and_matrix_free_agree(torch, L):
+    case = SMALL_CASES[4].with_(gamma=1e-4)
+    dev = Dev(torch)
+    plan = assembled_plan(L, case)
+    T, v = f32(case.template()), f32(case.velocity())
+    b = f32(case.direction(6))
+    assert L.lag_jacobian_assemble(plan, dev.put(v), dev.put(T))
+    xa, xm = dev.empty(plan.n_unknowns), dev.empty(plan.n_unknowns)
+    ia = L.lag_pcg_assembled(plan, None, dev.put(b), xa, tol=1e-4, maxit=200)
+    im = L.lag_pcg(plan, dev.put(v), dev.put(T), None, dev.put(b), xm, tol=1e-4, maxit=200)
+    assert ia["relres"] <= 1e-4 and im["relres"] <= 1e-4
+    assert relerr(dev.get(xa), dev.get(xm)) < 1e-3
+    # the solution satisfies the oracle's system
+    OP = oracle_problem(case)
+    Hx = O.hessmat(OP, v, T, dev.get(xa).reshape(OP.vel_shape))
+    assert relerr(Hx, b) < 1e-3
+
+
+@pytest.mark.parametrize("k", [0, 8])
+def test_gn_solve_2d(torch, L, k):
+    """Gauss-Newton on the 2-D 64^2 workload, matrix-free (k=0) and assembled."""
+    case = SMALL_CASES[0]
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    plan = assembled_plan(L, case, k=k)
+    T = f32(case.template())
+    vt = case.velocity()
+    R = f32(O.objective(OP, vt, T, np.zeros(plan.n_points))["u"])
+    v = torch.zeros(plan.n_unknowns, device="cuda")
+    opt = L.lag_gn_default_options()
+    opt.pcg_maxit = 20
+    info = L.lag_gn_solve(plan, dev.put(T), dev.put(R), v, opt)
+    print("gn", k, info, flush=True)
+    assert info["converged"] and info["status"] == L.LAG_OK
+    assert info["gnorm"] <= 1e-2 * info["g0"]
+    assert info["J"] < 0.2 * info["J0"]
+    # iterate-wise parity: the oracle agrees with the GPU's objective at the
+    # GPU's solution and at v = 0
+    vg = dev.get(v).reshape(OP.vel_shape)
+    Jo = O.objective(OP, vg, T, R)["J"]
+    assert abs(Jo - info["J"]) <= 1e-5 * abs(Jo)
+    J0o = O.objective(OP, np.zeros(OP.vel_shape), T, R)["J"]
+    assert abs(J0o - info["J0"]) <= 1e-5 * abs(J0o)
+    g0o = np.linalg.norm(O.gradient(OP, np.zeros(OP.vel_shape), T, R)[0])
+    assert abs(g0o - info["g0"]) <= 1e-4 * g0o
+    # the oracle's own solve reaches a comparable objective
+    vo, hist = O.gn_solve(OP, T, R, pcg_maxit=20)
+    assert hist["status"] == "converged"
+    assert info["J"] <= 1.5 * hist["J"][-1]
+
+
+def test_gn_step_monotone(torch, L):
+    """Successive Gauss-Newton steps decrease J (3-D, assembled)."""
+    case = SMALL_CASES[4]
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    plan = assembled_plan(L, case)
+    T = f32(case.template())
+    R = f32(O.objective(OP, case.velocity(), T, np.zeros(plan.n_points))["u"])
+    v = torch.zeros(plan.n_unknowns, device="cuda")
+    vn = torch.empty_like(v)
+    Js = []
+    for _ in range(3):
+        info = L.lag_gn_step(plan, dev.put(T), dev.put(R), v, vn)
+        assert info["status"] == L.LAG_OK and info["accepted"] and info["assembled"]
+        Js.append((info["J"], info["J_next"]))
+        # oracle objective at the accepted iterate
+        Jo = O.objective(OP, dev.get(vn).reshape(OP.vel_shape), T, R)["J"]
+        assert abs(Jo - info["J_next"]) <= 1e-5 * abs(Jo)
+        v.copy_(vn)
+    assert all(b < a for a, b in Js)
