@@ -50,6 +50,9 @@ def parse():
                     help="assembled-Jacobian capacity in cell blocks per characteristic")
     ap.add_argument("--matrix-free", action="store_true",
                     help="use the matrix-free Gauss-Newton matvec instead of the assembled Jacobian")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run one device-to-device copy of this many bytes before timing "
+                         "(a known-size reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -96,6 +99,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     L.load()
+    if args.copy_bytes > 0:
+        n4 = args.copy_bytes // 4
+        src = torch.ones(n4, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(args, f"reference copy of {4 * n4} bytes done")
+        del src, dst
     w = workload(args.workload)
     log(args, f"workload {w.name}: image {w.img_m}, velocity {w.vel_m}, N={w.nsteps}")
     T = w.template().ravel().astype(np.float32)

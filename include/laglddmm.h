@@ -183,7 +183,7 @@ int spectral_precond_apply(lag_plan plan, const float* r, float* z, void* stream
 
 /* ---- assembled Jacobian (transport model, stationary velocity) ----------
  * The paper notes that the sparse derivative can be built explicitly to
- * speed up matrix-vector products (Sec. 1 contributions; Sec. 3.3).  Row i of
+ * speed up matrix-vector products (Sec. 1.1; Sec. 3.3).  Row i of
  * J = d u1/d v, grad T(y_i)^T d y_i/d v, is stored as one block of
  * 2^d x dim values per velocity cell the characteristic's RK4 samples visit
  * (plan capacity: jac_blocks blocks per characteristic).  Assembly costs
@@ -311,6 +311,33 @@ int lag_gn_step(lag_plan plan, const float* T, const float* R, const float* v, f
  * accepted iterate). */
 int lag_gn_solve(lag_plan plan, const float* T, const float* R, float* v,
                  const lag_gn_options* opt, lag_gn_info* info, void* stream);
+
+/* ---- multilevel continuation (Sec. 3.2, last paragraph) -----------------
+ * Level l+1 has half the image and velocity cells of level l along every
+ * axis (all sizes even and >= 4 on every level but the coarsest). */
+
+/* Restrict an image of the plan's image grid to the grid with half the cells
+ * per axis: each coarse value is the mean of its 2^d fine cells.  f: image-
+ * shaped for the plan; coarse: (prod img_m / 2^d) floats. */
+int lag_restrict_image(lag_plan plan, const float* f, float* coarse, void* stream);
+
+/* Refine a velocity from the grid with half the cells per axis to the plan's
+ * velocity grid by cell-centred periodic (bi/tri)linear interpolation (axis
+ * weights 3/4 and 1/4), per component and time node.  v_coarse:
+ * n_unknowns / 2^d floats; v_fine: velocity-shaped for the plan. */
+int lag_prolong_velocity(lag_plan plan, const float* v_coarse, float* v_fine, void* stream);
+
+/* Coarse-to-fine Gauss-Newton: `levels` levels (1..8; level 0 = `finest`),
+ * T and R restricted level by level, lag_gn_solve on each level starting
+ * from the refined solution of the level below (zero on the coarsest).  v
+ * (velocity-shaped for `finest`) receives the finest solution; its input is
+ * the start value only when levels = 1.  infos: host array of `levels`
+ * entries (coarsest first) or NULL.  Allocating: creates one plan and the
+ * restricted images per level and frees them before returning; synchronises
+ * `stream`.  Returns LAG_ELINESEARCH if a level's line search failed (the
+ * later levels still run). */
+int lag_multilevel_solve(const lag_problem* finest, int32_t levels, const float* T, const float* R,
+                         float* v, const lag_gn_options* opt, lag_gn_info* infos, void* stream);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,7 @@ and intensity-preserving diffeomorphic image registration"):
 * ``precond``     - the spectral preconditioner (Sec. 3.2, PCG paragraph).
 * ``gn``          - PCG and inexact Gauss-Newton with Armijo line search
                     (eq. solveGN).
+* ``multilevel``  - coarse-to-fine continuation (Sec. 3.2, last paragraph).
 
 Readings of passages that are silent, ambiguous or garbled are listed in the
 module docstrings where they are used.  Functions pinned only by
@@ -38,6 +39,7 @@ from .objective import (ssd, regularizer_apply, regularizer_energy, objective,
                         gradient, hessmat, laplacian_apply)
 from .precond import spectral_precond_apply, spectral_symbol
 from .gn import pcg, gn_solve
+from .multilevel import restrict_image, prolong_velocity, coarsen_problem, multilevel_solve
 
 __all__ = [
     "Problem", "time_weights", "node_weights",
@@ -46,4 +48,5 @@ __all__ = [
     "hessmat", "laplacian_apply",
     "spectral_precond_apply", "spectral_symbol",
     "pcg", "gn_solve",
+    "restrict_image", "prolong_velocity", "coarsen_problem", "multilevel_solve",
 ]

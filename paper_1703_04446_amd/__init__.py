@@ -16,7 +16,8 @@ from ._lib import (  # noqa: F401
     spectral_precond_apply, lag_reg_apply, lag_objective, lag_gradient, lag_dot,
     lag_pcg, lag_gn_default_options, lag_gn_solve, lag_profile_enable, lag_profile_read,
     lag_jacobian_assemble, gn_hessmat_assembled, lag_vjp_assembled, lag_gradient_assembled,
-    lag_pcg_assembled, lag_gn_step, lag_jacobian_info,
+    lag_pcg_assembled, lag_gn_step, lag_jacobian_info, lag_restrict_image, lag_prolong_velocity,
+    lag_multilevel_solve,
 )
 
 LIB_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__), "liblaglddmm.so")

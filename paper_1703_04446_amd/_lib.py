@@ -103,6 +103,10 @@ _SIGS = {
     "lag_pcg": (_I, [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int32,
                      ctypes.POINTER(LagPcgInfo), _P]),
     "lag_gn_default_options": (None, [ctypes.POINTER(LagGnOptions)]),
+    "lag_restrict_image": (_I, [_P, _P, _P, _P]),
+    "lag_prolong_velocity": (_I, [_P, _P, _P, _P]),
+    "lag_multilevel_solve": (_I, [ctypes.POINTER(LagProblem), ctypes.c_int32, _P, _P, _P,
+                                  ctypes.POINTER(LagGnOptions), ctypes.POINTER(LagGnInfo), _P]),
     "lag_jacobian_assemble": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
     "gn_hessmat_assembled": (_I, [_P, _P, _P, _P, _P]),
     "lag_jacobian_info": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
@@ -382,6 +386,36 @@ def lag_gn_step(plan, T, R, v, v_next, options=None, gstop=0.0):
     d = {f: getattr(info, f) for f, _ in LagGnStepInfo._fields_}
     d["status"] = st
     return d
+
+
+def lag_restrict_image(plan, f, coarse):
+    n = plan.n_points
+    _check("lag_restrict_image", load().lag_restrict_image(
+        plan.handle, _ptr(f, n, "f"), _ptr(coarse, n >> plan.prob.dim, "coarse"), _stream()))
+
+
+def lag_prolong_velocity(plan, v_coarse, v_fine):
+    nu = plan.n_unknowns
+    _check("lag_prolong_velocity", load().lag_prolong_velocity(
+        plan.handle, _ptr(v_coarse, nu >> plan.prob.dim, "v_coarse"), _ptr(v_fine, nu, "v_fine"), _stream()))
+
+
+def lag_multilevel_solve(prob, levels, T, R, v, options=None):
+    """Coarse-to-fine solve; returns one info dict per level (coarsest first)."""
+    o = options if options is not None else lag_gn_default_options()
+    n_points, n_unknowns = lag_problem_sizes(prob)
+    infos = (LagGnInfo * levels)()
+    st = load().lag_multilevel_solve(ctypes.byref(prob), int(levels), _ptr(T, n_points, "T"),
+                                     _ptr(R, n_points, "R"), _ptr(v, n_unknowns, "v"), ctypes.byref(o),
+                                     infos, _stream())
+    if st not in (LAG_OK, LAG_ELINESEARCH):
+        _check("lag_multilevel_solve", st)
+    out = []
+    for i in range(levels):
+        d = {f: getattr(infos[i], f) for f, _ in LagGnInfo._fields_}
+        d["converged"] = bool(d["converged"])
+        out.append(d)
+    return out, st
 
 
 def lag_gn_default_options():

@@ -73,6 +73,41 @@ static void choose_bricks(lag_plan P) {
       break;
     }
   }
+  // Pad the tile's row and plane strides so that the 64 lanes of a wave,
+  // which start one velocity cell apart on a 4x4x4 (3-D) or 8x8 (2-D)
+  // lattice, fall into distinct LDS banks for the same corner/component
+  // (fewest lanes per bank for 32 and for 64 banks, then smallest tile).
+  {
+    const int lat[3] = {lane[0], lane[1], lane[2]};
+    auto worst = [&](int t0, int t1, int nb) {
+      int cnt[64] = {0};
+      int w = 0;
+      for (int z = 0; z < lat[2]; ++z)
+        for (int y = 0; y < lat[1]; ++y)
+          for (int x = 0; x < lat[0]; ++x) {
+            int b = (x + t0 * y + t0 * t1 * z) % nb;
+            w = std::max(w, ++cnt[b]);
+          }
+      return w;
+    };
+    int best0 = B.tdim[0], best1 = B.tdim[1];
+    long long bestkey = -1;
+    const int span1 = D == 3 ? 32 : 1;
+    for (int t0 = B.tdim[0]; t0 < B.tdim[0] + 32; ++t0)
+      for (int t1 = B.tdim[1]; t1 < B.tdim[1] + span1; ++t1) {
+        long long vol = (long long)t0 * t1 * B.tdim[2];
+        if (sizeof(float) * (size_t)P->fields * vol > budget && !(t0 == B.tdim[0] && t1 == B.tdim[1])) continue;
+        long long key = ((long long)worst(t0, t1, 32) * 65 + worst(t0, t1, 64)) * (1LL << 32) + vol;
+        if (bestkey < 0 || key < bestkey) {
+          bestkey = key;
+          best0 = t0;
+          best1 = t1;
+        }
+      }
+    B.tdim[0] = best0;
+    B.tdim[1] = best1;
+    B.tvol = B.tdim[0] * B.tdim[1] * B.tdim[2];
+  }
   B.halo = halo;
   B.nbricks = 1;
   for (int a = 0; a < 3; ++a) {

@@ -96,3 +96,13 @@ SMALL_CASES = [
     Case("3d_transport_equal_grids", 3, (16, 16, 16), (16, 16, 16), nsteps=3, extent=(1.0, 1.2, 0.9),
          seed=7600),
 ]
+
+# Smallest grids the ABI accepts: bricks and LDS tiles are larger than the
+# whole grid (every tile wraps the periodic domain several times), FFT sizes
+# 2 and 3, a single RK4 step.
+MIN_CASES = [
+    Case("2d_min_transport", 2, (2, 2), (2, 2), nsteps=1, nblobs=1, kmax=1, amplitude=0.3, seed=7700),
+    Case("3d_min_transport", 3, (4, 2, 2), (2, 2, 2), nsteps=2, nblobs=1, kmax=1, amplitude=0.3, seed=7800),
+    Case("2d_min_continuity", 2, (3, 2), (3, 2), model="continuity", nsteps=1, nblobs=1, kmax=1,
+         amplitude=0.3, seed=7900, gamma=1e-3),
+]

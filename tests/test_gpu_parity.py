@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from cases import SMALL_CASES, Case, gpu_problem, oracle_problem, relerr
+from cases import MIN_CASES, SMALL_CASES, Case, gpu_problem, oracle_problem, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -196,6 +196,18 @@ def test_small_case_parity(case, torch, L):
         assert r["jvp_mass"] < 1e-5
     # the unmasked gradient includes kink characteristics on both sides
     assert r["grad_unmasked"] < 1e-3
+
+
+@pytest.mark.parametrize("case", MIN_CASES, ids=[c.name for c in MIN_CASES])
+def test_minimum_size_parity(case, torch, L):
+    """Smallest accepted grids: tiles wrap the domain, FFT sizes 2 and 3."""
+    r = run_case(case, torch, L)
+    print(case.name, {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in r.items()}, flush=True)
+    for key in ("trace", "state", "jvp", "vjp", "hessmat", "hessmat_data", "reg", "precond",
+                "obj_J", "obj_D", "obj_S"):
+        assert r[key] < TOL, (key, r[key])
+    if case.model == "continuity":
+        assert r["mass"] < 1e-6 and r["push_bitwise"]
 
 
 def test_zero_velocity_closed_form(torch, L):

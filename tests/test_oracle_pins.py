@@ -555,3 +555,63 @@ def test_gn_solve_converges_2d():
     assert np.all(np.diff(J) <= 0)
     assert hist["gnorm"][-1] <= 1e-2 * hist["g0"]
     assert J[-1] < 0.2 * J[0]
+
+
+# --------------------------------------------------------------------- multilevel
+def test_restriction_is_cell_average():
+    """Restriction keeps constants and the integral; on a separable image it is
+    the product of the 1-D pair averages."""
+    P = O.Problem(dim=2, img_m=(8, 6), vel_m=(4, 4))
+    np.testing.assert_allclose(O.restrict_image(P, np.full(48, 3.0)), 3.0, atol=1e-15)
+    rng = np.random.default_rng(0)
+    f, g = rng.standard_normal(8), rng.standard_normal(6)
+    img = np.outer(g, f)                      # (y, x)
+    ref = np.outer(0.5 * (g[0::2] + g[1::2]), 0.5 * (f[0::2] + f[1::2]))
+    np.testing.assert_allclose(O.restrict_image(P, img.ravel()), ref, atol=1e-14)
+    P3 = O.Problem(dim=3, img_m=(4, 6, 2), vel_m=(2, 2, 2))
+    x = rng.standard_normal(48)
+    assert abs(O.restrict_image(P3, x).sum() * 8 - x.sum()) < 1e-12
+
+
+def test_prolongation_brute_force_and_linear_exactness():
+    """Refinement equals periodic tent-weight interpolation written out point by
+    point, keeps constants, and reproduces linear functions away from the wrap."""
+    C = O.Problem(dim=2, img_m=(6, 4), vel_m=(6, 4))
+    rng = np.random.default_rng(1)
+    vc = rng.standard_normal(C.vel_shape)
+    vf = O.prolong_velocity(C, vc)
+    H = 1.0 / np.array([6, 4])
+    for jf in range(8):
+        for i_f in range(12):
+            xf = np.array([(i_f + 0.5) * H[0] / 2, (jf + 0.5) * H[1] / 2])
+            acc = np.zeros(2)
+            for jc in range(4):
+                for ic in range(6):
+                    xc = np.array([(ic + 0.5) * H[0], (jc + 0.5) * H[1]])
+                    d = np.abs(xf - xc)
+                    d = np.minimum(d, 1.0 - d)            # periodic distance
+                    wgt = np.prod(np.maximum(0.0, 1.0 - d / H))
+                    acc += wgt * vc[0, :, jc, ic]
+            np.testing.assert_allclose(vf[0, :, jf, i_f], acc, atol=1e-14)
+    np.testing.assert_allclose(O.prolong_velocity(C, np.full(C.vel_shape, 2.0)), 2.0, atol=1e-15)
+    # linear in x on the coarse centres: interior fine centres are exact
+    C3 = O.Problem(dim=3, img_m=(8, 4, 4), vel_m=(8, 4, 4))
+    xc = (np.arange(8) + 0.5) / 8
+    lin = np.broadcast_to(2.0 + 3.0 * xc, (4, 4, 8))
+    vc3 = np.zeros(C3.vel_shape)
+    vc3[0, 0] = lin
+    vf3 = O.prolong_velocity(C3, vc3)
+    xf = (np.arange(16) + 0.5) / 16
+    np.testing.assert_allclose(vf3[0, 0, 3, 5, 1:15], 2.0 + 3.0 * xf[1:15], atol=1e-14)
+
+
+def test_multilevel_solve_converges_2d():
+    P = O.Problem(dim=2, img_m=(32, 32), vel_m=(32, 32), nsteps=4, alpha=1e-2)
+    T = blob_image(P.img_m, 6, 2000).ravel()
+    vt = fourier_velocity(P.vel_m, 3, 0.05, 2001)
+    R = O.transport(P, T, O.trace(P, vt))
+    v, hists = O.multilevel_solve(P, T, R, levels=2, pcg_maxit=20)
+    assert [h["status"] for h in hists] == ["converged", "converged"]
+    assert v.shape == P.vel_shape
+    J_final = O.objective(P, v, T, R)["J"]
+    assert J_final < 0.2 * O.objective(P, np.zeros(P.vel_shape), T, R)["J"]
