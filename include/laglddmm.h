@@ -334,10 +334,52 @@ int lag_prolong_velocity(lag_plan plan, const float* v_coarse, float* v_fine, vo
  * the start value only when levels = 1.  infos: host array of `levels`
  * entries (coarsest first) or NULL.  Allocating: creates one plan and the
  * restricted images per level and frees them before returning; synchronises
- * `stream`.  Returns LAG_ELINESEARCH if a level's line search failed (the
- * later levels still run). */
+ * `stream`.  A coarse level whose line search stalls hands its last
+ * accepted iterate to the next level; LAG_ELINESEARCH is returned only if
+ * the finest level's line search fails. */
 int lag_multilevel_solve(const lag_problem* finest, int32_t levels, const float* T, const float* R,
                          float* v, const lag_gn_options* opt, lag_gn_info* infos, void* stream);
+
+/* ---- learned warm start: a 3-D U-Net on the MFMA units --------------------
+ * Maps the template and reference, resampled to a cubic grid of side `size`
+ * (the velocity grid), to a stationary velocity [3][size^3] that starts the
+ * Gauss-Newton solve.  Four levels (size, size/2, size/4, size/8), channels
+ * channels[0..3] in {16, 32, 64}, 3x3x3 periodic convolutions with ReLU,
+ * 2x average pooling, nearest-neighbour upsampling with skip
+ * concatenation, and a 1x1 output head scaled by out_scale.  Convolutions
+ * run as implicit GEMMs on bf16 MFMA with float32 accumulation; weights are
+ * kept in float32 for Adam and copied to bf16 for every pass.  Parameters
+ * are stored flat, layer by layer (e0a e0b e1a e1b e2a e2b ma mb d2 d1 d0
+ * head), each as W[taps][cin][cout] followed by b[cout] (taps = 27, 1 for
+ * the head; the first layer has cin = 2). */
+typedef struct lag_cnn_config {
+    int32_t size;          /* grid side, a multiple of 32 in [32, 256]        */
+    int32_t channels[4];   /* per level, each 16, 32 or 64                    */
+    float   in_scale;      /* multiplies T and R on input                     */
+    float   out_scale;     /* multiplies the head's output                    */
+    uint64_t seed;         /* He-normal initialisation                        */
+} lag_cnn_config;
+
+typedef struct lag_cnn_s* lag_cnn;
+
+void lag_cnn_default_config(lag_cnn_config* cfg);
+/* Allocating: parameters, Adam moments and activation buffers. */
+int lag_cnn_create(const lag_cnn_config* cfg, lag_cnn* out);
+int lag_cnn_destroy(lag_cnn net);
+int lag_cnn_param_count(lag_cnn net, int64_t* count);
+/* Host copies of the flat parameters / of the gradients of the last
+ * lag_cnn_backward (synchronising). */
+int lag_cnn_get_params(lag_cnn net, float* host);
+int lag_cnn_set_params(lag_cnn net, const float* host);
+int lag_cnn_get_grads(lag_cnn net, float* host);
+/* Inference: T, R are size^3 images (x fastest); v receives [3][size^3]. */
+int lag_cnn_forward(lag_cnn net, const float* T, const float* R, float* v, void* stream);
+/* Forward, loss = 1/2 mean (v - target)^2 written to *loss (device double),
+ * and the gradient of every parameter (kept in the net). */
+int lag_cnn_backward(lag_cnn net, const float* T, const float* R, const float* target, float* v,
+                     double* loss, void* stream);
+/* One Adam update of the parameters with the last gradients. */
+int lag_cnn_adam_step(lag_cnn net, float lr, float beta1, float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -208,8 +208,10 @@ int lag_multilevel_solve(const lag_problem* finest, int32_t levels, const float*
     lag_gn_info info;
     rc = lag_gn_solve(plans[l], Ts[l], Rs[l], vs[l], opt, &info, stream);
     if (infos) infos[levels - 1 - l] = info;
+    // a coarse level only provides the starting guess of the next one: a
+    // stalled line search there hands over its last accepted iterate
     if (rc == LAG_ELINESEARCH) {
-      status = rc;
+      if (l == 0) status = rc;
       rc = LAG_OK;
     }
     if (rc) break;
