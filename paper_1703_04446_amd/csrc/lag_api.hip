@@ -56,7 +56,8 @@ static void choose_bricks(lag_plan P) {
       }
       tvol *= B.tdim[a];
     }
-    size_t bytes = sizeof(float) * (size_t)P->fields * tvol;
+    // tile plus a few reduction slots
+    size_t bytes = sizeof(float) * ((size_t)P->fields * tvol + 8);
     if (bytes <= budget) {
       B.tvol = tvol;
       break;
@@ -93,10 +94,15 @@ static void choose_bricks(lag_plan P) {
     int best0 = B.tdim[0], best1 = B.tdim[1];
     long long bestkey = -1;
     const int span1 = D == 3 ? 32 : 1;
+    // padding must not lower the number of blocks an LDS of 160 KB holds
+    auto lds_bytes = [&](long long vol) { return sizeof(float) * ((size_t)P->fields * vol + 8); };
+    const size_t cu_lds = 160 * 1024;
+    const size_t fit0 = cu_lds / lds_bytes((long long)B.tdim[0] * B.tdim[1] * B.tdim[2]);
     for (int t0 = B.tdim[0]; t0 < B.tdim[0] + 32; ++t0)
       for (int t1 = B.tdim[1]; t1 < B.tdim[1] + span1; ++t1) {
         long long vol = (long long)t0 * t1 * B.tdim[2];
-        if (sizeof(float) * (size_t)P->fields * vol > budget && !(t0 == B.tdim[0] && t1 == B.tdim[1])) continue;
+        const size_t bytes = lds_bytes(vol);
+        if ((bytes > budget || cu_lds / bytes < fit0) && !(t0 == B.tdim[0] && t1 == B.tdim[1])) continue;
         long long key = ((long long)worst(t0, t1, 32) * 65 + worst(t0, t1, 64)) * (1LL << 32) + vol;
         if (bestkey < 0 || key < bestkey) {
           bestkey = key;

@@ -984,9 +984,74 @@ __device__ __forceinline__ float jac_block_dot(const Geo& g, const int cell[D], 
   return s;
 }
 
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int D>
+__device__ __forceinline__ void jac_load(const float4* __restrict__ vals, const int* __restrict__ cells,
+                                         long long nslots, long long slot, int k, const int org[3], int cell[D],
+                                         float f[4 * JacLayout<D>::NV4]) {
+  constexpr int NV4 = JacLayout<D>::NV4;
+  jac_block_cell<D>(cells[(long long)k * nslots + slot], org, cell);
+#pragma unroll
+  for (int j = 0; j < NV4; ++j) {
+    float4 q = vals[((long long)k * NV4 + j) * nslots + slot];
+    f[4 * j] = q.x; f[4 * j + 1] = q.y; f[4 * j + 2] = q.z; f[4 * j + 3] = q.w;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void jac_scatter(const Geo& g, const Bricks& B, const int org[3], int* tile,
+                                            float* __restrict__ out, const int cell[D],
+                                            const float f[4 * JacLayout<D>::NV4], float s, int e) {
+  bool tin = true;
+  int t[3] = {0, 0, 0};
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    t[ax] = cell[ax] - org[ax];
+    tin = tin && (t[ax] >= 0) && (t[ax] + 1 < B.tdim[ax]);
+  }
+  if (tin) {
+    const int tb0 = (t[2] * B.tdim[1] + t[1]) * B.tdim[0] + t[0];
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o) {
+      int off = tb0 + (o & 1) + ((o >> 1) & 1) * B.tdim[0];
+      if (D == 3) off += ((o >> 2) & 1) * B.tdim[0] * B.tdim[1];
+#pragma unroll
+      for (int c = 0; c < D; ++c) atomicAdd(&tile[c * B.tvol + off], __float2int_rn(ldexpf(s * f[o * D + c], e)));
+    }
+  } else {
+    // outside the tile: direct float atomics into the output
+    Loc<D> L;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) L.c[ax] = cell[ax];
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o) {
+      long long gi = corner_index<D>(L, g.mv, o);
+#pragma unroll
+      for (int c = 0; c < D; ++c) unsafeAtomicAdd(&out[(long long)c * g.nv + gi], s * f[o * D + c]);
+    }
+  }
+}
+
 // Apply the stored Jacobian: with wseed == null, s_i = scale W_i J_i p
 // (Gauss-Newton data term); otherwise s_i = scale wseed_i (transpose
 // product J^T w).  Then scatter s_i J_i^T into the brick's tile.
+//
+// The tile accumulates in 32-bit fixed point: integer LDS atomics are several
+// times faster than float ones, and an integer sum does not depend on the
+// order of the additions, so the result is reproducible bit for bit.  A
+// stored block adds at most one entry to each (node, component), so no
+// partial sum of the tile exceeds sum_i |s_i| R_i, R_i = sum_k max |J_ik|
+// (max over the entries of block k of row i).  The brick is processed in
+// rounds of one 64-row item per wave: each round forms its s_i (keeping the
+// first two blocks of a row in registers, so the blocks are read once), adds
+// its rows' share to that bound, and, when the bound needs a smaller power of
+// two to stay below 2^30, first rescales the tile by a rounding right shift;
+// then it scatters.  Every wave passes every round's barrier.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const float4* __restrict__ vals,
                                                       const int* __restrict__ cells,
@@ -999,53 +1064,117 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
   if (bid < 0) return;
   int O[3], org[3];
   brick_origin<D>(g, B, bid, O, org);
-  Stages none;
-  none.j0 = nullptr;
-  none.th = nullptr;
-  none.dt = 0.f;
-  TileAcc<D, false> acc = make_acc<D, false>(lds, out, g, none, B, org, D);
+  const int tot = D * B.tvol;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int* tile = (int*)lds;             // [D][tvol] fixed-point sums
+  float* red = lds + tot;            // [2][waves] per-round bounds
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) tile[i] = 0;
   const long long base = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2];
   constexpr int NV4 = JacLayout<D>::NV4;
-  for_brick_slots<D>(g, B, O, [&](const int idx[3], int local, bool in) {
-    if (!in) return;
-    const long long slot = base + local;
-    const int n = cnt[slot];
-    if (n == 0) return;
-    long long p = idx[0] + (long long)g.mi[0] * idx[1];
-    if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
-    float s;
-    if (wseed) {
-      s = scale * wseed[p];
-    } else {
-      s = 0.f;
-      for (int k = 0; k < n; ++k) {
-        int cell[D];
-        jac_block_cell<D>(cells[(long long)k * nslots + slot], org, cell);
-        float f[4 * NV4];
+  int l[3];
+  if (D == 3) {
+    l[0] = lane & 3; l[1] = (lane >> 2) & 3; l[2] = lane >> 4;
+  } else {
+    l[0] = lane & 7; l[1] = lane >> 3; l[2] = 0;
+  }
+  const int P = B.stride[0] * B.stride[1] * B.stride[2];
+  const int nitems = B.nreg[0] * B.nreg[1] * B.nreg[2] * P;
+  const int rounds = (nitems + nw - 1) / nw;
+  float btot = 0.f;                  // bound of all rows so far (same in every thread)
+  int e = 0;                         // current scale 2^e (valid once btot > 0)
+  bool finite = true;
+  for (int r = 0; r < rounds; ++r) {
+    const int w = wave + r * nw;
+    int n = 0;
+    long long slot = 0, p = 0;
+    if (w < nitems) {
+      const int reg = w / P, ph = w - reg * P;
+      const int r0 = reg % B.nreg[0], r1 = (reg / B.nreg[0]) % B.nreg[1], r2 = reg / (B.nreg[0] * B.nreg[1]);
+      const int p0 = ph % B.stride[0], p1 = (ph / B.stride[0]) % B.stride[1], p2 = ph / (B.stride[0] * B.stride[1]);
+      int idx[3];
+      idx[0] = O[0] + r0 * B.rdim[0] + l[0] * B.stride[0] + p0;
+      idx[1] = O[1] + r1 * B.rdim[1] + l[1] * B.stride[1] + p1;
+      idx[2] = O[2] + r2 * B.rdim[2] + l[2] * B.stride[2] + p2;
+      bool in = true;
 #pragma unroll
-        for (int j = 0; j < NV4; ++j) {
-          float4 q = vals[((long long)k * NV4 + j) * nslots + slot];
-          f[4 * j] = q.x; f[4 * j + 1] = q.y; f[4 * j + 2] = q.z; f[4 * j + 3] = q.w;
-        }
-        s += jac_block_dot<D>(g, cell, f, pp);
+      for (int a = 0; a < D; ++a) in = in && idx[a] < g.mi[a];
+      slot = base + w * 64 + lane;
+      if (in) {
+        n = cnt[slot];
+        p = idx[0] + (long long)g.mi[0] * idx[1];
+        if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
       }
-      s *= scale * (wvox ? wvox[p] : 1.f);
     }
-    if (s == 0.f) return;
-    for (int k = 0; k < n; ++k) {
+    float f0[4 * NV4], f1[4 * NV4];
+    int c0[D], c1[D];
+    float s = 0.f, rb = 0.f;
+    if (n > 0) {
+      jac_load<D>(vals, cells, nslots, slot, 0, org, c0, f0);
+      float m = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4 * NV4; ++j) m = fmaxf(m, fabsf(f0[j]));
+      rb = m;
+      if (!wseed) s = jac_block_dot<D>(g, c0, f0, pp);
+    }
+    if (n > 1) {
+      jac_load<D>(vals, cells, nslots, slot, 1, org, c1, f1);
+      float m = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4 * NV4; ++j) m = fmaxf(m, fabsf(f1[j]));
+      rb += m;
+      if (!wseed) s += jac_block_dot<D>(g, c1, f1, pp);
+    }
+    for (int k = 2; k < n; ++k) {
       int cell[D];
-      jac_block_cell<D>(cells[(long long)k * nslots + slot], org, cell);
-      float a[1][1 << D][D];
-      float* f = &a[0][0][0];
+      float f[4 * NV4];
+      jac_load<D>(vals, cells, nslots, slot, k, org, cell, f);
+      float m = 0.f;
 #pragma unroll
-      for (int j = 0; j < NV4; ++j) {
-        float4 q = vals[((long long)k * NV4 + j) * nslots + slot];
-        f[4 * j] = s * q.x; f[4 * j + 1] = s * q.y; f[4 * j + 2] = s * q.z; f[4 * j + 3] = s * q.w;
-      }
-      acc.template add_block<1>(cell, 0, a);
+      for (int j = 0; j < 4 * NV4; ++j) m = fmaxf(m, fabsf(f[j]));
+      rb += m;
+      if (!wseed) s += jac_block_dot<D>(g, cell, f, pp);
     }
-  });
-  flush_tile<D, false>(acc, D, part, bid);
+    if (n > 0) s = wseed ? scale * wseed[p] : s * scale * (wvox ? wvox[p] : 1.f);
+    // this round's share of the bound, summed in a fixed order
+    const float bw = wave_sum(fabsf(s) * rb);
+    float* rr = red + (r & 1) * nw;  // a wave runs at most one round ahead
+    if (lane == 0) rr[wave] = bw;
+    __syncthreads();
+    float bs = 0.f;
+    for (int q = 0; q < nw; ++q) bs += rr[q];
+    const float prev = btot;
+    btot += bs;
+    finite = finite && btot <= 3.0e38f;  // false for inf and NaN
+    if (!finite || btot == 0.f) continue;
+    int ex = 0;
+    (void)frexpf(btot, &ex);
+    const int enew = 30 - ex;        // btot * 2^enew < 2^30
+    if (prev == 0.f) {
+      e = enew;                      // tile still zero
+    } else if (enew < e) {
+      const int d = e - enew;        // rescale the sums of earlier rounds
+      for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int x = tile[i];
+        tile[i] = d >= 31 ? 0 : (int)(((long long)x + (1LL << (d - 1))) >> d);
+      }
+      e = enew;
+      __syncthreads();
+    }
+    if (s != 0.f) {
+      jac_scatter<D>(g, B, org, tile, out, c0, f0, s, e);
+      if (n > 1) jac_scatter<D>(g, B, org, tile, out, c1, f1, s, e);
+      for (int k = 2; k < n; ++k) {
+        int cell[D];
+        float f[4 * NV4];
+        jac_load<D>(vals, cells, nslots, slot, k, org, cell, f);
+        jac_scatter<D>(g, B, org, tile, out, cell, f, s, e);
+      }
+    }
+  }
+  __syncthreads();
+  float* dst = part + bid * (long long)tot;
+  const float nan = __int_as_float(0x7fc00000);
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) dst[i] = finite ? ldexpf((float)tile[i], -e) : nan;
 }
 
 // Sum the partial tiles into the velocity-grid output in a fixed order:
@@ -1338,7 +1467,7 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
                      hipStream_t s) {
   const lag::Bricks& B = P->bricks;
   unsigned grid = grid_for(B.nbricks);
-  size_t lds = sizeof(float) * (size_t)P->geo.dim * B.tvol;
+  const size_t lds = sizeof(float) * ((size_t)P->geo.dim * B.tvol + 2 * (kBlock / 64));
   if (!wseed) prof_begin(P, s);
   if (P->geo.dim == 3)
     hipLaunchKernelGGL(k_jac_apply<3>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,

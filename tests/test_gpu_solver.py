@@ -72,6 +72,10 @@ def test_assembled_products(case, torch, L):
     HD = dev.empty(nu)
     L.gn_hessmat_assembled(planD, dev.put(W), dev.put(p), HD)
     eD = relerr(dev.get(HD), O.hessmat(oracle_problem(cD), v, T, p, wvox=W))
+    # the tile sums are integers: a repeated product is identical bit for bit
+    HD2 = dev.empty(nu)
+    L.gn_hessmat_assembled(planD, dev.put(W), dev.put(p), HD2)
+    assert np.array_equal(dev.get(HD), dev.get(HD2))
     # transpose product
     JTw = dev.empty(nu)
     L.lag_vjp_assembled(plan, dev.put(w * keep), JTw)
