@@ -18,6 +18,10 @@ from ._lib import (  # noqa: F401
     lag_jacobian_assemble, gn_hessmat_assembled, lag_vjp_assembled, lag_gradient_assembled,
     lag_pcg_assembled, lag_gn_step, lag_jacobian_info, lag_restrict_image, lag_prolong_velocity,
     lag_multilevel_solve,
+    LagCnnConfig, Cnn, lag_cnn_default_config, lag_cnn_create, lag_cnn_destroy, lag_cnn_get_params,
+    lag_cnn_set_params, lag_cnn_get_grads, lag_cnn_forward, lag_cnn_backward, lag_cnn_adam_step,
 )
+
+from . import warmstart  # noqa: F401,E402
 
 LIB_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__), "liblaglddmm.so")

@@ -66,6 +66,11 @@ class LagGnInfo(ctypes.Structure):
                 ("g0", ctypes.c_double), ("gnorm", ctypes.c_double)]
 
 
+class LagCnnConfig(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("channels", ctypes.c_int32 * 4), ("in_scale", ctypes.c_float),
+                ("out_scale", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
 class LagError(RuntimeError):
     def __init__(self, name, status, detail=""):
         self.status = status
@@ -119,6 +124,16 @@ _SIGS = {
                          ctypes.POINTER(LagGnStepInfo), _P]),
     "lag_gn_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(LagGnOptions),
                           ctypes.POINTER(LagGnInfo), _P]),
+    "lag_cnn_default_config": (None, [ctypes.POINTER(LagCnnConfig)]),
+    "lag_cnn_create": (_I, [ctypes.POINTER(LagCnnConfig), ctypes.POINTER(_P)]),
+    "lag_cnn_destroy": (_I, [_P]),
+    "lag_cnn_param_count": (_I, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "lag_cnn_get_params": (_I, [_P, _P]),
+    "lag_cnn_set_params": (_I, [_P, _P]),
+    "lag_cnn_get_grads": (_I, [_P, _P]),
+    "lag_cnn_forward": (_I, [_P, _P, _P, _P, _P]),
+    "lag_cnn_backward": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "lag_cnn_adam_step": (_I, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
 }
 
 
@@ -440,3 +455,89 @@ def problem_arrays_to_device(*arrays):
     """float32 contiguous device copies of NumPy arrays (test/bench helper)."""
     import torch
     return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda() for a in arrays]
+
+
+# ---- learned warm start ------------------------------------------------------
+
+def lag_cnn_default_config():
+    c = LagCnnConfig()
+    load().lag_cnn_default_config(ctypes.byref(c))
+    return c
+
+
+class Cnn:
+    """Owns a ``lag_cnn`` (the warm-start U-Net); parameters live on the GPU."""
+
+    def __init__(self, config: LagCnnConfig | None = None):
+        self.config = config if config is not None else lag_cnn_default_config()
+        h = ctypes.c_void_p()
+        _check("lag_cnn_create", load().lag_cnn_create(ctypes.byref(self.config), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int64()
+        _check("lag_cnn_param_count", load().lag_cnn_param_count(h, ctypes.byref(n)))
+        self.n_params = n.value
+        self.size = self.config.size
+        self.n_voxels = self.size ** 3
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().lag_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def lag_cnn_create(config=None):
+    return Cnn(config)
+
+
+def lag_cnn_destroy(net):
+    net.close()
+
+
+def lag_cnn_get_params(net):
+    out = np.empty(net.n_params, dtype=np.float32)
+    _check("lag_cnn_get_params", load().lag_cnn_get_params(net.handle, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def lag_cnn_set_params(net, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.size != net.n_params:
+        raise ValueError(f"expected {net.n_params} parameters, got {a.size}")
+    _check("lag_cnn_set_params", load().lag_cnn_set_params(net.handle, a.ctypes.data_as(ctypes.c_void_p)))
+
+
+def lag_cnn_get_grads(net):
+    out = np.empty(net.n_params, dtype=np.float32)
+    _check("lag_cnn_get_grads", load().lag_cnn_get_grads(net.handle, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def lag_cnn_forward(net, T, R, v):
+    n = net.n_voxels
+    _check("lag_cnn_forward", load().lag_cnn_forward(net.handle, _ptr(T, n, "T"), _ptr(R, n, "R"),
+                                                     _ptr(v, 3 * n, "v"), _stream()))
+
+
+def lag_cnn_backward(net, T, R, target, v, loss):
+    """Forward, loss (device float64 scalar tensor) and parameter gradients."""
+    n = net.n_voxels
+    _check("lag_cnn_backward", load().lag_cnn_backward(net.handle, _ptr(T, n, "T"), _ptr(R, n, "R"),
+                                                       _ptr(target, 3 * n, "target"), _ptr(v, 3 * n, "v"),
+                                                       _ptr(loss, 1, "loss"), _stream()))
+
+
+def lag_cnn_adam_step(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check("lag_cnn_adam_step", load().lag_cnn_adam_step(net.handle, float(lr), float(beta1), float(beta2),
+                                                         float(eps), _stream()))

@@ -74,6 +74,29 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.lag_plan_destroy(nul) == L.LAG_OK
 
 
+def test_cnn_config_validation_without_device(lib):
+    """Bad U-Net configurations are refused before any device call."""
+    nul = ctypes.c_void_p()
+    good = L.lag_cnn_default_config()
+    assert good.size == 64 and list(good.channels) == [16, 32, 64, 64]
+    for field, value in [("size", 48), ("size", 16), ("size", 288)]:
+        c = L.lag_cnn_default_config()
+        setattr(c, field, value)
+        h = ctypes.c_void_p()
+        assert lib.lag_cnn_create(ctypes.byref(c), ctypes.byref(h)) == L.LAG_EINVAL, (field, value)
+        assert not h.value
+    for ch in (8, 24, 128):
+        c = L.lag_cnn_default_config()
+        c.channels[2] = ch
+        h = ctypes.c_void_p()
+        assert lib.lag_cnn_create(ctypes.byref(c), ctypes.byref(h)) == L.LAG_EINVAL, ch
+    assert lib.lag_cnn_create(None, None) == L.LAG_EINVAL
+    assert lib.lag_cnn_forward(nul, nul, nul, nul, nul) == L.LAG_EINVAL
+    assert lib.lag_cnn_backward(nul, nul, nul, nul, nul, nul, nul) == L.LAG_EINVAL
+    assert lib.lag_cnn_adam_step(nul, 1e-3, 0.9, 0.999, 1e-8, nul) == L.LAG_EINVAL
+    assert lib.lag_cnn_destroy(nul) == L.LAG_OK
+
+
 def test_strerror(lib):
     for code in range(7):
         assert L.strerror(code)

@@ -1,0 +1,172 @@
+"""Warm-start U-Net kernels on the GPU against the FP64 oracle (oracle.cnn).
+
+The oracle runs with ``quantize=True``: it rounds to bfloat16 exactly the
+tensors the GPU stores in bfloat16 (convolution inputs and weights, the
+pre-activation gradients fed to the backward convolutions), so that the
+comparison isolates accumulation order and precision.  That residue is not
+small: an FP32 partial sum differs from the FP64 one by about 1e-6
+relative, which sends a stored activation to the other side of a bfloat16
+rounding boundary (one unit = 2^-8 relative) now and then, and the ten
+convolution layers amplify those flips.  Measured with the oracle itself
+(its convolutions recomputed with FP32 accumulation, same bfloat16
+storage, S = 32, channels 16): output 2.9e-3 relative L2, loss 1.2e-6,
+parameter gradients up to 9.7e-3 (first layer's weights, a sum over every
+voxel of the whole backward chain).  The GPU's FP32 order is another one;
+the bars are about three times those figures: output 1e-2, loss 1e-4,
+gradients 3e-2 per layer.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cnn as C
+from synthetic import blob_image
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = [
+    (32, (16, 16, 16, 16), 11),
+    (32, (16, 32, 64, 32), 12),
+]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1703_04446_amd as _L
+    _L.load()
+    return _L
+
+
+def to_oracle(flat, c):
+    shapes = C.layer_shapes(c)
+    p, off = {}, 0
+    for k in C.LAYERS:
+        taps, ci, co = shapes[k]
+        n = taps * ci * co
+        p[k + ".w"] = flat[off:off + n].reshape(taps, ci, co).astype(np.float64)
+        off += n
+        p[k + ".b"] = flat[off:off + co].astype(np.float64)
+        off += co
+    assert off == flat.size
+    return p
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def make_net(L, S, ch, seed):
+    cfg = L.lag_cnn_default_config()
+    cfg.size = S
+    for i in range(4):
+        cfg.channels[i] = ch[i]
+    cfg.seed = seed
+    net = L.Cnn(cfg)
+    # non-zero biases so that every bias path is exercised
+    flat = L.lag_cnn_get_params(net)
+    po = to_oracle(flat, ch)
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in C.LAYERS:
+        out.append(po[k + ".w"].ravel())
+        out.append(0.05 * rng.standard_normal(po[k + ".b"].size))
+    L.lag_cnn_set_params(net, np.concatenate(out).astype(np.float32))
+    return net
+
+
+def inputs(S, seed):
+    T = blob_image((S, S, S), 4, seed).astype(np.float32).ravel()
+    R = blob_image((S, S, S), 4, seed + 1).astype(np.float32).ravel()
+    tgt = (0.05 * np.random.default_rng(seed + 2).standard_normal(3 * S ** 3)).astype(np.float32)
+    return T, R, tgt
+
+
+def oracle_x(T, R, S, scale):
+    return scale * np.stack([T.reshape(S, S, S), R.reshape(S, S, S)], axis=-1).astype(np.float64)
+
+
+def to_channel_last(v, S):
+    return np.asarray(v, dtype=np.float64).reshape(3, S, S, S).transpose(1, 2, 3, 0)
+
+
+@pytest.mark.parametrize("S,ch,seed", CONFIGS, ids=[f"{c[0]}_{'-'.join(map(str, c[1]))}" for c in CONFIGS])
+def test_forward_and_gradients(S, ch, seed, torch, L):
+    net = make_net(L, S, ch, seed)
+    T, R, tgt = inputs(S, seed)
+    dT, dR, dt = (torch.from_numpy(a).cuda() for a in (T, R, tgt))
+    v = torch.empty(3 * S ** 3, device="cuda")
+    L.lag_cnn_forward(net, dT, dR, v)
+    params = to_oracle(L.lag_cnn_get_params(net), ch)
+    x = oracle_x(T, R, S, net.config.in_scale)
+    out, _ = C.forward(params, x, scale=net.config.out_scale, quantize=True)
+    e_fwd = relerr(to_channel_last(v.cpu().numpy(), S), out)
+    # backward
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    v2 = torch.empty_like(v)
+    L.lag_cnn_backward(net, dT, dR, dt, v2, loss)
+    torch.cuda.synchronize()
+    assert torch.equal(v, v2), "forward is deterministic"
+    lo, go, _ = C.loss_and_grad(params, x, to_channel_last(tgt, S), scale=net.config.out_scale, quantize=True)
+    e_loss = abs(loss.item() - lo) / lo
+    gg = to_oracle(L.lag_cnn_get_grads(net), ch)
+    errs = {k: relerr(gg[k], go[k]) for k in go}
+    worst = max(errs, key=errs.get)
+    print(f"S={S} ch={ch}: forward {e_fwd:.2e} loss {e_loss:.2e} worst grad {worst} {errs[worst]:.2e}", flush=True)
+    assert e_fwd < 1e-2
+    assert e_loss < 1e-4
+    for k, e in errs.items():
+        assert e < 3e-2, (k, e)
+    net.close()
+
+
+def test_adam_step_matches_formula(torch, L):
+    S, ch, seed = 32, (16, 16, 16, 16), 21
+    net = make_net(L, S, ch, seed)
+    T, R, tgt = inputs(S, seed)
+    dT, dR, dt = (torch.from_numpy(a).cuda() for a in (T, R, tgt))
+    v = torch.empty(3 * S ** 3, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p0 = L.lag_cnn_get_params(net).astype(np.float64)
+    L.lag_cnn_backward(net, dT, dR, dt, v, loss)
+    g = L.lag_cnn_get_grads(net).astype(np.float64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    L.lag_cnn_adam_step(net, lr, b1, b2, eps)
+    p1 = L.lag_cnn_get_params(net).astype(np.float64)
+    m, s2 = (1 - b1) * g, (1 - b2) * g * g
+    expect = p0 - lr * (m / (1 - b1)) / (np.sqrt(s2 / (1 - b2)) + eps)
+    assert np.max(np.abs(p1 - expect)) < 1e-6 * max(1.0, np.max(np.abs(p0)))
+    net.close()
+
+
+def test_training_reduces_loss(torch, L):
+    """Adam on one input pair and a smooth target lowers the loss.
+
+    The same run with the oracle (FP64, He-normal start, lr 2e-3) ends at
+    0.17 of the first loss after 40 steps; the bar is 0.5."""
+    from synthetic import fourier_velocity
+    S, ch, seed = 32, (16, 16, 16, 16), 31
+    net = make_net(L, S, ch, seed)
+    T, R, _ = inputs(S, seed)
+    tgt = (fourier_velocity((S,) * 3, 2, 0.05, seed + 2)[0] + 0.02).astype(np.float32).ravel()
+    dT, dR, dt = (torch.from_numpy(a).cuda() for a in (T, R, tgt))
+    v = torch.empty(3 * S ** 3, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hist = []
+    for _ in range(40):
+        L.lag_cnn_backward(net, dT, dR, dt, v, loss)
+        hist.append(loss.item())
+        L.lag_cnn_adam_step(net, 2e-3)
+    print("loss", hist[0], "->", hist[-1], flush=True)
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.5 * hist[0]
+    net.close()
