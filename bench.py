@@ -18,7 +18,12 @@ The JSON line also carries:
   roofline     - the dominant kernel (the Gauss-Newton matvec kernel), timed
                  with HIP events on its own stream inside the timed region;
   cpu_baseline - the FP64 NumPy oracle's matvec on a sample of the
-                 characteristics of the same problem, scaled to matvecs/s.
+                 characteristics of the same problem, scaled to matvecs/s;
+  warm_start   - the second headline figure: wall time of a full
+                 Gauss-Newton solve from v = 0 against the solve refined
+                 from the warm-start network's prediction (network trained
+                 in the run on the solver's own solutions of other pairs),
+                 on held-out pairs of the same workload.
 """
 
 from __future__ import annotations
@@ -78,6 +83,8 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one device-to-device copy of this many bytes before timing "
                          "(a known-size reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--warm-start-steps", type=int, default=2000,
+                    help="training steps of the warm-start network (0 = skip the warm-start measurement)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -109,6 +116,85 @@ def cpu_baseline(w, v, p, nsample):
             "sample": f"{nsample} of {P.n_points} characteristics (uniform random, seed 12345); "
                       f"{dt:.2f} s measured, scaled by {P.n_points / nsample:.1f}; "
                       f"single-threaded NumPy float64"}
+
+
+def warm_start_measurement(args, w, plan, L, torch):
+    """Solve time of the Gauss-Newton solve from v = 0 against the solve
+    refined from the warm-start network's prediction, on held-out pairs of
+    the same workload.  Training pairs: 4 blob templates (seeds
+    seed_base + 300 + j) x 12 random Fourier velocities (seeds
+    seed_base + 400 + i), reference = template transported on the GPU;
+    targets = the solver's own solutions from v = 0.  Test pairs: the same
+    templates with 2 unseen velocities each (seeds seed_base + 500 + i)."""
+    from paper_1703_04446_amd import warmstart as WS
+    from synthetic import blob_image, fourier_velocity
+    if w.dim != 3 or w.model != "transport" or w.nodes != 1:
+        return None
+    n = plan.n_points
+    phi = torch.empty(3 * n, device="cuda")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()  # noqa: E731
+
+    def pairs(templates, vseeds):
+        out = []
+        for Tj in templates:
+            for s in vseeds:
+                L.lag_trace(plan, dev(fourier_velocity(w.vel_m, w.kmax, w.amplitude, s)), -1, phi)
+                R = torch.empty(n, device="cuda")
+                L.lag_transport(plan, Tj, phi, R)
+                out.append((Tj, R))
+        return out
+
+    t0 = time.perf_counter()
+    templates = [dev(blob_image(w.img_m, w.nblobs, w.seed_base + 300 + j)) for j in range(4)]
+    train_pairs = pairs(templates, range(w.seed_base + 400, w.seed_base + 412))
+    test_pairs = pairs(templates, range(w.seed_base + 500, w.seed_base + 502))
+    opts = L.lag_gn_default_options()
+    opts.pcg_tol, opts.pcg_maxit = w.pcg_tol, w.pcg_maxit
+    data = WS.solve_targets(plan, train_pairs, opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cfg = L.lag_cnn_default_config()
+    cfg.size = w.vel_m[0]
+    net = L.Cnn(cfg)
+    losses = WS.train(net, data, steps=args.warm_start_steps, lr=5e-4, seed=w.seed_base)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(args, f"warm start: {len(data)} training solves in {t1 - t0:.1f} s, {args.warm_start_steps} Adam steps "
+              f"in {t2 - t1:.1f} s, loss {losses[:20].mean():.3e} -> {losses[-20:].mean():.3e}")
+    out3 = torch.zeros(3, dtype=torch.float64, device="cuda")
+    u = torch.empty(n, device="cuda")
+    rows = []
+    for T, R in test_pairs:
+        v0 = torch.zeros(plan.n_unknowns, device="cuda")
+        vp = torch.empty_like(v0)
+        WS.plain_solve(plan, T, R, v0, opts)     # untimed: first solve of this pair warms caches equally
+        plain = WS.plain_solve(plan, T, R, v0, opts)
+        Tc, Rc = WS.velocity_grid_inputs(plan, T, R)
+        WS.predict(net, Tc, Rc, vp)
+        L.lag_objective(plan, vp, T, R, u, out3)
+        J_pred = out3[0].item()
+        warm = WS.warm_solve(plan, net, T, R, vp, opts)
+        rows.append((plain, warm, J_pred))
+    net.close()
+    mean = lambda xs: float(np.mean(xs))  # noqa: E731
+    plain_ms = mean([p["solve_s"] * 1e3 for p, _, _ in rows])
+    warm_ms = mean([(q["solve_s"] + q["predict_s"]) * 1e3 for _, q, _ in rows])
+    return {
+        "metric": "Gauss-Newton solve time to |g| <= 1e-2 |g(0)|, learned warm start vs plain",
+        "unit": "ms", "plain_ms": round(plain_ms, 3), "warm_ms": round(warm_ms, 3),
+        "speedup": round(plain_ms / warm_ms, 3),
+        "predict_ms": round(mean([q["predict_s"] * 1e3 for _, q, _ in rows]), 3),
+        "plain_gn_iters": mean([p["iters"] for p, _, _ in rows]),
+        "warm_gn_iters": mean([q["iters"] for _, q, _ in rows]),
+        "all_converged": bool(all(p["converged"] and q["converged"] for p, q, _ in rows)),
+        "objective_gap_closed_by_prediction": round(mean([(p["J0"] - Jp) / (p["J0"] - p["J"])
+                                                          for p, _, Jp in rows]), 4),
+        "test_pairs": len(rows),
+        "train": {"pairs": len(data), "steps": args.warm_start_steps, "lr": 5e-4, "seconds": round(t2 - t1, 2),
+                  "ms_per_step": round((t2 - t1) / max(args.warm_start_steps, 1) * 1e3, 3),
+                  "loss_first20": float(losses[:20].mean()), "loss_last20": float(losses[-20:].mean()),
+                  "network": {"size": cfg.size, "channels": list(cfg.channels), "dtype": "bf16 MFMA, fp32 accum"}},
+    }
 
 
 def main():
@@ -223,6 +309,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if args.warm_start_steps > 0:
+        res["warm_start"] = warm_start_measurement(args, w, plan, L, torch)
     plan.close()
     if args.cpu_sample > 0:
         log(args, f"timing the oracle on {args.cpu_sample} characteristics ...")
