@@ -21,9 +21,9 @@ The JSON line also carries:
                  characteristics of the same problem, scaled to matvecs/s;
   warm_start   - the second headline figure: wall time of a full
                  Gauss-Newton solve from v = 0 against the solve refined
-                 from the warm-start network's prediction (network trained
-                 in the run on the solver's own solutions of other pairs),
-                 on held-out pairs of the same workload.
+                 from the warm-start network's prediction on 10 held-out
+                 256x256x224 pairs (network trained in the run on the
+                 solver's own solutions of 2000 128^3 pairs).
 """
 
 from __future__ import annotations
@@ -83,8 +83,11 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one device-to-device copy of this many bytes before timing "
                          "(a known-size reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
-    ap.add_argument("--warm-start-steps", type=int, default=2000,
+    ap.add_argument("--warm-start-steps", type=int, default=4000,
                     help="training steps of the warm-start network (0 = skip the warm-start measurement)")
+    ap.add_argument("--ws-pairs", type=int, default=2000, help="warm-start training pairs")
+    ap.add_argument("--ws-templates", type=int, default=50, help="distinct templates among the training pairs")
+    ap.add_argument("--ws-lr", type=float, default=5e-4, help="Adam learning rate of the warm-start network")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -118,56 +121,71 @@ def cpu_baseline(w, v, p, nsample):
                       f"single-threaded NumPy float64"}
 
 
-def warm_start_measurement(args, w, plan, L, torch):
-    """Solve time of the Gauss-Newton solve from v = 0 against the solve
-    refined from the warm-start network's prediction, on held-out pairs of
-    the same workload.  Training pairs: 4 blob templates (seeds
-    seed_base + 300 + j) x 12 random Fourier velocities (seeds
-    seed_base + 400 + i), reference = template transported on the GPU;
-    targets = the solver's own solutions from v = 0.  Test pairs: the same
-    templates with 2 unseen velocities each (seeds seed_base + 500 + i)."""
+def warm_start_measurement(args, L, torch):
+    """Gauss-Newton solve time from v = 0 against the solve refined from the
+    warm-start network's prediction, on held-out pairs.
+
+    Training: `--ws-pairs` pairs on the 128^3/64^3 workload, pair j with
+    template seed 50000 + (j mod `--ws-templates`) and velocity seed 50000 + j
+    (blob templates and random Fourier velocities of that workload; the
+    reference is the template transported on the GPU); targets are the
+    solver's own solutions from v = 0.  Evaluation: 10 pairs on the
+    256x256x224/64^3 workload with unseen templates and velocities (seeds
+    60000..60009); the network sees T and R averaged over the 64^3 cells
+    (224 / 64 is not an integer ratio)."""
     from paper_1703_04446_amd import warmstart as WS
-    from synthetic import blob_image, fourier_velocity
-    if w.dim != 3 or w.model != "transport" or w.nodes != 1:
-        return None
-    n = plan.n_points
-    phi = torch.empty(3 * n, device="cuda")
+    from synthetic import blob_image, fourier_velocity, workload
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()  # noqa: E731
 
-    def pairs(templates, vseeds):
-        out = []
-        for Tj in templates:
-            for s in vseeds:
-                L.lag_trace(plan, dev(fourier_velocity(w.vel_m, w.kmax, w.amplitude, s)), -1, phi)
-                R = torch.empty(n, device="cuda")
-                L.lag_transport(plan, Tj, phi, R)
-                out.append((Tj, R))
-        return out
+    def make_plan(w):
+        return L.Plan(L.make_problem(3, w.img_m, w.vel_m, nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma,
+                                     jac_blocks=args.jac_blocks))
 
-    t0 = time.perf_counter()
-    templates = [dev(blob_image(w.img_m, w.nblobs, w.seed_base + 300 + j)) for j in range(4)]
-    train_pairs = pairs(templates, range(w.seed_base + 400, w.seed_base + 412))
-    test_pairs = pairs(templates, range(w.seed_base + 500, w.seed_base + 502))
+    def reference(plan, w, T, vseed, phi):
+        L.lag_trace(plan, dev(fourier_velocity(w.vel_m, w.kmax, w.amplitude, vseed)), -1, phi)
+        R = torch.empty(plan.n_points, device="cuda")
+        L.lag_transport(plan, T, phi, R)
+        return R
+
+    wt, we = workload("3d128_transport"), workload("3d256_transport")
     opts = L.lag_gn_default_options()
-    opts.pcg_tol, opts.pcg_maxit = w.pcg_tol, w.pcg_maxit
-    data = WS.solve_targets(plan, train_pairs, opts)
+    opts.pcg_tol, opts.pcg_maxit = wt.pcg_tol, wt.pcg_maxit
+    t0 = time.perf_counter()
+    plan = make_plan(wt)
+    phi = torch.empty(3 * plan.n_points, device="cuda")
+    templates = [dev(blob_image(wt.img_m, wt.nblobs, 50000 + j)) for j in range(args.ws_templates)]
+    data, iters = [], []
+    for j in range(args.ws_pairs):
+        T = templates[j % args.ws_templates]
+        R = reference(plan, wt, T, 50000 + j, phi)
+        (Tc, Rc, vs, info), = WS.solve_targets(plan, [(T, R)], opts)
+        data.append((Tc, Rc, vs))
+        iters.append(info["iters"])
+    del templates
+    plan.close()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     cfg = L.lag_cnn_default_config()
-    cfg.size = w.vel_m[0]
+    cfg.size = wt.vel_m[0]
     net = L.Cnn(cfg)
-    losses = WS.train(net, data, steps=args.warm_start_steps, lr=5e-4, seed=w.seed_base)
+    losses = WS.train(net, data, steps=args.warm_start_steps, lr=args.ws_lr, seed=50000)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    log(args, f"warm start: {len(data)} training solves in {t1 - t0:.1f} s, {args.warm_start_steps} Adam steps "
-              f"in {t2 - t1:.1f} s, loss {losses[:20].mean():.3e} -> {losses[-20:].mean():.3e}")
+    del data
+    log(args, f"warm start: {args.ws_pairs} training solves ({np.mean(iters):.2f} GN iterations each) in "
+              f"{t1 - t0:.1f} s, {args.warm_start_steps} Adam steps in {t2 - t1:.1f} s, "
+              f"loss {losses[:50].mean():.3e} -> {losses[-50:].mean():.3e}")
+    plan = make_plan(we)
+    phi = torch.empty(3 * plan.n_points, device="cuda")
     out3 = torch.zeros(3, dtype=torch.float64, device="cuda")
-    u = torch.empty(n, device="cuda")
+    u = torch.empty(plan.n_points, device="cuda")
     rows = []
-    for T, R in test_pairs:
+    for j in range(10):
+        T = dev(blob_image(we.img_m, we.nblobs, 60000 + j))
+        R = reference(plan, we, T, 60000 + j, phi)
         v0 = torch.zeros(plan.n_unknowns, device="cuda")
         vp = torch.empty_like(v0)
-        WS.plain_solve(plan, T, R, v0, opts)     # untimed: first solve of this pair warms caches equally
+        WS.plain_solve(plan, T, R, v0, opts)     # untimed first solve of the pair (caches, clocks)
         plain = WS.plain_solve(plan, T, R, v0, opts)
         Tc, Rc = WS.velocity_grid_inputs(plan, T, R)
         WS.predict(net, Tc, Rc, vp)
@@ -176,12 +194,13 @@ def warm_start_measurement(args, w, plan, L, torch):
         warm = WS.warm_solve(plan, net, T, R, vp, opts)
         rows.append((plain, warm, J_pred))
     net.close()
+    plan.close()
     mean = lambda xs: float(np.mean(xs))  # noqa: E731
     plain_ms = mean([p["solve_s"] * 1e3 for p, _, _ in rows])
     warm_ms = mean([(q["solve_s"] + q["predict_s"]) * 1e3 for _, q, _ in rows])
     return {
         "metric": "Gauss-Newton solve time to |g| <= 1e-2 |g(0)|, learned warm start vs plain",
-        "unit": "ms", "plain_ms": round(plain_ms, 3), "warm_ms": round(warm_ms, 3),
+        "workload": we.name, "unit": "ms", "plain_ms": round(plain_ms, 3), "warm_ms": round(warm_ms, 3),
         "speedup": round(plain_ms / warm_ms, 3),
         "predict_ms": round(mean([q["predict_s"] * 1e3 for _, q, _ in rows]), 3),
         "plain_gn_iters": mean([p["iters"] for p, _, _ in rows]),
@@ -190,9 +209,11 @@ def warm_start_measurement(args, w, plan, L, torch):
         "objective_gap_closed_by_prediction": round(mean([(p["J0"] - Jp) / (p["J0"] - p["J"])
                                                           for p, _, Jp in rows]), 4),
         "test_pairs": len(rows),
-        "train": {"pairs": len(data), "steps": args.warm_start_steps, "lr": 5e-4, "seconds": round(t2 - t1, 2),
+        "train": {"workload": wt.name, "pairs": args.ws_pairs, "templates": args.ws_templates,
+                  "steps": args.warm_start_steps, "lr": args.ws_lr, "solve_seconds": round(t1 - t0, 2),
+                  "train_seconds": round(t2 - t1, 2),
                   "ms_per_step": round((t2 - t1) / max(args.warm_start_steps, 1) * 1e3, 3),
-                  "loss_first20": float(losses[:20].mean()), "loss_last20": float(losses[-20:].mean()),
+                  "loss_first50": float(losses[:50].mean()), "loss_last50": float(losses[-50:].mean()),
                   "network": {"size": cfg.size, "channels": list(cfg.channels), "dtype": "bf16 MFMA, fp32 accum"}},
     }
 
@@ -309,9 +330,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
-    if args.warm_start_steps > 0:
-        res["warm_start"] = warm_start_measurement(args, w, plan, L, torch)
     plan.close()
+    if args.warm_start_steps > 0:
+        res["warm_start"] = warm_start_measurement(args, L, torch)
     if args.cpu_sample > 0:
         log(args, f"timing the oracle on {args.cpu_sample} characteristics ...")
         res["cpu_baseline"] = cpu_baseline(w, 0.5 * vt.astype(np.float64), p0.astype(np.float64),

@@ -327,6 +327,16 @@ int lag_restrict_image(lag_plan plan, const float* f, float* coarse, void* strea
  * n_unknowns / 2^d floats; v_fine: velocity-shaped for the plan. */
 int lag_prolong_velocity(lag_plan plan, const float* v_coarse, float* v_fine, void* stream);
 
+/* Average an image of the plan's image grid over the cells of the plan's
+ * velocity grid: each output value is the integral of the piecewise-constant
+ * image over a velocity cell divided by the cell's volume (per axis, fine
+ * cell i weighs its overlap with the coarse cell; any ratio img_m / vel_m
+ * >= 1, also a non-integer one such as 224 / 64).  For a ratio of 2 this is
+ * lag_restrict_image.  It feeds images to the warm-start network below.
+ * f: image-shaped; out: prod(vel_m) floats.  LAG_EINVAL if some
+ * img_m[a] < vel_m[a]. */
+int lag_resample_to_velocity_grid(lag_plan plan, const float* f, float* out, void* stream);
+
 /* Coarse-to-fine Gauss-Newton: `levels` levels (1..8; level 0 = `finest`),
  * T and R restricted level by level, lag_gn_solve on each level starting
  * from the refined solution of the level below (zero on the coarsest).  v

@@ -25,7 +25,10 @@ and intensity-preserving diffeomorphic image registration"):
 * ``precond``     - the spectral preconditioner (Sec. 3.2, PCG paragraph).
 * ``gn``          - PCG and inexact Gauss-Newton with Armijo line search
                     (eq. solveGN).
-* ``multilevel``  - coarse-to-fine continuation (Sec. 3.2, last paragraph).
+* ``multilevel``  - coarse-to-fine continuation (Sec. 3.2, last paragraph) and
+                    the cell average onto the velocity grid.
+* ``cnn``         - the warm-start U-Net (not in the paper; forward and
+                    backward in FP64).
 
 Readings of passages that are silent, ambiguous or garbled are listed in the
 module docstrings where they are used.  Functions pinned only by
@@ -39,7 +42,8 @@ from .objective import (ssd, regularizer_apply, regularizer_energy, objective,
                         gradient, hessmat, laplacian_apply)
 from .precond import spectral_precond_apply, spectral_symbol
 from .gn import pcg, gn_solve
-from .multilevel import restrict_image, prolong_velocity, coarsen_problem, multilevel_solve
+from .multilevel import (restrict_image, prolong_velocity, coarsen_problem, multilevel_solve,
+                         resample_to_velocity_grid)
 
 __all__ = [
     "Problem", "time_weights", "node_weights",
@@ -49,4 +53,5 @@ __all__ = [
     "spectral_precond_apply", "spectral_symbol",
     "pcg", "gn_solve",
     "restrict_image", "prolong_velocity", "coarsen_problem", "multilevel_solve",
+    "resample_to_velocity_grid",
 ]

@@ -50,6 +50,33 @@ def restrict_image(prob: Problem, f):
     return out / 8.0
 
 
+def cell_average_matrix(fine_m, coarse_m):
+    """Dense (coarse_m, fine_m) matrix of the cell average along one axis:
+    entry (I, i) = |fine cell i  intersect  coarse cell I| / |coarse cell I|
+    on [0, 1) with fine cells of width 1/fine_m and coarse cells 1/coarse_m."""
+    W = np.zeros((coarse_m, fine_m))
+    for I in range(coarse_m):
+        a, b = I / coarse_m, (I + 1) / coarse_m
+        for i in range(fine_m):
+            lo, hi = max(a, i / fine_m), min(b, (i + 1) / fine_m)
+            if hi > lo:
+                W[I, i] = (hi - lo) * coarse_m
+    return W
+
+
+def resample_to_velocity_grid(prob: Problem, f):
+    """Average of the piecewise-constant image over each velocity cell (any
+    ratio img_m / vel_m >= 1): the per-axis cell-average matrices applied
+    along every axis of the image array."""
+    f = np.asarray(f, dtype=np.float64).reshape(prob.img_shape)
+    out = f
+    for a in range(prob.dim):
+        W = cell_average_matrix(prob.img_m[a], prob.vel_m[a])
+        axis = prob.dim - 1 - a          # storage order is reversed (x last)
+        out = np.moveaxis(np.tensordot(W, out, axes=([1], [axis])), 0, axis)
+    return out
+
+
 def _prolong_axis(c, axis):
     """Cell-centred linear refinement of a periodic array along one axis."""
     left = np.roll(c, 1, axis=axis)    # c[i-1]

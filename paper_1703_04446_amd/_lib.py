@@ -110,6 +110,7 @@ _SIGS = {
     "lag_gn_default_options": (None, [ctypes.POINTER(LagGnOptions)]),
     "lag_restrict_image": (_I, [_P, _P, _P, _P]),
     "lag_prolong_velocity": (_I, [_P, _P, _P, _P]),
+    "lag_resample_to_velocity_grid": (_I, [_P, _P, _P, _P]),
     "lag_multilevel_solve": (_I, [ctypes.POINTER(LagProblem), ctypes.c_int32, _P, _P, _P,
                                   ctypes.POINTER(LagGnOptions), ctypes.POINTER(LagGnInfo), _P]),
     "lag_jacobian_assemble": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
@@ -212,14 +213,18 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t, n=None, name="tensor"):
+def _ptr(t, n=None, name="tensor", f64=False):
+    """Device pointer of a contiguous GPU tensor: float32, or float64 where
+    the C-ABI argument is a double* (f64=True)."""
     if t is None:
         return None
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name}: expected a torch.Tensor")
-    if t.dtype not in (torch.float32, torch.float64) or not t.is_cuda or not t.is_contiguous():
-        raise ValueError(f"{name}: expected a contiguous float tensor on the GPU")
+    want = torch.float64 if f64 else torch.float32
+    if t.dtype != want or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {want} tensor on the GPU, got {t.dtype} "
+                         f"({'GPU' if t.is_cuda else 'CPU'}, {'contiguous' if t.is_contiguous() else 'strided'})")
     if n is not None and t.numel() != n:
         raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
@@ -319,18 +324,18 @@ def lag_reg_apply(plan, p, out):
 def lag_objective(plan, v, T, R, u, out3):
     _check("lag_objective", load().lag_objective(plan.handle, _ptr(v, plan.n_unknowns, "v"),
                                                  _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
-                                                 _ptr(u, plan.n_points, "u"), _ptr(out3, 3, "out3"), _stream()))
+                                                 _ptr(u, plan.n_points, "u"), _ptr(out3, 3, "out3", f64=True), _stream()))
 
 
 def lag_gradient(plan, v, T, R, g, out3):
     _check("lag_gradient", load().lag_gradient(plan.handle, _ptr(v, plan.n_unknowns, "v"),
                                                _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
-                                               _ptr(g, plan.n_unknowns, "g"), _ptr(out3, 3, "out3"), _stream()))
+                                               _ptr(g, plan.n_unknowns, "g"), _ptr(out3, 3, "out3", f64=True), _stream()))
 
 
 def lag_dot(plan, x, y, out):
     n = x.numel()
-    _check("lag_dot", load().lag_dot(plan.handle, n, _ptr(x, n, "x"), _ptr(y, n, "y"), _ptr(out, 1, "out"),
+    _check("lag_dot", load().lag_dot(plan.handle, n, _ptr(x, n, "x"), _ptr(y, n, "y"), _ptr(out, 1, "out", f64=True),
                                      _stream()))
 
 
@@ -376,7 +381,7 @@ def lag_vjp_assembled(plan, w, JTw):
 def lag_gradient_assembled(plan, v, T, R, g, out3):
     _check("lag_gradient_assembled", load().lag_gradient_assembled(
         plan.handle, _ptr(v, plan.n_unknowns, "v"), _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
-        _ptr(g, plan.n_unknowns, "g"), _ptr(out3, 3, "out3"), _stream()))
+        _ptr(g, plan.n_unknowns, "g"), _ptr(out3, 3, "out3", f64=True), _stream()))
 
 
 def lag_pcg_assembled(plan, wvox, b, x, tol=0.1, maxit=50):
@@ -413,6 +418,12 @@ def lag_prolong_velocity(plan, v_coarse, v_fine):
     nu = plan.n_unknowns
     _check("lag_prolong_velocity", load().lag_prolong_velocity(
         plan.handle, _ptr(v_coarse, nu >> plan.prob.dim, "v_coarse"), _ptr(v_fine, nu, "v_fine"), _stream()))
+
+
+def lag_resample_to_velocity_grid(plan, f, out):
+    nvel = plan.n_unknowns // (plan.prob.nt_nodes * plan.prob.dim)
+    _check("lag_resample_to_velocity_grid", load().lag_resample_to_velocity_grid(
+        plan.handle, _ptr(f, plan.n_points, "f"), _ptr(out, nvel, "out"), _stream()))
 
 
 def lag_multilevel_solve(prob, levels, T, R, v, options=None):
@@ -535,7 +546,7 @@ def lag_cnn_backward(net, T, R, target, v, loss):
     n = net.n_voxels
     _check("lag_cnn_backward", load().lag_cnn_backward(net.handle, _ptr(T, n, "T"), _ptr(R, n, "R"),
                                                        _ptr(target, 3 * n, "target"), _ptr(v, 3 * n, "v"),
-                                                       _ptr(loss, 1, "loss"), _stream()))
+                                                       _ptr(loss, 1, "loss", f64=True), _stream()))
 
 
 def lag_cnn_adam_step(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -1,7 +1,9 @@
 // Multilevel continuation (Sec. 3.2, last paragraph): restriction of images
 // to a grid with half the cells per axis (mean of the 2^d children, the
 // midpoint-rule integral over the coarse cell) and cell-centred linear
-// refinement of velocities (weights 3/4 and 1/4 per axis, periodic).
+// refinement of velocities (weights 3/4 and 1/4 per axis, periodic).  Also
+// the cell average onto the velocity grid at any ratio, which feeds the
+// warm-start network.
 
 #include <vector>
 
@@ -88,6 +90,53 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const float* __restrict__ c,
   out[i] = s;
 }
 
+// Cell average over a coarser grid with any ratio: along axis a, in units of
+// 1 / (img_m * vel_m) of the domain, fine cell i spans [i vm, (i + 1) vm) and
+// coarse cell I spans [I im, (I + 1) im); the weight of i in I is their
+// integer overlap divided by im.  One coarse value per thread.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_resample(const float* __restrict__ f, float* __restrict__ out, int fx,
+                                                     int fy, int fz, int cx, int cy, int cz) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nc = (long long)cx * cy * cz;
+  if (i >= nc) return;
+  const int X = (int)(i % cx), Y = (int)((i / cx) % cy), Z = (int)(i / ((long long)cx * cy));
+  const int fm[3] = {fx, fy, fz}, cm[3] = {cx, cy, cz}, C[3] = {X, Y, Z};
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // fine cells overlapping [C im, (C + 1) im) (fine cell i covers [i vm, (i + 1) vm))
+    const long long b0 = (long long)C[a] * fm[a], b1 = b0 + fm[a];
+    lo[a] = (int)(b0 / cm[a]);
+    hi[a] = (int)((b1 + cm[a] - 1) / cm[a]);  // exclusive
+  }
+  if (D == 2) {
+    lo[2] = 0;
+    hi[2] = 1;
+  }
+  float s = 0.f;
+  for (int z = lo[2]; z < hi[2]; ++z) {
+    float wz = 1.f;
+    if (D == 3) {
+      const long long a0 = (long long)z * cm[2], a1 = a0 + cm[2];
+      const long long b0 = (long long)Z * fm[2], b1 = b0 + fm[2];
+      wz = (float)(min(a1, b1) - max(a0, b0)) / (float)fm[2];
+    }
+    for (int y = lo[1]; y < hi[1]; ++y) {
+      const long long a0 = (long long)y * cm[1], a1 = a0 + cm[1];
+      const long long b0 = (long long)Y * fm[1], b1 = b0 + fm[1];
+      const float wy = wz * (float)(min(a1, b1) - max(a0, b0)) / (float)fm[1];
+      for (int x = lo[0]; x < hi[0]; ++x) {
+        const long long c0 = (long long)x * cm[0], c1 = c0 + cm[0];
+        const long long d0 = (long long)X * fm[0], d1 = d0 + fm[0];
+        const float w = wy * (float)(min(c1, d1) - max(c0, d0)) / (float)fm[0];
+        s = fmaf(w, f[((long long)z * fy + y) * fx + x], s);
+      }
+    }
+  }
+  out[i] = s;
+}
+
 int launch_restrict(int dim, const int fine_m[3], const float* f, float* out, hipStream_t s) {
   const int cx = fine_m[0] / 2, cy = fine_m[1] / 2, cz = dim == 3 ? fine_m[2] / 2 : 1;
   const long long nc = (long long)cx * cy * cz;
@@ -143,6 +192,25 @@ int lag_prolong_velocity(lag_plan P, const float* v_coarse, float* v_fine, void*
   if (!P || !v_coarse || !v_fine) return LAG_EINVAL;
   if (!even_grids(&P->prob)) return LAG_EINVAL;
   return launch_prolong(P->prob.dim, P->prob.vel_m, P->fields, v_coarse, v_fine, (hipStream_t)stream);
+}
+
+int lag_resample_to_velocity_grid(lag_plan P, const float* f, float* out, void* stream) {
+  if (!P || !f || !out) return LAG_EINVAL;
+  const lag_problem& p = P->prob;
+  for (int a = 0; a < p.dim; ++a)
+    if (p.img_m[a] < p.vel_m[a]) return LAG_EINVAL;
+  const int fz = p.dim == 3 ? p.img_m[2] : 1, cz = p.dim == 3 ? p.vel_m[2] : 1;
+  const long long nc = (long long)p.vel_m[0] * p.vel_m[1] * cz;
+  const unsigned grid = (unsigned)((nc + kBlock - 1) / kBlock);
+  hipStream_t s = (hipStream_t)stream;
+  if (p.dim == 3)
+    hipLaunchKernelGGL(k_resample<3>, dim3(grid), dim3(kBlock), 0, s, f, out, p.img_m[0], p.img_m[1], fz,
+                       p.vel_m[0], p.vel_m[1], cz);
+  else
+    hipLaunchKernelGGL(k_resample<2>, dim3(grid), dim3(kBlock), 0, s, f, out, p.img_m[0], p.img_m[1], fz,
+                       p.vel_m[0], p.vel_m[1], cz);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
 }
 
 int lag_multilevel_solve(const lag_problem* finest, int32_t levels, const float* T, const float* R, float* v,

@@ -1,7 +1,8 @@
 """Learned warm start for the Gauss-Newton solve.
 
 A 3-D U-Net (``lag_cnn_*``, bf16 MFMA kernels) maps the template and the
-reference, restricted to the velocity grid, to a stationary velocity.  It is
+reference, averaged over the cells of the velocity grid, to a stationary
+velocity.  It is
 trained on image pairs and the Gauss-Newton solutions that the solver itself
 produces for them (``lag_gn_solve`` from v = 0); at solve time its
 prediction is the starting value that ``lag_gn_solve`` refines.  The
@@ -24,26 +25,19 @@ from . import _lib as L
 
 
 def velocity_grid_inputs(plan, T, R):
-    """T and R on the velocity grid: one 2x restriction (mean of the 8
-    children) when the image grid is twice the velocity grid, a copy when
-    they are equal.  The velocity grid must be a cube (the network's domain).
-    """
+    """T and R averaged over the cells of the velocity grid (any ratio of
+    image to velocity cells >= 1, lag_resample_to_velocity_grid).  The
+    velocity grid must be a cube: it is the network's domain."""
     import torch
     p = plan.prob
-    dim = p.dim
-    img = [p.img_m[a] for a in range(dim)]
-    vel = [p.vel_m[a] for a in range(dim)]
-    if dim != 3 or len(set(vel)) != 1:
+    vel = [p.vel_m[a] for a in range(p.dim)]
+    if p.dim != 3 or len(set(vel)) != 1:
         raise ValueError("the warm-start network needs a cubic 3-D velocity grid")
-    if img == vel:
-        return T.clone(), R.clone()
-    if img != [2 * m for m in vel]:
-        raise ValueError("image grid must equal the velocity grid or be twice it")
     n = vel[0] ** 3
     Tc = torch.empty(n, device=T.device, dtype=torch.float32)
     Rc = torch.empty(n, device=T.device, dtype=torch.float32)
-    L.lag_restrict_image(plan, T, Tc)
-    L.lag_restrict_image(plan, R, Rc)
+    L.lag_resample_to_velocity_grid(plan, T, Tc)
+    L.lag_resample_to_velocity_grid(plan, R, Rc)
     return Tc, Rc
 
 

@@ -47,23 +47,21 @@ def blob_image(m, nblobs, seed, extent=None, density=False):
     sigmas = rng.uniform(0.03, 0.1, size=nblobs)
     amps = rng.uniform(0.5, 1.0, size=nblobs)
     xs = cell_centres(m, extent)
-    out = np.zeros(_shape(m), dtype=np.float64)
-    for b in range(nblobs):
-        # Separable periodic profile: sum over the image copies at offsets
-        # -L, 0, +L along each axis of the 1-D Gaussian factor.
-        prof = []
-        for a in range(d):
-            c = centres[b, a] * extent[a]
-            s = sigmas[b] * extent[a]
-            g = np.zeros(m[a])
-            for o in (-1.0, 0.0, 1.0):
-                g += np.exp(-((xs[a] - c - o * extent[a]) ** 2) / (2.0 * s * s))
-            prof.append(g)
-        # outer product in storage order (last axis = x)
-        blob = prof[d - 1]
-        for a in range(d - 2, -1, -1):
-            blob = np.multiply.outer(blob, prof[a])
-        out += amps[b] * blob
+    # Separable periodic profiles: per blob and axis, the sum over the image
+    # copies at offsets -L, 0, +L of the 1-D Gaussian factor.
+    prof = []
+    for a in range(d):
+        c = centres[:, a, None] * extent[a]
+        s = sigmas[:, None] * extent[a]
+        g = np.zeros((nblobs, m[a]))
+        for o in (-1.0, 0.0, 1.0):
+            g += np.exp(-((xs[a][None, :] - c - o * extent[a]) ** 2) / (2.0 * s * s))
+        prof.append(g)
+    # sum over blobs of the outer products, in storage order (last axis = x)
+    if d == 2:
+        out = np.einsum("b,by,bx->yx", amps, prof[1], prof[0], optimize=True)
+    else:
+        out = np.einsum("b,bz,by,bx->zyx", amps, prof[2], prof[1], prof[0], optimize=True)
     if density:
         cell = float(np.prod([extent[a] / m[a] for a in range(d)]))
         out /= out.sum() * cell

@@ -68,3 +68,17 @@ def test_multilevel_solve(torch, L):
     # the finest level starts from the refined coarse solution, so it needs
     # fewer Gauss-Newton iterations than the coarsest level
     assert infos[-1]["iters"] <= infos[0]["iters"]
+
+
+@pytest.mark.parametrize("img,vel", [((28, 20, 24), (8, 8, 8)), ((256, 256, 224), (64, 64, 64)),
+                                     ((45, 36), (15, 18))], ids=["3d_ragged", "3d_256x256x224", "2d"])
+def test_resample_to_velocity_grid(img, vel, torch, L):
+    """Cell average onto the velocity grid at non-integer ratios (224 / 64)."""
+    dim = len(img)
+    OP = O.Problem(dim=dim, img_m=img, vel_m=vel)
+    plan = L.Plan(L.make_problem(dim, img, vel, nsteps=2))
+    f = f32(np.random.default_rng(sum(img)).uniform(0.0, 1.0, OP.n_points))
+    out = torch.empty(int(np.prod(vel)), device="cuda")
+    L.lag_resample_to_velocity_grid(plan, torch.from_numpy(f.astype(np.float32)).cuda(), out)
+    assert relerr(out.cpu().numpy(), O.resample_to_velocity_grid(OP, f)) < 1e-6
+    plan.close()

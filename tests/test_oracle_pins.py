@@ -615,3 +615,22 @@ def test_multilevel_solve_converges_2d():
     assert v.shape == P.vel_shape
     J_final = O.objective(P, v, T, R)["J"]
     assert J_final < 0.2 * O.objective(P, np.zeros(P.vel_shape), T, R)["J"]
+
+
+def test_resample_to_velocity_grid_pins():
+    """Cell average onto the velocity grid: ratio 2 is the 2^d mean, constants
+    and the integral are kept, and a non-integer ratio (7 -> 2, 5 -> 3)
+    equals the mean over a common refinement (each fine cell split into
+    coarse_m equal parts, each coarse cell then owning fine_m of them)."""
+    P2 = O.Problem(dim=3, img_m=(8, 6, 4), vel_m=(4, 3, 2))
+    x = np.random.default_rng(5).standard_normal(P2.n_points)
+    np.testing.assert_allclose(O.resample_to_velocity_grid(P2, x), O.restrict_image(P2, x), atol=1e-14)
+    P = O.Problem(dim=2, img_m=(7, 5), vel_m=(2, 3))
+    np.testing.assert_allclose(O.resample_to_velocity_grid(P, np.full(35, 2.5)), 2.5, atol=1e-14)
+    f = np.random.default_rng(6).standard_normal((5, 7))      # (y, x)
+    out = O.resample_to_velocity_grid(P, f.ravel())
+    assert abs(out.sum() * (1 / 6) - f.sum() * (1 / 35)) < 1e-13
+    # common refinement: x split 7*2 = 14 sub-cells, y split 5*3 = 15
+    fine = np.repeat(np.repeat(f, 3, axis=0), 2, axis=1)     # (15, 14)
+    ref = fine.reshape(3, 5, 2, 7).mean(axis=(1, 3))          # (vel y, vel x)
+    np.testing.assert_allclose(out, ref, atol=1e-14)
