@@ -261,6 +261,24 @@ int lag_pcg(lag_plan plan, const float* v, const float* T, const float* wvox,
 int lag_pcg_assembled(lag_plan plan, const float* wvox, const float* b, float* x, double tol,
                       int32_t maxit, lag_pcg_info* info, void* stream);
 
+/* lag_pcg with the stopping test on the device, so the iteration can run as
+ * a captured HIP graph: `iters_per_graph` (1..64) iterations are captured
+ * once per plan and argument set (v, T, wvox, b, x) and replayed; a device
+ * flag set by the residual test (or the iteration cap, or a breakdown)
+ * makes every kernel of the remaining captured iterations return at entry.
+ * The host reads the flag once per replay instead of once per iteration.
+ * Same iterates as lag_pcg.  Allocating on first use (a control block, a
+ * private capture stream, the graph); a cached graph is rebuilt when the
+ * arguments change and freed with the plan.  A plan's graph serves one
+ * stream at a time, like the plan. */
+int lag_pcg_graph(lag_plan plan, const float* v, const float* T, const float* wvox,
+                  const float* b, float* x, double tol, int32_t maxit, int32_t iters_per_graph,
+                  lag_pcg_info* info, void* stream);
+
+/* lag_pcg_graph with the assembled Gauss-Newton operator. */
+int lag_pcg_assembled_graph(lag_plan plan, const float* wvox, const float* b, float* x, double tol,
+                            int32_t maxit, int32_t iters_per_graph, lag_pcg_info* info, void* stream);
+
 typedef struct lag_gn_options {
     double  gtol;           /* stop when |g| <= gtol |g(v=0)|   (1e-2)        */
     int32_t max_gn;         /* Gauss-Newton iteration cap         (50)        */
@@ -268,6 +286,9 @@ typedef struct lag_gn_options {
     int32_t pcg_maxit;      /* PCG iteration cap                   (50)       */
     double  armijo_c1;      /* sufficient decrease constant        (1e-4)     */
     int32_t max_halvings;   /* line-search step halvings           (10)       */
+    int32_t graph_iters;    /* 0: host-driven PCG; k in 1..64: PCG with the
+                               stopping test on the device, k iterations per
+                               captured-graph replay (lag_pcg_graph)   (0) */
 } lag_gn_options;
 
 typedef struct lag_gn_info {

@@ -48,7 +48,8 @@ class LagPcgInfo(ctypes.Structure):
 class LagGnOptions(ctypes.Structure):
     _fields_ = [("gtol", ctypes.c_double), ("max_gn", ctypes.c_int32),
                 ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int32),
-                ("armijo_c1", ctypes.c_double), ("max_halvings", ctypes.c_int32)]
+                ("armijo_c1", ctypes.c_double), ("max_halvings", ctypes.c_int32),
+                ("graph_iters", ctypes.c_int32)]
 
 
 class LagGnStepInfo(ctypes.Structure):
@@ -121,6 +122,10 @@ _SIGS = {
     "lag_gradient_assembled": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "lag_pcg_assembled": (_I, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32,
                                ctypes.POINTER(LagPcgInfo), _P]),
+    "lag_pcg_graph": (_I, [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.POINTER(LagPcgInfo), _P]),
+    "lag_pcg_assembled_graph": (_I, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(LagPcgInfo), _P]),
     "lag_gn_step": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(LagGnOptions), ctypes.c_double,
                          ctypes.POINTER(LagGnStepInfo), _P]),
     "lag_gn_solve": (_I, [_P, _P, _P, _P, ctypes.POINTER(LagGnOptions),
@@ -391,6 +396,30 @@ def lag_pcg_assembled(plan, wvox, b, x, tol=0.1, maxit=50):
                                   _stream())
     if st not in (LAG_OK, LAG_EBREAKDOWN):
         _check("lag_pcg_assembled", st)
+    return {"iters": info.iters, "matvecs": info.matvecs, "breakdown": bool(info.breakdown),
+            "relres": info.relres, "status": st}
+
+
+def lag_pcg_graph(plan, v, T, wvox, b, x, tol=0.1, maxit=50, iters_per_graph=4):
+    info = LagPcgInfo()
+    st = load().lag_pcg_graph(plan.handle, _ptr(v, plan.n_unknowns, "v"), _ptr(T, plan.n_points, "T"),
+                              _ptr(wvox, plan.n_points, "wvox"), _ptr(b, plan.n_unknowns, "b"),
+                              _ptr(x, plan.n_unknowns, "x"), float(tol), int(maxit), int(iters_per_graph),
+                              ctypes.byref(info), _stream())
+    if st not in (LAG_OK, LAG_EBREAKDOWN):
+        _check("lag_pcg_graph", st)
+    return {"iters": info.iters, "matvecs": info.matvecs, "breakdown": bool(info.breakdown),
+            "relres": info.relres, "status": st}
+
+
+def lag_pcg_assembled_graph(plan, wvox, b, x, tol=0.1, maxit=50, iters_per_graph=4):
+    info = LagPcgInfo()
+    st = load().lag_pcg_assembled_graph(plan.handle, _ptr(wvox, plan.n_points, "wvox"),
+                                        _ptr(b, plan.n_unknowns, "b"), _ptr(x, plan.n_unknowns, "x"),
+                                        float(tol), int(maxit), int(iters_per_graph), ctypes.byref(info),
+                                        _stream())
+    if st not in (LAG_OK, LAG_EBREAKDOWN):
+        _check("lag_pcg_assembled_graph", st)
     return {"iters": info.iters, "matvecs": info.matvecs, "breakdown": bool(info.breakdown),
             "relres": info.relres, "status": st}
 

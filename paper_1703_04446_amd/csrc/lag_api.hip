@@ -20,8 +20,6 @@ int set_hip_error(hipError_t e) {
   return LAG_EHIP;
 }
 
-int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, hipStream_t s);
-int launch_pcg_p(long long n, float* p, const float* z, double* sc, hipStream_t s);
 int launch_scale_mul(long long n, float c, const float* a, const float* w, float* out, hipStream_t s);
 int launch_axpby(long long n, float a, const float* x, float b, const float* y, float* out, hipStream_t s);
 
@@ -134,6 +132,11 @@ static void free_plan(lag_plan P) {
                   P->jac_cell, P->jac_cnt, P->jac_max};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (P->ctl) (void)hipFree(P->ctl);
+  if (P->ctl_host) (void)hipHostFree(P->ctl_host);
+  if (P->sc_host) (void)hipHostFree(P->sc_host);
+  if (P->pcg_exec) (void)hipGraphExecDestroy(P->pcg_exec);
+  if (P->gstream) (void)hipStreamDestroy(P->gstream);
   for (int i = 0; i < 10; ++i)
     if (P->vec[i]) (void)hipFree(P->vec[i]);
   if (P->prof_on)
@@ -571,7 +574,8 @@ static int read_scalars(lag_plan P, double* host, int off, int cnt, hipStream_t 
 }  // extern "C"
 
 // Preconditioned CG with the Gauss-Newton operator `H` (a callable
-// H(p, Hp) -> status); device-side alpha/beta, one host sync per iteration.
+// H(p, Hp, stream) -> status); device-side alpha/beta, one host sync per
+// iteration.
 template <class Op>
 static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int32_t maxit, lag_pcg_info* info,
                     hipStream_t s) {
@@ -608,13 +612,13 @@ static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int3
       break;
     }
     if (sqrt(rr) <= tol * nb) break;
-    if ((rc = H(p, Hp))) return rc;
+    if ((rc = H(p, Hp, s))) return rc;
     loc.matvecs++;
     if ((rc = launch_dot(P, n, p, Hp, sc + 1, s))) return rc;
-    if ((rc = launch_pcg_xr(n, x, r, p, Hp, sc, s))) return rc;
+    if ((rc = launch_pcg_xr(n, x, r, p, Hp, sc, nullptr, s))) return rc;
     if ((rc = launch_precond(P, r, z, s))) return rc;
     if ((rc = launch_dot(P, n, r, z, sc + 2, s))) return rc;
-    if ((rc = launch_pcg_p(n, p, z, sc, s))) return rc;
+    if ((rc = launch_pcg_p(n, p, z, sc, nullptr, s))) return rc;
     loc.iters = it + 1;
   }
   if (status == LAG_OK) {
@@ -632,20 +636,140 @@ static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int3
   return status;
 }
 
+// Graph-captured PCG: the same iteration as pcg_impl, with the stopping test
+// on the device (k_pcg_check sets ctl[0]; every kernel of the iteration then
+// returns at entry).  `per_graph` iterations are captured into one graph,
+// built once per plan and argument set (key) and replayed; the host reads
+// the control block after each replay, i.e. once per `per_graph`
+// iterations.  The captured kernels take only the plan's buffers and the
+// pointers in `key`, so a replay is valid while those are unchanged.
+template <class Op>
+static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, const float* b, float* x,
+                          double tol, int32_t maxit, int32_t per_graph, lag_pcg_info* info, hipStream_t s) {
+  const long long n = P->n_unknowns;
+  float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
+  double* sc = P->scalars;  // as pcg_impl, plus [6] = tol^2 b.b
+  lag_pcg_info loc = {0, 0, 0, 0.0};
+  int rc;
+  if (!P->ctl) {
+    LAG_HIP(hipMalloc((void**)&P->ctl, sizeof(int) * 4));
+    LAG_HIP(hipHostMalloc((void**)&P->ctl_host, sizeof(int) * 4, hipHostMallocDefault));
+    LAG_HIP(hipHostMalloc((void**)&P->sc_host, sizeof(double) * 8, hipHostMallocDefault));
+    LAG_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+  }
+  // start: x = 0, r = b, z = M r, p = z (eager)
+  if ((rc = launch_fill(x, n, 0.f, s))) return rc;
+  if ((rc = launch_axpby(n, 1.f, b, 0.f, nullptr, r, s))) return rc;
+  if ((rc = launch_dot(P, n, b, b, sc + 5, s))) return rc;
+  hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 4, 0.0);
+  LAG_LAUNCH_CHECK();
+  LAG_HIP(hipMemcpyAsync(P->sc_host, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  const double bb = P->sc_host[5];
+  const double nb = sqrt(bb);
+  if (nb == 0.0) {
+    if (info) *info = loc;
+    return LAG_OK;
+  }
+  if ((rc = launch_precond(P, r, z, s))) return rc;
+  if ((rc = launch_dot(P, n, r, z, sc + 0, s))) return rc;
+  if ((rc = launch_axpby(n, 1.f, z, 0.f, nullptr, p, s))) return rc;
+  if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
+  hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 6, tol * tol * bb);
+  LAG_LAUNCH_CHECK();
+  if ((rc = launch_pcg_ctl_init(P->ctl, sc, maxit, s))) return rc;
+  // (re)capture when the arguments differ from the cached graph's
+  bool same = P->pcg_exec && P->pcg_key_i[0] == mode && P->pcg_key_i[1] == per_graph;
+  for (int k = 0; k < 6 && same; ++k) same = P->pcg_key[k] == key[k];
+  if (!same) {
+    if (P->pcg_exec) {
+      (void)hipGraphExecDestroy(P->pcg_exec);
+      P->pcg_exec = nullptr;
+    }
+    hipStream_t g = P->gstream;
+    LAG_HIP(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
+    P->geo.halt = P->ctl;
+    P->capturing = 1;
+    int crc = LAG_OK;
+    for (int u = 0; u < per_graph && crc == LAG_OK; ++u) {
+      if ((crc = H(p, Hp, g))) break;
+      if ((crc = launch_dot(P, n, p, Hp, sc + 1, g))) break;
+      if ((crc = launch_pcg_xr(n, x, r, p, Hp, sc, P->ctl, g))) break;
+      if ((crc = launch_precond(P, r, z, g))) break;
+      if ((crc = launch_dot(P, n, r, z, sc + 2, g))) break;
+      if ((crc = launch_pcg_p(n, p, z, sc, P->ctl, g))) break;
+      if ((crc = launch_dot(P, n, r, r, sc + 3, g))) break;
+      crc = launch_pcg_check(P->ctl, sc, g);
+    }
+    P->geo.halt = nullptr;
+    P->capturing = 0;
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(g, &graph);
+    if (crc != LAG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return crc;
+    }
+    if (ce != hipSuccess) return set_hip_error(ce);
+    const hipError_t ie = hipGraphInstantiate(&P->pcg_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      P->pcg_exec = nullptr;
+      return set_hip_error(ie);
+    }
+    for (int k = 0; k < 6; ++k) P->pcg_key[k] = key[k];
+    P->pcg_key_i[0] = mode;
+    P->pcg_key_i[1] = per_graph;
+  }
+  // replay until the device says stop (bounded by the iteration cap)
+  const int launches = (maxit + per_graph - 1) / per_graph + 1;
+  for (int l = 0; l < launches; ++l) {
+    LAG_HIP(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    LAG_HIP(hipStreamSynchronize(s));
+    if (P->ctl_host[0] != 0) break;
+    LAG_HIP(hipGraphLaunch(P->pcg_exec, s));
+  }
+  LAG_HIP(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipMemcpyAsync(P->sc_host, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  loc.iters = P->ctl_host[1];
+  loc.breakdown = P->ctl_host[0] == 2;
+  loc.matvecs = loc.iters + (loc.breakdown ? 1 : 0);
+  loc.relres = sqrt(P->sc_host[3]) / nb;
+  if (info) *info = loc;
+  return loc.breakdown ? LAG_EBREAKDOWN : LAG_OK;
+}
+
 extern "C" {
 
 int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const float* b, float* x, double tol,
             int32_t maxit, lag_pcg_info* info, void* stream) {
   LAG_CHECK(P && v && T && b && x && maxit >= 0 && tol >= 0.0);
-  auto H = [&](const float* p, float* Hp) { return gn_hessmat(P, v, T, wvox, p, Hp, stream); };
+  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat(P, v, T, wvox, p, Hp, st); };
   return pcg_impl(P, H, b, x, tol, maxit, info, S(stream));
+}
+
+int lag_pcg_graph(lag_plan P, const float* v, const float* T, const float* wvox, const float* b, float* x,
+                  double tol, int32_t maxit, int32_t iters_per_graph, lag_pcg_info* info, void* stream) {
+  LAG_CHECK(P && v && T && b && x && maxit >= 0 && tol >= 0.0 && iters_per_graph >= 1 && iters_per_graph <= 64);
+  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat(P, v, T, wvox, p, Hp, st); };
+  const void* key[6] = {v, T, wvox, b, x, nullptr};
+  return pcg_graph_impl(P, H, key, 0, b, x, tol, maxit, iters_per_graph, info, S(stream));
 }
 
 int lag_pcg_assembled(lag_plan P, const float* wvox, const float* b, float* x, double tol, int32_t maxit,
                       lag_pcg_info* info, void* stream) {
   LAG_CHECK(P && b && x && maxit >= 0 && tol >= 0.0 && P->jac_ready);
-  auto H = [&](const float* p, float* Hp) { return gn_hessmat_assembled(P, wvox, p, Hp, stream); };
+  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat_assembled(P, wvox, p, Hp, st); };
   return pcg_impl(P, H, b, x, tol, maxit, info, S(stream));
+}
+
+int lag_pcg_assembled_graph(lag_plan P, const float* wvox, const float* b, float* x, double tol, int32_t maxit,
+                            int32_t iters_per_graph, lag_pcg_info* info, void* stream) {
+  LAG_CHECK(P && b && x && maxit >= 0 && tol >= 0.0 && P->jac_ready && iters_per_graph >= 1 &&
+            iters_per_graph <= 64);
+  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat_assembled(P, wvox, p, Hp, st); };
+  const void* key[6] = {nullptr, nullptr, wvox, b, x, nullptr};
+  return pcg_graph_impl(P, H, key, 1, b, x, tol, maxit, iters_per_graph, info, S(stream));
 }
 
 void lag_gn_default_options(lag_gn_options* o) {
@@ -656,6 +780,7 @@ void lag_gn_default_options(lag_gn_options* o) {
   o->pcg_maxit = 50;
   o->armijo_c1 = 1e-4;
   o->max_halvings = 10;
+  o->graph_iters = 0;
 }
 
 int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, float* v_next,
@@ -664,7 +789,7 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
   lag_gn_options o;
   lag_gn_default_options(&o);
   if (opt) o = *opt;
-  LAG_CHECK(o.pcg_maxit >= 0 && o.max_halvings >= 0);
+  LAG_CHECK(o.pcg_maxit >= 0 && o.max_halvings >= 0 && o.graph_iters >= 0 && o.graph_iters <= 64);
   hipStream_t s = S(stream);
   const long long n = P->n_unknowns;
   float *g = P->vec[0], *rhs = P->vec[1], *dv = P->vec[2];
@@ -693,8 +818,13 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
   }
   if ((rc = launch_axpby(n, -1.f, g, 0.f, nullptr, rhs, s))) return rc;
   lag_pcg_info pi;
-  if (stored) rc = lag_pcg_assembled(P, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
-  else rc = lag_pcg(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
+  if (o.graph_iters > 0) {
+    if (stored) rc = lag_pcg_assembled_graph(P, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, o.graph_iters, &pi, stream);
+    else rc = lag_pcg_graph(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, o.graph_iters, &pi, stream);
+  } else {
+    if (stored) rc = lag_pcg_assembled(P, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
+    else rc = lag_pcg(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
+  }
   if (rc != LAG_OK && rc != LAG_EBREAKDOWN) return rc;
   loc.pcg_iters = pi.iters;
   loc.matvecs = pi.matvecs;
@@ -730,7 +860,8 @@ int lag_gn_solve(lag_plan P, const float* T, const float* R, float* v, const lag
   lag_gn_options o;
   lag_gn_default_options(&o);
   if (opt) o = *opt;
-  LAG_CHECK(o.max_gn >= 0 && o.pcg_maxit >= 0 && o.max_halvings >= 0 && o.gtol >= 0.0);
+  LAG_CHECK(o.max_gn >= 0 && o.pcg_maxit >= 0 && o.max_halvings >= 0 && o.gtol >= 0.0 && o.graph_iters >= 0 &&
+            o.graph_iters <= 64);
   hipStream_t s = S(stream);
   const long long n = P->n_unknowns;
   float *g = P->vec[0], *vn = P->vec[7], *zero = P->vec[8];

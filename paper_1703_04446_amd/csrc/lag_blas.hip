@@ -20,7 +20,9 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 __global__ void __launch_bounds__(kBlock) k_dot_partial(const float* __restrict__ x, const float* __restrict__ y,
-                                                         long long n, double* __restrict__ part) {
+                                                         long long n, double* __restrict__ part,
+                                                         const int* __restrict__ halt) {
+  if (halted(halt)) return;
   __shared__ double sh[kBlock];
   double s = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -45,7 +47,8 @@ __global__ void __launch_bounds__(kBlock) k_ssd_partial(const float* __restrict_
 }
 
 __global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__ part, int nparts, double scale,
-                                                       double* __restrict__ dst) {
+                                                       double* __restrict__ dst, const int* __restrict__ halt) {
+  if (halted(halt)) return;
   __shared__ double sh[kBlock];
   double s = 0.0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
@@ -64,9 +67,9 @@ static int reduce_launch(long long n, unsigned& blocks) {
 int launch_dot(lag_plan P, long long n, const float* x, const float* y, double* dst, hipStream_t s) {
   unsigned blocks;
   reduce_launch(n, blocks);
-  hipLaunchKernelGGL(k_dot_partial, dim3(blocks), dim3(kBlock), 0, s, x, y, n, P->red_partial);
+  hipLaunchKernelGGL(k_dot_partial, dim3(blocks), dim3(kBlock), 0, s, x, y, n, P->red_partial, P->geo.halt);
   LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, P->red_partial, (int)blocks, 1.0, dst);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, P->red_partial, (int)blocks, 1.0, dst, P->geo.halt);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
@@ -78,7 +81,7 @@ int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float sc
   hipLaunchKernelGGL(k_ssd_partial, dim3(blocks), dim3(kBlock), 0, s, u, R, wres, scale, n, P->red_partial);
   LAG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, P->red_partial, (int)blocks,
-                     0.5 * (double)P->geo.cell_img, dst);
+                     0.5 * (double)P->geo.cell_img, dst, P->geo.halt);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
@@ -112,7 +115,8 @@ int launch_combine_J(double* s3, double alpha, hipStream_t s) {
 
 __global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restrict__ x, float* __restrict__ r,
                                                     const float* __restrict__ p, const float* __restrict__ Hp,
-                                                    double* __restrict__ sc) {
+                                                    double* __restrict__ sc, const int* __restrict__ halt) {
+  if (halted(halt)) return;
   const double pHp = sc[1];
   const bool ok = pHp > 0.0;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,27 +128,67 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restric
 }
 
 __global__ void __launch_bounds__(kBlock) k_pcg_p(long long n, float* __restrict__ p, const float* __restrict__ z,
-                                                   const double* __restrict__ sc) {
+                                                   const double* __restrict__ sc, const int* __restrict__ halt) {
+  if (halted(halt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float beta = (float)(sc[2] / sc[0]);
   p[i] = fmaf(beta, p[i], z[i]);
 }
 
-__global__ void k_pcg_roll(double* sc) {
+__global__ void k_pcg_roll(double* sc, const int* __restrict__ halt) {
+  if (halted(halt)) return;
   if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = sc[2];
 }
 
-int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_xr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, x, r, p, Hp, sc);
+// Device-side PCG control for graph-captured iterations.  ctl[0] = halt
+// (0 running, 1 converged, 2 breakdown, 3 iteration cap), ctl[1] =
+// completed iterations, ctl[2] = iteration cap; sc[3] = r.r, sc[4] =
+// breakdown flag, sc[6] = tol^2 b.b.  Init evaluates the test before the
+// first iteration; check runs after each iteration.
+__global__ void k_pcg_ctl_init(int* ctl, const double* sc, int maxit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  ctl[1] = 0;
+  ctl[2] = maxit;
+  ctl[0] = sc[4] != 0.0 ? 2 : (sc[3] <= sc[6] ? 1 : (maxit <= 0 ? 3 : 0));
+}
+
+__global__ void k_pcg_check(int* ctl, const double* sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || ctl[0] != 0) return;
+  const int it = ctl[1] + 1;
+  if (sc[4] != 0.0) {     // this iteration broke down: it does not count
+    ctl[0] = 2;
+    return;
+  }
+  ctl[1] = it;
+  if (sc[3] <= sc[6]) ctl[0] = 1;
+  else if (it >= ctl[2]) ctl[0] = 3;
+}
+
+int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_ctl_init, dim3(1), dim3(64), 0, s, ctl, sc, maxit);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
 
-int launch_pcg_p(long long n, float* p, const float* z, double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_p, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, p, z, sc);
+int launch_pcg_check(int* ctl, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, s, ctl, sc);
   LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_pcg_roll, dim3(1), dim3(64), 0, s, sc);
+  return LAG_OK;
+}
+
+int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, const int* halt,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_xr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, x, r, p, Hp, sc,
+                     halt);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_pcg_p(long long n, float* p, const float* z, double* sc, const int* halt, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_p, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, p, z, sc, halt);
+  LAG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_pcg_roll, dim3(1), dim3(64), 0, s, sc, halt);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }

@@ -39,7 +39,12 @@ struct Geo {
   long long np;         // image cells = characteristics
   long long nv;         // velocity cells per field
   float cell_img;       // image cell volume h^d
+  // device flag of a graph-captured PCG loop: once non-zero, the kernels of
+  // the loop return at entry (null outside captured graphs)
+  const int* halt;
 };
+
+__device__ __forceinline__ bool halted(const int* h) { return h != nullptr && *h != 0; }
 
 // Per-call RK4 stage-time table: for stage q = 4k + s the lower node j0 and
 // the weight theta of node j0 + 1 (linear interpolation in time).

@@ -69,6 +69,16 @@ struct lag_plan_s {
   int2* cover_ent[3] = {nullptr, nullptr, nullptr};
   // status flags written by kernels (bit 0: singular RK4 step Jacobian)
   int* flags = nullptr;
+  // graph-captured PCG: device control block, pinned host mirror, capture
+  // stream and the cached executable with the arguments it was captured for
+  int* ctl = nullptr;          // device int[4]
+  int* ctl_host = nullptr;     // pinned host int[4]
+  double* sc_host = nullptr;   // pinned host double[8]
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t pcg_exec = nullptr;
+  const void* pcg_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int pcg_key_i[2] = {-1, -1};
+  int capturing = 0;
   // optional HIP-event timing of the dominant Gauss-Newton matvec kernel
   int prof_on = 0;
   int prof_n = 0;
@@ -121,13 +131,18 @@ int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float sc
                hipStream_t s);
 int launch_axpy(long long n, float a, const float* x, float* y, hipStream_t s);
 int launch_combine_J(double* s3, double alpha, hipStream_t s);
+int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, const int* halt,
+                  hipStream_t s);
+int launch_pcg_p(long long n, float* p, const float* z, double* sc, const int* halt, hipStream_t s);
+int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s);
+int launch_pcg_check(int* ctl, const double* sc, hipStream_t s);
 
 // profiling brackets around the dominant matvec kernel (no-ops unless enabled)
 inline void prof_begin(lag_plan P, hipStream_t s) {
-  if (P->prof_on && P->prof_n < 256) (void)hipEventRecord(P->prof_ev[2 * P->prof_n], s);
+  if (P->prof_on && !P->capturing && P->prof_n < 256) (void)hipEventRecord(P->prof_ev[2 * P->prof_n], s);
 }
 inline void prof_end(lag_plan P, hipStream_t s) {
-  if (P->prof_on && P->prof_n < 256) {
+  if (P->prof_on && !P->capturing && P->prof_n < 256) {
     (void)hipEventRecord(P->prof_ev[2 * P->prof_n + 1], s);
     ++P->prof_n;
   }

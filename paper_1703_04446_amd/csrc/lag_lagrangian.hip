@@ -467,7 +467,8 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
 
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_pack(const float* __restrict__ v, typename VecT<D>::T* __restrict__ out,
-                                                 long long nv, int nodes) {
+                                                 long long nv, int nodes, const int* __restrict__ halt) {
+  if (halted(halt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long tot = nv * nodes;
   if (i >= tot) return;
@@ -554,6 +555,7 @@ __global__ void __launch_bounds__(kBlock) k_jvp_cont_prep(Geo g, Stages st, cons
                                                           const typename VecT<D>::T* __restrict__ dp,
                                                           const float* __restrict__ T, int* __restrict__ base,
                                                           float* __restrict__ vals, int* __restrict__ count) {
+  if (halted(g.halt)) return;
   long long blk = xcd_block((g.np + kBlock - 1) / kBlock);
   if (blk < 0) return;
   long long p = blk * kBlock + threadIdx.x;
@@ -699,6 +701,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
                                                 const float* __restrict__ T, const float* __restrict__ w,
                                                 float* __restrict__ out, float* __restrict__ part,
                                                 int* __restrict__ flags) {
+  if (halted(g.halt)) return;
   extern __shared__ float lds[];
   long long bid = xcd_block(B.nbricks);
   if (bid < 0) return;
@@ -756,6 +759,7 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
                                                            const float* __restrict__ T, const float* __restrict__ wvox,
                                                            float* __restrict__ out, float* __restrict__ part,
                                                            int* __restrict__ flags) {
+  if (halted(g.halt)) return;
   extern __shared__ float lds[];
   long long bid = xcd_block(B.nbricks);
   if (bid < 0) return;
@@ -1059,6 +1063,7 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
                                                       const typename VecT<D>::T* __restrict__ pp,
                                                       const float* __restrict__ wvox, const float* __restrict__ wseed,
                                                       float scale, float* __restrict__ out, float* __restrict__ part) {
+  if (halted(g.halt)) return;
   extern __shared__ float lds[];
   long long bid = xcd_block(B.nbricks);
   if (bid < 0) return;
@@ -1185,6 +1190,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
                                                         const int* __restrict__ cs1, const int2* __restrict__ ce1,
                                                         const int* __restrict__ cs2, const int2* __restrict__ ce2,
                                                         float* __restrict__ out) {
+  if (halted(g.halt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nv * fields) return;
   const long long f = i / g.nv, r = i - f * g.nv;
@@ -1281,9 +1287,11 @@ int launch_pack(lag_plan P, const float* v, void* dst, hipStream_t s) {
   long long tot = P->geo.nv * P->geo.nodes;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
   if (P->geo.dim == 3)
-    hipLaunchKernelGGL(k_pack<3>, dim3(grid), dim3(kBlock), 0, s, v, (float4*)dst, P->geo.nv, P->geo.nodes);
+    hipLaunchKernelGGL(k_pack<3>, dim3(grid), dim3(kBlock), 0, s, v, (float4*)dst, P->geo.nv, P->geo.nodes,
+                       P->geo.halt);
   else
-    hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(kBlock), 0, s, v, (float2*)dst, P->geo.nv, P->geo.nodes);
+    hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(kBlock), 0, s, v, (float2*)dst, P->geo.nv, P->geo.nodes,
+                       P->geo.halt);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }

@@ -56,6 +56,7 @@ template <int D, bool CURV>
 __global__ void __launch_bounds__(kBlock) k_reg(Geo g, const float* __restrict__ p, float* __restrict__ out,
                                                 const float* __restrict__ scale, float gamma, int accumulate,
                                                 float ih2x, float ih2y, float ih2z) {
+  if (halted(g.halt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long tot = g.nv * g.nodes * D;
   if (i >= tot) return;
@@ -234,6 +235,7 @@ struct Symbol {
 template <int D, int MODE, bool IN_REAL, bool OUT_REAL>
 __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, FftLine L, Symbol sym,
                                                      const void* __restrict__ in, void* __restrict__ out) {
+  if (halted(g.halt)) return;
   extern __shared__ float2 sh[];
   const int n = L.n;
   float2* b0 = sh;
