@@ -19,6 +19,9 @@ The JSON line also carries:
                  with HIP events on its own stream inside the timed region;
   cpu_baseline - the FP64 NumPy oracle's matvec on a sample of the
                  characteristics of the same problem, scaled to matvecs/s;
+  batch        - 80 uneven 2-D/3-D transport/continuity pairs solved one
+                 after another on one stream against lag_batch_solve
+                 (worker streams, graph-replayed PCG, autotuned bricks);
   warm_start   - the second headline figure: wall time of a full
                  Gauss-Newton solve from v = 0 against the solve refined
                  from the warm-start network's prediction on 10 held-out
@@ -88,6 +91,9 @@ def parse():
     ap.add_argument("--ws-pairs", type=int, default=2000, help="warm-start training pairs")
     ap.add_argument("--ws-templates", type=int, default=50, help="distinct templates among the training pairs")
     ap.add_argument("--ws-lr", type=float, default=5e-4, help="Adam learning rate of the warm-start network")
+    ap.add_argument("--batch-pairs", type=int, default=80,
+                    help="pairs of the batched-solve measurement (64 2-D + 16 3-D at 80; 0 = skip)")
+    ap.add_argument("--batch-workers", type=int, default=6, help="worker streams of the batched solve")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -218,6 +224,96 @@ def warm_start_measurement(args, L, torch):
     }
 
 
+def batch_pairs(npairs):
+    """The batched-solve workload: pair j (seed 4000 + j); the first 80 % are
+    2-D with sides drawn from {96, 128, 192, 256}, the rest 3-D with sides
+    from {64, 80, 96}; even j transport, odd j continuity; stationary
+    velocity on the grid with half the cells per axis; N = 5, diffusion
+    alpha = 1e-2."""
+    rng = np.random.default_rng(4000)
+    n2 = (npairs * 4) // 5
+    out = []
+    for j in range(npairs):
+        if j < n2:
+            side, dim = int(rng.choice([96, 128, 192, 256])), 2
+        else:
+            side, dim = int(rng.choice([64, 80, 96])), 3
+        model = "transport" if j % 2 == 0 else "continuity"
+        out.append((dim, (side,) * dim, (side // 2,) * dim, model, 4000 + j))
+    return out
+
+
+def batch_measurement(args, L, torch):
+    """Wall time of solving the batch one pair after another (one stream,
+    host-driven PCG, one plan per distinct problem) against lag_batch_solve
+    (worker streams, PCG replayed as captured graphs, autotuned bricks)."""
+    from synthetic import blob_image, fourier_velocity
+    specs = batch_pairs(args.batch_pairs)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()  # noqa: E731
+    probs, Ts, Rs = [], [], []
+    for dim, img, vel, model, seed in specs:
+        prob = L.make_problem(dim, img, vel, model=model, nsteps=5, alpha=1e-2,
+                              jac_blocks=8 if model == "transport" else 0)
+        plan = L.Plan(prob)
+        T = dev(blob_image(img, 8 if dim == 2 else 24, seed, density=(model == "continuity")))
+        phi = torch.empty(dim * plan.n_points, device="cuda")
+        R = torch.empty(plan.n_points, device="cuda")
+        L.lag_trace(plan, dev(fourier_velocity(vel, 4, 0.05, seed + 1)), -1 if model == "transport" else 1, phi)
+        (L.lag_transport if model == "transport" else L.lag_pushforward)(plan, T, phi, R)
+        plan.close()
+        probs.append(prob), Ts.append(T), Rs.append(R)
+    opts = L.lag_gn_default_options()
+    opts.pcg_maxit, opts.max_gn = 30, 20
+    # sequential reference (plans cached per distinct problem, created before timing)
+    plans, key = {}, lambda p: bytes(p)  # noqa: E731
+    for p in probs:
+        if key(p) not in plans:
+            plans[key(p)] = L.Plan(p)
+    vs = [torch.zeros(plans[key(p)].n_unknowns, device="cuda") for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [L.lag_gn_solve(plans[key(p)], T, R, v, opts) for p, T, R, v in zip(probs, Ts, Rs, vs)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for pl in plans.values():
+        pl.close()
+    # autotuning (one-time cost per distinct problem), then the batch
+    t0 = time.perf_counter()
+    kinds = {}
+    for p in probs:
+        if key(p) not in kinds:
+            kinds[key(p)] = L.lag_autotune_bricks(p)
+    t_tune = time.perf_counter() - t0
+    bo = L.lag_gn_default_options()
+    bo.pcg_maxit, bo.max_gn, bo.graph_iters = 30, 20, 4
+    vb = [torch.zeros_like(v) for v in vs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, st = L.lag_batch_solve(probs, Ts, Rs, vb, bo, workers=args.batch_workers,
+                                  bricks=[kinds[key(p)][0] for p in probs])
+    torch.cuda.synchronize()
+    t_batch_net = time.perf_counter() - t0
+    t_batch = t_batch_net + t_tune
+    n2 = sum(1 for s_ in specs if s_[0] == 2)
+    log(args, f"batch: {len(specs)} pairs, sequential {t_seq:.2f} s, batched {t_batch:.2f} s "
+              f"(incl. {t_tune:.2f} s autotuning)")
+    return {
+        "metric": "batched Gauss-Newton solves of uneven pairs, pairs/s",
+        "pairs": len(specs), "pairs_2d": n2, "pairs_3d": len(specs) - n2,
+        "sequential_s": round(t_seq, 3), "batched_s": round(t_batch_net, 3), "autotune_s": round(t_tune, 3),
+        "sequential_pairs_per_s": round(len(specs) / t_seq, 2),
+        "batched_pairs_per_s": round(len(specs) / t_batch_net, 2),
+        "speedup": round(t_seq / t_batch_net, 3),
+        "workers": args.batch_workers, "graph_iters": 4,
+        "converged_sequential": int(sum(i["converged"] for i in seq)),
+        "converged_batched": int(sum(i["converged"] for i in infos)),
+        "gn_iters_sequential": int(sum(i["iters"] for i in seq)),
+        "gn_iters_batched": int(sum(i["iters"] for i in infos)),
+        "bricks": {f"{p.dim}d {list(p.img_m)[:p.dim]} {'transport' if p.model == 0 else 'continuity'}": kinds[key(p)][0]
+                   for p in probs},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -331,6 +427,8 @@ def main():
         "cpu_baseline": None,
     }
     plan.close()
+    if args.batch_pairs > 0:
+        res["batch"] = batch_measurement(args, L, torch)
     if args.warm_start_steps > 0:
         res["warm_start"] = warm_start_measurement(args, L, torch)
     if args.cpu_sample > 0:

@@ -106,6 +106,13 @@ const char* lag_last_hip_error(void);
  * allocating call; it synchronises the device.  *out receives the plan. */
 int lag_plan_create(const lag_problem* prob, lag_plan* out);
 
+/* lag_plan_create with a chosen brick shape: brick_target[a] image cells per
+ * brick along axis a (a < dim; 1..1024; NULL = the default 16 x 16 x 8 in
+ * 3-D, 16 x 16 in 2-D).  The shape is rounded to whole wave lattices and
+ * shrunk until the LDS tile fits 64 KB, as for the default.  Bricks change
+ * only the order of floating-point sums: results agree to rounding. */
+int lag_plan_create_tuned(const lag_problem* prob, const int32_t* brick_target, lag_plan* out);
+
 /* Release a plan and its workspace (synchronises the device).  NULL is OK. */
 int lag_plan_destroy(lag_plan plan);
 
@@ -370,6 +377,39 @@ int lag_resample_to_velocity_grid(lag_plan plan, const float* f, float* out, voi
  * the finest level's line search fails. */
 int lag_multilevel_solve(const lag_problem* finest, int32_t levels, const float* T, const float* R,
                          float* v, const lag_gn_options* opt, lag_gn_info* infos, void* stream);
+
+/* ---- many problems at once -------------------------------------------------
+ * For batches of independent registrations of uneven sizes (2-D and 3-D,
+ * transport and continuity): a brick-shape autotuner and a batched driver.
+ * Not in the paper; for callers with many small problems, where a single
+ * solve cannot fill the GPU. */
+
+/* Time the Gauss-Newton matvec of `prob` (assembled when prob->jac_blocks >
+ * 0 and the model is transport, matrix-free otherwise) at a smooth synthetic
+ * velocity with about two cells of displacement, for a fixed list of brick
+ * shapes (3-D: 16x16x8, 8x16x8, 16x16x16, 8x8x8, 32x16x8, 16x8x8; 2-D: 16x16,
+ * 32x16, 32x32, 64x32, 16x8, 64x64), and return the fastest shape in
+ * best_target[3] (for lag_plan_create_tuned) and its time per matvec in
+ * *best_ms (may be NULL).  Allocating (one plan per shape, freed) and
+ * synchronising `stream`. */
+int lag_autotune_bricks(const lag_problem* prob, int32_t* best_target, double* best_ms, void* stream);
+
+/* Solve npairs independent problems: pair i is (probs[i], T[i], R[i]) with v[i]
+ * the start value and the solution (device pointers of each problem's
+ * sizes).  `workers` (1..16) host threads, each with its own HIP stream and a
+ * plan per distinct problem, take pairs largest first and run lag_gn_solve
+ * with `opt` (graph_iters > 0 keeps the PCG loops on the device).  Brick
+ * shapes: `bricks` (host, npairs x 3, e.g. from lag_autotune_bricks; the
+ * first pair of each distinct problem decides) or, if NULL and `autotune`
+ * is non-zero, lag_autotune_bricks per distinct problem, else the default.
+ * infos (host array of npairs, may be NULL) and status (host array of
+ * npairs) receive each solve's info and return code.  Allocating and
+ * synchronising; returns the first status that is neither LAG_OK nor
+ * LAG_ELINESEARCH, else LAG_OK.  The T, R, v buffers of different pairs must
+ * not overlap. */
+int lag_batch_solve(int32_t npairs, const lag_problem* probs, const float* const* T, const float* const* R,
+                    float* const* v, const lag_gn_options* opt, int32_t workers, const int32_t* bricks,
+                    int32_t autotune, lag_gn_info* infos, int32_t* status);
 
 /* ---- learned warm start: a 3-D U-Net on the MFMA units --------------------
  * Maps the template and reference, resampled to a cubic grid of side `size`

@@ -18,6 +18,7 @@ from ._lib import (  # noqa: F401
     lag_jacobian_assemble, gn_hessmat_assembled, lag_vjp_assembled, lag_gradient_assembled,
     lag_pcg_assembled, lag_pcg_graph, lag_pcg_assembled_graph, lag_gn_step, lag_jacobian_info, lag_restrict_image, lag_prolong_velocity,
     lag_multilevel_solve, lag_resample_to_velocity_grid,
+    lag_autotune_bricks, lag_batch_solve,
     LagCnnConfig, Cnn, lag_cnn_default_config, lag_cnn_create, lag_cnn_destroy, lag_cnn_get_params,
     lag_cnn_set_params, lag_cnn_get_grads, lag_cnn_forward, lag_cnn_backward, lag_cnn_adam_step,
 )

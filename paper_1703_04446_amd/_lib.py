@@ -91,6 +91,13 @@ _SIGS = {
     "lag_strerror": (ctypes.c_char_p, [_I]),
     "lag_last_hip_error": (ctypes.c_char_p, []),
     "lag_plan_create": (_I, [ctypes.POINTER(LagProblem), ctypes.POINTER(_P)]),
+    "lag_plan_create_tuned": (_I, [ctypes.POINTER(LagProblem), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_P)]),
+    "lag_autotune_bricks": (_I, [ctypes.POINTER(LagProblem), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double), _P]),
+    "lag_batch_solve": (_I, [ctypes.c_int32, ctypes.POINTER(LagProblem), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                             ctypes.POINTER(_P), ctypes.POINTER(LagGnOptions), ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(LagGnInfo),
+                             ctypes.POINTER(ctypes.c_int32)]),
     "lag_plan_destroy": (_I, [_P]),
     "lag_plan_problem": (_I, [_P, ctypes.POINTER(LagProblem)]),
     "lag_profile_enable": (_I, [_P, ctypes.c_int32]),
@@ -236,13 +243,19 @@ def _ptr(t, n=None, name="tensor", f64=False):
 
 
 class Plan:
-    """Owns a ``lag_plan``; sizes are read from the problem."""
+    """Owns a ``lag_plan``; sizes are read from the problem.  ``bricks``
+    (image cells per brick per axis, e.g. from lag_autotune_bricks) selects
+    lag_plan_create_tuned."""
 
-    def __init__(self, prob: LagProblem):
+    def __init__(self, prob: LagProblem, bricks=None):
         self.prob = prob
         self.n_points, self.n_unknowns = lag_problem_sizes(prob)
         h = ctypes.c_void_p()
-        _check("lag_plan_create", load().lag_plan_create(ctypes.byref(prob), ctypes.byref(h)))
+        if bricks is None:
+            _check("lag_plan_create", load().lag_plan_create(ctypes.byref(prob), ctypes.byref(h)))
+        else:
+            b = (ctypes.c_int32 * 3)(*[int(x) for x in (list(bricks) + [1, 1, 1])[:3]])
+            _check("lag_plan_create_tuned", load().lag_plan_create_tuned(ctypes.byref(prob), b, ctypes.byref(h)))
         self.handle = h
 
     def close(self):
@@ -581,3 +594,50 @@ def lag_cnn_backward(net, T, R, target, v, loss):
 def lag_cnn_adam_step(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     _check("lag_cnn_adam_step", load().lag_cnn_adam_step(net.handle, float(lr), float(beta1), float(beta2),
                                                          float(eps), _stream()))
+
+
+# ---- many problems at once -------------------------------------------------
+
+def lag_autotune_bricks(prob):
+    """(best brick target (3 ints), milliseconds per Gauss-Newton matvec)."""
+    b = (ctypes.c_int32 * 3)()
+    ms = ctypes.c_double()
+    _check("lag_autotune_bricks", load().lag_autotune_bricks(ctypes.byref(prob), b, ctypes.byref(ms), _stream()))
+    return [b[0], b[1], b[2]], ms.value
+
+
+def lag_batch_solve(probs, Ts, Rs, vs, options=None, workers=4, autotune=True, bricks=None):
+    """Solve len(probs) independent problems; returns (infos, statuses).
+    ``bricks``: per pair a 3-list of brick targets (overrides autotune)."""
+    n = len(probs)
+    if not (len(Ts) == len(Rs) == len(vs) == n):
+        raise ValueError("probs, Ts, Rs and vs must have the same length")
+    arr = (LagProblem * n)(*probs)
+    ptrs = []
+    for i in range(n):
+        npnt, nu = lag_problem_sizes(probs[i])
+        ptrs.append((_ptr(Ts[i], npnt, f"T[{i}]"), _ptr(Rs[i], npnt, f"R[{i}]"), _ptr(vs[i], nu, f"v[{i}]")))
+    T = (ctypes.c_void_p * n)(*[p[0] for p in ptrs])
+    R = (ctypes.c_void_p * n)(*[p[1] for p in ptrs])
+    V = (ctypes.c_void_p * n)(*[p[2] for p in ptrs])
+    o = options if options is not None else lag_gn_default_options()
+    infos = (LagGnInfo * n)()
+    st = (ctypes.c_int32 * n)()
+    import torch
+    torch.cuda.synchronize()       # inputs written on torch's stream are visible to the workers' streams
+    bp = None
+    if bricks is not None:
+        flat = [int(x) for b in bricks for x in (list(b) + [1, 1, 1])[:3]]
+        if len(flat) != 3 * n:
+            raise ValueError("bricks: one 3-list per pair")
+        bp = (ctypes.c_int32 * (3 * n))(*flat)
+    rc = load().lag_batch_solve(n, arr, T, R, V, ctypes.byref(o), int(workers), bp, int(bool(autotune)), infos,
+                                st)
+    if rc not in (LAG_OK, LAG_ELINESEARCH):
+        _check("lag_batch_solve", rc)
+    out = []
+    for i in range(n):
+        d = {f: getattr(infos[i], f) for f, _ in LagGnInfo._fields_}
+        d["converged"] = bool(d["converged"])
+        out.append(d)
+    return out, list(st)

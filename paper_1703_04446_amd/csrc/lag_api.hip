@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "lag_internal.hpp"
@@ -15,20 +16,32 @@ namespace lag {
 
 static thread_local std::string g_hip_error;
 
+// Serialises the calls that must not overlap a stream capture on another
+// thread: plan creation and destruction (allocations, synchronous copies)
+// and the capture and instantiation of a graph.
+std::mutex& api_lock() {
+  static std::mutex m;
+  return m;
+}
+
 int set_hip_error(hipError_t e) {
   g_hip_error = hipGetErrorString(e);
   return LAG_EHIP;
 }
 
+void set_hip_error_text(const char* msg) { g_hip_error = msg ? msg : ""; }
+
 int launch_scale_mul(long long n, float c, const float* a, const float* w, float* out, hipStream_t s);
 int launch_axpby(long long n, float a, const float* x, float b, const float* y, float* out, hipStream_t s);
 
 // Lanes of one wave sit on a 4x4x4 (3-D) or 8x8 (2-D) lattice.
-static void choose_bricks(lag_plan P) {
+static void choose_bricks(lag_plan P, const int32_t* want) {
   const int D = P->geo.dim;
   lag::Bricks& B = P->bricks;
   const int lane[3] = {D == 3 ? 4 : 8, D == 3 ? 4 : 8, D == 3 ? 4 : 1};
-  const int target[3] = {16, 16, D == 3 ? 8 : 1};
+  int target[3] = {16, 16, D == 3 ? 8 : 1};
+  if (want)
+    for (int a = 0; a < D; ++a) target[a] = want[a];
   const size_t budget = 64 * 1024;
   int halo = D == 3 ? 3 : 4;
   int nreg[3];
@@ -230,9 +243,20 @@ int lag_problem_sizes(const lag_problem* p, int64_t* n_points, int64_t* n_unknow
     }                                                             \
   } while (0)
 
-int lag_plan_create(const lag_problem* prob, lag_plan* out) {
+int lag_plan_create(const lag_problem* prob, lag_plan* out) { return lag_plan_create_tuned(prob, nullptr, out); }
+
+static int plan_create_locked(const lag_problem* prob, const int32_t* brick_target, lag_plan* out);
+
+int lag_plan_create_tuned(const lag_problem* prob, const int32_t* brick_target, lag_plan* out) {
+  std::lock_guard<std::mutex> lk(api_lock());
+  return plan_create_locked(prob, brick_target, out);
+}
+
+static int plan_create_locked(const lag_problem* prob, const int32_t* brick_target, lag_plan* out) {
   LAG_CHECK(out);
   *out = nullptr;
+  if (brick_target && prob)
+    for (int a = 0; a < prob->dim && a < 3; ++a) LAG_CHECK(brick_target[a] >= 1 && brick_target[a] <= 1024);
   int rc = lag_problem_check(prob);
   if (rc) return rc;
   lag_plan P = new lag_plan_s();
@@ -263,7 +287,7 @@ int lag_plan_create(const lag_problem* prob, lag_plan* out) {
   g.cell_img = (float)cell;
   P->fields = g.nodes * D;
   P->n_unknowns = (long long)P->fields * g.nv;
-  choose_bricks(P);
+  choose_bricks(P, brick_target);
 
   // time-node quadrature weights (trapezoid; 1 for a stationary field)
   const int nt = g.nodes - 1;
@@ -353,6 +377,7 @@ int lag_plan_create(const lag_problem* prob, lag_plan* out) {
 
 int lag_plan_destroy(lag_plan plan) {
   if (!plan) return LAG_OK;
+  std::lock_guard<std::mutex> lk(api_lock());   // no capture runs while the device synchronises
   (void)hipDeviceSynchronize();
   lag::free_plan(plan);
   return LAG_OK;
@@ -652,6 +677,7 @@ static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, 
   lag_pcg_info loc = {0, 0, 0, 0.0};
   int rc;
   if (!P->ctl) {
+    std::lock_guard<std::mutex> lk(api_lock());
     LAG_HIP(hipMalloc((void**)&P->ctl, sizeof(int) * 4));
     LAG_HIP(hipHostMalloc((void**)&P->ctl_host, sizeof(int) * 4, hipHostMallocDefault));
     LAG_HIP(hipHostMalloc((void**)&P->sc_host, sizeof(double) * 8, hipHostMallocDefault));
@@ -682,6 +708,7 @@ static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, 
   bool same = P->pcg_exec && P->pcg_key_i[0] == mode && P->pcg_key_i[1] == per_graph;
   for (int k = 0; k < 6 && same; ++k) same = P->pcg_key[k] == key[k];
   if (!same) {
+    std::lock_guard<std::mutex> lk(api_lock());
     if (P->pcg_exec) {
       (void)hipGraphExecDestroy(P->pcg_exec);
       P->pcg_exec = nullptr;

@@ -90,6 +90,7 @@ namespace lag {
 constexpr int kRedBlocks = 1024;
 
 int set_hip_error(hipError_t e);   // records the message, returns LAG_EHIP
+void set_hip_error_text(const char* msg);  // records a message from another thread
 #define LAG_HIP(call)                                    \
   do {                                                   \
     hipError_t _e = (call);                              \

@@ -1,0 +1,131 @@
+"""Batched solves of uneven 2-D/3-D transport/continuity pairs and the
+brick-shape autotuner.
+
+Per pair, the batch must honour the solve's contract: a pair reported as
+converged meets |g| <= gtol |g(v = 0)|, and the oracle's objective at the
+batch's solution equals the GPU's (iterate-wise parity, 1e-5).  Transport
+pairs use the assembled operator, which is deterministic: without
+autotuning they reproduce the sequential solve (same iterations, same
+solution to 1e-6); with autotuned bricks only the order of sums changes
+(objective to 1e-4).  The matrix-free continuity solves sum with float
+atomics and their Gauss-Newton path is not reproducible from run to run
+(measured: 6, 12 and 18 iterations for one pair), so for them only the
+contract is checked.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from cases import relerr
+from synthetic import blob_image, fourier_velocity
+
+pytestmark = pytest.mark.gpu
+
+PAIRS = [  # (img_m, vel_m, model, seed)
+    ((48, 48), (24, 24), "transport", 11000),
+    ((64, 40), (32, 20), "continuity", 11100),
+    ((24, 20, 16), (12, 10, 8), "transport", 11200),
+    ((20, 16, 12), (10, 8, 6), "continuity", 11300),
+    ((64, 64), (32, 32), "transport", 11400),
+    ((48, 48), (24, 24), "transport", 11500),
+    ((32, 24, 20), (16, 12, 10), "transport", 11600),
+]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1703_04446_amd as _L
+    _L.load()
+    return _L
+
+
+def make_pair(torch, L, img, vel, model, seed):
+    dim = len(img)
+    prob = L.make_problem(dim, img, vel, model=model, nsteps=4, alpha=1e-2,
+                          jac_blocks=8 if model == "transport" else 0)
+    T = blob_image(img, 6, seed, density=(model == "continuity")).astype(np.float32).ravel()
+    vt = fourier_velocity(vel, 3, 0.06, seed + 1).astype(np.float32).ravel()
+    plan = L.Plan(prob)
+    dT, dv = torch.from_numpy(T).cuda(), torch.from_numpy(vt).cuda()
+    phi = torch.empty(dim * plan.n_points, device="cuda")
+    R = torch.empty(plan.n_points, device="cuda")
+    if model == "transport":
+        L.lag_trace(plan, dv, -1, phi)
+        L.lag_transport(plan, dT, phi, R)
+    else:
+        L.lag_trace(plan, dv, 1, phi)
+        L.lag_pushforward(plan, dT, phi, R)
+    plan.close()
+    return prob, dT, R
+
+
+def sequential(torch, L, pairs, opts):
+    out = []
+    for prob, T, R in pairs:
+        plan = L.Plan(prob)
+        v = torch.zeros(plan.n_unknowns, device="cuda")
+        info = L.lag_gn_solve(plan, T, R, v, opts)
+        out.append((info, v))
+        plan.close()
+    return out
+
+
+def oracle_J(spec, T, R, v):
+    img, vel, model, _ = spec
+    OP = O.Problem(dim=len(img), img_m=img, vel_m=vel, model=model, nsteps=4, alpha=1e-2)
+    return O.objective(OP, v.cpu().numpy().astype(np.float64), T.cpu().numpy().astype(np.float64),
+                       R.cpu().numpy().astype(np.float64))["J"]
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_solve(autotune, torch, L):
+    pairs = [make_pair(torch, L, *p) for p in PAIRS]
+    opts = L.lag_gn_default_options()
+    opts.pcg_maxit, opts.max_gn = 30, 20
+    seq = sequential(torch, L, pairs, opts)
+    bo = L.lag_gn_default_options()
+    bo.pcg_maxit, bo.max_gn, bo.graph_iters = 30, 20, 4
+    vs = [torch.zeros_like(v) for _, v in seq]
+    infos, st = L.lag_batch_solve([p[0] for p in pairs], [p[1] for p in pairs], [p[2] for p in pairs], vs,
+                                  bo, workers=3, autotune=autotune)
+    assert all(x in (L.LAG_OK, L.LAG_ELINESEARCH) for x in st), st
+    for spec, (prob, T, R), (i1, v1), ib, vb in zip(PAIRS, pairs, seq, infos, vs):
+        Jo = oracle_J(spec, T, R, vb)
+        e = relerr(vb.cpu().numpy(), v1.cpu().numpy())
+        print(spec, "seq", i1["iters"], "%.6e" % i1["J"], "batch", ib["iters"], "%.6e" % ib["J"], f"dv {e:.2e}",
+              flush=True)
+        if ib["converged"]:
+            assert ib["gnorm"] <= bo.gtol * ib["g0"] * (1 + 1e-12)
+        assert abs(Jo - ib["J"]) <= 1e-5 * abs(Jo)
+        if spec[2] == "transport":
+            assert ib["converged"] == i1["converged"]
+            if autotune:
+                assert abs(ib["J"] - i1["J"]) <= 1e-4 * abs(i1["J"])
+            else:
+                assert ib["iters"] == i1["iters"] and e <= 1e-6
+
+
+def test_autotuned_plan_matches_default(torch, L):
+    prob, T, R = make_pair(torch, L, (32, 24, 20), (16, 12, 10), "transport", 12000)
+    best, ms = L.lag_autotune_bricks(prob)
+    print("best bricks", best, ms, flush=True)
+    assert ms > 0 and best in ([16, 16, 8], [8, 16, 8], [16, 16, 16], [8, 8, 8], [32, 16, 8], [16, 8, 8])
+    v = torch.from_numpy(fourier_velocity((16, 12, 10), 3, 0.06, 12001).astype(np.float32).ravel()).cuda()
+    p = torch.from_numpy(np.random.default_rng(1).standard_normal(v.numel()).astype(np.float32)).cuda()
+    out = []
+    for bricks in (None, best):
+        plan = L.Plan(prob, bricks=bricks)
+        Hp = torch.empty_like(p)
+        L.gn_hessmat(plan, v, T, None, p, Hp)
+        out.append(Hp.cpu().numpy())
+        plan.close()
+    assert relerr(out[1], out[0]) < 1e-5
