@@ -101,12 +101,17 @@ def test_matrix_free_graph_pcg(case, torch, L):
     T, v = f32(case.template()), f32(case.velocity())
     b = rhs(case, OP, T, v, 3)
     dv, dT, db = dev.put(v), dev.put(T), dev.put(b)
-    xe, xe2 = dev.empty(plan.n_unknowns), dev.empty(plan.n_unknowns)
+    xe = dev.empty(plan.n_unknowns)
     ie = L.lag_pcg(plan, dv, dT, None, db, xe, tol=0.1, maxit=30)
-    L.lag_pcg(plan, dv, dT, None, db, xe2, tol=0.1, maxit=30)
     # float atomics make the matrix-free operator vary from run to run; the
-    # graph must add nothing beyond that variation (or the 1e-5 bar)
-    bar = max(1e-5, 10 * relerr(dev.get(xe2), dev.get(xe)))
+    # graph must add nothing beyond that variation (largest deviation of
+    # three eager reruns from the first run, times ten) or the 1e-5 bar
+    noise = 0.0
+    for _ in range(3):
+        xr = dev.empty(plan.n_unknowns)
+        L.lag_pcg(plan, dv, dT, None, db, xr, tol=0.1, maxit=30)
+        noise = max(noise, relerr(dev.get(xr), dev.get(xe)))
+    bar = max(1e-5, 10 * noise)
     for rep in range(2):
         xg = dev.empty(plan.n_unknowns)
         ig = L.lag_pcg_graph(plan, dv, dT, None, db, xg, tol=0.1, maxit=30, iters_per_graph=3)
