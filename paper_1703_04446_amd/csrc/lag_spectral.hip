@@ -143,10 +143,11 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-LDS Stockham FFT of `lines` lines of length n (buffers [lines][n]).
-// Returns the buffer holding the result.  INV selects exp(+2 pi i ...).
+// In-LDS Stockham FFT of `lines` lines of length n (buffers [lines][ls],
+// line stride ls >= n).  Returns the buffer holding the result.  INV selects
+// exp(+2 pi i ...).
 template <bool INV>
-__device__ float2* lds_fft(const FftLine& L, int lines, float2* b0, float2* b1) {
+__device__ float2* lds_fft(const FftLine& L, int lines, int ls, float2* b0, float2* b1) {
   const int n = L.n;
   int Ns = 1;
   for (int st = 0; st < L.nrad; ++st) {
@@ -156,8 +157,8 @@ __device__ float2* lds_fft(const FftLine& L, int lines, float2* b0, float2* b1) 
     const int step = n / R;             // small-DFT root stride
     for (int b = threadIdx.x; b < lines * nb; b += blockDim.x) {
       const int line = b / nb, j = b - (b / nb) * nb;
-      const float2* src = b0 + line * n;
-      float2* dst = b1 + line * n;
+      const float2* src = b0 + line * ls;
+      float2* dst = b1 + line * ls;
       const int k = j % Ns;
       float2 v[5];
 #pragma unroll
@@ -238,8 +239,9 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
   if (halted(g.halt)) return;
   extern __shared__ float2 sh[];
   const int n = L.n;
+  const int ls = n | 1;     // odd line stride: the y and z passes write across lines without bank conflicts
   float2* b0 = sh;
-  float2* b1 = sh + lpb * n;
+  float2* b1 = sh + lpb * ls;
   const int m0 = g.mv[0], m1 = g.mv[1], m2 = D == 3 ? g.mv[2] : 1;
   const int fields = g.nodes * D;
   // group decomposition
@@ -279,21 +281,30 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
     lstride = 1;
     c1 = axis == 1 ? 0 : c1;
   }
-  // load (lines contiguous in x for axes 1, 2 -> coalesced)
+  // load: for the x pass consecutive threads walk along a line, for the y
+  // and z passes across lines (neighbouring x columns); both are contiguous
+  const bool along = lstride != 1;
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    int i = e / nlines, l = e - (e / nlines) * nlines;
+    int i, l;
+    if (along) {
+      l = e / n;
+      i = e - l * n;
+    } else {
+      i = e / nlines;
+      l = e - i * nlines;
+    }
     long long a = base + (long long)l * lstride + (long long)i * estride;
     float2 v;
     if (IN_REAL) v = make_float2(((const float*)in)[a], 0.f);
     else v = ((const float2*)in)[a];
-    b0[l * n + i] = v;
+    b0[l * ls + i] = v;
   }
   __syncthreads();
   float2* res;
   if (MODE == 1) {
-    res = lds_fft<true>(L, nlines, b0, b1);
+    res = lds_fft<true>(L, nlines, ls, b0, b1);
   } else {
-    res = lds_fft<false>(L, nlines, b0, b1);
+    res = lds_fft<false>(L, nlines, ls, b0, b1);
   }
   if (MODE == 2) {
     // divide by the symbol; the fused axis is the last one
@@ -319,16 +330,23 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
       float mu = fmaf(sym.scale[j], lam, sym.gamma);
       if (mu == 0.f) mu = sym.mu1[j];
       float inv = 1.f / (mu * sym.nv);
-      float2 v = res[e];
-      res[e] = make_float2(v.x * inv, v.y * inv);
+      float2 v = res[l * ls + i];
+      res[l * ls + i] = make_float2(v.x * inv, v.y * inv);
     }
     __syncthreads();
-    res = lds_fft<true>(L, nlines, res, other);
+    res = lds_fft<true>(L, nlines, ls, res, other);
   }
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    int i = e / nlines, l = e - (e / nlines) * nlines;
+    int i, l;
+    if (along) {
+      l = e / n;
+      i = e - l * n;
+    } else {
+      i = e / nlines;
+      l = e - i * nlines;
+    }
     long long a = base + (long long)l * lstride + (long long)i * estride;
-    float2 v = res[l * n + i];
+    float2 v = res[l * ls + i];
     if (OUT_REAL) ((float*)out)[a] = v.x;
     else ((float2*)out)[a] = v;
   }
@@ -391,10 +409,13 @@ int precond_setup(lag_plan P) {
   return LAG_OK;
 }
 
+// About 1024 elements (4 per thread) and at most 16 lines per block, so that
+// a 64^3 field splits into enough blocks to fill the chip; the lines of the
+// y and z passes are neighbouring x columns, read as runs of lpb values.
 static int lines_per_block(int n, int axis, int m0) {
-  int lpb = 2048 / n;
+  int lpb = 1024 / n;
   if (lpb < 1) lpb = 1;
-  if (lpb > 32) lpb = 32;
+  if (lpb > 16) lpb = 16;
   if (axis != 0 && lpb > m0) lpb = m0;
   return lpb;
 }
@@ -423,7 +444,7 @@ static int fft_pass(lag_plan P, int axis, const void* in, void* out, hipStream_t
     long long xg = (m0 + lpb - 1) / lpb;
     groups = xg * (axis == 1 ? m2 : m1) * P->fields;
   }
-  size_t lds = sizeof(float2) * 2 * (size_t)lpb * L.n;
+  size_t lds = sizeof(float2) * 2 * (size_t)lpb * (L.n | 1);
   hipLaunchKernelGGL((k_fft_axis<D, MODE, IR, OR>), dim3((unsigned)groups), dim3(kBlock), lds, s, P->geo, axis, lpb,
                      L, sym, in, out);
   LAG_LAUNCH_CHECK();
