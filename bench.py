@@ -74,8 +74,8 @@ def measured_traffic(workload_name):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="3d128_transport")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="characteristics in the oracle's timed sample (0 = skip the CPU baseline)")
@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--batch-pairs", type=int, default=80,
                     help="pairs of the batched-solve measurement (64 2-D + 16 3-D at 80; 0 = skip)")
     ap.add_argument("--batch-workers", type=int, default=6, help="worker streams of the batched solve")
+    ap.add_argument("--graph-iters", type=int, default=0,
+                    help="PCG iterations per replayed graph inside the timed steps (0 = host-driven PCG)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -359,6 +361,7 @@ def main():
     v_next = torch.empty_like(v)
     opts = L.lag_gn_default_options()
     opts.pcg_tol, opts.pcg_maxit = w.pcg_tol, w.pcg_maxit
+    opts.graph_iters = args.graph_iters
 
     def gn_iteration():
         return L.lag_gn_step(plan, Td, Rd, v, v_next, opts)
@@ -384,26 +387,30 @@ def main():
     log(args, f"timed {args.steps} steps in {dt:.3f} s, {matvecs} matvecs, pcg iters {iters}; "
               f"matvec kernel {kern_ms / max(kern_n, 1):.3f} ms avg over {kern_n} launches")
 
-    # roofline of the dominant kernel
-    kern_avg_s = kern_ms / max(kern_n, 1) / 1e3
+    # roofline of the dominant kernel (its launches are timed individually
+    # only when PCG is host-driven; graph replays carry no per-kernel events)
+    kern_avg_s = kern_ms / max(kern_n, 1) / 1e3 if kern_n > 0 else float("nan")
     if all(assembled):
         # assembled matvec: algorithmic bytes = stored Jacobian blocks + one
         # count byte per row slot + p read + Hp written (4 B per unknown each)
         blocks, kmax_seen, bpb = L.lag_jacobian_info(plan)
         alg_bytes = blocks * bpb + n + 2 * 4 * nu
         achieved = alg_bytes / kern_avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": f"k_jac_apply<{w.dim}>", "achieved": round(achieved, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+        roof = {"bound": "hbm", "kernel": f"k_jac_apply<{w.dim}>",
+                "achieved": round(achieved, 1) if kern_n > 0 else None,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4) if kern_n > 0 else None,
                 "traffic": measured_traffic(w.name), "alg_bytes_per_launch": int(alg_bytes),
                 "jac_blocks": int(blocks),
                 "blocks_per_row_max": kmax_seen}
     else:
         flops = n * (w.nsteps * FLOP_PER_CHAR_STEP_3D + FLOP_PER_CHAR_END_3D)
         achieved = flops / kern_avg_s / 1e12
-        roof = {"bound": "alu", "kernel": f"k_hess_transport<{w.dim},false>", "achieved": round(achieved, 3),
+        roof = {"bound": "alu", "kernel": f"k_hess_transport<{w.dim},false>",
+                "achieved": round(achieved, 3) if kern_n > 0 else None,
                 "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None}
-    roof["kernel_ms"] = round(kern_avg_s * 1e3, 4)
+                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4) if kern_n > 0 else None, "traffic": None}
+    roof["kernel_ms"] = round(kern_avg_s * 1e3, 4) if kern_n > 0 else None
     roof["launches_timed"] = kern_n
     res = {
         "metric": "GN Hessian matvecs/s at 128^3",
@@ -423,6 +430,7 @@ def main():
                    "iterate": "v_true/2", "pcg_tol": w.pcg_tol, "pcg_maxit": w.pcg_maxit},
         "matvecs_per_step": matvecs / args.steps,
         "assembled_jacobian": bool(all(assembled)),
+        "pcg_graph_iters": args.graph_iters,
         "roofline": roof,
         "cpu_baseline": None,
     }
