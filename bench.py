@@ -53,10 +53,10 @@ PEAK_HBM_GBS = 8000.0
 # measured on: reported as null once that file changes.
 MEASURED_TRAFFIC = {
     "source": "paper_1703_04446_amd/csrc/lag_lagrangian.hip",
-    "sha256": "919858b1ec06ebc11bc328c6a8486b06bc2b6fa30ca10cb6691548bed2addab6",
+    "sha256": "597d3bbb97f8c54edecef081713938468e8567c914faf47ca81eb6c2f0569d0a",
     "workload": "3d128_transport",
-    "fetch_kib": 210001.854, "fetch_scale": 1.999749,
-    "write_kib": 50415.597, "write_scale": 1.0,
+    "fetch_kib": 209878.847, "fetch_scale": 1.999743,
+    "write_kib": 50415.389, "write_scale": 1.0,
 }
 
 
@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="3d128_transport")
-    ap.add_argument("--cpu-sample", type=int, default=65536,
+    ap.add_argument("--cpu-sample", type=int, default=262144,
                     help="characteristics in the oracle's timed sample (0 = skip the CPU baseline)")
     ap.add_argument("--jac-blocks", type=int, default=8,
                     help="assembled-Jacobian capacity in cell blocks per characteristic")
@@ -119,9 +119,11 @@ def cpu_baseline(w, v, p, nsample):
     T = w.template().ravel()
     rng = np.random.default_rng(12345)
     pts = np.sort(rng.choice(P.n_points, nsample, replace=False))
-    t0 = time.perf_counter()
-    O.hessmat(P, v, T, p, points=pts)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.hessmat(P, v, T, p, points=pts)
+        dt = time.perf_counter() - t0
     t_full = dt * P.n_points / nsample
     return {"value": 1.0 / t_full, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
             "sample": f"{nsample} of {P.n_points} characteristics (uniform random, seed 12345); "
