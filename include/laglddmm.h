@@ -107,9 +107,11 @@ const char* lag_last_hip_error(void);
 int lag_plan_create(const lag_problem* prob, lag_plan* out);
 
 /* lag_plan_create with a chosen brick shape: brick_target[a] image cells per
- * brick along axis a (a < dim; 1..1024; NULL = the default 16 x 16 x 8 in
- * 3-D, 16 x 16 in 2-D).  The shape is rounded to whole wave lattices and
- * shrunk until the LDS tile fits 64 KB, as for the default.  Bricks change
+ * brick along axis a (a < dim; 1..1024; NULL = the default 16 x 16 x 12 in
+ * 3-D, 16 x 16 in 2-D).  A wave's 64 lanes cover a 4 x 4 x 4 or 8 x 4 x 2
+ * lattice of velocity cells in 3-D (the one that divides the shape), 8 x 8
+ * in 2-D.  The shape is rounded to whole wave lattices and shrunk until the
+ * LDS tile fits 64 KB, as for the default.  Bricks change
  * only the order of floating-point sums: results agree to rounding. */
 int lag_plan_create_tuned(const lag_problem* prob, const int32_t* brick_target, lag_plan* out);
 
@@ -387,7 +389,7 @@ int lag_multilevel_solve(const lag_problem* finest, int32_t levels, const float*
 /* Time the Gauss-Newton matvec of `prob` (assembled when prob->jac_blocks >
  * 0 and the model is transport, matrix-free otherwise) at a smooth synthetic
  * velocity with about two cells of displacement, for a fixed list of brick
- * shapes (3-D: 16x16x8, 8x16x8, 16x16x16, 8x8x8, 32x16x8, 16x8x8; 2-D: 16x16,
+ * shapes (3-D: 16x16x12, 16x16x8, 8x16x8, 16x16x16, 8x8x8, 32x16x8, 16x8x8; 2-D: 16x16,
  * 32x16, 32x32, 64x32, 16x8, 64x64), and return the fastest shape in
  * best_target[3] (for lag_plan_create_tuned) and its time per matvec in
  * *best_ms (may be NULL).  Allocating (one plan per shape, freed) and

@@ -38,13 +38,14 @@ int launch_axpby(long long n, float a, const float* x, float b, const float* y, 
 static void choose_bricks(lag_plan P, const int32_t* want) {
   const int D = P->geo.dim;
   lag::Bricks& B = P->bricks;
-  const int lane[3] = {D == 3 ? 4 : 8, D == 3 ? 4 : 8, D == 3 ? 4 : 1};
-  int target[3] = {16, 16, D == 3 ? 8 : 1};
+  // 16 x 16 x 12 bricks at the usual 2:1 image-to-velocity ratio keep the
+  // fixed-point tile at 52 KB (three blocks per CU) and give few enough
+  // bricks for one resident generation on 256 CUs at 128^3.
+  int target[3] = {16, 16, D == 3 ? 12 : 1};
   if (want)
     for (int a = 0; a < D; ++a) target[a] = want[a];
   const size_t budget = 64 * 1024;
   int halo = D == 3 ? 3 : 4;
-  int nreg[3];
   for (int a = 0; a < 3; ++a) {
     if (a < D) {
       double r = (double)P->prob.img_m[a] / P->prob.vel_m[a];
@@ -52,6 +53,30 @@ static void choose_bricks(lag_plan P, const int32_t* want) {
     } else {
       B.stride[a] = 1;
     }
+  }
+  // Lane lattice of a wave (log2 extents, 64 lanes): 2-D 8 x 8; 3-D 4 x 4 x 4
+  // or 8 x 4 x 2, the first whose regions divide the target on most axes.
+  {
+    const int lat3[2][3] = {{2, 2, 2}, {3, 2, 1}};
+    const int lat2[3] = {3, 3, 0};
+    int best = -1, best_fit = -1;
+    for (int c = 0; c < (D == 3 ? 2 : 1); ++c) {
+      const int* ls = D == 3 ? lat3[c] : lat2;
+      int fit = 0;
+      for (int a = 0; a < D; ++a) {
+        const int rd = (1 << ls[a]) * B.stride[a];
+        fit += target[a] >= rd && target[a] % rd == 0;
+      }
+      if (fit > best_fit) {
+        best_fit = fit;
+        best = c;
+      }
+    }
+    for (int a = 0; a < 3; ++a) B.lsh[a] = D == 3 ? lat3[best][a] : lat2[a];
+  }
+  int lane[3], nreg[3];
+  for (int a = 0; a < 3; ++a) {
+    lane[a] = 1 << B.lsh[a];
     B.rdim[a] = lane[a] * B.stride[a];
     nreg[a] = a < D ? std::max(1, target[a] / B.rdim[a]) : 1;
   }
@@ -86,9 +111,9 @@ static void choose_bricks(lag_plan P, const int32_t* want) {
     }
   }
   // Pad the tile's row and plane strides so that the 64 lanes of a wave,
-  // which start one velocity cell apart on a 4x4x4 (3-D) or 8x8 (2-D)
-  // lattice, fall into distinct LDS banks for the same corner/component
-  // (fewest lanes per bank for 32 and for 64 banks, then smallest tile).
+  // which start one velocity cell apart on the lane lattice, fall into
+  // distinct LDS banks for the same corner/component (fewest lanes per bank
+  // for 32 and for 64 banks, then smallest tile).
   {
     const int lat[3] = {lane[0], lane[1], lane[2]};
     auto worst = [&](int t0, int t1, int nb) {

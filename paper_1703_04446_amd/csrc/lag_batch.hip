@@ -58,7 +58,7 @@ bool same_problem(const lag_problem& a, const lag_problem& b) { return memcmp(&a
 // Candidate brick targets (image cells per axis) for the autotuner.
 std::vector<std::array<int32_t, 3>> candidates(int dim) {
   if (dim == 3)
-    return {{16, 16, 8}, {8, 16, 8}, {16, 16, 16}, {8, 8, 8}, {32, 16, 8}, {16, 8, 8}};
+    return {{16, 16, 12}, {16, 16, 8}, {8, 16, 8}, {16, 16, 16}, {8, 8, 8}, {32, 16, 8}, {16, 8, 8}};
   return {{16, 16, 1}, {32, 16, 1}, {32, 32, 1}, {64, 32, 1}, {16, 8, 1}, {64, 64, 1}};
 }
 

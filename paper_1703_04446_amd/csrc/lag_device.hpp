@@ -61,12 +61,20 @@ struct Bricks {
   int nb[3];          // bricks per axis
   int nbricks;        // total
   int stride[3];      // lane stride in image cells (about m_img / m_vel)
-  int rdim[3];        // wave region = (4 or 8) * stride per axis
+  int lsh[3];         // log2 of the wave's lane lattice per axis (lane bits x, then y, then z)
+  int rdim[3];        // wave region = lattice extent * stride per axis
   int nreg[3];        // regions per brick per axis
   int tdim[3];        // LDS tile size in velocity cells
   int halo;           // tile margin in velocity cells
   int tvol;           // tdim product
 };
+
+// A lane's position on the wave's lane lattice.
+__device__ __forceinline__ void lane_lattice(const Bricks& B, int lane, int l[3]) {
+  l[0] = lane & ((1 << B.lsh[0]) - 1);
+  l[1] = (lane >> B.lsh[0]) & ((1 << B.lsh[1]) - 1);
+  l[2] = lane >> (B.lsh[0] + B.lsh[1]);
+}
 
 __device__ __forceinline__ int wrapi(int c, int m) {
   if ((unsigned)c < (unsigned)m) return c;

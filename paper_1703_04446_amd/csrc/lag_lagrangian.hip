@@ -633,32 +633,41 @@ __device__ __forceinline__ void brick_origin(const Geo& g, const Bricks& B, long
   }
 }
 
-// Iterate over the characteristics of a brick.  Each wave takes (region,
-// phase) items; within an item the 64 lanes sit `stride` image cells apart so
-// that they start in distinct velocity cells (few LDS atomic collisions).
+// A brick is split into 64-row items, (region, phase) pairs: within an item
+// the 64 lanes sit `stride` image cells apart on the lane lattice, so that
+// they start in distinct velocity cells (few LDS atomic collisions).
+__device__ __forceinline__ int brick_items(const Bricks& B) {
+  return B.nreg[0] * B.nreg[1] * B.nreg[2] * B.stride[0] * B.stride[1] * B.stride[2];
+}
+
+// Image cell of the row that lattice position l takes in item w of the brick
+// with origin O; false when that cell lies outside the image.
+template <int D>
+__device__ __forceinline__ bool item_cell(const Geo& g, const Bricks& B, const int O[3], int w, const int l[3],
+                                          int idx[3]) {
+  const int P = B.stride[0] * B.stride[1] * B.stride[2];
+  const int reg = w / P, ph = w - reg * P;
+  const int r0 = reg % B.nreg[0], r1 = (reg / B.nreg[0]) % B.nreg[1], r2 = reg / (B.nreg[0] * B.nreg[1]);
+  const int p0 = ph % B.stride[0], p1 = (ph / B.stride[0]) % B.stride[1], p2 = ph / (B.stride[0] * B.stride[1]);
+  idx[0] = O[0] + r0 * B.rdim[0] + l[0] * B.stride[0] + p0;
+  idx[1] = O[1] + r1 * B.rdim[1] + l[1] * B.stride[1] + p1;
+  idx[2] = O[2] + r2 * B.rdim[2] + l[2] * B.stride[2] + p2;
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) in = in && idx[a] < g.mi[a];
+  return in;
+}
+
+// Iterate over the characteristics of a brick, one item per wave at a time.
 template <int D, class Body>
 __device__ __forceinline__ void for_brick_points(const Geo& g, const Bricks& B, const int O[3], Body body) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int l[3];
-  if (D == 3) {
-    l[0] = lane & 3; l[1] = (lane >> 2) & 3; l[2] = lane >> 4;
-  } else {
-    l[0] = lane & 7; l[1] = lane >> 3; l[2] = 0;
-  }
-  const int P = B.stride[0] * B.stride[1] * B.stride[2];
-  const int nreg = B.nreg[0] * B.nreg[1] * B.nreg[2];
-  for (int w = wave; w < nreg * P; w += nw) {
-    int reg = w / P, ph = w - (w / P) * P;
-    int r0 = reg % B.nreg[0], r1 = (reg / B.nreg[0]) % B.nreg[1], r2 = reg / (B.nreg[0] * B.nreg[1]);
-    int p0 = ph % B.stride[0], p1 = (ph / B.stride[0]) % B.stride[1], p2 = ph / (B.stride[0] * B.stride[1]);
+  lane_lattice(B, lane, l);
+  const int items = brick_items(B);
+  for (int w = wave; w < items; w += nw) {
     int idx[3];
-    idx[0] = O[0] + r0 * B.rdim[0] + l[0] * B.stride[0] + p0;
-    idx[1] = O[1] + r1 * B.rdim[1] + l[1] * B.stride[1] + p1;
-    idx[2] = O[2] + r2 * B.rdim[2] + l[2] * B.stride[2] + p2;
-    bool in = true;
-#pragma unroll
-    for (int a = 0; a < D; ++a) in = in && idx[a] < g.mi[a];
-    if (in) body(idx);
+    if (item_cell<D>(g, B, O, w, l, idx)) body(idx);
   }
 }
 
@@ -858,33 +867,9 @@ struct JacWriter {
   }
 };
 
-// Visit every slot of a brick (including slots outside the image, flagged).
-template <int D, class Body>
-__device__ __forceinline__ void for_brick_slots(const Geo& g, const Bricks& B, const int O[3], Body body) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int l[3];
-  if (D == 3) {
-    l[0] = lane & 3; l[1] = (lane >> 2) & 3; l[2] = lane >> 4;
-  } else {
-    l[0] = lane & 7; l[1] = lane >> 3; l[2] = 0;
-  }
-  const int P = B.stride[0] * B.stride[1] * B.stride[2];
-  const int nreg = B.nreg[0] * B.nreg[1] * B.nreg[2];
-  for (int w = wave; w < nreg * P; w += nw) {
-    int reg = w / P, ph = w - (w / P) * P;
-    int r0 = reg % B.nreg[0], r1 = (reg / B.nreg[0]) % B.nreg[1], r2 = reg / (B.nreg[0] * B.nreg[1]);
-    int p0 = ph % B.stride[0], p1 = (ph / B.stride[0]) % B.stride[1], p2 = ph / (B.stride[0] * B.stride[1]);
-    int idx[3];
-    idx[0] = O[0] + r0 * B.rdim[0] + l[0] * B.stride[0] + p0;
-    idx[1] = O[1] + r1 * B.rdim[1] + l[1] * B.stride[1] + p1;
-    idx[2] = O[2] + r2 * B.rdim[2] + l[2] * B.stride[2] + p2;
-    bool in = true;
-#pragma unroll
-    for (int a = 0; a < D; ++a) in = in && idx[a] < g.mi[a];
-    body(idx, w * 64 + lane, in);
-  }
-}
-
+// Assemble the stored Jacobian, one wave per 64-row item over all bricks
+// (rows are independent here, so the launch is not tied to one block per
+// brick).  Slot of a row: brick, item, lane, as the matvec reads them.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Bricks B,
                                                          const typename VecT<D>::T* __restrict__ vp,
@@ -892,19 +877,24 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
                                                          int* __restrict__ cells, unsigned char* __restrict__ cnt,
                                                          long long nslots, int kmax, int* __restrict__ maxcount,
                                                          int* __restrict__ flags) {
-  long long bid = xcd_block(B.nbricks);
-  if (bid < 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int items = brick_items(B);
+  const long long nitems = (long long)B.nbricks * items;
+  const long long blk = xcd_block((nitems + nw - 1) / nw);
+  if (blk < 0) return;
+  const long long item = blk * nw + wave;
+  if (item >= nitems) return;  // whole wave
+  const long long bid = item / items;
+  const int w = (int)(item - bid * items);
   int O[3], org[3];
   brick_origin<D>(g, B, bid, O, org);
-  const long long base = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2];
-  int mymax = 0, mysum = 0;
+  int l[3], idx[3];
+  lane_lattice(B, lane, l);
+  const bool in = item_cell<D>(g, B, O, w, l, idx);
+  const long long slot = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2] + (long long)w * 64 + lane;
+  int count = 0;
   bool bad = false;
-  for_brick_slots<D>(g, B, O, [&](const int idx[3], int local, bool in) {
-    const long long slot = base + local;
-    if (!in) {
-      cnt[slot] = 0;
-      return;
-    }
+  if (in) {
     Start<D> S;
     make_start_idx<D>(g, idx, S);
     float phi[D], dphi[D], F[D][D];
@@ -916,35 +906,42 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
     bool nz = false;
 #pragma unroll
     for (int a = 0; a < D; ++a) nz = nz || (gT[a] != 0.f);
-    if (!nz) {
-      cnt[slot] = 0;
-      return;
+    if (nz) {
+      float y0[D];
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        float t = 0.f;
+#pragma unroll
+        for (int a = 0; a < D; ++a) t = fmaf(F[a][b], gT[a], t);
+        y0[b] = t;
+      }
+      JacWriter<D> jw;
+      jw.vals = vals;
+      jw.cells = cells;
+      jw.nslots = nslots;
+      jw.slot = slot;
+      jw.kmax = kmax;
+      jw.count = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) jw.org[a] = org[a];
+      if (!adjoint_pass<D, false>(g, st, vp, S, y0, jw)) bad = true;
+      count = jw.count;
     }
-    float y0[D];
+  }
+  cnt[slot] = (unsigned char)min(count, 255);
+  // one set of atomics per wave
+  int wmax = count, wsum = min(count, kmax);
 #pragma unroll
-    for (int b = 0; b < D; ++b) {
-      float t = 0.f;
-#pragma unroll
-      for (int a = 0; a < D; ++a) t = fmaf(F[a][b], gT[a], t);
-      y0[b] = t;
-    }
-    JacWriter<D> jw;
-    jw.vals = vals;
-    jw.cells = cells;
-    jw.nslots = nslots;
-    jw.slot = slot;
-    jw.kmax = kmax;
-    jw.count = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) jw.org[a] = org[a];
-    if (!adjoint_pass<D, false>(g, st, vp, S, y0, jw)) bad = true;
-    cnt[slot] = (unsigned char)min(jw.count, 255);
-    mymax = max(mymax, jw.count);
-    mysum += min(jw.count, kmax);
-  });
-  if (mymax > 0) atomicMax(maxcount, mymax);
-  if (mysum > 0) atomicAdd(maxcount + 1, mysum);
-  if (bad) atomicOr(flags, 1);
+  for (int off = 32; off > 0; off >>= 1) {
+    wmax = max(wmax, __shfl_xor(wmax, off, 64));
+    wsum += __shfl_xor(wsum, off, 64);
+  }
+  const bool wbad = __ballot(bad) != 0;
+  if (lane == 0) {
+    if (wmax > 0) atomicMax(maxcount, wmax);
+    if (wsum > 0) atomicAdd(maxcount + 1, wsum);
+    if (wbad) atomicOr(flags, 1);
+  }
 }
 
 // Corner values of one stored block: dot with p (gather) or scale.
@@ -1077,13 +1074,8 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
   const long long base = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2];
   constexpr int NV4 = JacLayout<D>::NV4;
   int l[3];
-  if (D == 3) {
-    l[0] = lane & 3; l[1] = (lane >> 2) & 3; l[2] = lane >> 4;
-  } else {
-    l[0] = lane & 7; l[1] = lane >> 3; l[2] = 0;
-  }
-  const int P = B.stride[0] * B.stride[1] * B.stride[2];
-  const int nitems = B.nreg[0] * B.nreg[1] * B.nreg[2] * P;
+  lane_lattice(B, lane, l);
+  const int nitems = brick_items(B);
   const int rounds = (nitems + nw - 1) / nw;
   float btot = 0.f;                  // bound of all rows so far (same in every thread)
   int e = 0;                         // current scale 2^e (valid once btot > 0)
@@ -1093,16 +1085,8 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
     int n = 0;
     long long slot = 0, p = 0;
     if (w < nitems) {
-      const int reg = w / P, ph = w - reg * P;
-      const int r0 = reg % B.nreg[0], r1 = (reg / B.nreg[0]) % B.nreg[1], r2 = reg / (B.nreg[0] * B.nreg[1]);
-      const int p0 = ph % B.stride[0], p1 = (ph / B.stride[0]) % B.stride[1], p2 = ph / (B.stride[0] * B.stride[1]);
       int idx[3];
-      idx[0] = O[0] + r0 * B.rdim[0] + l[0] * B.stride[0] + p0;
-      idx[1] = O[1] + r1 * B.rdim[1] + l[1] * B.stride[1] + p1;
-      idx[2] = O[2] + r2 * B.rdim[2] + l[2] * B.stride[2] + p2;
-      bool in = true;
-#pragma unroll
-      for (int a = 0; a < D; ++a) in = in && idx[a] < g.mi[a];
+      const bool in = item_cell<D>(g, B, O, w, l, idx);
       slot = base + w * 64 + lane;
       if (in) {
         n = cnt[slot];
@@ -1458,7 +1442,9 @@ int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, cons
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, hipStream_t s) {
   Stages st = stages_for(P, -1);
   const lag::Bricks& B = P->bricks;
-  unsigned grid = grid_for(B.nbricks);
+  const long long items = (long long)B.nbricks * B.nreg[0] * B.nreg[1] * B.nreg[2] * B.stride[0] * B.stride[1] *
+                          B.stride[2];
+  unsigned grid = grid_for((items + kBlock / 64 - 1) / (kBlock / 64));
   int rc = launch_zero_i(P->jac_max, 2, s);
   if (rc) return rc;
   if (P->geo.dim == 3)
