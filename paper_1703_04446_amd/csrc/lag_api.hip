@@ -175,6 +175,8 @@ static void free_plan(lag_plan P) {
   if (P->sc_host) (void)hipHostFree(P->sc_host);
   if (P->pcg_exec) (void)hipGraphExecDestroy(P->pcg_exec);
   if (P->gstream) (void)hipStreamDestroy(P->gstream);
+  for (hipEvent_t e : P->ctl_ev)
+    if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < 10; ++i)
     if (P->vec[i]) (void)hipFree(P->vec[i]);
   if (P->prof_on)
@@ -623,92 +625,29 @@ static int read_scalars(lag_plan P, double* host, int off, int cnt, hipStream_t 
 
 }  // extern "C"
 
-// Preconditioned CG with the Gauss-Newton operator `H` (a callable
-// H(p, Hp, stream) -> status); device-side alpha/beta, one host sync per
-// iteration.
-template <class Op>
-static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int32_t maxit, lag_pcg_info* info,
-                    hipStream_t s) {
-  const long long n = P->n_unknowns;
-  float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
-  double* sc = P->scalars;  // [0] rz, [1] pHp, [2] rz_new, [3] rr, [4] breakdown, [5] bb
-  lag_pcg_info loc = {0, 0, 0, 0.0};
-  int rc;
-  if ((rc = launch_fill(x, n, 0.f, s))) return rc;
-  if ((rc = launch_axpby(n, 1.f, b, 0.f, nullptr, r, s))) return rc;
-  if ((rc = launch_dot(P, n, b, b, sc + 5, s))) return rc;
-  hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 4, 0.0);
-  LAG_LAUNCH_CHECK();
-  double h[6];
-  if ((rc = read_scalars(P, h, 0, 6, s))) return rc;
-  const double nb = sqrt(h[5]);
-  if (nb == 0.0) {
-    if (info) *info = loc;
-    return LAG_OK;
-  }
-  if ((rc = launch_precond(P, r, z, s))) return rc;
-  if ((rc = launch_dot(P, n, r, z, sc + 0, s))) return rc;
-  if ((rc = launch_axpby(n, 1.f, z, 0.f, nullptr, p, s))) return rc;
-  double rr = h[5];
-  int status = LAG_OK;
-  for (int it = 0; it < maxit; ++it) {
-    if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
-    if ((rc = read_scalars(P, h, 0, 5, s))) return rc;
-    rr = h[3];
-    if (h[4] != 0.0) {
-      status = LAG_EBREAKDOWN;
-      loc.breakdown = 1;
-      if (loc.iters > 0) loc.iters--;
-      break;
-    }
-    if (sqrt(rr) <= tol * nb) break;
-    if ((rc = H(p, Hp, s))) return rc;
-    loc.matvecs++;
-    if ((rc = launch_dot(P, n, p, Hp, sc + 1, s))) return rc;
-    if ((rc = launch_pcg_xr(n, x, r, p, Hp, sc, nullptr, s))) return rc;
-    if ((rc = launch_precond(P, r, z, s))) return rc;
-    if ((rc = launch_dot(P, n, r, z, sc + 2, s))) return rc;
-    if ((rc = launch_pcg_p(n, p, z, sc, nullptr, s))) return rc;
-    loc.iters = it + 1;
-  }
-  if (status == LAG_OK) {
-    if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
-    if ((rc = read_scalars(P, h, 0, 5, s))) return rc;
-    rr = h[3];
-    if (h[4] != 0.0) {
-      status = LAG_EBREAKDOWN;
-      loc.breakdown = 1;
-      if (loc.iters > 0) loc.iters--;
-    }
-  }
-  loc.relres = sqrt(rr) / nb;
-  if (info) *info = loc;
-  return status;
+// PCG control block (device flags, pinned host mirrors, capture stream, copy
+// events), allocated on a plan's first PCG call.
+static int ensure_pcg_ctl(lag_plan P) {
+  if (P->ctl && P->ctl_ev[1]) return LAG_OK;
+  std::lock_guard<std::mutex> lk(api_lock());
+  if (!P->ctl_host) LAG_HIP(hipHostMalloc((void**)&P->ctl_host, sizeof(int) * 8, hipHostMallocDefault));
+  if (!P->sc_host) LAG_HIP(hipHostMalloc((void**)&P->sc_host, sizeof(double) * 8, hipHostMallocDefault));
+  if (!P->gstream) LAG_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+  for (int k = 0; k < 2; ++k)
+    if (!P->ctl_ev[k]) LAG_HIP(hipEventCreateWithFlags(&P->ctl_ev[k], hipEventDisableTiming));
+  if (!P->ctl) LAG_HIP(hipMalloc((void**)&P->ctl, sizeof(int) * 4));
+  return LAG_OK;
 }
 
-// Graph-captured PCG: the same iteration as pcg_impl, with the stopping test
-// on the device (k_pcg_check sets ctl[0]; every kernel of the iteration then
-// returns at entry).  `per_graph` iterations are captured into one graph,
-// built once per plan and argument set (key) and replayed; the host reads
-// the control block after each replay, i.e. once per `per_graph`
-// iterations.  The captured kernels take only the plan's buffers and the
-// pointers in `key`, so a replay is valid while those are unchanged.
-template <class Op>
-static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, const float* b, float* x,
-                          double tol, int32_t maxit, int32_t per_graph, lag_pcg_info* info, hipStream_t s) {
+// PCG start: x = 0, r = b, z = M r, p = z, device scalars and control block
+// (sc[0] = r.z, sc[3] = r.r, sc[4] = breakdown flag, sc[5] = b.b, sc[6] =
+// tol^2 b.b).  Synchronises once for |b|; *nb = 0 means b = 0 (nothing
+// else launched).
+static int pcg_start(lag_plan P, const float* b, float* x, double tol, int32_t maxit, double* nb, hipStream_t s) {
   const long long n = P->n_unknowns;
-  float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
-  double* sc = P->scalars;  // as pcg_impl, plus [6] = tol^2 b.b
-  lag_pcg_info loc = {0, 0, 0, 0.0};
+  float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5];
+  double* sc = P->scalars;
   int rc;
-  if (!P->ctl) {
-    std::lock_guard<std::mutex> lk(api_lock());
-    LAG_HIP(hipMalloc((void**)&P->ctl, sizeof(int) * 4));
-    LAG_HIP(hipHostMalloc((void**)&P->ctl_host, sizeof(int) * 4, hipHostMallocDefault));
-    LAG_HIP(hipHostMalloc((void**)&P->sc_host, sizeof(double) * 8, hipHostMallocDefault));
-    LAG_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
-  }
-  // start: x = 0, r = b, z = M r, p = z (eager)
   if ((rc = launch_fill(x, n, 0.f, s))) return rc;
   if ((rc = launch_axpby(n, 1.f, b, 0.f, nullptr, r, s))) return rc;
   if ((rc = launch_dot(P, n, b, b, sc + 5, s))) return rc;
@@ -717,18 +656,113 @@ static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, 
   LAG_HIP(hipMemcpyAsync(P->sc_host, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
   LAG_HIP(hipStreamSynchronize(s));
   const double bb = P->sc_host[5];
-  const double nb = sqrt(bb);
-  if (nb == 0.0) {
-    if (info) *info = loc;
-    return LAG_OK;
-  }
+  *nb = sqrt(bb);
+  if (*nb == 0.0) return LAG_OK;
   if ((rc = launch_precond(P, r, z, s))) return rc;
   if ((rc = launch_dot(P, n, r, z, sc + 0, s))) return rc;
   if ((rc = launch_axpby(n, 1.f, z, 0.f, nullptr, p, s))) return rc;
   if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
   hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 6, tol * tol * bb);
   LAG_LAUNCH_CHECK();
-  if ((rc = launch_pcg_ctl_init(P->ctl, sc, maxit, s))) return rc;
+  return launch_pcg_ctl_init(P->ctl, sc, maxit, s);
+}
+
+// One PCG iteration on stream g (alpha, beta and the stopping test on the
+// device; every kernel returns at entry once ctl[0] is set).
+template <class Op>
+static int pcg_iteration(lag_plan P, Op& H, float* x, hipStream_t g) {
+  const long long n = P->n_unknowns;
+  float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
+  double* sc = P->scalars;
+  int rc;
+  if ((rc = H(p, Hp, g))) return rc;
+  if ((rc = launch_dot(P, n, p, Hp, sc + 1, g))) return rc;
+  if ((rc = launch_pcg_xr(n, x, r, p, Hp, sc, P->ctl, g))) return rc;
+  if ((rc = launch_precond(P, r, z, g))) return rc;
+  if ((rc = launch_dot(P, n, r, z, sc + 2, g))) return rc;
+  if ((rc = launch_pcg_p(n, p, z, sc, P->ctl, g))) return rc;
+  if ((rc = launch_dot(P, n, r, r, sc + 3, g))) return rc;
+  return launch_pcg_check(P->ctl, sc, g);
+}
+
+// Read the control block and scalars after the last iteration.
+static int pcg_finish(lag_plan P, double nb, lag_pcg_info* info, hipStream_t s) {
+  LAG_HIP(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipMemcpyAsync(P->sc_host, P->scalars, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  lag_pcg_info loc;
+  loc.iters = P->ctl_host[1];
+  loc.breakdown = P->ctl_host[0] == 2;
+  loc.matvecs = loc.iters + (loc.breakdown ? 1 : 0);
+  loc.relres = sqrt(P->sc_host[3]) / nb;
+  if (info) *info = loc;
+  return loc.breakdown ? LAG_EBREAKDOWN : LAG_OK;
+}
+
+// Preconditioned CG with the Gauss-Newton operator `H` (a callable
+// H(p, Hp, stream) -> status), launched eagerly.  The stopping test runs on
+// the device, so the host enqueues iteration k + 1 before it reads the
+// control block of iteration k: the GPU does not wait for the host between
+// iterations, and at most one enqueued iteration finds the halt flag set and
+// does nothing.  Timed matvec launches of such an iteration are dropped.
+template <class Op>
+static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int32_t maxit, lag_pcg_info* info,
+                    hipStream_t s) {
+  int rc;
+  if ((rc = ensure_pcg_ctl(P))) return rc;
+  double nb = 0.0;
+  if ((rc = pcg_start(P, b, x, tol, maxit, &nb, s))) return rc;
+  if (nb == 0.0) {
+    if (info) *info = lag_pcg_info{0, 0, 0, 0.0};
+    return LAG_OK;
+  }
+  std::vector<int> prof_at;
+  prof_at.reserve(maxit > 0 ? maxit : 0);
+  int enq = 0;
+  P->geo.halt = P->ctl;
+  for (int it = 0; it < maxit; ++it) {
+    prof_at.push_back(P->prof_n);
+    if ((rc = pcg_iteration(P, H, x, s))) break;
+    ++enq;
+    const int slot = it & 1;
+    if (hipMemcpyAsync(P->ctl_host + 4 * slot, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(P->ctl_ev[slot], s) != hipSuccess) {
+      rc = set_hip_error(hipGetLastError());
+      break;
+    }
+    if (it > 0) {
+      const hipError_t e = hipEventSynchronize(P->ctl_ev[slot ^ 1]);
+      if (e != hipSuccess) {
+        rc = set_hip_error(e);
+        break;
+      }
+      if (P->ctl_host[4 * (slot ^ 1)] != 0) break;
+    }
+  }
+  P->geo.halt = nullptr;
+  if (rc) return rc;
+  rc = pcg_finish(P, nb, info, s);
+  const int ran = P->ctl_host[1] + (P->ctl_host[0] == 2 ? 1 : 0);
+  if (ran < enq && P->prof_n > prof_at[ran]) P->prof_n = prof_at[ran];
+  return rc;
+}
+
+// Graph-captured PCG: the iteration of pcg_impl, `per_graph` iterations per
+// graph, built once per plan and argument set (key) and replayed; the host
+// reads the control block after each replay, i.e. once per `per_graph`
+// iterations.  The captured kernels take only the plan's buffers and the
+// pointers in `key`, so a replay is valid while those are unchanged.
+template <class Op>
+static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, const float* b, float* x,
+                          double tol, int32_t maxit, int32_t per_graph, lag_pcg_info* info, hipStream_t s) {
+  int rc;
+  if ((rc = ensure_pcg_ctl(P))) return rc;
+  double nb = 0.0;
+  if ((rc = pcg_start(P, b, x, tol, maxit, &nb, s))) return rc;
+  if (nb == 0.0) {
+    if (info) *info = lag_pcg_info{0, 0, 0, 0.0};
+    return LAG_OK;
+  }
   // (re)capture when the arguments differ from the cached graph's
   bool same = P->pcg_exec && P->pcg_key_i[0] == mode && P->pcg_key_i[1] == per_graph;
   for (int k = 0; k < 6 && same; ++k) same = P->pcg_key[k] == key[k];
@@ -743,16 +777,7 @@ static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, 
     P->geo.halt = P->ctl;
     P->capturing = 1;
     int crc = LAG_OK;
-    for (int u = 0; u < per_graph && crc == LAG_OK; ++u) {
-      if ((crc = H(p, Hp, g))) break;
-      if ((crc = launch_dot(P, n, p, Hp, sc + 1, g))) break;
-      if ((crc = launch_pcg_xr(n, x, r, p, Hp, sc, P->ctl, g))) break;
-      if ((crc = launch_precond(P, r, z, g))) break;
-      if ((crc = launch_dot(P, n, r, z, sc + 2, g))) break;
-      if ((crc = launch_pcg_p(n, p, z, sc, P->ctl, g))) break;
-      if ((crc = launch_dot(P, n, r, r, sc + 3, g))) break;
-      crc = launch_pcg_check(P->ctl, sc, g);
-    }
+    for (int u = 0; u < per_graph && crc == LAG_OK; ++u) crc = pcg_iteration(P, H, x, g);
     P->geo.halt = nullptr;
     P->capturing = 0;
     hipGraph_t graph = nullptr;
@@ -772,23 +797,21 @@ static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, 
     P->pcg_key_i[0] = mode;
     P->pcg_key_i[1] = per_graph;
   }
-  // replay until the device says stop (bounded by the iteration cap)
-  const int launches = (maxit + per_graph - 1) / per_graph + 1;
+  // replay until the device says stop (bounded by the iteration cap); as in
+  // pcg_impl, replay l + 1 is enqueued before the control block of replay l
+  // is read
+  const int launches = (maxit + per_graph - 1) / per_graph;
   for (int l = 0; l < launches; ++l) {
-    LAG_HIP(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
-    LAG_HIP(hipStreamSynchronize(s));
-    if (P->ctl_host[0] != 0) break;
+    const int slot = l & 1;
     LAG_HIP(hipGraphLaunch(P->pcg_exec, s));
+    LAG_HIP(hipMemcpyAsync(P->ctl_host + 4 * slot, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    LAG_HIP(hipEventRecord(P->ctl_ev[slot], s));
+    if (l > 0) {
+      LAG_HIP(hipEventSynchronize(P->ctl_ev[slot ^ 1]));
+      if (P->ctl_host[4 * (slot ^ 1)] != 0) break;
+    }
   }
-  LAG_HIP(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
-  LAG_HIP(hipMemcpyAsync(P->sc_host, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
-  LAG_HIP(hipStreamSynchronize(s));
-  loc.iters = P->ctl_host[1];
-  loc.breakdown = P->ctl_host[0] == 2;
-  loc.matvecs = loc.iters + (loc.breakdown ? 1 : 0);
-  loc.relres = sqrt(P->sc_host[3]) / nb;
-  if (info) *info = loc;
-  return loc.breakdown ? LAG_EBREAKDOWN : LAG_OK;
+  return pcg_finish(P, nb, info, s);
 }
 
 extern "C" {

@@ -69,11 +69,13 @@ struct lag_plan_s {
   int2* cover_ent[3] = {nullptr, nullptr, nullptr};
   // status flags written by kernels (bit 0: singular RK4 step Jacobian)
   int* flags = nullptr;
-  // graph-captured PCG: device control block, pinned host mirror, capture
-  // stream and the cached executable with the arguments it was captured for
+  // PCG control: device control block, pinned host mirrors (two slots, read
+  // one iteration late), their copy events, the capture stream and the
+  // cached graph executable with the arguments it was captured for
   int* ctl = nullptr;          // device int[4]
-  int* ctl_host = nullptr;     // pinned host int[4]
+  int* ctl_host = nullptr;     // pinned host int[2][4]
   double* sc_host = nullptr;   // pinned host double[8]
+  hipEvent_t ctl_ev[2] = {nullptr, nullptr};
   hipStream_t gstream = nullptr;
   hipGraphExec_t pcg_exec = nullptr;
   const void* pcg_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
