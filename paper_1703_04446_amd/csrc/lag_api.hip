@@ -163,7 +163,7 @@ static void free_plan(lag_plan P) {
   if (!P) return;
   void* ptrs[] = {P->pack_v, P->pack_p, P->st_j0[0], P->st_j0[1], P->st_th[0], P->st_th[1], P->reg_scale,
                   P->img_a, P->img_b, P->phi, P->bin_count, P->bin_start, P->bin_cursor, P->bin_items,
-                  P->part_base, P->part_vals, P->scan_blocks, P->red_partial, P->scalars, P->fft_buf,
+                  P->part_base, P->part_vals, P->scan_blocks, P->red_partial, P->red_partial2, P->scalars, P->fft_buf,
                   P->fft_tw[0], P->fft_tw[1], P->fft_tw[2], P->fft_lam[0], P->fft_lam[1], P->fft_lam[2],
                   P->fft_mu1, P->flags, P->tile_part, P->cover_start[0], P->cover_start[1],
                   P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2], P->jac_vals,
@@ -372,6 +372,7 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
   ALLOC(P->part_vals, sizeof(float) * g.np * (1 << D));
   ALLOC(P->scan_blocks, sizeof(int) * ((g.np + 1023) / 1024 + 2));
   ALLOC(P->red_partial, sizeof(double) * kRedBlocks);
+  ALLOC(P->red_partial2, sizeof(double) * kRedBlocks);
   ALLOC(P->scalars, sizeof(double) * 32);
   HIPC(hipMemset(P->scalars, 0, sizeof(double) * 32));
   for (int i = 0; i < 10; ++i) ALLOC(P->vec[i], sizeof(float) * P->n_unknowns);
@@ -673,16 +674,14 @@ template <class Op>
 static int pcg_iteration(lag_plan P, Op& H, float* x, hipStream_t g) {
   const long long n = P->n_unknowns;
   float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
-  double* sc = P->scalars;
   int rc;
   if ((rc = H(p, Hp, g))) return rc;
-  if ((rc = launch_dot(P, n, p, Hp, sc + 1, g))) return rc;
-  if ((rc = launch_pcg_xr(n, x, r, p, Hp, sc, P->ctl, g))) return rc;
+  if ((rc = launch_dot_partial(P, n, p, Hp, P->red_partial, g))) return rc;
+  if ((rc = launch_pcg_xr(P, x, r, p, Hp, g))) return rc;   // also r.r partials
   if ((rc = launch_precond(P, r, z, g))) return rc;
-  if ((rc = launch_dot(P, n, r, z, sc + 2, g))) return rc;
-  if ((rc = launch_pcg_p(n, p, z, sc, P->ctl, g))) return rc;
-  if ((rc = launch_dot(P, n, r, r, sc + 3, g))) return rc;
-  return launch_pcg_check(P->ctl, sc, g);
+  if ((rc = launch_dot_partial(P, n, r, z, P->red_partial, g))) return rc;
+  if ((rc = launch_pcg_p(P, p, z, g))) return rc;
+  return launch_pcg_check(P, g);
 }
 
 // Read the control block and scalars after the last iteration.

@@ -46,13 +46,19 @@ __global__ void __launch_bounds__(kBlock) k_ssd_partial(const float* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// Sum of the block partials of a reduction, in the same order in every block
+// of kBlock threads (so consumers can take it without a separate launch).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nparts, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+  return block_sum(s, sh);
+}
+
 __global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__ part, int nparts, double scale,
                                                        double* __restrict__ dst, const int* __restrict__ halt) {
   if (halted(halt)) return;
   __shared__ double sh[kBlock];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
-  double t = block_sum(s, sh);
+  double t = sum_partials(part, nparts, sh);
   if (threadIdx.x == 0) *dst = scale * t;
 }
 
@@ -70,6 +76,14 @@ int launch_dot(lag_plan P, long long n, const float* x, const float* y, double* 
   hipLaunchKernelGGL(k_dot_partial, dim3(blocks), dim3(kBlock), 0, s, x, y, n, P->red_partial, P->geo.halt);
   LAG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, P->red_partial, (int)blocks, 1.0, dst, P->geo.halt);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+int launch_dot_partial(lag_plan P, long long n, const float* x, const float* y, double* part, hipStream_t s) {
+  unsigned blocks;
+  reduce_launch(n, blocks);
+  hipLaunchKernelGGL(k_dot_partial, dim3(blocks), dim3(kBlock), 0, s, x, y, n, part, P->geo.halt);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
@@ -111,34 +125,51 @@ int launch_combine_J(double* s3, double alpha, hipStream_t s) {
 
 // ---- PCG updates with device scalars --------------------------------------
 // sc[0] = r.z (current), sc[1] = p.Hp, sc[2] = r.z (new), sc[3] = r.r,
-// sc[4] = breakdown flag (p.Hp <= 0)
+// sc[4] = breakdown flag (p.Hp <= 0).  The update kernels finish the inner
+// products they need from the block partials of k_dot_partial themselves.
 
+// x += alpha p, r -= alpha Hp with alpha = sc[0] / p.Hp (p.Hp from `php`
+// partials; no update when p.Hp <= 0), and the block partials of the new
+// r.r into `rr` (the grid and order of k_dot_partial over r, r).
 __global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restrict__ x, float* __restrict__ r,
                                                     const float* __restrict__ p, const float* __restrict__ Hp,
-                                                    double* __restrict__ sc, const int* __restrict__ halt) {
+                                                    double* __restrict__ sc, const double* __restrict__ php,
+                                                    int nphp, double* __restrict__ rr, const int* __restrict__ halt) {
   if (halted(halt)) return;
-  const double pHp = sc[1];
+  __shared__ double sh[kBlock];
+  const double pHp = sum_partials(php, nphp, sh);
   const bool ok = pHp > 0.0;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && !ok) sc[4] = 1.0;
-  if (!ok || i >= n) return;
-  const float a = (float)(sc[0] / pHp);
-  x[i] = fmaf(a, p[i], x[i]);
-  r[i] = fmaf(-a, Hp[i], r[i]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[1] = pHp;
+    if (!ok) sc[4] = 1.0;
+  }
+  const float a = ok ? (float)(sc[0] / pHp) : 0.f;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    float ri = r[i];
+    if (ok) {
+      x[i] = fmaf(a, p[i], x[i]);
+      ri = fmaf(-a, Hp[i], ri);
+      r[i] = ri;
+    }
+    s += (double)ri * (double)ri;
+  }
+  __syncthreads();  // every thread has read sh[0] of the first sum
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) rr[blockIdx.x] = t;
 }
 
+// p = z + beta p with beta = r.z (from `rz` partials, stored to sc[2]) / sc[0]
 __global__ void __launch_bounds__(kBlock) k_pcg_p(long long n, float* __restrict__ p, const float* __restrict__ z,
-                                                   const double* __restrict__ sc, const int* __restrict__ halt) {
+                                                   double* __restrict__ sc, const double* __restrict__ rz, int nrz,
+                                                   const int* __restrict__ halt) {
   if (halted(halt)) return;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float beta = (float)(sc[2] / sc[0]);
-  p[i] = fmaf(beta, p[i], z[i]);
-}
-
-__global__ void k_pcg_roll(double* sc, const int* __restrict__ halt) {
-  if (halted(halt)) return;
-  if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = sc[2];
+  __shared__ double sh[kBlock];
+  const double rznew = sum_partials(rz, nrz, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[2] = rznew;
+  const float beta = (float)(rznew / sc[0]);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = fmaf(beta, p[i], z[i]);
 }
 
 // Device-side PCG control for graph-captured iterations.  ctl[0] = halt
@@ -153,15 +184,22 @@ __global__ void k_pcg_ctl_init(int* ctl, const double* sc, int maxit) {
   ctl[0] = sc[4] != 0.0 ? 2 : (sc[3] <= sc[6] ? 1 : (maxit <= 0 ? 3 : 0));
 }
 
-__global__ void k_pcg_check(int* ctl, const double* sc) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || ctl[0] != 0) return;
+// After an iteration: sc[3] = r.r from the `rr` partials, sc[0] = sc[2] (the
+// new r.z becomes current), then the stopping test.
+__global__ void __launch_bounds__(kBlock) k_pcg_check(int* ctl, double* sc, const double* __restrict__ rr, int nrr) {
+  if (ctl[0] != 0) return;
+  __shared__ double sh[kBlock];
+  const double t = sum_partials(rr, nrr, sh);
+  if (threadIdx.x != 0) return;
+  sc[3] = t;
+  sc[0] = sc[2];
   const int it = ctl[1] + 1;
   if (sc[4] != 0.0) {     // this iteration broke down: it does not count
     ctl[0] = 2;
     return;
   }
   ctl[1] = it;
-  if (sc[3] <= sc[6]) ctl[0] = 1;
+  if (t <= sc[6]) ctl[0] = 1;
   else if (it >= ctl[2]) ctl[0] = 3;
 }
 
@@ -171,24 +209,33 @@ int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s) {
   return LAG_OK;
 }
 
-int launch_pcg_check(int* ctl, const double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, s, ctl, sc);
+int launch_pcg_check(lag_plan P, hipStream_t s) {
+  unsigned blocks;
+  reduce_launch(P->n_unknowns, blocks);
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(kBlock), 0, s, P->ctl, P->scalars, P->red_partial2, (int)blocks);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
 
-int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, const int* halt,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_xr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, x, r, p, Hp, sc,
-                     halt);
+// x, r update with the p.Hp partials in red_partial; new r.r partials go to
+// red_partial2 (consumed by launch_pcg_check)
+int launch_pcg_xr(lag_plan P, float* x, float* r, const float* p, const float* Hp, hipStream_t s) {
+  const long long n = P->n_unknowns;
+  unsigned blocks;
+  reduce_launch(n, blocks);
+  hipLaunchKernelGGL(k_pcg_xr, dim3(blocks), dim3(kBlock), 0, s, n, x, r, p, Hp, P->scalars, P->red_partial,
+                     (int)blocks, P->red_partial2, P->ctl);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
 
-int launch_pcg_p(long long n, float* p, const float* z, double* sc, const int* halt, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_p, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, p, z, sc, halt);
-  LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_pcg_roll, dim3(1), dim3(64), 0, s, sc, halt);
+// p update with the r.z partials in red_partial
+int launch_pcg_p(lag_plan P, float* p, const float* z, hipStream_t s) {
+  const long long n = P->n_unknowns;
+  unsigned blocks;
+  reduce_launch(n, blocks);
+  hipLaunchKernelGGL(k_pcg_p, dim3(blocks), dim3(kBlock), 0, s, n, p, z, P->scalars, P->red_partial, (int)blocks,
+                     P->ctl);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }

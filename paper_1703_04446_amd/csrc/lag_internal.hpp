@@ -40,6 +40,7 @@ struct lag_plan_s {
   int* scan_blocks = nullptr;  // block sums for the scan
   // reductions
   double* red_partial = nullptr;  // kRedBlocks
+  double* red_partial2 = nullptr; // kRedBlocks (PCG: r.r partials)
   double* scalars = nullptr;      // 16 device scalars
   // velocity-sized scratch (PCG / GN vectors)
   float* vec[10] = {nullptr};
@@ -134,11 +135,11 @@ int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float sc
                hipStream_t s);
 int launch_axpy(long long n, float a, const float* x, float* y, hipStream_t s);
 int launch_combine_J(double* s3, double alpha, hipStream_t s);
-int launch_pcg_xr(long long n, float* x, float* r, const float* p, const float* Hp, double* sc, const int* halt,
-                  hipStream_t s);
-int launch_pcg_p(long long n, float* p, const float* z, double* sc, const int* halt, hipStream_t s);
+int launch_dot_partial(lag_plan P, long long n, const float* x, const float* y, double* part, hipStream_t s);
+int launch_pcg_xr(lag_plan P, float* x, float* r, const float* p, const float* Hp, hipStream_t s);
+int launch_pcg_p(lag_plan P, float* p, const float* z, hipStream_t s);
 int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s);
-int launch_pcg_check(int* ctl, const double* sc, hipStream_t s);
+int launch_pcg_check(lag_plan P, hipStream_t s);
 
 // profiling brackets around the dominant matvec kernel (no-ops unless enabled)
 inline void prof_begin(lag_plan P, hipStream_t s) {
