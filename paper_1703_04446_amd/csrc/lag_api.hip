@@ -522,6 +522,21 @@ __global__ void k_set(double* x, double v) {
 
 extern "C" {
 
+// Objective (eq. SSD plus the regulariser) from the deformed template uu:
+// out3 = {J, distance, regulariser}; wres = cell volume * (uu - R) when not
+// null.
+static int objective_from_image(lag_plan P, const float* v, const float* uu, const float* R, float* wres,
+                                double* out3, hipStream_t s) {
+  int rc;
+  if ((rc = launch_ssd(P, uu, R, wres, P->geo.cell_img, out3 + 1, s))) return rc;
+  float* tmp = P->vec[9];
+  if ((rc = launch_reg(P, v, tmp, 0, 0, 0.f, s))) return rc;
+  if ((rc = launch_dot(P, P->n_unknowns, v, tmp, out3 + 2, s))) return rc;
+  hipLaunchKernelGGL(lag::k_halve, dim3(1), dim3(64), 0, s, out3 + 2);
+  LAG_LAUNCH_CHECK();
+  return launch_combine_J(out3, P->prob.alpha, s);
+}
+
 static int objective_full(lag_plan P, const float* v, const float* T, const float* R, float* u, float* wres,
                           double* out3, hipStream_t s) {
   const int dir = P->prob.model == LAG_TRANSPORT ? -1 : 1;
@@ -532,13 +547,7 @@ static int objective_full(lag_plan P, const float* v, const float* T, const floa
   if (P->prob.model == LAG_TRANSPORT) rc = launch_transport(P, T, P->phi, uu, s);
   else rc = launch_pushforward(P, T, P->phi, uu, s);
   if (rc) return rc;
-  if ((rc = launch_ssd(P, uu, R, wres, P->geo.cell_img, out3 + 1, s))) return rc;
-  float* tmp = P->vec[9];
-  if ((rc = launch_reg(P, v, tmp, 0, 0, 0.f, s))) return rc;
-  if ((rc = launch_dot(P, P->n_unknowns, v, tmp, out3 + 2, s))) return rc;
-  hipLaunchKernelGGL(lag::k_halve, dim3(1), dim3(64), 0, s, out3 + 2);
-  LAG_LAUNCH_CHECK();
-  return launch_combine_J(out3, P->prob.alpha, s);
+  return objective_from_image(P, v, uu, R, wres, out3, s);
 }
 
 int lag_objective(lag_plan P, const float* v, const float* T, const float* R, float* u, double* out3,
@@ -560,15 +569,14 @@ int lag_gradient(lag_plan P, const float* v, const float* T, const float* R, flo
 
 // ---- assembled Jacobian ------------------------------------------------------
 
-int lag_jacobian_assemble(lag_plan P, const float* v, const float* T, int32_t* stored, void* stream) {
-  LAG_CHECK(P && v && T && stored);
+// Assemble J at v; with u != null also write the transported image T(phi).
+static int jacobian_assemble(lag_plan P, const float* v, const float* T, float* u, int32_t* stored, hipStream_t s) {
   *stored = 0;
   P->jac_ready = 0;
   if (P->jac_k == 0) return LAG_EUNSUPPORTED;
-  hipStream_t s = S(stream);
   int rc = launch_pack(P, v, P->pack_v, s);
   if (rc) return rc;
-  if ((rc = launch_jac_assemble(P, P->pack_v, T, s))) return rc;
+  if ((rc = launch_jac_assemble(P, P->pack_v, T, u, s))) return rc;
   int mx[2] = {0, 0};
   LAG_HIP(hipMemcpyAsync(mx, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
   LAG_HIP(hipStreamSynchronize(s));
@@ -577,6 +585,11 @@ int lag_jacobian_assemble(lag_plan P, const float* v, const float* T, int32_t* s
   P->jac_max_seen = mx[0];
   *stored = P->jac_ready;
   return LAG_OK;
+}
+
+int lag_jacobian_assemble(lag_plan P, const float* v, const float* T, int32_t* stored, void* stream) {
+  LAG_CHECK(P && v && T && stored);
+  return jacobian_assemble(P, v, T, nullptr, stored, S(stream));
 }
 
 int lag_jacobian_info(lag_plan P, int64_t* blocks, int32_t* max_blocks, int32_t* bytes_per_block) {
@@ -605,15 +618,23 @@ int lag_vjp_assembled(lag_plan P, const float* w, float* JTw, void* stream) {
   return launch_jac_apply(P, P->pack_p, nullptr, w, 1.f, JTw, s);
 }
 
-int lag_gradient_assembled(lag_plan P, const float* v, const float* T, const float* R, float* g, double* out3,
-                           void* stream) {
-  LAG_CHECK(P && v && T && R && g && P->jac_ready);
-  hipStream_t s = S(stream);
-  int rc = objective_full(P, v, T, R, nullptr, P->img_b, out3 ? out3 : P->scalars + 8, s);
+// Objective and gradient with the stored Jacobian; u = T(phi) at v when the
+// assembly already produced it, else traced here.
+static int gradient_assembled(lag_plan P, const float* v, const float* T, const float* R, const float* u, float* g,
+                              double* out3, hipStream_t s) {
+  int rc = u ? objective_from_image(P, v, u, R, P->img_b, out3, s)
+             : objective_full(P, v, T, R, nullptr, P->img_b, out3, s);
   if (rc) return rc;
   if ((rc = launch_fill(g, P->n_unknowns, 0.f, s))) return rc;
   if ((rc = launch_jac_apply(P, P->pack_p, nullptr, P->img_b, 1.f, g, s))) return rc;
   return launch_reg(P, v, g, 1, 0, 1.f, s);
+}
+
+int lag_gradient_assembled(lag_plan P, const float* v, const float* T, const float* R, float* g, double* out3,
+                           void* stream) {
+  LAG_CHECK(P && v && T && R && g && P->jac_ready);
+  hipStream_t s = S(stream);
+  return gradient_assembled(P, v, T, R, nullptr, g, out3 ? out3 : P->scalars + 8, s);
 }
 
 // ---- PCG / Gauss-Newton ------------------------------------------------------
@@ -874,10 +895,11 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
   int rc;
   int32_t stored = 0;
   if (P->jac_k > 0) {
-    if ((rc = lag_jacobian_assemble(P, v, T, &stored, stream))) return rc;
+    if ((rc = jacobian_assemble(P, v, T, P->img_a, &stored, s))) return rc;
   }
   loc.assembled = stored;
-  if (stored) rc = lag_gradient_assembled(P, v, T, R, g, sc + 8, stream);
+  // the assembly's forward pass left T(phi) at v in img_a: no second trace
+  if (stored) rc = gradient_assembled(P, v, T, R, P->img_a, g, sc + 8, s);
   else rc = lag_gradient(P, v, T, R, g, sc + 8, stream);
   if (rc) return rc;
   if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;

@@ -119,7 +119,7 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
 int launch_tile_reduce(lag_plan P, float* out, hipStream_t s);
-int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, hipStream_t s);
+int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);
 int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
                      hipStream_t s);
 int tiles_setup(lag_plan P);       // partial-tile buffer + cover tables (plan creation)

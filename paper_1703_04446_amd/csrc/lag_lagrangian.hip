@@ -869,14 +869,16 @@ struct JacWriter {
 
 // Assemble the stored Jacobian, one wave per 64-row item over all bricks
 // (rows are independent here, so the launch is not tied to one block per
-// brick).  Slot of a row: brick, item, lane, as the matvec reads them.
+// brick).  Slot of a row: brick, item, lane, as the matvec reads them.  With
+// u != null also writes the transported image u = T(phi) (eq. rhoEndIR),
+// which the forward pass samples anyway.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Bricks B,
                                                          const typename VecT<D>::T* __restrict__ vp,
                                                          const float* __restrict__ T, float4* __restrict__ vals,
                                                          int* __restrict__ cells, unsigned char* __restrict__ cnt,
                                                          long long nslots, int kmax, int* __restrict__ maxcount,
-                                                         int* __restrict__ flags) {
+                                                         int* __restrict__ flags, float* __restrict__ u) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int items = brick_items(B);
   const long long nitems = (long long)B.nbricks * items;
@@ -902,7 +904,12 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
     Loc<D> L;
     locate_i<D>(g, S, phi, L);
     float gT[D], val;
-    sample_img<D, false, true>(T, g, L, val, gT);
+    sample_img<D, true, true>(T, g, L, val, gT);
+    if (u) {  // the transported image T(phi(x)) comes for free
+      long long pi = idx[0] + (long long)g.mi[0] * idx[1];
+      if (D == 3) pi += (long long)g.mi[0] * g.mi[1] * idx[2];
+      u[pi] = val;
+    }
     bool nz = false;
 #pragma unroll
     for (int a = 0; a < D; ++a) nz = nz || (gT[a] != 0.f);
@@ -1439,7 +1446,7 @@ int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, cons
   return launch_tile_reduce(P, out, s);
 }
 
-int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, hipStream_t s) {
+int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s) {
   Stages st = stages_for(P, -1);
   const lag::Bricks& B = P->bricks;
   const long long items = (long long)B.nbricks * B.nreg[0] * B.nreg[1] * B.nreg[2] * B.stride[0] * B.stride[1] *
@@ -1449,10 +1456,10 @@ int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, hipStream
   if (rc) return rc;
   if (P->geo.dim == 3)
     hipLaunchKernelGGL(k_jac_assemble<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, st, B, (const float4*)vpack, T,
-                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags);
+                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags, u);
   else
     hipLaunchKernelGGL(k_jac_assemble<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, st, B, (const float2*)vpack, T,
-                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags);
+                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags, u);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }

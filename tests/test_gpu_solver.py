@@ -182,6 +182,13 @@ def test_gn_step_monotone(torch, L):
         info = L.lag_gn_step(plan, dev.put(T), dev.put(R), v, vn)
         assert info["status"] == L.LAG_OK and info["accepted"] and info["assembled"]
         Js.append((info["J"], info["J_next"]))
+        # the step takes T(phi) at v from the assembly's forward pass; the
+        # traced objective at v must give the same J
+        out3 = torch.empty(3, dtype=torch.float64, device="cuda")
+        L.lag_objective(plan, v, dev.put(T), dev.put(R), dev.empty(plan.n_points), out3)
+        Jt = float(out3[0])
+        print("J step", info["J"], "J traced", Jt, flush=True)
+        assert abs(Jt - info["J"]) <= 1e-6 * abs(Jt)
         # oracle objective at the accepted iterate
         Jo = O.objective(OP, dev.get(vn).reshape(OP.vel_shape), T, R)["J"]
         assert abs(Jo - info["J_next"]) <= 1e-5 * abs(Jo)
