@@ -68,6 +68,7 @@ struct lag_plan_s {
   float* tile_part = nullptr;
   int* cover_start[3] = {nullptr, nullptr, nullptr};
   int2* cover_ent[3] = {nullptr, nullptr, nullptr};
+  int cover_max = 0;  // most covering bricks of a node along one axis
   // status flags written by kernels (bit 0: singular RK4 step Jacobian)
   int* flags = nullptr;
   // PCG control: device control block, pinned host mirrors (two slots, read

@@ -1174,8 +1174,10 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
 }
 
 // Sum the partial tiles into the velocity-grid output in a fixed order:
-// out[f][node] += sum over covering bricks (z, then y, then x order).
-template <int D>
+// out[f][node] += sum over covering bricks (z, then y, then x order).  With
+// K > 0 (at most K covering bricks per axis) all loads are issued before the
+// sum, which adds the same terms in the same order as the generic loops.
+template <int D, int K>
 __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fields, const float* __restrict__ part,
                                                         const int* __restrict__ cs0, const int2* __restrict__ ce0,
                                                         const int* __restrict__ cs1, const int2* __restrict__ ce1,
@@ -1189,18 +1191,53 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
   const int Y = (int)((r / g.mv[0]) % g.mv[1]);
   const int Z = D == 3 ? (int)(r / ((long long)g.mv[0] * g.mv[1])) : 0;
   const long long tsz = (long long)fields * B.tvol;
+  const float* pf = part + f * B.tvol;
   float sum = 0.f;
-  for (int ez = cs2[Z]; ez < cs2[Z + 1]; ++ez) {
-    const int2 cz = ce2[ez];
-    for (int ey = cs1[Y]; ey < cs1[Y + 1]; ++ey) {
-      const int2 cy = ce1[ey];
-      const int bzy = cy.x + B.nb[1] * cz.x;
-      const int tzy = cy.y + B.tdim[1] * cz.y;
-      for (int ex = cs0[X]; ex < cs0[X + 1]; ++ex) {
-        const int2 cx = ce0[ex];
-        const long long b = cx.x + (long long)B.nb[0] * bzy;
-        const int t = cx.y + B.tdim[0] * tzy;
-        sum += part[b * tsz + f * B.tvol + t];
+  if constexpr (K > 0) {
+    const int sx = cs0[X], nx = cs0[X + 1] - sx;
+    const int sy = cs1[Y], ny = cs1[Y + 1] - sy;
+    const int sz = cs2[Z], nz = cs2[Z + 1] - sz;
+    int2 cx[K], cy[K], cz[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      cx[k] = k < nx ? ce0[sx + k] : make_int2(0, 0);
+      cy[k] = k < ny ? ce1[sy + k] : make_int2(0, 0);
+      cz[k] = k < nz ? ce2[sz + k] : make_int2(0, 0);
+    }
+    float v[K][K][K];
+#pragma unroll
+    for (int kz = 0; kz < K; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < K; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx) {
+          v[kz][ky][kx] = 0.f;
+          if (kz < nz && ky < ny && kx < nx) {
+            const long long b = cx[kx].x + (long long)B.nb[0] * (cy[ky].x + B.nb[1] * cz[kz].x);
+            const int t = cx[kx].y + B.tdim[0] * (cy[ky].y + B.tdim[1] * cz[kz].y);
+            v[kz][ky][kx] = pf[b * tsz + t];
+          }
+        }
+#pragma unroll
+    for (int kz = 0; kz < K; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < K; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < K; ++kx)
+          if (kz < nz && ky < ny && kx < nx) sum += v[kz][ky][kx];
+  } else {
+    for (int ez = cs2[Z]; ez < cs2[Z + 1]; ++ez) {
+      const int2 cz = ce2[ez];
+      for (int ey = cs1[Y]; ey < cs1[Y + 1]; ++ey) {
+        const int2 cy = ce1[ey];
+        const int bzy = cy.x + B.nb[1] * cz.x;
+        const int tzy = cy.y + B.tdim[1] * cz.y;
+        for (int ex = cs0[X]; ex < cs0[X + 1]; ++ex) {
+          const int2 cx = ce0[ex];
+          const long long b = cx.x + (long long)B.nb[0] * bzy;
+          const int t = cx.y + B.tdim[0] * tzy;
+          sum += pf[b * tsz + t];
+        }
       }
     }
   }
@@ -1210,14 +1247,19 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
 int launch_tile_reduce(lag_plan P, float* out, hipStream_t s) {
   const long long tot = P->geo.nv * P->fields;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
-  if (P->geo.dim == 3)
-    hipLaunchKernelGGL(k_tile_reduce<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields, P->tile_part,
-                       P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1], P->cover_start[2],
-                       P->cover_ent[2], out);
-  else
-    hipLaunchKernelGGL(k_tile_reduce<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields, P->tile_part,
-                       P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1], P->cover_start[2],
-                       P->cover_ent[2], out);
+#define LAG_REDUCE(DIM, K)                                                                                       \
+  hipLaunchKernelGGL((k_tile_reduce<DIM, K>), dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields,      \
+                     P->tile_part, P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1],       \
+                     P->cover_start[2], P->cover_ent[2], out)
+  const bool small = P->cover_max <= 3;
+  if (P->geo.dim == 3) {
+    if (small) LAG_REDUCE(3, 3);
+    else LAG_REDUCE(3, 0);
+  } else {
+    if (small) LAG_REDUCE(2, 3);
+    else LAG_REDUCE(2, 0);
+  }
+#undef LAG_REDUCE
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
@@ -1247,6 +1289,7 @@ int tiles_setup(lag_plan P) {
       ent.insert(ent.end(), lists[X].begin(), lists[X].end());
     }
     start[m] = (int)ent.size();
+    for (int X = 0; X < m; ++X) P->cover_max = std::max(P->cover_max, (int)lists[X].size());
     LAG_HIP(hipMalloc(&P->cover_start[a], sizeof(int) * (m + 1)));
     LAG_HIP(hipMalloc(&P->cover_ent[a], sizeof(int2) * std::max<size_t>(ent.size(), 1)));
     LAG_HIP(hipMemcpy(P->cover_start[a], start.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice));
