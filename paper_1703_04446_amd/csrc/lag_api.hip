@@ -312,6 +312,15 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
     }
   }
   g.cell_img = (float)cell;
+  g.nvp = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.pv[a] = a < D ? g.mv[a] + 1 : 1;
+    g.nvp *= g.pv[a];
+  }
+  if (g.nvp >= (1LL << 31)) {  // packed-field offsets are 32-bit
+    free_plan(P);
+    return LAG_EUNSUPPORTED;
+  }
   P->fields = g.nodes * D;
   P->n_unknowns = (long long)P->fields * g.nv;
   choose_bricks(P, brick_target);
@@ -359,8 +368,8 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
   }
 
   const size_t vec = D == 3 ? sizeof(float4) : sizeof(float2);
-  ALLOC(P->pack_v, vec * g.nv * g.nodes);
-  ALLOC(P->pack_p, vec * g.nv * g.nodes);
+  ALLOC(P->pack_v, vec * g.nvp * g.nodes);
+  ALLOC(P->pack_p, vec * g.nvp * g.nodes);
   ALLOC(P->img_a, sizeof(float) * g.np);
   ALLOC(P->img_b, sizeof(float) * g.np);
   ALLOC(P->phi, sizeof(float) * g.np * D);

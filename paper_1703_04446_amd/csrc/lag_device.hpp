@@ -38,6 +38,8 @@ struct Geo {
   double ratio[3];      // m_vel / m_img
   long long np;         // image cells = characteristics
   long long nv;         // velocity cells per field
+  int pv[3];            // packed-field extents: mv + 1 on used axes (periodic ghost layer), else 1
+  long long nvp;        // packed-field nodes per time node
   float cell_img;       // image cell volume h^d
   // device flag of a graph-captured PCG loop: once non-zero, the kernels of
   // the loop return at entry (null outside captured graphs)
@@ -160,20 +162,24 @@ __device__ __forceinline__ void locate_i(const Geo& g, const Start<D>& S, const 
 // Vector field sampling: value and (optionally) spatial Jacobian G[c][a] =
 // d v_c / d y_a of the trilinear interpolant.  One-sided on grid lines
 // (the floor-selected cell), consistent with the oracle.
+// Packed fields carry a periodic ghost layer (k_pack), so the eight corners
+// of a cell sit at fixed offsets from its lower corner: +1 along x, +pv[0]
+// along y, +pv[0] pv[1] along z.
+__device__ __forceinline__ unsigned packed_corner(const Geo& g, int x0, int y0, int z0) {
+  return ((unsigned)z0 * (unsigned)g.pv[1] + (unsigned)y0) * (unsigned)g.pv[0] + (unsigned)x0;
+}
+
 template <bool GRAD>
 __device__ __forceinline__ void sample_vec(const float4* __restrict__ f, const Geo& g, const Loc<3>& L,
                                            float val[3], float G[3][3]) {
-  const int mx = g.mv[0], my = g.mv[1], mz = g.mv[2];
-  int x0 = wrapi(L.c[0], mx), y0 = wrapi(L.c[1], my), z0 = wrapi(L.c[2], mz);
-  int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
-  int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
-  int z1 = (z0 + 1 == mz) ? 0 : z0 + 1;
-  int r00 = (z0 * my + y0) * mx, r01 = (z0 * my + y1) * mx;
-  int r10 = (z1 * my + y0) * mx, r11 = (z1 * my + y1) * mx;
-  float4 a000 = f[r00 + x0], a100 = f[r00 + x1];
-  float4 a010 = f[r01 + x0], a110 = f[r01 + x1];
-  float4 a001 = f[r10 + x0], a101 = f[r10 + x1];
-  float4 a011 = f[r11 + x0], a111 = f[r11 + x1];
+  const int x0 = wrapi(L.c[0], g.mv[0]), y0 = wrapi(L.c[1], g.mv[1]), z0 = wrapi(L.c[2], g.mv[2]);
+  const unsigned sy = (unsigned)g.pv[0], sz = (unsigned)g.pv[0] * (unsigned)g.pv[1];
+  const float4* c0 = f + packed_corner(g, x0, y0, z0);
+  const float4* c1 = c0 + sz;
+  float4 a000 = c0[0], a100 = c0[1];
+  float4 a010 = c0[sy], a110 = c0[sy + 1];
+  float4 a001 = c1[0], a101 = c1[1];
+  float4 a011 = c1[sy], a111 = c1[sy + 1];
   const float fx = L.f[0], fy = L.f[1], fz = L.f[2];
 #define LAG_COMP(c, FLD)                                                         \
   {                                                                             \
@@ -198,12 +204,11 @@ __device__ __forceinline__ void sample_vec(const float4* __restrict__ f, const G
 template <bool GRAD>
 __device__ __forceinline__ void sample_vec(const float2* __restrict__ f, const Geo& g, const Loc<2>& L,
                                            float val[2], float G[2][2]) {
-  const int mx = g.mv[0], my = g.mv[1];
-  int x0 = wrapi(L.c[0], mx), y0 = wrapi(L.c[1], my);
-  int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
-  int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
-  float2 a00 = f[y0 * mx + x0], a10 = f[y0 * mx + x1];
-  float2 a01 = f[y1 * mx + x0], a11 = f[y1 * mx + x1];
+  const int x0 = wrapi(L.c[0], g.mv[0]), y0 = wrapi(L.c[1], g.mv[1]);
+  const unsigned sy = (unsigned)g.pv[0];
+  const float2* c0 = f + packed_corner(g, x0, y0, 0);
+  float2 a00 = c0[0], a10 = c0[1];
+  float2 a01 = c0[sy], a11 = c0[sy + 1];
   const float fx = L.f[0], fy = L.f[1];
 #define LAG_COMP(c, FLD)                                                   \
   {                                                                       \
@@ -231,8 +236,8 @@ __device__ __forceinline__ void sample_vel(const typename VecT<D>::T* __restrict
     int j0 = st.j0[q];
     float th = st.th[q];
     float v0[D], v1[D], G0[D][D], G1[D][D];
-    sample_vec<GRAD>(f + (long long)j0 * g.nv, g, L, v0, G0);
-    sample_vec<GRAD>(f + (long long)(j0 + 1) * g.nv, g, L, v1, G1);
+    sample_vec<GRAD>(f + (long long)j0 * g.nvp, g, L, v0, G0);
+    sample_vec<GRAD>(f + (long long)(j0 + 1) * g.nvp, g, L, v1, G1);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       val[c] = lerpf(v0[c], v1[c], th);

@@ -465,15 +465,21 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
 // ---------------------------------------------------------------------------
 // kernels
 
+// Interleave the D components of each node (per time node) and add the
+// periodic ghost layer: packed node (X, Y, Z), X <= mv[0] etc., holds grid
+// node (X mod mv[0], Y mod mv[1], Z mod mv[2]).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_pack(const float* __restrict__ v, typename VecT<D>::T* __restrict__ out,
-                                                 long long nv, int nodes, const int* __restrict__ halt) {
+                                                 Geo g, const int* __restrict__ halt) {
   if (halted(halt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long tot = nv * nodes;
+  const long long tot = g.nvp * g.nodes;
   if (i >= tot) return;
-  long long j = i / nv, x = i - j * nv;
-  const float* b = v + j * D * nv + x;
+  const long long j = i / g.nvp, q = i - j * g.nvp;
+  const int X = (int)(q % g.pv[0]), Y = (int)((q / g.pv[0]) % g.pv[1]), Z = (int)(q / ((long long)g.pv[0] * g.pv[1]));
+  const int x = X == g.mv[0] ? 0 : X, y = Y == g.mv[1] ? 0 : Y, z = Z == g.mv[2] ? 0 : Z;
+  const long long nv = g.nv;
+  const float* b = v + j * D * nv + ((long long)z * g.mv[1] + y) * g.mv[0] + x;
   if constexpr (D == 3) {
     out[i] = make_float4(b[0], b[nv], b[2 * nv], 0.f);
   } else {
@@ -963,28 +969,25 @@ __device__ __forceinline__ float jac_block_dot(const Geo& g, const int cell[D], 
                                                const typename VecT<D>::T* __restrict__ pp) {
   float s = 0.f;
   if constexpr (D == 3) {
-    const int mx = g.mv[0], my = g.mv[1], mz = g.mv[2];
-    int x0 = wrapi(cell[0], mx), y0 = wrapi(cell[1], my), z0 = wrapi(cell[2], mz);
-    int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
-    int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
-    int z1 = (z0 + 1 == mz) ? 0 : z0 + 1;
-    const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+    const int x0 = wrapi(cell[0], g.mv[0]), y0 = wrapi(cell[1], g.mv[1]), z0 = wrapi(cell[2], g.mv[2]);
+    const unsigned sy = (unsigned)g.pv[0], sz = (unsigned)g.pv[0] * (unsigned)g.pv[1];
+    const float4* c0 = pp + packed_corner(g, x0, y0, z0);
+    const unsigned off[8] = {0u, 1u, sy, sy + 1u, sz, sz + 1u, sz + sy, sz + sy + 1u};
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
-      float4 q = pp[((long long)zs[(o >> 2) & 1] * my + ys[(o >> 1) & 1]) * mx + xs[o & 1]];
+      float4 q = c0[off[o]];
       s = fmaf(f[3 * o], q.x, s);
       s = fmaf(f[3 * o + 1], q.y, s);
       s = fmaf(f[3 * o + 2], q.z, s);
     }
   } else {
-    const int mx = g.mv[0], my = g.mv[1];
-    int x0 = wrapi(cell[0], mx), y0 = wrapi(cell[1], my);
-    int x1 = (x0 + 1 == mx) ? 0 : x0 + 1;
-    int y1 = (y0 + 1 == my) ? 0 : y0 + 1;
-    const int xs[2] = {x0, x1}, ys[2] = {y0, y1};
+    const int x0 = wrapi(cell[0], g.mv[0]), y0 = wrapi(cell[1], g.mv[1]);
+    const unsigned sy = (unsigned)g.pv[0];
+    const float2* c0 = pp + packed_corner(g, x0, y0, 0);
+    const unsigned off[4] = {0u, 1u, sy, sy + 1u};
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
-      float2 q = pp[(long long)ys[(o >> 1) & 1] * mx + xs[o & 1]];
+      float2 q = c0[off[o]];
       s = fmaf(f[2 * o], q.x, s);
       s = fmaf(f[2 * o + 1], q.y, s);
     }
@@ -1318,14 +1321,12 @@ static inline Stages stages_for(lag_plan P, int dir) {
 static inline int model_dir(lag_plan P) { return P->prob.model == LAG_TRANSPORT ? -1 : 1; }
 
 int launch_pack(lag_plan P, const float* v, void* dst, hipStream_t s) {
-  long long tot = P->geo.nv * P->geo.nodes;
+  long long tot = P->geo.nvp * P->geo.nodes;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
   if (P->geo.dim == 3)
-    hipLaunchKernelGGL(k_pack<3>, dim3(grid), dim3(kBlock), 0, s, v, (float4*)dst, P->geo.nv, P->geo.nodes,
-                       P->geo.halt);
+    hipLaunchKernelGGL(k_pack<3>, dim3(grid), dim3(kBlock), 0, s, v, (float4*)dst, P->geo, P->geo.halt);
   else
-    hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(kBlock), 0, s, v, (float2*)dst, P->geo.nv, P->geo.nodes,
-                       P->geo.halt);
+    hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(kBlock), 0, s, v, (float2*)dst, P->geo, P->geo.halt);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
