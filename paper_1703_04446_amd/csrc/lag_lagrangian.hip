@@ -462,6 +462,121 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
   return ok;
 }
 
+// Stored-trajectory variant for the assembly.  Pass 1 records the step start
+// points phi_k (k = 0..N-1) of the characteristic, with the same operations
+// as forward_pass without tangents; pass 2 runs the exact reverse sweep of
+// the discrete RK4 map (eq. phiRK4): from lambda_N = grad T(phi_N), each step
+// back forms the stage adjoints and lambda_k = lambda_{k+1} + sum_i G_i^T kb_i,
+// and scatters kb_i at the stage points (last stage first).  No flow
+// Jacobian and no 3x3 solves: fewer operations than forward recovery, and
+// no failure when a step Jacobian is singular.  `traj` is this thread's
+// slice of an LDS array with stride `ts` floats between entries.
+template <int D>
+__device__ __forceinline__ void forward_record(const Geo& g, const Stages& st,
+                                               const typename VecT<D>::T* __restrict__ vp, const Start<D>& S,
+                                               float phi[D], float* traj, int ts) {
+  const float dt = st.dt, hdt = 0.5f * dt;
+  float G[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) phi[a] = 0.f;
+  for (int k = 0; k < g.nsteps; ++k) {
+    const int q = 4 * k;
+#pragma unroll
+    for (int a = 0; a < D; ++a) traj[(k * D + a) * ts] = phi[a];
+    float k1[D], k2[D], k3[D], k4[D], P[D];
+    Loc<D> L;
+    locate_v<D>(g, S, phi, L);
+    sample_vel<D, false, false>(vp, g, st, q, L, k1, G);
+    stage_pos<D>(phi, hdt, k1, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, false, false>(vp, g, st, q + 1, L, k2, G);
+    stage_pos<D>(phi, hdt, k2, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, false, false>(vp, g, st, q + 2, L, k3, G);
+    stage_pos<D>(phi, dt, k3, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, false, false>(vp, g, st, q + 3, L, k4, G);
+    rk4_update<D>(phi, dt, k1, k2, k3, k4);
+  }
+}
+
+template <int D, class Acc>
+__device__ __forceinline__ void reverse_sweep(const Geo& g, const Stages& st,
+                                              const typename VecT<D>::T* __restrict__ vp, const Start<D>& S,
+                                              const float* traj, int ts, float lam[D], Acc& acc) {
+  const float dt = st.dt, hdt = 0.5f * dt;
+  const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
+  Merge<D, false> mg;
+  mg.reset();
+  for (int k = g.nsteps - 1; k >= 0; --k) {
+    const int q = 4 * k;
+    float phi[D], k1[D], k2[D], k3[D], k4[D], P[D];
+    float G1[D][D], G2[D][D], G3[D][D], G4[D][D];
+    Loc<D> L1, L2, L3, L4;
+#pragma unroll
+    for (int a = 0; a < D; ++a) phi[a] = traj[(k * D + a) * ts];
+    locate_v<D>(g, S, phi, L1);
+    sample_vel<D, false, true>(vp, g, st, q, L1, k1, G1);
+    stage_pos<D>(phi, hdt, k1, P);
+    locate_v<D>(g, S, P, L2);
+    sample_vel<D, false, true>(vp, g, st, q + 1, L2, k2, G2);
+    stage_pos<D>(phi, hdt, k2, P);
+    locate_v<D>(g, S, P, L3);
+    sample_vel<D, false, true>(vp, g, st, q + 2, L3, k3, G3);
+    stage_pos<D>(phi, dt, k3, P);
+    locate_v<D>(g, S, P, L4);
+    sample_vel<D, false, true>(vp, g, st, q + 3, L4, k4, G4);
+    (void)k4;
+    float kb1[D], kb2[D], kb3[D], kb4[D], pb[D], sum[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb4[a] = c6 * lam[a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float t = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) t = fmaf(G4[c][a], kb4[c], t);
+      pb[a] = t;
+      sum[a] = t;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb3[a] = fmaf(dt, pb[a], c3 * lam[a]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float t = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) t = fmaf(G3[c][a], kb3[c], t);
+      pb[a] = t;
+      sum[a] += t;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb2[a] = fmaf(hdt, pb[a], c3 * lam[a]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float t = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) t = fmaf(G2[c][a], kb2[c], t);
+      pb[a] = t;
+      sum[a] += t;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) kb1[a] = fmaf(hdt, pb[a], c6 * lam[a]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float t = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) t = fmaf(G1[c][a], kb1[c], t);
+      sum[a] += t;
+    }
+    mg.add(acc, st, L4, q + 3, kb4);
+    mg.add(acc, st, L3, q + 2, kb3);
+    mg.add(acc, st, L2, q + 1, kb2);
+    mg.add(acc, st, L1, q, kb1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) lam[a] += sum[a];
+  }
+  mg.flush(acc);
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 
@@ -878,7 +993,7 @@ struct JacWriter {
 // brick).  Slot of a row: brick, item, lane, as the matvec reads them.  With
 // u != null also writes the transported image u = T(phi) (eq. rhoEndIR),
 // which the forward pass samples anyway.
-template <int D>
+template <int D, bool STORED>
 __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Bricks B,
                                                          const typename VecT<D>::T* __restrict__ vp,
                                                          const float* __restrict__ T, float4* __restrict__ vals,
@@ -902,11 +1017,14 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
   const long long slot = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2] + (long long)w * 64 + lane;
   int count = 0;
   bool bad = false;
+  extern __shared__ float traj_lds[];  // STORED: [step][axis][thread]
+  float* traj = traj_lds + threadIdx.x;
   if (in) {
     Start<D> S;
     make_start_idx<D>(g, idx, S);
     float phi[D], dphi[D], F[D][D];
-    forward_pass<D, false, false, true>(g, st, vp, nullptr, S, phi, dphi, F);
+    if constexpr (STORED) forward_record<D>(g, st, vp, S, phi, traj, kBlock);
+    else forward_pass<D, false, false, true>(g, st, vp, nullptr, S, phi, dphi, F);
     Loc<D> L;
     locate_i<D>(g, S, phi, L);
     float gT[D], val;
@@ -921,12 +1039,17 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
     for (int a = 0; a < D; ++a) nz = nz || (gT[a] != 0.f);
     if (nz) {
       float y0[D];
+      if constexpr (STORED) {
 #pragma unroll
-      for (int b = 0; b < D; ++b) {
-        float t = 0.f;
+        for (int b = 0; b < D; ++b) y0[b] = gT[b];  // adjoint at t = 1
+      } else {
 #pragma unroll
-        for (int a = 0; a < D; ++a) t = fmaf(F[a][b], gT[a], t);
-        y0[b] = t;
+        for (int b = 0; b < D; ++b) {  // adjoint at t = 0 (forward recovery)
+          float t = 0.f;
+#pragma unroll
+          for (int a = 0; a < D; ++a) t = fmaf(F[a][b], gT[a], t);
+          y0[b] = t;
+        }
       }
       JacWriter<D> jw;
       jw.vals = vals;
@@ -937,7 +1060,8 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
       jw.count = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) jw.org[a] = org[a];
-      if (!adjoint_pass<D, false>(g, st, vp, S, y0, jw)) bad = true;
+      if constexpr (STORED) reverse_sweep<D>(g, st, vp, S, traj, kBlock, y0, jw);
+      else if (!adjoint_pass<D, false>(g, st, vp, S, y0, jw)) bad = true;
       count = jw.count;
     }
   }
@@ -1498,12 +1622,21 @@ int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u,
   unsigned grid = grid_for((items + kBlock / 64 - 1) / (kBlock / 64));
   int rc = launch_zero_i(P->jac_max, 2, s);
   if (rc) return rc;
-  if (P->geo.dim == 3)
-    hipLaunchKernelGGL(k_jac_assemble<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, st, B, (const float4*)vpack, T,
-                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags, u);
-  else
-    hipLaunchKernelGGL(k_jac_assemble<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, st, B, (const float2*)vpack, T,
-                       P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags, u);
+  // the stored-trajectory sweep keeps N step start points per thread in LDS
+  const size_t traj = sizeof(float) * (size_t)P->geo.nsteps * P->geo.dim * kBlock;
+  const bool stored = traj <= 64 * 1024;
+  const size_t lds = stored ? traj : 0;
+#define LAG_ASM(DIM, ST, VT)                                                                                     \
+  hipLaunchKernelGGL((k_jac_assemble<DIM, ST>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B, (const VT*)vpack, \
+                     T, P->jac_vals, P->jac_cell, P->jac_cnt, P->jac_slots, P->jac_k, P->jac_max, P->flags, u)
+  if (P->geo.dim == 3) {
+    if (stored) LAG_ASM(3, true, float4);
+    else LAG_ASM(3, false, float4);
+  } else {
+    if (stored) LAG_ASM(2, true, float2);
+    else LAG_ASM(2, false, float2);
+  }
+#undef LAG_ASM
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
