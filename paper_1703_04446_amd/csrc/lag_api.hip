@@ -661,12 +661,12 @@ static int read_scalars(lag_plan P, double* host, int off, int cnt, hipStream_t 
 static int ensure_pcg_ctl(lag_plan P) {
   if (P->ctl && P->ctl_ev[1]) return LAG_OK;
   std::lock_guard<std::mutex> lk(api_lock());
-  if (!P->ctl_host) LAG_HIP(hipHostMalloc((void**)&P->ctl_host, sizeof(int) * 8, hipHostMallocDefault));
+  if (!P->ctl_host) LAG_HIP(hipHostMalloc((void**)&P->ctl_host, sizeof(int) * 16, hipHostMallocDefault));
   if (!P->sc_host) LAG_HIP(hipHostMalloc((void**)&P->sc_host, sizeof(double) * 8, hipHostMallocDefault));
   if (!P->gstream) LAG_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
   for (int k = 0; k < 2; ++k)
     if (!P->ctl_ev[k]) LAG_HIP(hipEventCreateWithFlags(&P->ctl_ev[k], hipEventDisableTiming));
-  if (!P->ctl) LAG_HIP(hipMalloc((void**)&P->ctl, sizeof(int) * 4));
+  if (!P->ctl) LAG_HIP(hipMalloc((void**)&P->ctl, sizeof(int) * 8));
   return LAG_OK;
 }
 
@@ -733,7 +733,10 @@ static int pcg_finish(lag_plan P, double nb, lag_pcg_info* info, hipStream_t s) 
 // the device, so the host enqueues iteration k + 1 before it reads the
 // control block of iteration k: the GPU does not wait for the host between
 // iterations, and at most one enqueued iteration finds the halt flag set and
-// does nothing.  Timed matvec launches of such an iteration are dropped.
+// does nothing.  When the residual trend says iteration k will meet the
+// tolerance, the host waits for it instead of enqueuing k + 1 (scheduling
+// only; the arithmetic is the same).  Timed matvec launches of an iteration
+// that found the halt flag set are dropped.
 template <class Op>
 static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int32_t maxit, lag_pcg_info* info,
                     hipStream_t s) {
@@ -748,25 +751,37 @@ static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int3
   std::vector<int> prof_at;
   prof_at.reserve(maxit > 0 ? maxit : 0);
   int enq = 0;
+  const double thresh = tol * tol * nb * nb;
+  double rr_prev = nb * nb;  // r.r after iteration it - 2 (b.b before the first)
+  auto wait_slot = [&](int slot, bool* stop, double* rr) {
+    const hipError_t e = hipEventSynchronize(P->ctl_ev[slot]);
+    if (e != hipSuccess) return set_hip_error(e);
+    const int* c = P->ctl_host + 8 * slot;
+    *stop = c[0] != 0;
+    *rr = reinterpret_cast<const double*>(c)[2];
+    return (int)LAG_OK;
+  };
   P->geo.halt = P->ctl;
   for (int it = 0; it < maxit; ++it) {
     prof_at.push_back(P->prof_n);
     if ((rc = pcg_iteration(P, H, x, s))) break;
     ++enq;
     const int slot = it & 1;
-    if (hipMemcpyAsync(P->ctl_host + 4 * slot, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipMemcpyAsync(P->ctl_host + 8 * slot, P->ctl, sizeof(int) * 6, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipEventRecord(P->ctl_ev[slot], s) != hipSuccess) {
       rc = set_hip_error(hipGetLastError());
       break;
     }
-    if (it > 0) {
-      const hipError_t e = hipEventSynchronize(P->ctl_ev[slot ^ 1]);
-      if (e != hipSuccess) {
-        rc = set_hip_error(e);
-        break;
-      }
-      if (P->ctl_host[4 * (slot ^ 1)] != 0) break;
-    }
+    if (it == 0) continue;
+    bool stop = false;
+    double rr = 0.0;
+    if ((rc = wait_slot(slot ^ 1, &stop, &rr)) || stop) break;
+    // r.r after iteration it, extrapolated from the last ratio: when it
+    // comes within a factor 2 of the tolerance (residuals fall unevenly),
+    // wait for iteration it instead of enqueuing it + 1
+    const bool likely = rr_prev > 0.0 && rr * (rr / rr_prev) <= 4.0 * thresh;
+    rr_prev = rr;
+    if (likely && ((rc = wait_slot(slot, &stop, &rr)) || stop)) break;
   }
   P->geo.halt = nullptr;
   if (rc) return rc;
@@ -833,11 +848,11 @@ static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, 
   for (int l = 0; l < launches; ++l) {
     const int slot = l & 1;
     LAG_HIP(hipGraphLaunch(P->pcg_exec, s));
-    LAG_HIP(hipMemcpyAsync(P->ctl_host + 4 * slot, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    LAG_HIP(hipMemcpyAsync(P->ctl_host + 8 * slot, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
     LAG_HIP(hipEventRecord(P->ctl_ev[slot], s));
     if (l > 0) {
       LAG_HIP(hipEventSynchronize(P->ctl_ev[slot ^ 1]));
-      if (P->ctl_host[4 * (slot ^ 1)] != 0) break;
+      if (P->ctl_host[8 * (slot ^ 1)] != 0) break;
     }
   }
   return pcg_finish(P, nb, info, s);

@@ -184,14 +184,16 @@ __global__ void k_pcg_ctl_init(int* ctl, const double* sc, int maxit) {
   ctl[0] = sc[4] != 0.0 ? 2 : (sc[3] <= sc[6] ? 1 : (maxit <= 0 ? 3 : 0));
 }
 
-// After an iteration: sc[3] = r.r from the `rr` partials, sc[0] = sc[2] (the
-// new r.z becomes current), then the stopping test.
+// After an iteration: sc[3] = r.r from the `rr` partials (mirrored into the
+// control block for the host), sc[0] = sc[2] (the new r.z becomes current),
+// then the stopping test.
 __global__ void __launch_bounds__(kBlock) k_pcg_check(int* ctl, double* sc, const double* __restrict__ rr, int nrr) {
   if (ctl[0] != 0) return;
   __shared__ double sh[kBlock];
   const double t = sum_partials(rr, nrr, sh);
   if (threadIdx.x != 0) return;
   sc[3] = t;
+  reinterpret_cast<double*>(ctl)[2] = t;
   sc[0] = sc[2];
   const int it = ctl[1] + 1;
   if (sc[4] != 0.0) {     // this iteration broke down: it does not count

@@ -74,8 +74,8 @@ struct lag_plan_s {
   // PCG control: device control block, pinned host mirrors (two slots, read
   // one iteration late), their copy events, the capture stream and the
   // cached graph executable with the arguments it was captured for
-  int* ctl = nullptr;          // device int[4]
-  int* ctl_host = nullptr;     // pinned host int[2][4]
+  int* ctl = nullptr;          // device int[8]: status, iterations, cap, -, r.r (double at [4])
+  int* ctl_host = nullptr;     // pinned host int[2][8]
   double* sc_host = nullptr;   // pinned host double[8]
   hipEvent_t ctl_ev[2] = {nullptr, nullptr};
   hipStream_t gstream = nullptr;
