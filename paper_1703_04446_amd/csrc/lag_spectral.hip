@@ -144,10 +144,10 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // In-LDS Stockham FFT of `lines` lines of length n (buffers [lines][ls],
-// line stride ls >= n).  Returns the buffer holding the result.  INV selects
-// exp(+2 pi i ...).
+// line stride ls >= n), twiddles tw (the table of L staged in LDS).  Returns
+// the buffer holding the result.  INV selects exp(+2 pi i ...).
 template <bool INV>
-__device__ float2* lds_fft(const FftLine& L, int lines, int ls, float2* b0, float2* b1) {
+__device__ float2* lds_fft(const FftLine& L, const float2* tw, int lines, int ls, float2* b0, float2* b1) {
   const int n = L.n;
   int Ns = 1;
   for (int st = 0; st < L.nrad; ++st) {
@@ -165,7 +165,7 @@ __device__ float2* lds_fft(const FftLine& L, int lines, int ls, float2* b0, floa
       for (int r = 0; r < 5; ++r) {
         if (r < R) {
           float2 x = src[j + r * nb];
-          float2 t = L.tw[r * k * span];
+          float2 t = tw[r * k * span];
           if (INV) t.y = -t.y;
           v[r] = r ? cmul(x, t) : x;
         }
@@ -194,7 +194,7 @@ __device__ float2* lds_fft(const FftLine& L, int lines, int ls, float2* b0, floa
 #pragma unroll
             for (int r = 1; r < 5; ++r) {
               if (r < R) {
-                float2 t = L.tw[((r * s) % R) * step];
+                float2 t = tw[((r * s) % R) * step];
                 if (INV) t.y = -t.y;
                 float2 m = cmul(v[r], t);
                 acc.x += m.x;
@@ -235,14 +235,18 @@ struct Symbol {
 // IN_REAL: read float input (imaginary 0); OUT_REAL: write the real part.
 template <int D, int MODE, bool IN_REAL, bool OUT_REAL>
 __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, FftLine L, Symbol sym,
-                                                     const void* __restrict__ in, void* __restrict__ out) {
+                                                     const void* __restrict__ in, void* __restrict__ out, int cx) {
   if (halted(g.halt)) return;
   extern __shared__ float2 sh[];
   const int n = L.n;
   const int ls = n | 1;     // odd line stride: the y and z passes write across lines without bank conflicts
   float2* b0 = sh;
   float2* b1 = sh + lpb * ls;
-  const int m0 = g.mv[0], m1 = g.mv[1], m2 = D == 3 ? g.mv[2] : 1;
+  float2* twl = sh + 2 * lpb * ls;  // twiddles, staged with the first load
+  for (int q = threadIdx.x; q < n; q += blockDim.x) twl[q] = L.tw[q];
+  // y and z passes run over the half spectrum along x: cx = m_x / 2 + 1 columns
+  const int m0 = cx, m1 = g.mv[1], m2 = D == 3 ? g.mv[2] : 1;
+  const long long fstride = (long long)m0 * m1 * m2;
   const int fields = g.nodes * D;
   // group decomposition
   long long group = blockIdx.x;
@@ -270,11 +274,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
     int x0 = xg * lpb;
     nlines = min(lpb, m0 - x0);
     if (axis == 1) {
-      base = (long long)f * g.nv + (long long)o * m0 * m1 + x0;
+      base = (long long)f * fstride + (long long)o * m0 * m1 + x0;
       estride = m0;
       c2 = o;
     } else {
-      base = (long long)f * g.nv + (long long)o * m0 + x0;
+      base = (long long)f * fstride + (long long)o * m0 + x0;
       estride = (long long)m0 * m1;
       c1 = o;
     }
@@ -302,9 +306,9 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
   __syncthreads();
   float2* res;
   if (MODE == 1) {
-    res = lds_fft<true>(L, nlines, ls, b0, b1);
+    res = lds_fft<true>(L, twl, nlines, ls, b0, b1);
   } else {
-    res = lds_fft<false>(L, nlines, ls, b0, b1);
+    res = lds_fft<false>(L, twl, nlines, ls, b0, b1);
   }
   if (MODE == 2) {
     // divide by the symbol; the fused axis is the last one
@@ -334,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
       res[l * ls + i] = make_float2(v.x * inv, v.y * inv);
     }
     __syncthreads();
-    res = lds_fft<true>(L, nlines, ls, res, other);
+    res = lds_fft<true>(L, twl, nlines, ls, res, other);
   }
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
     int i, l;
@@ -349,6 +353,83 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
     float2 v = res[l * ls + i];
     if (OUT_REAL) ((float*)out)[a] = v.x;
     else ((float2*)out)[a] = v;
+  }
+}
+
+// x pass, forward, real input: rows 2p and 2p + 1 of the real field form one
+// complex line a + i b; after its FFT Z the half spectra of the two rows are
+// A(k) = (Z(k) + conj Z(n-k)) / 2 and B(k) = (Z(k) - conj Z(n-k)) / 2i,
+// stored for k = 0 .. n/2 (the rest follows from Hermitian symmetry).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fft_x_r2c(Geo g, int lpb, FftLine L, const float* __restrict__ in,
+                                                      float2* __restrict__ out, long long rows, int cx) {
+  if (halted(g.halt)) return;
+  extern __shared__ float2 sh[];
+  const int n = L.n, ls = n | 1;
+  float2* b0 = sh;
+  float2* b1 = sh + lpb * ls;
+  float2* twl = sh + 2 * lpb * ls;  // twiddles, staged with the first load
+  for (int q = threadIdx.x; q < n; q += blockDim.x) twl[q] = L.tw[q];
+  const long long pairs = (rows + 1) / 2;
+  const long long pr0 = (long long)blockIdx.x * lpb;
+  if (pr0 >= pairs) return;
+  const int nlines = (int)min((long long)lpb, pairs - pr0);
+  for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
+    const int l = e / n, i = e - l * n;
+    const long long ra = 2 * (pr0 + l);
+    const float a = in[ra * n + i];
+    const float b = ra + 1 < rows ? in[(ra + 1) * n + i] : 0.f;
+    b0[l * ls + i] = make_float2(a, b);
+  }
+  __syncthreads();
+  const float2* res = lds_fft<false>(L, twl, nlines, ls, b0, b1);
+  for (int e = threadIdx.x; e < nlines * cx; e += blockDim.x) {
+    const int l = e / cx, k = e - l * cx;
+    const long long ra = 2 * (pr0 + l);
+    const float2 z = res[l * ls + k], zm = res[l * ls + (k == 0 ? 0 : n - k)];
+    out[ra * cx + k] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+    if (ra + 1 < rows) out[(ra + 1) * cx + k] = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
+  }
+}
+
+// x pass, inverse, real output: the inverse of k_fft_x_r2c.  The two rows'
+// half spectra A, B are extended by Hermitian symmetry, the line A + i B is
+// transformed back, and its real and imaginary parts are the two rows.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fft_x_c2r(Geo g, int lpb, FftLine L, const float2* __restrict__ in,
+                                                      float* __restrict__ out, long long rows, int cx) {
+  if (halted(g.halt)) return;
+  extern __shared__ float2 sh[];
+  const int n = L.n, ls = n | 1;
+  float2* b0 = sh;
+  float2* b1 = sh + lpb * ls;
+  float2* twl = sh + 2 * lpb * ls;  // twiddles, staged with the first load
+  for (int q = threadIdx.x; q < n; q += blockDim.x) twl[q] = L.tw[q];
+  const long long pairs = (rows + 1) / 2;
+  const long long pr0 = (long long)blockIdx.x * lpb;
+  if (pr0 >= pairs) return;
+  const int nlines = (int)min((long long)lpb, pairs - pr0);
+  for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
+    const int l = e / n, i = e - l * n;
+    const long long ra = 2 * (pr0 + l);
+    const bool direct = i < cx;
+    const int k = direct ? i : n - i;
+    float2 a = in[ra * cx + k];
+    float2 b = ra + 1 < rows ? in[(ra + 1) * cx + k] : make_float2(0.f, 0.f);
+    if (!direct) {
+      a.y = -a.y;
+      b.y = -b.y;
+    }
+    b0[l * ls + i] = make_float2(a.x - b.y, a.y + b.x);
+  }
+  __syncthreads();
+  const float2* res = lds_fft<true>(L, twl, nlines, ls, b0, b1);
+  for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
+    const int l = e / n, i = e - l * n;
+    const long long ra = 2 * (pr0 + l);
+    const float2 v = res[l * ls + i];
+    out[ra * n + i] = v.x;
+    if (ra + 1 < rows) out[(ra + 1) * n + i] = v.y;
   }
 }
 
@@ -434,19 +515,40 @@ static int fft_pass(lag_plan P, int axis, const void* in, void* out, hipStream_t
   sym.gamma = (float)P->prob.gamma;
   sym.curv = P->prob.reg == LAG_CURVATURE;
   sym.nv = (float)P->geo.nv;
-  const int m0 = P->prob.vel_m[0], m1 = P->prob.vel_m[1], m2 = D == 3 ? P->prob.vel_m[2] : 1;
-  const int lpb = lines_per_block(L.n, axis, m0);
-  long long groups;
-  if (axis == 0) {
-    long long rows = (long long)P->fields * m1 * m2;
-    groups = (rows + lpb - 1) / lpb;
-  } else {
-    long long xg = (m0 + lpb - 1) / lpb;
-    groups = xg * (axis == 1 ? m2 : m1) * P->fields;
-  }
-  size_t lds = sizeof(float2) * 2 * (size_t)lpb * (L.n | 1);
+  const int m1 = P->prob.vel_m[1], m2 = D == 3 ? P->prob.vel_m[2] : 1;
+  const int cx = P->prob.vel_m[0] / 2 + 1;  // half spectrum along x
+  const int lpb = lines_per_block(L.n, axis, cx);
+  const long long xg = (cx + lpb - 1) / lpb;
+  const long long groups = xg * (axis == 1 ? m2 : m1) * P->fields;
+  size_t lds = sizeof(float2) * (2 * (size_t)lpb * (L.n | 1) + L.n);
   hipLaunchKernelGGL((k_fft_axis<D, MODE, IR, OR>), dim3((unsigned)groups), dim3(kBlock), lds, s, P->geo, axis, lpb,
-                     L, sym, in, out);
+                     L, sym, in, out, cx);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
+// x pass of the real field (forward: real rows -> half spectra; inverse:
+// half spectra -> real rows), two rows per complex line
+template <int D>
+static int fft_x(lag_plan P, bool inverse, const void* in, void* out, hipStream_t s) {
+  FftLine L;
+  L.n = P->prob.vel_m[0];
+  L.nrad = P->fft_nrad[0];
+  for (int i = 0; i < 16; ++i) L.rad[i] = P->fft_rad[0][i];
+  L.tw = P->fft_tw[0];
+  const int m1 = P->prob.vel_m[1], m2 = D == 3 ? P->prob.vel_m[2] : 1;
+  const int cx = L.n / 2 + 1;
+  const long long rows = (long long)P->fields * m1 * m2;
+  const long long pairs = (rows + 1) / 2;
+  const int lpb = lines_per_block(L.n, 0, cx);
+  const unsigned groups = (unsigned)((pairs + lpb - 1) / lpb);
+  const size_t lds = sizeof(float2) * (2 * (size_t)lpb * (L.n | 1) + L.n);
+  if (inverse)
+    hipLaunchKernelGGL(k_fft_x_c2r<D>, dim3(groups), dim3(kBlock), lds, s, P->geo, lpb, L, (const float2*)in,
+                       (float*)out, rows, cx);
+  else
+    hipLaunchKernelGGL(k_fft_x_r2c<D>, dim3(groups), dim3(kBlock), lds, s, P->geo, lpb, L, (const float*)in,
+                       (float2*)out, rows, cx);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
@@ -457,15 +559,15 @@ int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s) {
   float2* buf = P->fft_buf;
   int rc;
   if (P->geo.dim == 3) {
-    if ((rc = fft_pass<3, 0, true, false>(P, 0, r, buf, s))) return rc;
+    if ((rc = fft_x<3>(P, false, r, buf, s))) return rc;
     if ((rc = fft_pass<3, 0, false, false>(P, 1, buf, buf, s))) return rc;
     if ((rc = fft_pass<3, 2, false, false>(P, 2, buf, buf, s))) return rc;
     if ((rc = fft_pass<3, 1, false, false>(P, 1, buf, buf, s))) return rc;
-    if ((rc = fft_pass<3, 1, false, true>(P, 0, buf, z, s))) return rc;
+    if ((rc = fft_x<3>(P, true, buf, z, s))) return rc;
   } else {
-    if ((rc = fft_pass<2, 0, true, false>(P, 0, r, buf, s))) return rc;
+    if ((rc = fft_x<2>(P, false, r, buf, s))) return rc;
     if ((rc = fft_pass<2, 2, false, false>(P, 1, buf, buf, s))) return rc;
-    if ((rc = fft_pass<2, 1, false, true>(P, 0, buf, z, s))) return rc;
+    if ((rc = fft_x<2>(P, true, buf, z, s))) return rc;
   }
   return LAG_OK;
 }
