@@ -167,7 +167,7 @@ static void free_plan(lag_plan P) {
                   P->fft_tw[0], P->fft_tw[1], P->fft_tw[2], P->fft_lam[0], P->fft_lam[1], P->fft_lam[2],
                   P->fft_mu1, P->flags, P->tile_part, P->cover_start[0], P->cover_start[1],
                   P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2], P->jac_vals,
-                  P->jac_cell, P->jac_cnt, P->jac_max};
+                  P->jac_cell, P->jac_cnt, P->jac_max, P->jac_fb};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->ctl) (void)hipFree(P->ctl);
@@ -396,6 +396,8 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
     ALLOC(P->jac_cell, sizeof(int) * (size_t)P->jac_k * P->jac_slots);
     ALLOC(P->jac_cnt, (size_t)P->jac_slots);
     ALLOC(P->jac_max, sizeof(int) * 2);
+    ALLOC(P->jac_fb, sizeof(float) * (size_t)P->n_unknowns);
+    HIPC(hipMemset(P->jac_fb, 0, sizeof(float) * (size_t)P->n_unknowns));
   }
   rc = tiles_setup(P);
   if (rc) {
@@ -614,17 +616,13 @@ int gn_hessmat_assembled(lag_plan P, const float* wvox, const float* p, float* H
   hipStream_t s = S(stream);
   int rc = launch_pack(P, p, P->pack_p, s);
   if (rc) return rc;
-  if ((rc = launch_fill(Hp, P->n_unknowns, 0.f, s))) return rc;
   if ((rc = launch_jac_apply(P, P->pack_p, wvox, nullptr, P->geo.cell_img, Hp, s))) return rc;
   return launch_reg(P, p, Hp, 1, 1, 1.f, s);
 }
 
 int lag_vjp_assembled(lag_plan P, const float* w, float* JTw, void* stream) {
   LAG_CHECK(P && w && JTw && P->jac_ready);
-  hipStream_t s = S(stream);
-  int rc = launch_fill(JTw, P->n_unknowns, 0.f, s);
-  if (rc) return rc;
-  return launch_jac_apply(P, P->pack_p, nullptr, w, 1.f, JTw, s);
+  return launch_jac_apply(P, P->pack_p, nullptr, w, 1.f, JTw, S(stream));
 }
 
 // Objective and gradient with the stored Jacobian; u = T(phi) at v when the
@@ -634,7 +632,6 @@ static int gradient_assembled(lag_plan P, const float* v, const float* T, const 
   int rc = u ? objective_from_image(P, v, u, R, P->img_b, out3, s)
              : objective_full(P, v, T, R, nullptr, P->img_b, out3, s);
   if (rc) return rc;
-  if ((rc = launch_fill(g, P->n_unknowns, 0.f, s))) return rc;
   if ((rc = launch_jac_apply(P, P->pack_p, nullptr, P->img_b, 1.f, g, s))) return rc;
   return launch_reg(P, v, g, 1, 0, 1.f, s);
 }

@@ -69,6 +69,9 @@ struct lag_plan_s {
   int* cover_start[3] = {nullptr, nullptr, nullptr};
   int2* cover_ent[3] = {nullptr, nullptr, nullptr};
   int cover_max = 0;  // most covering bricks of a node along one axis
+  // assembled matvec: out-of-tile contributions (float atomics), added and
+  // cleared by the tile reduction, so outputs need no fill beforehand
+  float* jac_fb = nullptr;
   // status flags written by kernels (bit 0: singular RK4 step Jacobian)
   int* flags = nullptr;
   // PCG control: device control block, pinned host mirrors (two slots, read
@@ -119,7 +122,7 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
                hipStream_t s);
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
-int launch_tile_reduce(lag_plan P, float* out, hipStream_t s);
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s);
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);
 int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
                      hipStream_t s);

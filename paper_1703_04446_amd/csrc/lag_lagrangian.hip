@@ -1301,7 +1301,9 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
 }
 
 // Sum the partial tiles into the velocity-grid output in a fixed order:
-// out[f][node] += sum over covering bricks (z, then y, then x order).  With
+// out[f][node] += sum over covering bricks (z, then y, then x order), or,
+// with fb != null, out = sum + fb and fb = 0 (fb holds the kernel's
+// out-of-tile atomics, so out needs no fill beforehand).  With
 // K > 0 (at most K covering bricks per axis) all loads are issued before the
 // sum, which adds the same terms in the same order as the generic loops.
 template <int D, int K>
@@ -1309,7 +1311,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
                                                         const int* __restrict__ cs0, const int2* __restrict__ ce0,
                                                         const int* __restrict__ cs1, const int2* __restrict__ ce1,
                                                         const int* __restrict__ cs2, const int2* __restrict__ ce2,
-                                                        float* __restrict__ out) {
+                                                        float* __restrict__ fb, float* __restrict__ out) {
   if (halted(g.halt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nv * fields) return;
@@ -1368,16 +1370,21 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
       }
     }
   }
-  out[i] += sum;
+  if (fb) {
+    out[i] = sum + fb[i];
+    fb[i] = 0.f;
+  } else {
+    out[i] += sum;
+  }
 }
 
-int launch_tile_reduce(lag_plan P, float* out, hipStream_t s) {
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s) {
   const long long tot = P->geo.nv * P->fields;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
 #define LAG_REDUCE(DIM, K)                                                                                       \
   hipLaunchKernelGGL((k_tile_reduce<DIM, K>), dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields,      \
                      P->tile_part, P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1],       \
-                     P->cover_start[2], P->cover_ent[2], out)
+                     P->cover_start[2], P->cover_ent[2], fb, out)
   const bool small = P->cover_max <= 3;
   if (P->geo.dim == 3) {
     if (small) LAG_REDUCE(3, 3);
@@ -1584,7 +1591,7 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
   }
 #undef LAG_VJP
   LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, s);
+  return launch_tile_reduce(P, out, nullptr, s);
 }
 
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T, const float* wvox,
@@ -1611,7 +1618,7 @@ int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, cons
   }
   prof_end(P, s);
   LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, s);
+  return launch_tile_reduce(P, out, nullptr, s);
 }
 
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s) {
@@ -1649,13 +1656,15 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
   if (!wseed) prof_begin(P, s);
   if (P->geo.dim == 3)
     hipLaunchKernelGGL(k_jac_apply<3>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
-                       P->jac_cnt, P->jac_slots, (const float4*)ppack, wvox, wseed, scale, out, P->tile_part);
+                       P->jac_cnt, P->jac_slots, (const float4*)ppack, wvox, wseed, scale, P->jac_fb,
+                       P->tile_part);
   else
     hipLaunchKernelGGL(k_jac_apply<2>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
-                       P->jac_cnt, P->jac_slots, (const float2*)ppack, wvox, wseed, scale, out, P->tile_part);
+                       P->jac_cnt, P->jac_slots, (const float2*)ppack, wvox, wseed, scale, P->jac_fb,
+                       P->tile_part);
   if (!wseed) prof_end(P, s);
   LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, s);
+  return launch_tile_reduce(P, out, P->jac_fb, s);  // assigns out
 }
 
 }  // namespace lag

@@ -496,7 +496,7 @@ int precond_setup(lag_plan P) {
 static int lines_per_block(int n, int axis, int m0) {
   int lpb = 1024 / n;
   if (lpb < 1) lpb = 1;
-  if (lpb > 16) lpb = 16;
+  if (lpb > 8) lpb = 8;
   if (axis != 0 && lpb > m0) lpb = m0;
   return lpb;
 }
