@@ -1214,16 +1214,25 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
   float btot = 0.f;                  // bound of all rows so far (same in every thread)
   int e = 0;                         // current scale 2^e (valid once btot > 0)
   bool finite = true;
+  const bool need_p = wvox || wseed;
+  unsigned long long pk = 0;
   for (int r = 0; r < rounds; ++r) {
     const int w = wave + r * nw;
-    int n = 0;
+    if ((r & 7) == 0) {  // counts of rounds r .. r + 7 in one trip (0 outside the image)
+      pk = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int wj = wave + (r + j) * nw;
+        if (r + j < rounds && wj < nitems) pk |= (unsigned long long)cnt[base + (long long)wj * 64 + lane] << (8 * j);
+      }
+    }
+    int n = (int)((pk >> (8 * (r & 7))) & 0xff);
     long long slot = 0, p = 0;
     if (w < nitems) {
-      int idx[3];
-      const bool in = item_cell<D>(g, B, O, w, l, idx);
       slot = base + w * 64 + lane;
-      if (in) {
-        n = cnt[slot];
+      if (need_p && n > 0) {
+        int idx[3];
+        (void)item_cell<D>(g, B, O, w, l, idx);
         p = idx[0] + (long long)g.mi[0] * idx[1];
         if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
       }
