@@ -580,21 +580,32 @@ int lag_gradient(lag_plan P, const float* v, const float* T, const float* R, flo
 
 // ---- assembled Jacobian ------------------------------------------------------
 
-// Assemble J at v; with u != null also write the transported image T(phi).
-static int jacobian_assemble(lag_plan P, const float* v, const float* T, float* u, int32_t* stored, hipStream_t s) {
-  *stored = 0;
+// Assemble J at v (launch only); with u != null also write the transported
+// image T(phi).  jacobian_assembled() completes it from the block counts
+// {largest per row, total} read back from P->jac_max.
+static int jacobian_assemble_launch(lag_plan P, const float* v, const float* T, float* u, hipStream_t s) {
   P->jac_ready = 0;
   if (P->jac_k == 0) return LAG_EUNSUPPORTED;
   int rc = launch_pack(P, v, P->pack_v, s);
   if (rc) return rc;
-  if ((rc = launch_jac_assemble(P, P->pack_v, T, u, s))) return rc;
-  int mx[2] = {0, 0};
-  LAG_HIP(hipMemcpyAsync(mx, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-  LAG_HIP(hipStreamSynchronize(s));
+  return launch_jac_assemble(P, P->pack_v, T, u, s);
+}
+
+static int32_t jacobian_assembled(lag_plan P, const int mx[2]) {
   P->jac_ready = mx[0] <= P->jac_k;
   P->jac_blocks_stored = mx[1];
   P->jac_max_seen = mx[0];
-  *stored = P->jac_ready;
+  return P->jac_ready;
+}
+
+static int jacobian_assemble(lag_plan P, const float* v, const float* T, float* u, int32_t* stored, hipStream_t s) {
+  *stored = 0;
+  int rc = jacobian_assemble_launch(P, v, T, u, s);
+  if (rc) return rc;
+  int mx[2] = {0, 0};
+  LAG_HIP(hipMemcpyAsync(mx, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  *stored = jacobian_assembled(P, mx);
   return LAG_OK;
 }
 
@@ -659,7 +670,7 @@ static int ensure_pcg_ctl(lag_plan P) {
   if (P->ctl && P->ctl_ev[1]) return LAG_OK;
   std::lock_guard<std::mutex> lk(api_lock());
   if (!P->ctl_host) LAG_HIP(hipHostMalloc((void**)&P->ctl_host, sizeof(int) * 16, hipHostMallocDefault));
-  if (!P->sc_host) LAG_HIP(hipHostMalloc((void**)&P->sc_host, sizeof(double) * 8, hipHostMallocDefault));
+  if (!P->sc_host) LAG_HIP(hipHostMalloc((void**)&P->sc_host, sizeof(double) * 16, hipHostMallocDefault));
   if (!P->gstream) LAG_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
   for (int k = 0; k < 2; ++k)
     if (!P->ctl_ev[k]) LAG_HIP(hipEventCreateWithFlags(&P->ctl_ev[k], hipEventDisableTiming));
@@ -667,23 +678,38 @@ static int ensure_pcg_ctl(lag_plan P) {
   return LAG_OK;
 }
 
+// Options of an internal PCG call: bb >= 0 is b.b, known to the caller (no
+// synchronisation for it); with gdot != null the final read also returns
+// gdx = gdot . x.
+struct PcgExtra {
+  double bb = -1.0;
+  const float* gdot = nullptr;
+  double gdx = 0.0;
+};
+
 // PCG start: x = 0, r = b, z = M r, p = z, device scalars and control block
 // (sc[0] = r.z, sc[3] = r.r, sc[4] = breakdown flag, sc[5] = b.b, sc[6] =
-// tol^2 b.b).  Synchronises once for |b|; *nb = 0 means b = 0 (nothing
-// else launched).
-static int pcg_start(lag_plan P, const float* b, float* x, double tol, int32_t maxit, double* nb, hipStream_t s) {
+// tol^2 b.b).  Synchronises once for |b| unless the caller knows it; *nb = 0
+// means b = 0 (nothing else launched).
+static int pcg_start(lag_plan P, const float* b, float* x, double tol, int32_t maxit, double* nb, hipStream_t s,
+                     const PcgExtra* ex) {
   const long long n = P->n_unknowns;
   float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5];
   double* sc = P->scalars;
   int rc;
   if ((rc = launch_fill(x, n, 0.f, s))) return rc;
   if ((rc = launch_axpby(n, 1.f, b, 0.f, nullptr, r, s))) return rc;
-  if ((rc = launch_dot(P, n, b, b, sc + 5, s))) return rc;
   hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 4, 0.0);
   LAG_LAUNCH_CHECK();
-  LAG_HIP(hipMemcpyAsync(P->sc_host, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
-  LAG_HIP(hipStreamSynchronize(s));
-  const double bb = P->sc_host[5];
+  double bb;
+  if (ex && ex->bb >= 0.0) {
+    bb = ex->bb;
+  } else {
+    if ((rc = launch_dot(P, n, b, b, sc + 5, s))) return rc;
+    LAG_HIP(hipMemcpyAsync(P->sc_host, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+    LAG_HIP(hipStreamSynchronize(s));
+    bb = P->sc_host[5];
+  }
   *nb = sqrt(bb);
   if (*nb == 0.0) return LAG_OK;
   if ((rc = launch_precond(P, r, z, s))) return rc;
@@ -711,11 +737,19 @@ static int pcg_iteration(lag_plan P, Op& H, float* x, hipStream_t g) {
   return launch_pcg_check(P, g);
 }
 
-// Read the control block and scalars after the last iteration.
-static int pcg_finish(lag_plan P, double nb, lag_pcg_info* info, hipStream_t s) {
+// Read the control block and scalars after the last iteration (and, with
+// ex->gdot, gdot . x into ex->gdx in the same read).
+static int pcg_finish(lag_plan P, double nb, const float* x, lag_pcg_info* info, hipStream_t s, PcgExtra* ex) {
+  int nsc = 6;
+  if (ex && ex->gdot) {
+    const int rc = launch_dot(P, P->n_unknowns, ex->gdot, x, P->scalars + 12, s);
+    if (rc) return rc;
+    nsc = 13;
+  }
   LAG_HIP(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
-  LAG_HIP(hipMemcpyAsync(P->sc_host, P->scalars, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipMemcpyAsync(P->sc_host, P->scalars, sizeof(double) * nsc, hipMemcpyDeviceToHost, s));
   LAG_HIP(hipStreamSynchronize(s));
+  if (ex && ex->gdot) ex->gdx = P->sc_host[12];
   lag_pcg_info loc;
   loc.iters = P->ctl_host[1];
   loc.breakdown = P->ctl_host[0] == 2;
@@ -736,13 +770,14 @@ static int pcg_finish(lag_plan P, double nb, lag_pcg_info* info, hipStream_t s) 
 // that found the halt flag set are dropped.
 template <class Op>
 static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int32_t maxit, lag_pcg_info* info,
-                    hipStream_t s) {
+                    hipStream_t s, PcgExtra* ex = nullptr) {
   int rc;
   if ((rc = ensure_pcg_ctl(P))) return rc;
   double nb = 0.0;
-  if ((rc = pcg_start(P, b, x, tol, maxit, &nb, s))) return rc;
-  if (nb == 0.0) {
+  if ((rc = pcg_start(P, b, x, tol, maxit, &nb, s, ex))) return rc;
+  if (nb == 0.0) {  // x = 0
     if (info) *info = lag_pcg_info{0, 0, 0, 0.0};
+    if (ex) ex->gdx = 0.0;
     return LAG_OK;
   }
   std::vector<int> prof_at;
@@ -782,7 +817,7 @@ static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int3
   }
   P->geo.halt = nullptr;
   if (rc) return rc;
-  rc = pcg_finish(P, nb, info, s);
+  rc = pcg_finish(P, nb, x, info, s, ex);
   const int ran = P->ctl_host[1] + (P->ctl_host[0] == 2 ? 1 : 0);
   if (ran < enq && P->prof_n > prof_at[ran]) P->prof_n = prof_at[ran];
   return rc;
@@ -795,13 +830,15 @@ static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int3
 // pointers in `key`, so a replay is valid while those are unchanged.
 template <class Op>
 static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, const float* b, float* x,
-                          double tol, int32_t maxit, int32_t per_graph, lag_pcg_info* info, hipStream_t s) {
+                          double tol, int32_t maxit, int32_t per_graph, lag_pcg_info* info, hipStream_t s,
+                          PcgExtra* ex = nullptr) {
   int rc;
   if ((rc = ensure_pcg_ctl(P))) return rc;
   double nb = 0.0;
-  if ((rc = pcg_start(P, b, x, tol, maxit, &nb, s))) return rc;
-  if (nb == 0.0) {
+  if ((rc = pcg_start(P, b, x, tol, maxit, &nb, s, ex))) return rc;
+  if (nb == 0.0) {  // x = 0
     if (info) *info = lag_pcg_info{0, 0, 0, 0.0};
+    if (ex) ex->gdx = 0.0;
     return LAG_OK;
   }
   // (re)capture when the arguments differ from the cached graph's
@@ -852,7 +889,7 @@ static int pcg_graph_impl(lag_plan P, Op H, const void* const key[6], int mode, 
       if (P->ctl_host[8 * (slot ^ 1)] != 0) break;
     }
   }
-  return pcg_finish(P, nb, info, s);
+  return pcg_finish(P, nb, x, info, s, ex);
 }
 
 extern "C" {
@@ -899,6 +936,26 @@ void lag_gn_default_options(lag_gn_options* o) {
   o->graph_iters = 0;
 }
 
+// The Gauss-Newton step's PCG solve (assembled or matrix-free, eager or
+// graph-replayed) with the step's extras (known b.b, g . dv in the last read).
+static int gn_pcg(lag_plan P, bool stored, const float* v, const float* T, const float* b, float* x,
+                  const lag_gn_options& o, lag_pcg_info* pi, hipStream_t s, PcgExtra* ex) {
+  if (stored) {
+    auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat_assembled(P, nullptr, p, Hp, st); };
+    if (o.graph_iters > 0) {
+      const void* key[6] = {nullptr, nullptr, nullptr, b, x, nullptr};
+      return pcg_graph_impl(P, H, key, 1, b, x, o.pcg_tol, o.pcg_maxit, o.graph_iters, pi, s, ex);
+    }
+    return pcg_impl(P, H, b, x, o.pcg_tol, o.pcg_maxit, pi, s, ex);
+  }
+  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat(P, v, T, nullptr, p, Hp, st); };
+  if (o.graph_iters > 0) {
+    const void* key[6] = {v, T, nullptr, b, x, nullptr};
+    return pcg_graph_impl(P, H, key, 0, b, x, o.pcg_tol, o.pcg_maxit, o.graph_iters, pi, s, ex);
+  }
+  return pcg_impl(P, H, b, x, o.pcg_tol, o.pcg_maxit, pi, s, ex);
+}
+
 int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, float* v_next,
                 const lag_gn_options* opt, double gstop, lag_gn_step_info* info, void* stream) {
   LAG_CHECK(P && T && R && v && v_next && v != v_next);
@@ -916,15 +973,25 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
   int rc;
   int32_t stored = 0;
   if (P->jac_k > 0) {
-    if ((rc = jacobian_assemble(P, v, T, P->img_a, &stored, s))) return rc;
+    // Assemble J and take the gradient from it without waiting for the
+    // overflow check, which is read back with the objective (the stored
+    // counts never exceed the capacity, so the speculative product stays in
+    // bounds); on overflow the gradient is redone matrix-free.  The
+    // assembly's forward pass leaves T(phi) at v in img_a: no second trace.
+    int mx[2] = {0, 0};
+    if ((rc = jacobian_assemble_launch(P, v, T, P->img_a, s))) return rc;
+    if ((rc = gradient_assembled(P, v, T, R, P->img_a, g, sc + 8, s))) return rc;
+    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+    LAG_HIP(hipMemcpyAsync(mx, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
+    stored = jacobian_assembled(P, mx);
+  }
+  if (!stored) {
+    if ((rc = lag_gradient(P, v, T, R, g, sc + 8, stream))) return rc;
+    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
   }
   loc.assembled = stored;
-  // the assembly's forward pass left T(phi) at v in img_a: no second trace
-  if (stored) rc = gradient_assembled(P, v, T, R, P->img_a, g, sc + 8, s);
-  else rc = lag_gradient(P, v, T, R, g, sc + 8, stream);
-  if (rc) return rc;
-  if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
-  if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
   loc.J = h[0];
   loc.gnorm = sqrt(h[3]);
   loc.J_next = loc.J;
@@ -935,19 +1002,14 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
   }
   if ((rc = launch_axpby(n, -1.f, g, 0.f, nullptr, rhs, s))) return rc;
   lag_pcg_info pi;
-  if (o.graph_iters > 0) {
-    if (stored) rc = lag_pcg_assembled_graph(P, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, o.graph_iters, &pi, stream);
-    else rc = lag_pcg_graph(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, o.graph_iters, &pi, stream);
-  } else {
-    if (stored) rc = lag_pcg_assembled(P, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
-    else rc = lag_pcg(P, v, T, nullptr, rhs, dv, o.pcg_tol, o.pcg_maxit, &pi, stream);
-  }
+  PcgExtra ex;
+  ex.bb = h[3];   // rhs = -g: rhs . rhs = g . g exactly
+  ex.gdot = g;    // slope g . dv, read with the solver's last scalars
+  rc = gn_pcg(P, stored != 0, v, T, rhs, dv, o, &pi, s, &ex);
   if (rc != LAG_OK && rc != LAG_EBREAKDOWN) return rc;
   loc.pcg_iters = pi.iters;
   loc.matvecs = pi.matvecs;
-  if ((rc = launch_dot(P, n, g, dv, sc + 12, s))) return rc;
-  if ((rc = read_scalars(P, h + 4, 12, 1, s))) return rc;
-  const double slope = h[4];
+  const double slope = ex.gdx;
   double mu = 1.0;
   for (int k = 0; k <= o.max_halvings; ++k) {
     if ((rc = launch_axpby(n, 1.f, v, (float)mu, dv, v_next, s))) return rc;

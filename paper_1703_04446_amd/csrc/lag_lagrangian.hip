@@ -1065,7 +1065,7 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
       count = jw.count;
     }
   }
-  cnt[slot] = (unsigned char)min(count, 255);
+  cnt[slot] = (unsigned char)min(count, kmax);  // never more than stored (an overflow shows in maxcount)
   // one set of atomics per wave
   int wmax = count, wsum = min(count, kmax);
 #pragma unroll
