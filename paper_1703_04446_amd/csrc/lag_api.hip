@@ -380,7 +380,7 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
   ALLOC(P->part_base, sizeof(int) * g.np);
   ALLOC(P->part_vals, sizeof(float) * g.np * (1 << D));
   ALLOC(P->scan_blocks, sizeof(int) * ((g.np + 1023) / 1024 + 2));
-  ALLOC(P->red_partial, sizeof(double) * kRedBlocks);
+  ALLOC(P->red_partial, sizeof(double) * std::max<long long>(kRedBlocks, (P->n_unknowns + kBlock - 1) / kBlock));
   ALLOC(P->red_partial2, sizeof(double) * kRedBlocks);
   ALLOC(P->scalars, sizeof(double) * 32);
   HIPC(hipMemset(P->scalars, 0, sizeof(double) * 32));
@@ -622,18 +622,35 @@ int lag_jacobian_info(lag_plan P, int64_t* blocks, int32_t* max_blocks, int32_t*
   return LAG_OK;
 }
 
-int gn_hessmat_assembled(lag_plan P, const float* wvox, const float* p, float* Hp, void* stream) {
-  LAG_CHECK(P && p && Hp && P->jac_ready);
-  hipStream_t s = S(stream);
+// Assembled Gauss-Newton matvec; with part != null also the block partials
+// of p . Hp (count in P->php_n), for PCG.
+static int hessmat_assembled(lag_plan P, const float* wvox, const float* p, float* Hp, double* part, hipStream_t s) {
   int rc = launch_pack(P, p, P->pack_p, s);
   if (rc) return rc;
-  if ((rc = launch_jac_apply(P, P->pack_p, wvox, nullptr, P->geo.cell_img, Hp, s))) return rc;
-  return launch_reg(P, p, Hp, 1, 1, 1.f, s);
+  const RegTail rt = reg_tail(P, p, 1, 1.f, part);  // + alpha A p + gamma p, fused into the tile reduction
+  return launch_jac_apply(P, P->pack_p, wvox, nullptr, P->geo.cell_img, Hp, s, &rt);
+}
+
+int gn_hessmat_assembled(lag_plan P, const float* wvox, const float* p, float* Hp, void* stream) {
+  LAG_CHECK(P && p && Hp && P->jac_ready);
+  return hessmat_assembled(P, wvox, p, Hp, nullptr, S(stream));
+}
+
+// Matrix-free Gauss-Newton matvec; with part != null also the block
+// partials of p . Hp (count in P->php_n), for PCG.
+static int hessmat_free(lag_plan P, const float* v, const float* T, const float* wvox, const float* p, float* Hp,
+                        double* part, hipStream_t s) {
+  int rc = gn_hessmat(P, v, T, wvox, p, Hp, s);
+  if (rc || !part) return rc;
+  const long long n = P->n_unknowns;
+  if ((rc = launch_dot_partial(P, n, p, Hp, part, s))) return rc;
+  P->php_n = (int)std::min<long long>(kRedBlocks, std::max<long long>(1, (n + kBlock - 1) / kBlock));
+  return LAG_OK;
 }
 
 int lag_vjp_assembled(lag_plan P, const float* w, float* JTw, void* stream) {
   LAG_CHECK(P && w && JTw && P->jac_ready);
-  return launch_jac_apply(P, P->pack_p, nullptr, w, 1.f, JTw, S(stream));
+  return launch_jac_apply(P, P->pack_p, nullptr, w, 1.f, JTw, S(stream), nullptr);
 }
 
 // Objective and gradient with the stored Jacobian; u = T(phi) at v when the
@@ -643,8 +660,8 @@ static int gradient_assembled(lag_plan P, const float* v, const float* T, const 
   int rc = u ? objective_from_image(P, v, u, R, P->img_b, out3, s)
              : objective_full(P, v, T, R, nullptr, P->img_b, out3, s);
   if (rc) return rc;
-  if ((rc = launch_jac_apply(P, P->pack_p, nullptr, P->img_b, 1.f, g, s))) return rc;
-  return launch_reg(P, v, g, 1, 0, 1.f, s);
+  const RegTail rt = reg_tail(P, v, 0, 1.f, nullptr);  // + alpha A v, fused into the tile reduction
+  return launch_jac_apply(P, P->pack_p, nullptr, P->img_b, 1.f, g, s, &rt);
 }
 
 int lag_gradient_assembled(lag_plan P, const float* v, const float* T, const float* R, float* g, double* out3,
@@ -728,8 +745,7 @@ static int pcg_iteration(lag_plan P, Op& H, float* x, hipStream_t g) {
   const long long n = P->n_unknowns;
   float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
   int rc;
-  if ((rc = H(p, Hp, g))) return rc;
-  if ((rc = launch_dot_partial(P, n, p, Hp, P->red_partial, g))) return rc;
+  if ((rc = H(p, Hp, g, P->red_partial))) return rc;      // also the p.Hp partials (P->php_n)
   if ((rc = launch_pcg_xr(P, x, r, p, Hp, g))) return rc;   // also r.r partials
   if ((rc = launch_precond(P, r, z, g))) return rc;
   if ((rc = launch_dot_partial(P, n, r, z, P->red_partial, g))) return rc;
@@ -897,14 +913,18 @@ extern "C" {
 int lag_pcg(lag_plan P, const float* v, const float* T, const float* wvox, const float* b, float* x, double tol,
             int32_t maxit, lag_pcg_info* info, void* stream) {
   LAG_CHECK(P && v && T && b && x && maxit >= 0 && tol >= 0.0);
-  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat(P, v, T, wvox, p, Hp, st); };
+  auto H = [&](const float* p, float* Hp, hipStream_t st, double* part) {
+    return hessmat_free(P, v, T, wvox, p, Hp, part, st);
+  };
   return pcg_impl(P, H, b, x, tol, maxit, info, S(stream));
 }
 
 int lag_pcg_graph(lag_plan P, const float* v, const float* T, const float* wvox, const float* b, float* x,
                   double tol, int32_t maxit, int32_t iters_per_graph, lag_pcg_info* info, void* stream) {
   LAG_CHECK(P && v && T && b && x && maxit >= 0 && tol >= 0.0 && iters_per_graph >= 1 && iters_per_graph <= 64);
-  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat(P, v, T, wvox, p, Hp, st); };
+  auto H = [&](const float* p, float* Hp, hipStream_t st, double* part) {
+    return hessmat_free(P, v, T, wvox, p, Hp, part, st);
+  };
   const void* key[6] = {v, T, wvox, b, x, nullptr};
   return pcg_graph_impl(P, H, key, 0, b, x, tol, maxit, iters_per_graph, info, S(stream));
 }
@@ -912,7 +932,9 @@ int lag_pcg_graph(lag_plan P, const float* v, const float* T, const float* wvox,
 int lag_pcg_assembled(lag_plan P, const float* wvox, const float* b, float* x, double tol, int32_t maxit,
                       lag_pcg_info* info, void* stream) {
   LAG_CHECK(P && b && x && maxit >= 0 && tol >= 0.0 && P->jac_ready);
-  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat_assembled(P, wvox, p, Hp, st); };
+  auto H = [&](const float* p, float* Hp, hipStream_t st, double* part) {
+    return hessmat_assembled(P, wvox, p, Hp, part, st);
+  };
   return pcg_impl(P, H, b, x, tol, maxit, info, S(stream));
 }
 
@@ -920,7 +942,9 @@ int lag_pcg_assembled_graph(lag_plan P, const float* wvox, const float* b, float
                             int32_t iters_per_graph, lag_pcg_info* info, void* stream) {
   LAG_CHECK(P && b && x && maxit >= 0 && tol >= 0.0 && P->jac_ready && iters_per_graph >= 1 &&
             iters_per_graph <= 64);
-  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat_assembled(P, wvox, p, Hp, st); };
+  auto H = [&](const float* p, float* Hp, hipStream_t st, double* part) {
+    return hessmat_assembled(P, wvox, p, Hp, part, st);
+  };
   const void* key[6] = {nullptr, nullptr, wvox, b, x, nullptr};
   return pcg_graph_impl(P, H, key, 1, b, x, tol, maxit, iters_per_graph, info, S(stream));
 }
@@ -941,14 +965,18 @@ void lag_gn_default_options(lag_gn_options* o) {
 static int gn_pcg(lag_plan P, bool stored, const float* v, const float* T, const float* b, float* x,
                   const lag_gn_options& o, lag_pcg_info* pi, hipStream_t s, PcgExtra* ex) {
   if (stored) {
-    auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat_assembled(P, nullptr, p, Hp, st); };
+    auto H = [&](const float* p, float* Hp, hipStream_t st, double* part) {
+      return hessmat_assembled(P, nullptr, p, Hp, part, st);
+    };
     if (o.graph_iters > 0) {
       const void* key[6] = {nullptr, nullptr, nullptr, b, x, nullptr};
       return pcg_graph_impl(P, H, key, 1, b, x, o.pcg_tol, o.pcg_maxit, o.graph_iters, pi, s, ex);
     }
     return pcg_impl(P, H, b, x, o.pcg_tol, o.pcg_maxit, pi, s, ex);
   }
-  auto H = [&](const float* p, float* Hp, hipStream_t st) { return gn_hessmat(P, v, T, nullptr, p, Hp, st); };
+  auto H = [&](const float* p, float* Hp, hipStream_t st, double* part) {
+    return hessmat_free(P, v, T, nullptr, p, Hp, part, st);
+  };
   if (o.graph_iters > 0) {
     const void* key[6] = {v, T, nullptr, b, x, nullptr};
     return pcg_graph_impl(P, H, key, 0, b, x, o.pcg_tol, o.pcg_maxit, o.graph_iters, pi, s, ex);

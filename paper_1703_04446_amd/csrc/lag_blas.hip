@@ -9,16 +9,6 @@
 
 namespace lag {
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
-  }
-  return sh[0];
-}
-
 __global__ void __launch_bounds__(kBlock) k_dot_partial(const float* __restrict__ x, const float* __restrict__ y,
                                                          long long n, double* __restrict__ part,
                                                          const int* __restrict__ halt) {
@@ -219,14 +209,15 @@ int launch_pcg_check(lag_plan P, hipStream_t s) {
   return LAG_OK;
 }
 
-// x, r update with the p.Hp partials in red_partial; new r.r partials go to
-// red_partial2 (consumed by launch_pcg_check)
+// x, r update with the p.Hp partials in red_partial (P->php_n of them, from
+// the matvec); new r.r partials go to red_partial2 (consumed by
+// launch_pcg_check)
 int launch_pcg_xr(lag_plan P, float* x, float* r, const float* p, const float* Hp, hipStream_t s) {
   const long long n = P->n_unknowns;
   unsigned blocks;
   reduce_launch(n, blocks);
   hipLaunchKernelGGL(k_pcg_xr, dim3(blocks), dim3(kBlock), 0, s, n, x, r, p, Hp, P->scalars, P->red_partial,
-                     (int)blocks, P->red_partial2, P->ctl);
+                     P->php_n, P->red_partial2, P->ctl);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }

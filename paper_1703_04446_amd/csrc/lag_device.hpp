@@ -162,6 +162,99 @@ __device__ __forceinline__ void locate_i(const Geo& g, const Start<D>& S, const 
 // Vector field sampling: value and (optionally) spatial Jacobian G[c][a] =
 // d v_c / d y_a of the trilinear interpolant.  One-sided on grid lines
 // (the floor-selected cell), consistent with the oracle.
+// Regulariser value at entry i of a velocity-shaped field p (Sec. 2.1):
+// s_j A p_{j,c} (+ gamma p) with A = -Laplace_h (diffusion) or Laplace_h^2
+// (curvature) on the periodic grid, s_j = scale[node]; differences are
+// formed before scaling so smooth fields lose little to cancellation.
+template <int D>
+__device__ __forceinline__ float lap_at(const float* __restrict__ f, const int m[3], const float ih2[3],
+                                        int x, int y, int z) {
+  // -Laplace_h f at (x, y, z); arguments already wrapped
+  const float c = f[((long long)z * m[1] + y) * m[0] + x];
+  float s = 0.f;
+  {
+    int xp = x + 1 == m[0] ? 0 : x + 1, xm = x == 0 ? m[0] - 1 : x - 1;
+    float a = f[((long long)z * m[1] + y) * m[0] + xp] - c;
+    float b = f[((long long)z * m[1] + y) * m[0] + xm] - c;
+    s = fmaf(-(a + b), ih2[0], s);
+  }
+  {
+    int yp = y + 1 == m[1] ? 0 : y + 1, ym = y == 0 ? m[1] - 1 : y - 1;
+    float a = f[((long long)z * m[1] + yp) * m[0] + x] - c;
+    float b = f[((long long)z * m[1] + ym) * m[0] + x] - c;
+    s = fmaf(-(a + b), ih2[1], s);
+  }
+  if (D == 3) {
+    int zp = z + 1 == m[2] ? 0 : z + 1, zm = z == 0 ? m[2] - 1 : z - 1;
+    float a = f[((long long)zp * m[1] + y) * m[0] + x] - c;
+    float b = f[((long long)zm * m[1] + y) * m[0] + x] - c;
+    s = fmaf(-(a + b), ih2[2], s);
+  }
+  return s;
+}
+
+template <int D, bool CURV>
+__device__ __forceinline__ float reg_value(const Geo& g, const float* __restrict__ p, const float* __restrict__ scale,
+                                           float gamma, const float ih2[3], long long i) {
+  const long long f = i / g.nv;
+  const long long r = i - f * g.nv;
+  const int j = (int)(f / D);
+  const float* fld = p + f * g.nv;
+  const int m[3] = {g.mv[0], g.mv[1], D == 3 ? g.mv[2] : 1};
+  const int x = (int)(r % m[0]), y = (int)((r / m[0]) % m[1]), z = (int)(r / ((long long)m[0] * m[1]));
+  float a;
+  if (!CURV) {
+    a = lap_at<D>(fld, m, ih2, x, y, z);
+  } else {
+    // (-Laplace)(-Laplace p) by differences of the inner Laplacian
+    const float c = lap_at<D>(fld, m, ih2, x, y, z);
+    float s = 0.f;
+    {
+      int xp = x + 1 == m[0] ? 0 : x + 1, xm = x == 0 ? m[0] - 1 : x - 1;
+      float u = lap_at<D>(fld, m, ih2, xp, y, z) - c, w = lap_at<D>(fld, m, ih2, xm, y, z) - c;
+      s = fmaf(-(u + w), ih2[0], s);
+    }
+    {
+      int yp = y + 1 == m[1] ? 0 : y + 1, ym = y == 0 ? m[1] - 1 : y - 1;
+      float u = lap_at<D>(fld, m, ih2, x, yp, z) - c, w = lap_at<D>(fld, m, ih2, x, ym, z) - c;
+      s = fmaf(-(u + w), ih2[1], s);
+    }
+    if (D == 3) {
+      int zp = z + 1 == m[2] ? 0 : z + 1, zm = z == 0 ? m[2] - 1 : z - 1;
+      float u = lap_at<D>(fld, m, ih2, x, y, zp) - c, w = lap_at<D>(fld, m, ih2, x, y, zm) - c;
+      s = fmaf(-(u + w), ih2[2], s);
+    }
+    a = s;
+  }
+  float val = scale[j] * a;
+  if (gamma != 0.f) val = fmaf(gamma, fld[r], val);
+  return val;
+}
+
+// Block-wide float64 sum in a fixed tree (every thread of the block calls
+// it; all get the total).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Regulariser term fused into the tile reduction of the assembled products:
+// out = reg_value(p) + (tile sum); with part != null also the block partials
+// of p . out (float64).
+struct RegTail {
+  const float* p = nullptr;
+  const float* scale = nullptr;
+  float gamma = 0.f;
+  float ih2[3] = {0.f, 0.f, 0.f};
+  int curv = 0;
+  double* part = nullptr;
+};
+
 // Packed fields carry a periodic ghost layer (k_pack), so the eight corners
 // of a cell sit at fixed offsets from its lower corner: +1 along x, +pv[0]
 // along y, +pv[0] pv[1] along z.

@@ -39,8 +39,9 @@ struct lag_plan_s {
   float* part_vals = nullptr;  // 2^d * np
   int* scan_blocks = nullptr;  // block sums for the scan
   // reductions
-  double* red_partial = nullptr;  // kRedBlocks
+  double* red_partial = nullptr;  // max(kRedBlocks, one per kBlock unknowns)
   double* red_partial2 = nullptr; // kRedBlocks (PCG: r.r partials)
+  int php_n = 0;                  // p.Hp partials in red_partial from the last PCG matvec
   double* scalars = nullptr;      // 16 device scalars
   // velocity-sized scratch (PCG / GN vectors)
   float* vec[10] = {nullptr};
@@ -122,13 +123,15 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
                hipStream_t s);
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
-int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s);
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt);
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);
 int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
-                     hipStream_t s);
+                     hipStream_t s, const RegTail* rt);
 int tiles_setup(lag_plan P);       // partial-tile buffer + cover tables (plan creation)
 int launch_reg(lag_plan P, const float* p, float* out, int accumulate, int with_gamma,
                float extra_scale, hipStream_t s);
+// Regulariser parameters for the tile reduction (same tables as launch_reg).
+RegTail reg_tail(lag_plan P, const float* p, int with_gamma, float extra_scale, double* part);
 int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s);
 int precond_setup(lag_plan P);     // host tables + allocations (plan creation)
 

@@ -1316,14 +1316,10 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
 // K > 0 (at most K covering bricks per axis) all loads are issued before the
 // sum, which adds the same terms in the same order as the generic loops.
 template <int D, int K>
-__global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fields, const float* __restrict__ part,
-                                                        const int* __restrict__ cs0, const int2* __restrict__ ce0,
-                                                        const int* __restrict__ cs1, const int2* __restrict__ ce1,
-                                                        const int* __restrict__ cs2, const int2* __restrict__ ce2,
-                                                        float* __restrict__ fb, float* __restrict__ out) {
-  if (halted(g.halt)) return;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nv * fields) return;
+__device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fields, const float* __restrict__ part,
+                                          const int* __restrict__ cs0, const int2* __restrict__ ce0,
+                                          const int* __restrict__ cs1, const int2* __restrict__ ce1,
+                                          const int* __restrict__ cs2, const int2* __restrict__ ce2, long long i) {
   const long long f = i / g.nv, r = i - f * g.nv;
   const int X = (int)(r % g.mv[0]);
   const int Y = (int)((r / g.mv[0]) % g.mv[1]);
@@ -1379,31 +1375,79 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
       }
     }
   }
-  if (fb) {
-    out[i] = sum + fb[i];
-    fb[i] = 0.f;
-  } else {
-    out[i] += sum;
+  return sum;
+}
+
+// REG = 1 (diffusion) or 2 (curvature): out = reg_value(rt.p) + (tile sum
+// + fb), the operation order of the separate regulariser kernel, and with
+// rt.part the block partials of rt.p . out.
+template <int D, int K, int REG>
+__global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fields, const float* __restrict__ part,
+                                                        const int* __restrict__ cs0, const int2* __restrict__ ce0,
+                                                        const int* __restrict__ cs1, const int2* __restrict__ ce1,
+                                                        const int* __restrict__ cs2, const int2* __restrict__ ce2,
+                                                        float* __restrict__ fb, float* __restrict__ out, RegTail rt) {
+  if (halted(g.halt)) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < g.nv * fields;
+  float val = 0.f;
+  if (valid) {
+    const float sum = tile_sum<D, K>(g, B, fields, part, cs0, ce0, cs1, ce1, cs2, ce2, i);
+    float t;
+    if (fb) {
+      t = sum + fb[i];
+      fb[i] = 0.f;
+    } else {
+      t = out[i] + sum;
+    }
+    if constexpr (REG != 0) {
+      val = reg_value<D, REG == 2>(g, rt.p, rt.scale, rt.gamma, rt.ih2, i);
+      val += t;
+    } else {
+      val = t;
+    }
+    out[i] = val;
+  }
+  if constexpr (REG != 0) {
+    if (rt.part) {  // kernel argument: the whole block takes this branch
+      __shared__ double sh[kBlock];
+      const double d = valid ? (double)rt.p[i] * (double)val : 0.0;
+      const double tb = block_sum(d, sh);
+      if (threadIdx.x == 0) rt.part[blockIdx.x] = tb;
+    }
   }
 }
 
-int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s) {
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt) {
   const long long tot = P->geo.nv * P->fields;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
-#define LAG_REDUCE(DIM, K)                                                                                       \
-  hipLaunchKernelGGL((k_tile_reduce<DIM, K>), dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields,      \
+  const RegTail none;
+  const RegTail& r = rt ? *rt : none;
+  const int reg = r.p ? (r.curv ? 2 : 1) : 0;
+#define LAG_REDUCE(DIM, K, RG)                                                                                   \
+  hipLaunchKernelGGL((k_tile_reduce<DIM, K, RG>), dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields,  \
                      P->tile_part, P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1],       \
-                     P->cover_start[2], P->cover_ent[2], fb, out)
-  const bool small = P->cover_max <= 3;
+                     P->cover_start[2], P->cover_ent[2], fb, out, r)
+#define LAG_REDUCE_K(DIM, RG)          \
+  do {                                 \
+    if (P->cover_max <= 3)             \
+      LAG_REDUCE(DIM, 3, RG);          \
+    else                               \
+      LAG_REDUCE(DIM, 0, RG);          \
+  } while (0)
   if (P->geo.dim == 3) {
-    if (small) LAG_REDUCE(3, 3);
-    else LAG_REDUCE(3, 0);
+    if (reg == 0) LAG_REDUCE_K(3, 0);
+    else if (reg == 1) LAG_REDUCE_K(3, 1);
+    else LAG_REDUCE_K(3, 2);
   } else {
-    if (small) LAG_REDUCE(2, 3);
-    else LAG_REDUCE(2, 0);
+    if (reg == 0) LAG_REDUCE_K(2, 0);
+    else if (reg == 1) LAG_REDUCE_K(2, 1);
+    else LAG_REDUCE_K(2, 2);
   }
+#undef LAG_REDUCE_K
 #undef LAG_REDUCE
   LAG_LAUNCH_CHECK();
+  if (r.part) P->php_n = (int)grid;
   return LAG_OK;
 }
 
@@ -1600,7 +1644,7 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
   }
 #undef LAG_VJP
   LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, nullptr, s);
+  return launch_tile_reduce(P, out, nullptr, s, nullptr);
 }
 
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T, const float* wvox,
@@ -1627,7 +1671,7 @@ int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, cons
   }
   prof_end(P, s);
   LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, nullptr, s);
+  return launch_tile_reduce(P, out, nullptr, s, nullptr);
 }
 
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s) {
@@ -1658,7 +1702,7 @@ int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u,
 }
 
 int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
-                     hipStream_t s) {
+                     hipStream_t s, const RegTail* rt) {
   const lag::Bricks& B = P->bricks;
   unsigned grid = grid_for(B.nbricks);
   const size_t lds = sizeof(float) * ((size_t)P->geo.dim * B.tvol + 2 * (kBlock / 64));
@@ -1673,7 +1717,7 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
                        P->tile_part);
   if (!wseed) prof_end(P, s);
   LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, P->jac_fb, s);  // assigns out
+  return launch_tile_reduce(P, out, P->jac_fb, s, rt);  // assigns out
 }
 
 }  // namespace lag

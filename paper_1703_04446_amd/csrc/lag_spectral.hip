@@ -10,9 +10,11 @@
 // Gauss-Newton matrix is circulant on the periodic grid, so it is inverted
 // in Fourier space: z = F^-1[F(r) / mu(k)], mu(k) = s_j lambda_A(k) + gamma.
 // The transform is a hand-written Stockham autosort FFT of radix 4/2/3/5
-// performed line by line in LDS; the forward and inverse transforms along
-// the last axis are fused with the division.  Twiddles and eigenvalue tables
-// are computed on the host in double precision at plan creation.
+// performed line by line in LDS; r is real and mu(k) real and even, so only
+// the half spectrum along x is formed (two real rows per complex line), and
+// the forward and inverse transforms along the last axis are fused with the
+// division.  Twiddles and eigenvalue tables are computed on the host in
+// double precision at plan creation.
 
 #include <math.h>
 
@@ -25,76 +27,31 @@ namespace lag {
 // ---------------------------------------------------------------------------
 // regulariser
 
-template <int D>
-__device__ __forceinline__ float lap_at(const float* __restrict__ f, const int m[3], const float ih2[3],
-                                        int x, int y, int z) {
-  // -Laplace_h f at (x, y, z); arguments already wrapped
-  const float c = f[((long long)z * m[1] + y) * m[0] + x];
-  float s = 0.f;
-  {
-    int xp = x + 1 == m[0] ? 0 : x + 1, xm = x == 0 ? m[0] - 1 : x - 1;
-    float a = f[((long long)z * m[1] + y) * m[0] + xp] - c;
-    float b = f[((long long)z * m[1] + y) * m[0] + xm] - c;
-    s = fmaf(-(a + b), ih2[0], s);
-  }
-  {
-    int yp = y + 1 == m[1] ? 0 : y + 1, ym = y == 0 ? m[1] - 1 : y - 1;
-    float a = f[((long long)z * m[1] + yp) * m[0] + x] - c;
-    float b = f[((long long)z * m[1] + ym) * m[0] + x] - c;
-    s = fmaf(-(a + b), ih2[1], s);
-  }
-  if (D == 3) {
-    int zp = z + 1 == m[2] ? 0 : z + 1, zm = z == 0 ? m[2] - 1 : z - 1;
-    float a = f[((long long)zp * m[1] + y) * m[0] + x] - c;
-    float b = f[((long long)zm * m[1] + y) * m[0] + x] - c;
-    s = fmaf(-(a + b), ih2[2], s);
-  }
-  return s;
-}
-
 template <int D, bool CURV>
 __global__ void __launch_bounds__(kBlock) k_reg(Geo g, const float* __restrict__ p, float* __restrict__ out,
                                                 const float* __restrict__ scale, float gamma, int accumulate,
                                                 float ih2x, float ih2y, float ih2z) {
   if (halted(g.halt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long tot = g.nv * g.nodes * D;
-  if (i >= tot) return;
-  const long long f = i / g.nv;
-  const long long r = i - f * g.nv;
-  const int j = (int)(f / D);
-  const float* fld = p + f * g.nv;
-  const int m[3] = {g.mv[0], g.mv[1], D == 3 ? g.mv[2] : 1};
+  if (i >= g.nv * g.nodes * D) return;
   const float ih2[3] = {ih2x, ih2y, ih2z};
-  const int x = (int)(r % m[0]), y = (int)((r / m[0]) % m[1]), z = (int)(r / ((long long)m[0] * m[1]));
-  float a;
-  if (!CURV) {
-    a = lap_at<D>(fld, m, ih2, x, y, z);
-  } else {
-    // (-Laplace)(-Laplace p) by differences of the inner Laplacian
-    const float c = lap_at<D>(fld, m, ih2, x, y, z);
-    float s = 0.f;
-    {
-      int xp = x + 1 == m[0] ? 0 : x + 1, xm = x == 0 ? m[0] - 1 : x - 1;
-      float u = lap_at<D>(fld, m, ih2, xp, y, z) - c, w = lap_at<D>(fld, m, ih2, xm, y, z) - c;
-      s = fmaf(-(u + w), ih2[0], s);
-    }
-    {
-      int yp = y + 1 == m[1] ? 0 : y + 1, ym = y == 0 ? m[1] - 1 : y - 1;
-      float u = lap_at<D>(fld, m, ih2, x, yp, z) - c, w = lap_at<D>(fld, m, ih2, x, ym, z) - c;
-      s = fmaf(-(u + w), ih2[1], s);
-    }
-    if (D == 3) {
-      int zp = z + 1 == m[2] ? 0 : z + 1, zm = z == 0 ? m[2] - 1 : z - 1;
-      float u = lap_at<D>(fld, m, ih2, x, y, zp) - c, w = lap_at<D>(fld, m, ih2, x, y, zm) - c;
-      s = fmaf(-(u + w), ih2[2], s);
-    }
-    a = s;
-  }
-  float val = scale[j] * a;
-  if (gamma != 0.f) val = fmaf(gamma, fld[r], val);
+  float val = reg_value<D, CURV>(g, p, scale, gamma, ih2, i);
   if (accumulate) val += out[i];
   out[i] = val;
+}
+
+RegTail reg_tail(lag_plan P, const float* p, int with_gamma, float extra_scale, double* part) {
+  RegTail r;
+  r.p = p;
+  r.scale = P->reg_scale + (extra_scale != 0.f ? 0 : P->geo.nodes);
+  r.gamma = with_gamma ? (float)P->prob.gamma : 0.f;
+  for (int a = 0; a < 3; ++a) {
+    double h = P->prob.extent[a] / P->prob.vel_m[a];
+    r.ih2[a] = (float)(1.0 / (h * h));
+  }
+  r.curv = P->prob.reg == LAG_CURVATURE;
+  r.part = part;
+  return r;
 }
 
 int launch_reg(lag_plan P, const float* p, float* out, int accumulate, int with_gamma, float extra_scale,
@@ -230,78 +187,42 @@ struct Symbol {
   float nv;
 };
 
-// One pass along `axis` for all lines of all fields.
-// MODE 0: forward; 1: inverse; 2: forward, divide by mu, inverse.
-// IN_REAL: read float input (imaginary 0); OUT_REAL: write the real part.
-template <int D, int MODE, bool IN_REAL, bool OUT_REAL>
+// One pass along y (axis 1) or z (axis 2) for all lines of all fields of the
+// half spectrum along x (cx = m_x / 2 + 1 columns; layout [field][z][y][cx]).
+// MODE 0: forward; 1: inverse; 2: forward, divide by mu, inverse (the last
+// axis).  A block takes lpb neighbouring x columns of one (field, z or y).
+template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, FftLine L, Symbol sym,
-                                                     const void* __restrict__ in, void* __restrict__ out, int cx) {
+                                                     const float2* __restrict__ in, float2* __restrict__ out, int cx) {
   if (halted(g.halt)) return;
   extern __shared__ float2 sh[];
   const int n = L.n;
-  const int ls = n | 1;     // odd line stride: the y and z passes write across lines without bank conflicts
+  const int ls = n | 1;     // odd line stride: writes across lines hit distinct banks
   float2* b0 = sh;
   float2* b1 = sh + lpb * ls;
   float2* twl = sh + 2 * lpb * ls;  // twiddles, staged with the first load
   for (int q = threadIdx.x; q < n; q += blockDim.x) twl[q] = L.tw[q];
-  // y and z passes run over the half spectrum along x: cx = m_x / 2 + 1 columns
   const int m0 = cx, m1 = g.mv[1], m2 = D == 3 ? g.mv[2] : 1;
   const long long fstride = (long long)m0 * m1 * m2;
   const int fields = g.nodes * D;
-  // group decomposition
-  long long group = blockIdx.x;
-  long long base;           // address of element 0 of line 0
-  long long lstride;        // address step between lines of the group
-  long long estride;        // address step along the line
-  int nlines;               // valid lines in this group
-  int f, c1 = 0, c2 = 0;    // field and coordinates of line 0 (for the symbol)
-  if (axis == 0) {
-    long long rows = (long long)fields * m1 * m2;
-    long long row0 = group * lpb;
-    if (row0 >= rows) return;
-    nlines = (int)min((long long)lpb, rows - row0);
-    base = row0 * m0;
-    lstride = m0;
-    estride = 1;
-    f = 0;
-  } else {
-    int xg = (int)(group % ((m0 + lpb - 1) / lpb));
-    long long rest = group / ((m0 + lpb - 1) / lpb);
-    int other = axis == 1 ? m2 : m1;
-    int o = (int)(rest % other);
-    f = (int)(rest / other);
-    if (f >= fields) return;
-    int x0 = xg * lpb;
-    nlines = min(lpb, m0 - x0);
-    if (axis == 1) {
-      base = (long long)f * fstride + (long long)o * m0 * m1 + x0;
-      estride = m0;
-      c2 = o;
-    } else {
-      base = (long long)f * fstride + (long long)o * m0 + x0;
-      estride = (long long)m0 * m1;
-      c1 = o;
-    }
-    lstride = 1;
-    c1 = axis == 1 ? 0 : c1;
-  }
-  // load: for the x pass consecutive threads walk along a line, for the y
-  // and z passes across lines (neighbouring x columns); both are contiguous
-  const bool along = lstride != 1;
+  const long long group = blockIdx.x;
+  const int xg = (int)(group % ((m0 + lpb - 1) / lpb));
+  const long long rest = group / ((m0 + lpb - 1) / lpb);
+  const int other = axis == 1 ? m2 : m1;
+  const int o = (int)(rest % other);
+  const int f = (int)(rest / other);  // field
+  if (f >= fields) return;
+  const int x0 = xg * lpb;
+  const int nlines = min(lpb, m0 - x0);
+  // element 0 of line 0, step along the line; lines are neighbouring columns
+  const long long base = axis == 1 ? (long long)f * fstride + (long long)o * m0 * m1 + x0
+                                   : (long long)f * fstride + (long long)o * m0 + x0;
+  const long long estride = axis == 1 ? (long long)m0 : (long long)m0 * m1;
+  const int c1 = axis == 1 ? 0 : o;  // y of the lines (z pass)
+  // load across lines (neighbouring x columns): contiguous runs of nlines
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    int i, l;
-    if (along) {
-      l = e / n;
-      i = e - l * n;
-    } else {
-      i = e / nlines;
-      l = e - i * nlines;
-    }
-    long long a = base + (long long)l * lstride + (long long)i * estride;
-    float2 v;
-    if (IN_REAL) v = make_float2(((const float*)in)[a], 0.f);
-    else v = ((const float2*)in)[a];
-    b0[l * ls + i] = v;
+    const int i = e / nlines, l = e - i * nlines;
+    b0[l * ls + i] = in[base + l + (long long)i * estride];
   }
   __syncthreads();
   float2* res;
@@ -315,19 +236,10 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
     float2* other = (res == b0) ? b1 : b0;
     for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
       int l = e / n, i = e - (e / n) * n;
-      int kx, ky, kz = 0;
-      if (axis == 0) {
-        // only used when the grid is 1-D along x (not reachable for D >= 2)
-        kx = i; ky = 0;
-      } else if (D == 2) {
-        // axis 1 lines: x varies across lines, y along the line
-        kx = ((int)(group % ((m0 + lpb - 1) / lpb))) * lpb + l;
-        ky = i;
-      } else {
-        kx = ((int)(group % ((m0 + lpb - 1) / lpb))) * lpb + l;
-        ky = c1;
-        kz = i;
-      }
+      // x frequency across lines; in 2-D the fused axis is y, in 3-D z
+      const int kx = x0 + l;
+      const int ky = D == 2 ? i : c1;
+      const int kz = D == 2 ? 0 : i;
       float lam = sym.lam[0][kx] + sym.lam[1][ky] + (D == 3 ? sym.lam[2][kz] : 0.f);
       if (sym.curv) lam = lam * lam;
       const int j = f / D;
@@ -341,18 +253,8 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
     res = lds_fft<true>(L, twl, nlines, ls, res, other);
   }
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    int i, l;
-    if (along) {
-      l = e / n;
-      i = e - l * n;
-    } else {
-      i = e / nlines;
-      l = e - i * nlines;
-    }
-    long long a = base + (long long)l * lstride + (long long)i * estride;
-    float2 v = res[l * ls + i];
-    if (OUT_REAL) ((float*)out)[a] = v.x;
-    else ((float2*)out)[a] = v;
+    const int i = e / nlines, l = e - i * nlines;
+    out[base + l + (long long)i * estride] = res[l * ls + i];
   }
 }
 
@@ -501,8 +403,8 @@ static int lines_per_block(int n, int axis, int m0) {
   return lpb;
 }
 
-template <int D, int MODE, bool IR, bool OR>
-static int fft_pass(lag_plan P, int axis, const void* in, void* out, hipStream_t s) {
+template <int D, int MODE>
+static int fft_pass(lag_plan P, int axis, const float2* in, float2* out, hipStream_t s) {
   FftLine L;
   L.n = P->prob.vel_m[axis];
   L.nrad = P->fft_nrad[axis];
@@ -521,8 +423,8 @@ static int fft_pass(lag_plan P, int axis, const void* in, void* out, hipStream_t
   const long long xg = (cx + lpb - 1) / lpb;
   const long long groups = xg * (axis == 1 ? m2 : m1) * P->fields;
   size_t lds = sizeof(float2) * (2 * (size_t)lpb * (L.n | 1) + L.n);
-  hipLaunchKernelGGL((k_fft_axis<D, MODE, IR, OR>), dim3((unsigned)groups), dim3(kBlock), lds, s, P->geo, axis, lpb,
-                     L, sym, in, out, cx);
+  hipLaunchKernelGGL((k_fft_axis<D, MODE>), dim3((unsigned)groups), dim3(kBlock), lds, s, P->geo, axis, lpb, L,
+                     sym, in, out, cx);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
@@ -560,13 +462,13 @@ int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s) {
   int rc;
   if (P->geo.dim == 3) {
     if ((rc = fft_x<3>(P, false, r, buf, s))) return rc;
-    if ((rc = fft_pass<3, 0, false, false>(P, 1, buf, buf, s))) return rc;
-    if ((rc = fft_pass<3, 2, false, false>(P, 2, buf, buf, s))) return rc;
-    if ((rc = fft_pass<3, 1, false, false>(P, 1, buf, buf, s))) return rc;
+    if ((rc = fft_pass<3, 0>(P, 1, buf, buf, s))) return rc;
+    if ((rc = fft_pass<3, 2>(P, 2, buf, buf, s))) return rc;
+    if ((rc = fft_pass<3, 1>(P, 1, buf, buf, s))) return rc;
     if ((rc = fft_x<3>(P, true, buf, z, s))) return rc;
   } else {
     if ((rc = fft_x<2>(P, false, r, buf, s))) return rc;
-    if ((rc = fft_pass<2, 2, false, false>(P, 1, buf, buf, s))) return rc;
+    if ((rc = fft_pass<2, 2>(P, 1, buf, buf, s))) return rc;
     if ((rc = fft_x<2>(P, true, buf, z, s))) return rc;
   }
   return LAG_OK;
