@@ -335,6 +335,99 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_c2r(Geo g, int lpb, FftLine L,
   }
 }
 
+// 3-D: x and y transforms of one z-plane of one field in LDS.  Forward: the
+// plane's real rows, two per complex line, are transformed along x and split
+// into their half spectra (as in k_fft_x_r2c), written transposed
+// ([kx][y], odd stride) into the other buffer, transformed along y, and
+// stored as [field][z][y][cx].  One block per (field, z).
+__global__ void __launch_bounds__(kBlock) k_fft_xy_fwd(Geo g, FftLine Lx, FftLine Ly, const float* __restrict__ in,
+                                                       float2* __restrict__ out, int cx) {
+  if (halted(g.halt)) return;
+  extern __shared__ float2 sh[];
+  const int nx = Lx.n, ny = Ly.n, lsx = nx | 1, lsy = ny | 1;
+  const int pairs = (ny + 1) / 2;
+  const int cap = max(pairs * lsx, cx * lsy);
+  float2* b0 = sh;
+  float2* b1 = sh + cap;
+  float2* twx = sh + 2 * cap;
+  float2* twy = twx + nx;
+  for (int q = threadIdx.x; q < nx; q += blockDim.x) twx[q] = Lx.tw[q];
+  for (int q = threadIdx.x; q < ny; q += blockDim.x) twy[q] = Ly.tw[q];
+  const long long plane = blockIdx.x;
+  const float* src = in + plane * nx * ny;
+  for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
+    const int l = e / nx, i = e - l * nx;
+    const int y = 2 * l;
+    const float a = src[y * nx + i];
+    const float b = y + 1 < ny ? src[(y + 1) * nx + i] : 0.f;
+    b0[l * lsx + i] = make_float2(a, b);
+  }
+  __syncthreads();
+  float2* rx = lds_fft<false>(Lx, twx, pairs, lsx, b0, b1);
+  float2* t = rx == b0 ? b1 : b0;
+  for (int e = threadIdx.x; e < pairs * cx; e += blockDim.x) {
+    const int l = e / cx, k = e - l * cx;
+    const float2 z = rx[l * lsx + k], zm = rx[l * lsx + (k == 0 ? 0 : nx - k)];
+    t[k * lsy + 2 * l] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+    if (2 * l + 1 < ny) t[k * lsy + 2 * l + 1] = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
+  }
+  __syncthreads();
+  const float2* ry = lds_fft<false>(Ly, twy, cx, lsy, t, rx);
+  float2* dst = out + plane * ny * cx;
+  for (int e = threadIdx.x; e < ny * cx; e += blockDim.x) {
+    const int y = e / cx, k = e - y * cx;
+    dst[y * cx + k] = ry[k * lsy + y];
+  }
+}
+
+// Inverse of k_fft_xy_fwd: y transform of the plane's half spectrum, then
+// the row pairs' lines A + i B rebuilt by Hermitian symmetry (as in
+// k_fft_x_c2r), transformed along x and written as real rows.
+__global__ void __launch_bounds__(kBlock) k_fft_xy_inv(Geo g, FftLine Lx, FftLine Ly, const float2* __restrict__ in,
+                                                       float* __restrict__ out, int cx) {
+  if (halted(g.halt)) return;
+  extern __shared__ float2 sh[];
+  const int nx = Lx.n, ny = Ly.n, lsx = nx | 1, lsy = ny | 1;
+  const int pairs = (ny + 1) / 2;
+  const int cap = max(pairs * lsx, cx * lsy);
+  float2* b0 = sh;
+  float2* b1 = sh + cap;
+  float2* twx = sh + 2 * cap;
+  float2* twy = twx + nx;
+  for (int q = threadIdx.x; q < nx; q += blockDim.x) twx[q] = Lx.tw[q];
+  for (int q = threadIdx.x; q < ny; q += blockDim.x) twy[q] = Ly.tw[q];
+  const long long plane = blockIdx.x;
+  const float2* src = in + plane * ny * cx;
+  for (int e = threadIdx.x; e < ny * cx; e += blockDim.x) {
+    const int y = e / cx, k = e - y * cx;
+    b0[k * lsy + y] = src[y * cx + k];
+  }
+  __syncthreads();
+  float2* ry = lds_fft<true>(Ly, twy, cx, lsy, b0, b1);
+  float2* t = ry == b0 ? b1 : b0;
+  for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
+    const int l = e / nx, i = e - l * nx;
+    const bool direct = i < cx;
+    const int k = direct ? i : nx - i;
+    float2 a = ry[k * lsy + 2 * l];
+    float2 b = 2 * l + 1 < ny ? ry[k * lsy + 2 * l + 1] : make_float2(0.f, 0.f);
+    if (!direct) {
+      a.y = -a.y;
+      b.y = -b.y;
+    }
+    t[l * lsx + i] = make_float2(a.x - b.y, a.y + b.x);
+  }
+  __syncthreads();
+  const float2* rx = lds_fft<true>(Lx, twx, pairs, lsx, t, ry);
+  float* dst = out + plane * nx * ny;
+  for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
+    const int l = e / nx, i = e - l * nx;
+    const float2 v = rx[l * lsx + i];
+    dst[2 * l * nx + i] = v.x;
+    if (2 * l + 1 < ny) dst[(2 * l + 1) * nx + i] = v.y;
+  }
+}
+
 static bool factor_radices(int n, int* rad, int* nrad) {
   int k = 0;
   int m = n;
@@ -403,6 +496,15 @@ static int lines_per_block(int n, int axis, int m0) {
   return lpb;
 }
 
+static FftLine fft_line(lag_plan P, int axis) {
+  FftLine L;
+  L.n = P->prob.vel_m[axis];
+  L.nrad = P->fft_nrad[axis];
+  for (int i = 0; i < 16; ++i) L.rad[i] = P->fft_rad[axis][i];
+  L.tw = P->fft_tw[axis];
+  return L;
+}
+
 template <int D, int MODE>
 static int fft_pass(lag_plan P, int axis, const float2* in, float2* out, hipStream_t s) {
   FftLine L;
@@ -461,6 +563,19 @@ int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s) {
   float2* buf = P->fft_buf;
   int rc;
   if (P->geo.dim == 3) {
+    const int nx = P->prob.vel_m[0], ny = P->prob.vel_m[1], cx = nx / 2 + 1;
+    const size_t cap = std::max<size_t>((size_t)((ny + 1) / 2) * (nx | 1), (size_t)cx * (ny | 1));
+    const size_t lds = sizeof(float2) * (2 * cap + nx + ny);
+    if (lds <= 64 * 1024) {  // x and y of a plane together, then z
+      FftLine Lx = fft_line(P, 0), Ly = fft_line(P, 1);
+      const unsigned planes = (unsigned)(P->fields * P->prob.vel_m[2]);
+      hipLaunchKernelGGL(k_fft_xy_fwd, dim3(planes), dim3(kBlock), lds, s, P->geo, Lx, Ly, r, buf, cx);
+      LAG_LAUNCH_CHECK();
+      if ((rc = fft_pass<3, 2>(P, 2, buf, buf, s))) return rc;
+      hipLaunchKernelGGL(k_fft_xy_inv, dim3(planes), dim3(kBlock), lds, s, P->geo, Lx, Ly, buf, z, cx);
+      LAG_LAUNCH_CHECK();
+      return LAG_OK;
+    }
     if ((rc = fft_x<3>(P, false, r, buf, s))) return rc;
     if ((rc = fft_pass<3, 0>(P, 1, buf, buf, s))) return rc;
     if ((rc = fft_pass<3, 2>(P, 2, buf, buf, s))) return rc;
