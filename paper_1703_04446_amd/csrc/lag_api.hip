@@ -742,13 +742,11 @@ static int pcg_start(lag_plan P, const float* b, float* x, double tol, int32_t m
 // device; every kernel returns at entry once ctl[0] is set).
 template <class Op>
 static int pcg_iteration(lag_plan P, Op& H, float* x, hipStream_t g) {
-  const long long n = P->n_unknowns;
   float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5], *Hp = P->vec[6];
   int rc;
   if ((rc = H(p, Hp, g, P->red_partial))) return rc;      // also the p.Hp partials (P->php_n)
   if ((rc = launch_pcg_xr(P, x, r, p, Hp, g))) return rc;   // also r.r partials
-  if ((rc = launch_precond(P, r, z, g))) return rc;
-  if ((rc = launch_dot_partial(P, n, r, z, P->red_partial, g))) return rc;
+  if ((rc = launch_precond(P, r, z, g, P->red_partial, &P->rz_n))) return rc;  // also the r.z partials
   if ((rc = launch_pcg_p(P, p, z, g))) return rc;
   return launch_pcg_check(P, g);
 }

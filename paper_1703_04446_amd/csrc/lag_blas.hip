@@ -222,12 +222,13 @@ int launch_pcg_xr(lag_plan P, float* x, float* r, const float* p, const float* H
   return LAG_OK;
 }
 
-// p update with the r.z partials in red_partial
+// p update with the r.z partials in red_partial (P->rz_n of them, from the
+// preconditioner)
 int launch_pcg_p(lag_plan P, float* p, const float* z, hipStream_t s) {
   const long long n = P->n_unknowns;
   unsigned blocks;
   reduce_launch(n, blocks);
-  hipLaunchKernelGGL(k_pcg_p, dim3(blocks), dim3(kBlock), 0, s, n, p, z, P->scalars, P->red_partial, (int)blocks,
+  hipLaunchKernelGGL(k_pcg_p, dim3(blocks), dim3(kBlock), 0, s, n, p, z, P->scalars, P->red_partial, P->rz_n,
                      P->ctl);
   LAG_LAUNCH_CHECK();
   return LAG_OK;

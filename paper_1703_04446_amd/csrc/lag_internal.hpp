@@ -42,6 +42,7 @@ struct lag_plan_s {
   double* red_partial = nullptr;  // max(kRedBlocks, one per kBlock unknowns)
   double* red_partial2 = nullptr; // kRedBlocks (PCG: r.r partials)
   int php_n = 0;                  // p.Hp partials in red_partial from the last PCG matvec
+  int rz_n = 0;                   // r.z partials in red_partial from the last PCG preconditioning
   double* scalars = nullptr;      // 16 device scalars
   // velocity-sized scratch (PCG / GN vectors)
   float* vec[10] = {nullptr};
@@ -132,7 +133,8 @@ int launch_reg(lag_plan P, const float* p, float* out, int accumulate, int with_
                float extra_scale, hipStream_t s);
 // Regulariser parameters for the tile reduction (same tables as launch_reg).
 RegTail reg_tail(lag_plan P, const float* p, int with_gamma, float extra_scale, double* part);
-int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s);
+// z = M r; with rz != null also the block partials of r . z (count in *nrz)
+int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s, double* rz = nullptr, int* nrz = nullptr);
 int precond_setup(lag_plan P);     // host tables + allocations (plan creation)
 
 // reductions: result written to dst (device double)

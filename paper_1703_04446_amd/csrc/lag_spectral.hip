@@ -389,7 +389,8 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_fwd(Geo g, FftLine Lx, F
 // the row pairs' lines A + i B rebuilt by Hermitian symmetry (as in
 // k_fft_x_c2r), transformed along x and written as real rows.
 __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_inv(Geo g, FftLine Lx, FftLine Ly, const float2* __restrict__ in,
-                                                       float* __restrict__ out, int cx) {
+                                                       float* __restrict__ out, int cx, const float* __restrict__ r,
+                                                       double* __restrict__ rz) {
   if (halted(g.halt)) return;
   extern __shared__ float2 sh[];
   const int nx = Lx.n, ny = Ly.n, lsx = nx | 1, lsy = ny | 1;
@@ -425,11 +426,22 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_inv(Geo g, FftLine Lx, F
   __syncthreads();
   const float2* rx = lds_fft<true>(Lx, twx, pairs, lsx, t, ry);
   float* dst = out + plane * nx * ny;
+  const float* rp = r ? r + plane * nx * ny : nullptr;
+  double acc = 0.0;
   for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
     const int l = e / nx, i = e - l * nx;
     const float2 v = rx[l * lsx + i];
     dst[2 * l * nx + i] = v.x;
-    if (2 * l + 1 < ny) dst[(2 * l + 1) * nx + i] = v.y;
+    if (rp) acc += (double)rp[2 * l * nx + i] * (double)v.x;
+    if (2 * l + 1 < ny) {
+      dst[(2 * l + 1) * nx + i] = v.y;
+      if (rp) acc += (double)rp[(2 * l + 1) * nx + i] * (double)v.y;
+    }
+  }
+  if (rz) {  // r . z partial of this plane (kernel argument: the whole block)
+    __shared__ double sh[kPlaneBlock];
+    const double tb = block_sum(acc, sh);
+    if (threadIdx.x == 0) rz[blockIdx.x] = tb;
   }
 }
 
@@ -562,7 +574,7 @@ static int fft_x(lag_plan P, bool inverse, const void* in, void* out, hipStream_
   return LAG_OK;
 }
 
-int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s) {
+int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s, double* rz, int* nrz) {
   if (!P->fft_ok) return LAG_EUNSUPPORTED;
   if (!(P->prob.alpha > 0.0) && !(P->prob.gamma > 0.0)) return LAG_EINVAL;
   float2* buf = P->fft_buf;
@@ -577,8 +589,10 @@ int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s) {
       hipLaunchKernelGGL(k_fft_xy_fwd, dim3(planes), dim3(kPlaneBlock), lds, s, P->geo, Lx, Ly, r, buf, cx);
       LAG_LAUNCH_CHECK();
       if ((rc = fft_pass<3, 2>(P, 2, buf, buf, s))) return rc;
-      hipLaunchKernelGGL(k_fft_xy_inv, dim3(planes), dim3(kPlaneBlock), lds, s, P->geo, Lx, Ly, buf, z, cx);
+      hipLaunchKernelGGL(k_fft_xy_inv, dim3(planes), dim3(kPlaneBlock), lds, s, P->geo, Lx, Ly, buf, z, cx,
+                         rz ? r : nullptr, rz);
       LAG_LAUNCH_CHECK();
+      if (rz) *nrz = (int)planes;
       return LAG_OK;
     }
     if ((rc = fft_x<3>(P, false, r, buf, s))) return rc;
@@ -590,6 +604,10 @@ int launch_precond(lag_plan P, const float* r, float* z, hipStream_t s) {
     if ((rc = fft_x<2>(P, false, r, buf, s))) return rc;
     if ((rc = fft_pass<2, 2>(P, 1, buf, buf, s))) return rc;
     if ((rc = fft_x<2>(P, true, buf, z, s))) return rc;
+  }
+  if (rz) {  // the separate passes: a separate inner product
+    if ((rc = launch_dot_partial(P, P->n_unknowns, r, z, rz, s))) return rc;
+    *nrz = (int)std::min<long long>(kRedBlocks, std::max<long long>(1, (P->n_unknowns + kBlock - 1) / kBlock));
   }
   return LAG_OK;
 }
