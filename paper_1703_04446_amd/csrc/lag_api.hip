@@ -6,8 +6,9 @@
 #include <string.h>
 
 #include <algorithm>
-#include <string>
+#include <functional>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "lag_internal.hpp"
@@ -702,6 +703,10 @@ struct PcgExtra {
   double bb = -1.0;
   const float* gdot = nullptr;
   double gdx = 0.0;
+  // enqueued after the solve and before its last read (which then returns
+  // scalars 0..15); set to true when it ran
+  std::function<int(hipStream_t)> before_read;
+  bool ran = false;
 };
 
 // PCG start: x = 0, r = b, z = M r, p = z, device scalars and control block
@@ -759,6 +764,12 @@ static int pcg_finish(lag_plan P, double nb, const float* x, lag_pcg_info* info,
     const int rc = launch_dot(P, P->n_unknowns, ex->gdot, x, P->scalars + 12, s);
     if (rc) return rc;
     nsc = 13;
+  }
+  if (ex && ex->before_read) {
+    const int rc = ex->before_read(s);
+    if (rc) return rc;
+    ex->ran = true;
+    nsc = 16;
   }
   LAG_HIP(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
   LAG_HIP(hipMemcpyAsync(P->sc_host, P->scalars, sizeof(double) * nsc, hipMemcpyDeviceToHost, s));
@@ -1031,6 +1042,12 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
   PcgExtra ex;
   ex.bb = h[3];   // rhs = -g: rhs . rhs = g . g exactly
   ex.gdot = g;    // slope g . dv, read with the solver's last scalars
+  // the line search's first trial (mu = 1) is enqueued before that read too
+  ex.before_read = [&](hipStream_t st) {
+    int r2 = launch_axpby(n, 1.f, v, 1.f, dv, v_next, st);
+    if (r2) return r2;
+    return objective_full(P, v_next, T, R, nullptr, nullptr, sc + 13, st);
+  };
   rc = gn_pcg(P, stored != 0, v, T, rhs, dv, o, &pi, s, &ex);
   if (rc != LAG_OK && rc != LAG_EBREAKDOWN) return rc;
   loc.pcg_iters = pi.iters;
@@ -1038,9 +1055,13 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
   const double slope = ex.gdx;
   double mu = 1.0;
   for (int k = 0; k <= o.max_halvings; ++k) {
-    if ((rc = launch_axpby(n, 1.f, v, (float)mu, dv, v_next, s))) return rc;
-    if ((rc = objective_full(P, v_next, T, R, nullptr, nullptr, sc + 13, s))) return rc;
-    if ((rc = read_scalars(P, h + 5, 13, 1, s))) return rc;
+    if (k == 0 && ex.ran) {
+      h[5] = P->sc_host[13];
+    } else {
+      if ((rc = launch_axpby(n, 1.f, v, (float)mu, dv, v_next, s))) return rc;
+      if ((rc = objective_full(P, v_next, T, R, nullptr, nullptr, sc + 13, s))) return rc;
+      if ((rc = read_scalars(P, h + 5, 13, 1, s))) return rc;
+    }
     if (h[5] <= loc.J + o.armijo_c1 * mu * slope) {
       loc.accepted = 1;
       loc.J_next = h[5];
