@@ -476,6 +476,7 @@ int lag_jvp(lag_plan P, const float* v, const float* T, const float* dv, float* 
   LAG_CHECK(P && v && T && dv && Jdv);
   int rc = launch_pack(P, v, P->pack_v, S(stream));
   if (rc) return rc;
+  P->packed_by_pcg = nullptr;
   if ((rc = launch_pack(P, dv, P->pack_p, S(stream)))) return rc;
   return launch_jvp(P, P->pack_v, P->pack_p, T, Jdv, S(stream));
 }
@@ -493,6 +494,7 @@ int gn_hessmat(lag_plan P, const float* v, const float* T, const float* wvox, co
   hipStream_t s = S(stream);
   int rc = launch_pack(P, v, P->pack_v, s);
   if (rc) return rc;
+  P->packed_by_pcg = nullptr;
   if ((rc = launch_pack(P, p, P->pack_p, s))) return rc;
   if (P->prob.model == LAG_TRANSPORT) {
     if ((rc = launch_fill(Hp, P->n_unknowns, 0.f, s))) return rc;
@@ -625,9 +627,16 @@ int lag_jacobian_info(lag_plan P, int64_t* blocks, int32_t* max_blocks, int32_t*
 
 // Assembled Gauss-Newton matvec; with part != null also the block partials
 // of p . Hp (count in P->php_n), for PCG.
+// Pack a direction into P->pack_p (clears the PCG's already-packed mark).
+static int pack_direction(lag_plan P, const float* p, hipStream_t s) {
+  P->packed_by_pcg = nullptr;
+  return launch_pack(P, p, P->pack_p, s);
+}
+
 static int hessmat_assembled(lag_plan P, const float* wvox, const float* p, float* Hp, double* part, hipStream_t s) {
-  int rc = launch_pack(P, p, P->pack_p, s);
-  if (rc) return rc;
+  int rc = LAG_OK;
+  // the PCG update leaves its direction packed (k_pcg_p_pack); others pack here
+  if (P->packed_by_pcg != p && (rc = pack_direction(P, p, s))) return rc;
   const RegTail rt = reg_tail(P, p, 1, 1.f, part);  // + alpha A p + gamma p, fused into the tile reduction
   return launch_jac_apply(P, P->pack_p, wvox, nullptr, P->geo.cell_img, Hp, s, &rt);
 }
@@ -719,6 +728,7 @@ static int pcg_start(lag_plan P, const float* b, float* x, double tol, int32_t m
   float *r = P->vec[3], *z = P->vec[4], *p = P->vec[5];
   double* sc = P->scalars;
   int rc;
+  P->packed_by_pcg = nullptr;  // p is rewritten below
   if ((rc = launch_fill(x, n, 0.f, s))) return rc;
   if ((rc = launch_axpby(n, 1.f, b, 0.f, nullptr, r, s))) return rc;
   hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 4, 0.0);

@@ -149,17 +149,42 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restric
   if (threadIdx.x == 0) rr[blockIdx.x] = t;
 }
 
-// p = z + beta p with beta = r.z (from `rz` partials, stored to sc[2]) / sc[0]
-__global__ void __launch_bounds__(kBlock) k_pcg_p(long long n, float* __restrict__ p, const float* __restrict__ z,
-                                                   double* __restrict__ sc, const double* __restrict__ rz, int nrz,
-                                                   const int* __restrict__ halt) {
+// p = z + beta p with beta = r.z (from `rz` partials, stored to sc[2]) / sc[0],
+// one thread per grid node (all D components), which also writes the packed
+// copy of p that the next matvec gathers from: the node and its periodic
+// ghost images (index + m on the axes where it is 0), the layout of k_pack.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_pcg_p_pack(Geo g, float* __restrict__ p, const float* __restrict__ z,
+                                                        double* __restrict__ sc, const double* __restrict__ rz,
+                                                        int nrz, const int* __restrict__ halt,
+                                                        typename VecT<D>::T* __restrict__ pk) {
   if (halted(halt)) return;
   __shared__ double sh[kBlock];
   const double rznew = sum_partials(rz, nrz, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[2] = rznew;
   const float beta = (float)(rznew / sc[0]);
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = fmaf(beta, p[i], z[i]);
+  const long long nv = g.nv, tot = nv * g.nodes;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    const long long j = t / nv, q = t - j * nv;
+    float v[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const long long i = (j * D + c) * nv + q;
+      v[c] = fmaf(beta, p[i], z[i]);
+      p[i] = v[c];
+    }
+    typename VecT<D>::T val;
+    if constexpr (D == 3) val = make_float4(v[0], v[1], v[2], 0.f);
+    else val = make_float2(v[0], v[1]);
+    const int x = (int)(q % g.mv[0]), y = (int)((q / g.mv[0]) % g.mv[1]);
+    const int zc = D == 3 ? (int)(q / ((long long)g.mv[0] * g.mv[1])) : 0;
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o) {
+      if (((o & 1) && x != 0) || ((o & 2) && y != 0) || ((o & 4) && zc != 0)) continue;
+      const int X = (o & 1) ? g.mv[0] : x, Y = (o & 2) ? g.mv[1] : y, Z = (o & 4) ? g.mv[2] : zc;
+      pk[j * g.nvp + ((long long)Z * g.pv[1] + Y) * g.pv[0] + X] = val;
+    }
+  }
 }
 
 // Device-side PCG control for graph-captured iterations.  ctl[0] = halt
@@ -228,9 +253,14 @@ int launch_pcg_p(lag_plan P, float* p, const float* z, hipStream_t s) {
   const long long n = P->n_unknowns;
   unsigned blocks;
   reduce_launch(n, blocks);
-  hipLaunchKernelGGL(k_pcg_p, dim3(blocks), dim3(kBlock), 0, s, n, p, z, P->scalars, P->red_partial, P->rz_n,
-                     P->ctl);
+  if (P->geo.dim == 3)
+    hipLaunchKernelGGL(k_pcg_p_pack<3>, dim3(blocks), dim3(kBlock), 0, s, P->geo, p, z, P->scalars, P->red_partial,
+                       P->rz_n, P->ctl, (float4*)P->pack_p);
+  else
+    hipLaunchKernelGGL(k_pcg_p_pack<2>, dim3(blocks), dim3(kBlock), 0, s, P->geo, p, z, P->scalars, P->red_partial,
+                       P->rz_n, P->ctl, (float2*)P->pack_p);
   LAG_LAUNCH_CHECK();
+  P->packed_by_pcg = p;  // the next matvec of the solve needs no pack
   return LAG_OK;
 }
 

@@ -43,6 +43,7 @@ struct lag_plan_s {
   double* red_partial2 = nullptr; // kRedBlocks (PCG: r.r partials)
   int php_n = 0;                  // p.Hp partials in red_partial from the last PCG matvec
   int rz_n = 0;                   // r.z partials in red_partial from the last PCG preconditioning
+  const float* packed_by_pcg = nullptr;  // PCG direction whose packed copy pack_p holds (set by its update)
   double* scalars = nullptr;      // 16 device scalars
   // velocity-sized scratch (PCG / GN vectors)
   float* vec[10] = {nullptr};
