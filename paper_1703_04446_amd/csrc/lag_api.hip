@@ -526,9 +526,6 @@ int lag_dot(lag_plan P, int64_t n, const float* x, const float* y, double* out, 
 }  // extern "C"
 
 namespace lag {
-__global__ void k_halve(double* x) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *x *= 0.5;
-}
 __global__ void k_set(double* x, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *x = v;
 }
@@ -543,11 +540,7 @@ static int objective_from_image(lag_plan P, const float* v, const float* uu, con
                                 double* out3, hipStream_t s) {
   int rc;
   if ((rc = launch_ssd(P, uu, R, wres, P->geo.cell_img, out3 + 1, s))) return rc;
-  float* tmp = P->vec[9];
-  if ((rc = launch_reg(P, v, tmp, 0, 0, 0.f, s))) return rc;
-  if ((rc = launch_dot(P, P->n_unknowns, v, tmp, out3 + 2, s))) return rc;
-  hipLaunchKernelGGL(lag::k_halve, dim3(1), dim3(64), 0, s, out3 + 2);
-  LAG_LAUNCH_CHECK();
+  if ((rc = launch_reg_energy(P, v, out3 + 2, s))) return rc;
   return launch_combine_J(out3, P->prob.alpha, s);
 }
 
@@ -747,7 +740,12 @@ static int pcg_start(lag_plan P, const float* b, float* x, double tol, int32_t m
   if ((rc = launch_precond(P, r, z, s))) return rc;
   if ((rc = launch_dot(P, n, r, z, sc + 0, s))) return rc;
   if ((rc = launch_axpby(n, 1.f, z, 0.f, nullptr, p, s))) return rc;
-  if ((rc = launch_dot(P, n, r, r, sc + 3, s))) return rc;
+  if (ex && ex->bb >= 0.0) {  // r = b: r.r is the caller's b.b
+    hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 3, bb);
+    LAG_LAUNCH_CHECK();
+  } else if ((rc = launch_dot(P, n, r, r, sc + 3, s))) {
+    return rc;
+  }
   hipLaunchKernelGGL(lag::k_set, dim3(1), dim3(64), 0, s, sc + 6, tol * tol * bb);
   LAG_LAUNCH_CHECK();
   return launch_pcg_ctl_init(P->ctl, sc, maxit, s);

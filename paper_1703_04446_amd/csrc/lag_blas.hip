@@ -78,6 +78,46 @@ int launch_dot_partial(lag_plan P, long long n, const float* x, const float* y, 
   return LAG_OK;
 }
 
+// Regulariser energy 0.5 v . (s_j A v), s_j = h_v^d w_j: block partials of
+// v_i reg_value(v)_i on the grid of k_dot_partial, then the fixed-order final
+// sum times 1/2: the terms and order of a regulariser pass, an inner product
+// and a halving, in two launches.
+template <int D, bool CURV>
+__global__ void __launch_bounds__(kBlock) k_reg_energy(Geo g, const float* __restrict__ v,
+                                                        const float* __restrict__ scale, float ih2x, float ih2y,
+                                                        float ih2z, long long n, double* __restrict__ part) {
+  if (halted(g.halt)) return;
+  __shared__ double sh[kBlock];
+  const float ih2[3] = {ih2x, ih2y, ih2z};
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    s += (double)v[i] * (double)reg_value<D, CURV>(g, v, scale, 0.f, ih2, i);
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+int launch_reg_energy(lag_plan P, const float* v, double* dst, hipStream_t s) {
+  const long long n = P->n_unknowns;
+  unsigned blocks;
+  reduce_launch(n, blocks);
+  const RegTail r = reg_tail(P, v, 0, 0.f, nullptr);
+#define LAG_RE(DD, CV)                                                                                      \
+  hipLaunchKernelGGL((k_reg_energy<DD, CV>), dim3(blocks), dim3(kBlock), 0, s, P->geo, v, r.scale, r.ih2[0], \
+                     r.ih2[1], r.ih2[2], n, P->red_partial)
+  if (P->geo.dim == 3) {
+    if (r.curv) LAG_RE(3, true);
+    else LAG_RE(3, false);
+  } else {
+    if (r.curv) LAG_RE(2, true);
+    else LAG_RE(2, false);
+  }
+#undef LAG_RE
+  LAG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, P->red_partial, (int)blocks, 0.5, dst, P->geo.halt);
+  LAG_LAUNCH_CHECK();
+  return LAG_OK;
+}
+
 int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float scale, double* dst, hipStream_t s) {
   unsigned blocks;
   const long long n = P->geo.np;

@@ -146,6 +146,8 @@ int launch_ssd(lag_plan P, const float* u, const float* R, float* wres, float sc
 int launch_axpy(long long n, float a, const float* x, float* y, hipStream_t s);
 int launch_combine_J(double* s3, double alpha, hipStream_t s);
 int launch_dot_partial(lag_plan P, long long n, const float* x, const float* y, double* part, hipStream_t s);
+// *dst = 0.5 v . (h_v^d w_j A v), the regulariser energy
+int launch_reg_energy(lag_plan P, const float* v, double* dst, hipStream_t s);
 int launch_pcg_xr(lag_plan P, float* x, float* r, const float* p, const float* Hp, hipStream_t s);
 int launch_pcg_p(lag_plan P, float* p, const float* z, hipStream_t s);
 int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s);
