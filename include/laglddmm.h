@@ -77,7 +77,9 @@ typedef struct lag_problem {
     int32_t jac_blocks;   /* capacity of the assembled Jacobian, in velocity-
                              cell blocks per characteristic (0 = no assembled
                              Jacobian; used only by the transport model with
-                             a stationary velocity; <= 255)                    */
+                             a stationary velocity; <= 255).  lag_gn_step
+                             raises it when an assembly overflows (see
+                             there); lag_jacobian_assemble never does.         */
 } lag_problem;
 
 typedef struct lag_plan_s* lag_plan;
@@ -209,8 +211,9 @@ int lag_jacobian_assemble(lag_plan plan, const float* v, const float* T, int32_t
 
 /* Size of the last assembly (host pointers): stored blocks (0 if none is
  * stored), the largest block count of any characteristic (may exceed the
- * capacity, which is why an assembly was not stored), and the bytes one
- * block occupies (values plus packed cell). */
+ * capacity, which is why an assembly was not stored; above 255 if a block
+ * lay beyond the packed cell offset's reach of 512 cells, which no capacity
+ * can store), and the bytes one block occupies (values plus packed cell). */
 int lag_jacobian_info(lag_plan plan, int64_t* blocks, int32_t* max_blocks, int32_t* bytes_per_block);
 
 /* gn_hessmat with the assembled J of the last successful assembly:
@@ -237,6 +240,16 @@ int lag_objective(lag_plan plan, const float* v, const float* T, const float* R,
  * objective (out3 as in lag_objective; may be NULL). */
 int lag_gradient(lag_plan plan, const float* v, const float* T, const float* R,
                  float* g, double* out3, void* stream);
+
+/* lag_gradient at v = 0 without tracing: the RK4 map of a zero field is the
+ * identity, so the characteristics stay at the cell centres and the adjoint
+ * sweep reduces to the sum of the RK4 stage weights at the start points
+ * (Sec. 3.1 with v = 0; both models, stationary or time-dependent).  Same
+ * result as lag_gradient with v = 0 up to float rounding; used by
+ * lag_gn_solve for the reference norm |g(0)| of its stopping test.  g
+ * velocity-shaped output; out3 as in lag_gradient (may be NULL). */
+int lag_gradient_at_zero(lag_plan plan, const float* T, const float* R, float* g, double* out3,
+                         void* stream);
 
 /* Dot product of two n-vectors with float64 accumulation, deterministic
  * order; result written to out (device, 1 double). n <= 2^31. */
@@ -325,7 +338,11 @@ typedef struct lag_gn_step_info {
 
 /* One inexact Gauss-Newton iteration (Sec. 3.2, eq. solveGN): gradient at v,
  * PCG for H(v) dv = -g (assembled Jacobian when the plan has one and it
- * fits, else matrix-free), Armijo backtracking, v_next = v + mu dv.  If
+ * fits, else matrix-free), Armijo backtracking, v_next = v + mu dv.  When
+ * the assembly overflows the plan's capacity, the step reallocates the
+ * Jacobian storage once for the longest row seen plus a quarter (at most
+ * 255 blocks; only if the new arrays fit in half of the free device memory)
+ * and assembles again; the larger capacity stays with the plan.  If
  * |g| <= gstop, no step is taken and v_next = v.  v and v_next are distinct
  * velocity-shaped device buffers.  Synchronises `stream`.  Returns
  * LAG_ELINESEARCH if no acceptable step was found (v_next = v). */

@@ -13,7 +13,7 @@ from ._lib import (  # noqa: F401
     LagProblem, LagError, Plan, make_problem, load, header_symbols, strerror,
     lag_problem_check, lag_problem_sizes, lag_plan_create, lag_plan_destroy,
     lag_trace, lag_transport, lag_pushforward, lag_jvp, lag_vjp, gn_hessmat,
-    spectral_precond_apply, lag_reg_apply, lag_objective, lag_gradient, lag_dot,
+    spectral_precond_apply, lag_reg_apply, lag_objective, lag_gradient, lag_gradient_at_zero, lag_dot,
     lag_pcg, lag_gn_default_options, lag_gn_solve, lag_profile_enable, lag_profile_read,
     lag_jacobian_assemble, gn_hessmat_assembled, lag_vjp_assembled, lag_gradient_assembled,
     lag_pcg_assembled, lag_pcg_graph, lag_pcg_assembled_graph, lag_gn_step, lag_jacobian_info, lag_restrict_image, lag_prolong_velocity,

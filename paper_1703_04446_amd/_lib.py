@@ -112,6 +112,7 @@ _SIGS = {
     "lag_reg_apply": (_I, [_P, _P, _P, _P]),
     "lag_objective": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "lag_gradient": (_I, [_P, _P, _P, _P, _P, _P, _P]),
+    "lag_gradient_at_zero": (_I, [_P, _P, _P, _P, _P, _P]),
     "lag_dot": (_I, [_P, ctypes.c_int64, _P, _P, _P, _P]),
     "lag_pcg": (_I, [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int32,
                      ctypes.POINTER(LagPcgInfo), _P]),
@@ -349,6 +350,12 @@ def lag_gradient(plan, v, T, R, g, out3):
     _check("lag_gradient", load().lag_gradient(plan.handle, _ptr(v, plan.n_unknowns, "v"),
                                                _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"),
                                                _ptr(g, plan.n_unknowns, "g"), _ptr(out3, 3, "out3", f64=True), _stream()))
+
+
+def lag_gradient_at_zero(plan, T, R, g, out3=None):
+    _check("lag_gradient_at_zero", load().lag_gradient_at_zero(
+        plan.handle, _ptr(T, plan.n_points, "T"), _ptr(R, plan.n_points, "R"), _ptr(g, plan.n_unknowns, "g"),
+        _ptr(out3, 3, "out3", f64=True), _stream()))
 
 
 def lag_dot(plan, x, y, out):

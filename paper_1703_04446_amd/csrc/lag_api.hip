@@ -574,6 +574,27 @@ int lag_gradient(lag_plan P, const float* v, const float* T, const float* R, flo
   return launch_reg(P, v, g, 1, 0, 1.f, s);
 }
 
+// Gradient at v = 0: the characteristics do not move (the RK4 map of a zero
+// field is the identity, phi = 0), so the trace is a fill and the adjoint
+// sweep a sum of the RK4 weights at the start points; the regulariser of
+// v = 0 adds nothing.
+static int gradient_at_zero(lag_plan P, const float* T, const float* R, float* g, double* out3, hipStream_t s) {
+  float* zero = P->vec[8];
+  int rc = launch_fill(zero, P->n_unknowns, 0.f, s);
+  if (rc) return rc;
+  if ((rc = launch_fill(P->phi, P->geo.np * P->geo.dim, 0.f, s))) return rc;
+  if (P->prob.model == LAG_TRANSPORT) rc = launch_transport(P, T, P->phi, P->img_a, s);
+  else rc = launch_pushforward(P, T, P->phi, P->img_a, s);
+  if (rc) return rc;
+  if ((rc = objective_from_image(P, zero, P->img_a, R, P->img_b, out3, s))) return rc;
+  return launch_vjp(P, nullptr, T, P->img_b, g, s, true);
+}
+
+int lag_gradient_at_zero(lag_plan P, const float* T, const float* R, float* g, double* out3, void* stream) {
+  LAG_CHECK(P && T && R && g);
+  return gradient_at_zero(P, T, R, g, out3 ? out3 : P->scalars + 8, S(stream));
+}
+
 // ---- assembled Jacobian ------------------------------------------------------
 
 // Assemble J at v (launch only); with u != null also write the transported
@@ -603,6 +624,44 @@ static int jacobian_assemble(lag_plan P, const float* v, const float* T, float* 
   LAG_HIP(hipStreamSynchronize(s));
   *stored = jacobian_assembled(P, mx);
   return LAG_OK;
+}
+
+// Raise the capacity to hold rows of `need` blocks (plus a quarter of
+// headroom, at most 255: a slot's count is one byte) when the new arrays fit
+// in half of the free device memory beside the old ones.  Block k of a row
+// lives at [k][...][slot] whatever the capacity, so only the value and cell
+// arrays are replaced; a captured PCG graph holding their old addresses is
+// dropped.  The caller's stream must be idle (hipFree waits for the device).
+// Returns true if the capacity grew; on an allocation failure the old arrays
+// stay and the error is cleared.
+static bool jacobian_grow(lag_plan P, int need) {
+  if (P->jac_k == 0 || need <= P->jac_k || need > 255) return false;
+  const int k = std::min(255, std::max(need, P->jac_k + (P->jac_k + 3) / 4));
+  const int nv4 = P->geo.dim == 3 ? 6 : 2;
+  const size_t vb = sizeof(float4) * (size_t)k * nv4 * (size_t)P->jac_slots;
+  const size_t cb = sizeof(int) * (size_t)k * (size_t)P->jac_slots;
+  size_t fr = 0, total = 0;
+  if (hipMemGetInfo(&fr, &total) != hipSuccess || vb + cb > fr / 2) {
+    (void)hipGetLastError();
+    return false;
+  }
+  float4* nvals = nullptr;
+  int* ncell = nullptr;
+  if (hipMalloc(&nvals, vb) != hipSuccess || hipMalloc(&ncell, cb) != hipSuccess) {
+    if (nvals) (void)hipFree(nvals);
+    (void)hipGetLastError();
+    return false;
+  }
+  (void)hipFree(P->jac_vals);
+  (void)hipFree(P->jac_cell);
+  P->jac_vals = nvals;
+  P->jac_cell = ncell;
+  P->jac_k = k;
+  if (P->pcg_exec) {
+    (void)hipGraphExecDestroy(P->pcg_exec);
+    P->pcg_exec = nullptr;
+  }
+  return true;
 }
 
 int lag_jacobian_assemble(lag_plan P, const float* v, const float* T, int32_t* stored, void* stream) {
@@ -1023,13 +1082,18 @@ int lag_gn_step(lag_plan P, const float* T, const float* R, const float* v, floa
     // counts never exceed the capacity, so the speculative product stays in
     // bounds); on overflow the gradient is redone matrix-free.  The
     // assembly's forward pass leaves T(phi) at v in img_a: no second trace.
-    int mx[2] = {0, 0};
-    if ((rc = jacobian_assemble_launch(P, v, T, P->img_a, s))) return rc;
-    if ((rc = gradient_assembled(P, v, T, R, P->img_a, g, sc + 8, s))) return rc;
-    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
-    LAG_HIP(hipMemcpyAsync(mx, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
-    stored = jacobian_assembled(P, mx);
+    // After an overflow the capacity grows once to the largest row seen and
+    // the assembly is repeated; without room the step runs matrix-free.
+    for (int attempt = 0; attempt < 2 && !stored; ++attempt) {
+      int mx[2] = {0, 0};
+      if ((rc = jacobian_assemble_launch(P, v, T, P->img_a, s))) return rc;
+      if ((rc = gradient_assembled(P, v, T, R, P->img_a, g, sc + 8, s))) return rc;
+      if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+      LAG_HIP(hipMemcpyAsync(mx, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+      if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
+      stored = jacobian_assembled(P, mx);
+      if (!stored && (attempt > 0 || !jacobian_grow(P, mx[0]))) break;
+    }
   }
   if (!stored) {
     if ((rc = lag_gradient(P, v, T, R, g, sc + 8, stream))) return rc;
@@ -1098,26 +1162,37 @@ int lag_gn_solve(lag_plan P, const float* T, const float* R, float* v, const lag
             o.graph_iters <= 64);
   hipStream_t s = S(stream);
   const long long n = P->n_unknowns;
-  float *g = P->vec[0], *vn = P->vec[7], *zero = P->vec[8];
+  float *g = P->vec[0], *vn = P->vec[7];
   double* sc = P->scalars;
   double h[8];
   lag_gn_info loc;
   memset(&loc, 0, sizeof(loc));
   int rc;
-  // reference gradient norm at v = 0
-  if ((rc = launch_fill(zero, n, 0.f, s))) return rc;
-  if ((rc = lag_gradient(P, zero, T, R, g, sc + 8, stream))) return rc;
-  if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
-  if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
-  loc.g0 = sqrt(h[3]);
-  const double gstop = o.gtol * loc.g0;
+  // reference gradient norm at v = 0; a start at v = 0 takes it from the
+  // first step's own gradient (the step then stops only if g = 0, or
+  // always if gtol >= 1, as |g| <= gtol |g| would)
+  if ((rc = launch_dot(P, n, v, v, sc + 16, s))) return rc;
+  if ((rc = read_scalars(P, h, 16, 1, s))) return rc;
+  const bool from_zero = h[0] == 0.0;
+  if (!from_zero) {
+    if ((rc = gradient_at_zero(P, T, R, g, sc + 8, s))) return rc;
+    if ((rc = launch_dot(P, n, g, g, sc + 11, s))) return rc;
+    if ((rc = read_scalars(P, h, 8, 4, s))) return rc;
+    loc.g0 = sqrt(h[3]);
+  }
+  double gstop = o.gtol * loc.g0;
   int status = LAG_OK;
   for (int it = 0; it <= o.max_gn; ++it) {
     lag_gn_step_info si;
     // the last pass only evaluates the gradient (gstop = +inf)
-    const double stop_here = it == o.max_gn ? 1e300 : gstop;
+    double stop_here = it == o.max_gn ? 1e300 : gstop;
+    if (it == 0 && from_zero && it != o.max_gn) stop_here = o.gtol >= 1.0 ? 1e300 : 0.0;
     rc = lag_gn_step(P, T, R, v, vn, &o, stop_here, &si, stream);
     if (rc != LAG_OK && rc != LAG_ELINESEARCH) return rc;
+    if (it == 0 && from_zero) {
+      loc.g0 = si.gnorm;
+      gstop = o.gtol * loc.g0;
+    }
     if (it == 0) loc.J0 = si.J;
     loc.J = si.J;
     loc.gnorm = si.gnorm;

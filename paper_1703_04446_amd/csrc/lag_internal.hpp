@@ -122,7 +122,7 @@ int launch_jvp(lag_plan P, const void* vpack, const void* dpack, const float* T,
 // seed: transport -> per-characteristic weights w (image-shaped);
 //       continuity -> image-shaped field w whose interpolant gradient is taken.
 int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, float* out,
-               hipStream_t s);
+               hipStream_t s, bool zero = false);
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
 int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt);

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from cases import SMALL_CASES, Case, gpu_problem, oracle_problem, relerr
+from cases import MIN_CASES, SMALL_CASES, Case, gpu_problem, oracle_problem, relerr
 from test_gpu_parity import MASK_CELLS, Dev, f32
 
 pytestmark = pytest.mark.gpu
@@ -194,3 +194,57 @@ def test_gn_step_monotone(torch, L):
         assert abs(Jo - info["J_next"]) <= 1e-5 * abs(Jo)
         v.copy_(vn)
     assert all(b < a for a, b in Js)
+
+
+def test_gn_step_grows_jacobian_capacity(torch, L):
+    """A Gauss-Newton step whose assembly overflows the plan's capacity (one
+    block per characteristic here) raises the capacity and stays on the
+    assembled path; its step matches a plan that had room from the start."""
+    case = SMALL_CASES[0]
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    T = f32(case.template())
+    v0 = f32(case.velocity(scale=4.0))
+    R = f32(O.objective(OP, case.velocity(scale=3.0), T, np.zeros(case.n_points))["u"])
+    small, roomy = assembled_plan(L, case, k=1), assembled_plan(L, case, k=16)
+    Td, Rd = dev.put(T), dev.put(R)
+    assert not L.lag_jacobian_assemble(small, dev.put(v0), Td)
+    outs = []
+    for plan in (small, roomy):
+        v, vn = dev.put(v0), dev.empty(plan.n_unknowns)
+        info = L.lag_gn_step(plan, Td, Rd, v, vn)
+        print("grow", info, flush=True)
+        assert info["status"] == L.LAG_OK and info["assembled"] and info["accepted"]
+        outs.append((info, dev.get(vn)))
+    (a, va), (b, vb) = outs
+    assert abs(a["J"] - b["J"]) <= 1e-6 * abs(b["J"])
+    assert abs(a["J_next"] - b["J_next"]) <= 1e-5 * abs(b["J_next"])
+    assert relerr(va, vb) < 1e-5
+    # the larger capacity stays with the plan
+    assert L.lag_jacobian_assemble(small, dev.put(v0), Td)
+    small.close()
+    roomy.close()
+
+
+@pytest.mark.parametrize("case", SMALL_CASES + MIN_CASES, ids=lambda c: c.name)
+def test_gradient_at_zero(case, torch, L):
+    """The untraced gradient at v = 0 equals lag_gradient at v = 0 and the
+    oracle's gradient there (both models, stationary and time-dependent)."""
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    plan = L.Plan(gpu_problem(case))
+    T = f32(case.template())
+    R = f32(O.objective(OP, case.velocity(), T, np.zeros(case.n_points))["u"])
+    Td, Rd = dev.put(T), dev.put(R)
+    gz, gr = dev.empty(plan.n_unknowns), dev.empty(plan.n_unknowns)
+    oz = torch.empty(3, dtype=torch.float64, device="cuda")
+    orr = torch.empty_like(oz)
+    L.lag_gradient_at_zero(plan, Td, Rd, gz, oz)
+    L.lag_gradient(plan, torch.zeros(plan.n_unknowns, device="cuda"), Td, Rd, gr, orr)
+    g_o, obj_o = O.gradient(OP, np.zeros(OP.vel_shape), T, R)
+    e_ref, e_orc = relerr(dev.get(gz), dev.get(gr)), relerr(dev.get(gz), g_o)
+    print("gradient at zero", case.name, e_ref, e_orc, flush=True)
+    assert e_ref < 1e-6 and e_orc < 1e-5
+    Jz, Jr = dev.get(oz), dev.get(orr)
+    assert np.array_equal(Jz, Jr)
+    assert abs(Jz[0] - obj_o["J"]) <= 1e-6 * abs(obj_o["J"])
