@@ -827,6 +827,124 @@ __device__ __forceinline__ void for_brick_points(const Geo& g, const Bricks& B, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// RK4 trace through an LDS-staged velocity tile (stationary fields).  One
+// block per brick stages the brick's velocity footprint (the same tile
+// geometry as the accumulation tiles: brick plus halo, padded strides) as
+// D planes of floats, then traces the brick's characteristics reading the
+// eight corners of every sample from LDS; a sample whose cell leaves the
+// tile reads the packed field in HBM instead.  The interpolation performs
+// the same operations in the same order as sample_vec, so the result is
+// bitwise that of k_trace.
+template <int D>
+struct VelTile {
+  const float* lds;  // [D][tvol]
+  int org[3];
+  int td[3];
+  int tvol;
+};
+
+template <int D>
+__device__ __forceinline__ void sample_tile(const typename VecT<D>::T* __restrict__ vp, const Geo& g,
+                                            const VelTile<D>& T, const Loc<D>& L, float val[D]) {
+  bool in = true;
+  int t[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    t[a] = L.c[a] - T.org[a];
+    in = in && (t[a] >= 0) && (t[a] + 1 < T.td[a]);
+  }
+  if (!in) {
+    float G[D][D];
+    sample_vec<false>(vp, g, L, val, G);
+    return;
+  }
+  const int sy = T.td[0];
+  if constexpr (D == 3) {
+    const int sz = T.td[0] * T.td[1];
+    const int b = (t[2] * T.td[1] + t[1]) * T.td[0] + t[0];
+    const float fx = L.f[0], fy = L.f[1], fz = L.f[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float* f = T.lds + c * T.tvol + b;
+      const float a000 = f[0], a100 = f[1], a010 = f[sy], a110 = f[sy + 1];
+      const float a001 = f[sz], a101 = f[sz + 1], a011 = f[sz + sy], a111 = f[sz + sy + 1];
+      const float e00 = lerpf(a000, a100, fx), e10 = lerpf(a010, a110, fx);
+      const float e01 = lerpf(a001, a101, fx), e11 = lerpf(a011, a111, fx);
+      const float g0 = lerpf(e00, e10, fy), g1 = lerpf(e01, e11, fy);
+      val[c] = lerpf(g0, g1, fz);
+    }
+  } else {
+    const int b = t[1] * T.td[0] + t[0];
+    const float fx = L.f[0], fy = L.f[1];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const float* f = T.lds + c * T.tvol + b;
+      const float e0 = lerpf(f[0], f[1], fx), e1 = lerpf(f[sy], f[sy + 1], fx);
+      val[c] = lerpf(e0, e1, fy);
+    }
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_trace_tile(Geo g, Stages st, Bricks B,
+                                                       const typename VecT<D>::T* __restrict__ vp,
+                                                       float* __restrict__ phi_out) {
+  extern __shared__ float vtile[];
+  const long long bid = xcd_block(B.nbricks);
+  if (bid < 0) return;
+  int O[3], org[3];
+  brick_origin<D>(g, B, bid, O, org);
+  VelTile<D> T;
+  T.lds = vtile;
+  T.tvol = B.tvol;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T.org[a] = org[a];
+    T.td[a] = B.tdim[a];
+  }
+  // stage the footprint: node (org + t) of the periodic grid, one packed
+  // vector load per node
+  for (int i = threadIdx.x; i < B.tvol; i += blockDim.x) {
+    const int t0 = i % B.tdim[0], t1 = (i / B.tdim[0]) % B.tdim[1], t2 = i / (B.tdim[0] * B.tdim[1]);
+    const int x = wrapi(org[0] + t0, g.mv[0]), y = wrapi(org[1] + t1, g.mv[1]);
+    const int z = D == 3 ? wrapi(org[2] + t2, g.mv[2]) : 0;
+    const auto q = vp[packed_corner(g, x, y, z)];
+    vtile[i] = q.x;
+    vtile[B.tvol + i] = q.y;
+    if constexpr (D == 3) vtile[2 * B.tvol + i] = q.z;
+  }
+  __syncthreads();
+  const float dt = st.dt, hdt = 0.5f * dt;
+  for_brick_points<D>(g, B, O, [&](const int idx[3]) {
+    Start<D> S;
+    make_start_idx<D>(g, idx, S);
+    float phi[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) phi[a] = 0.f;
+    for (int k = 0; k < g.nsteps; ++k) {
+      float k1[D], k2[D], k3[D], k4[D], P[D];
+      Loc<D> L;
+      locate_v<D>(g, S, phi, L);
+      sample_tile<D>(vp, g, T, L, k1);
+      stage_pos<D>(phi, hdt, k1, P);
+      locate_v<D>(g, S, P, L);
+      sample_tile<D>(vp, g, T, L, k2);
+      stage_pos<D>(phi, hdt, k2, P);
+      locate_v<D>(g, S, P, L);
+      sample_tile<D>(vp, g, T, L, k3);
+      stage_pos<D>(phi, dt, k3, P);
+      locate_v<D>(g, S, P, L);
+      sample_tile<D>(vp, g, T, L, k4);
+      rk4_update<D>(phi, dt, k1, k2, k3, k4);
+    }
+    long long p = idx[0] + (long long)g.mi[0] * idx[1];
+    if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
+#pragma unroll
+    for (int a = 0; a < D; ++a) phi_out[a * g.np + p] = phi[a];
+  });
+}
+
 // Write the block's tile to its slot of the partial-tile buffer; a separate
 // kernel sums the overlapping tiles per velocity node in a fixed order.
 template <int D, bool NS>
@@ -1583,6 +1701,17 @@ int launch_fill(float* x, long long n, float val, hipStream_t s) {
 
 int launch_trace(lag_plan P, const void* vpack, int dir, float* phi, hipStream_t s) {
   Stages st = stages_for(P, dir);
+  const lag::Bricks& B = P->bricks;
+  const size_t tile = sizeof(float) * (size_t)P->geo.dim * B.tvol;
+  if (P->geo.nodes == 1 && tile <= 64 * 1024) {  // LDS-staged velocity tile per brick
+    unsigned grid = grid_for(B.nbricks);
+    if (P->geo.dim == 3)
+      hipLaunchKernelGGL(k_trace_tile<3>, dim3(grid), dim3(kBlock), tile, s, P->geo, st, B, (const float4*)vpack, phi);
+    else
+      hipLaunchKernelGGL(k_trace_tile<2>, dim3(grid), dim3(kBlock), tile, s, P->geo, st, B, (const float2*)vpack, phi);
+    LAG_LAUNCH_CHECK();
+    return LAG_OK;
+  }
   unsigned grid = grid_for((P->geo.np + kBlock - 1) / kBlock);
   if (P->geo.dim == 3) {
     if (P->geo.nodes > 1)

@@ -297,3 +297,24 @@ def test_hessmat_equals_composition(torch, L):
         L.lag_reg_apply(plan, dev.put(p), R)
         comp = dev.get(JTJp) + dev.get(R)
         assert relerr(dev.get(Hp), comp) < 1e-5, case.name
+
+
+@pytest.mark.parametrize("case", [
+    SMALL_CASES[4].with_(name="3d_far", amplitude=1.2),
+    SMALL_CASES[0].with_(name="2d_far", amplitude=0.5, nsteps=8),
+], ids=lambda c: c.name)
+def test_trace_far_displacement(case, torch, L):
+    """Characteristics that travel several velocity cells beyond a brick's
+    staged velocity tile read the field from HBM: the trace still matches
+    the oracle."""
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    plan = L.Plan(gpu_problem(case))
+    v = f32(case.velocity())
+    phi_o = O.trace(OP, v)
+    phi_g = dev.empty(case.dim * plan.n_points)
+    L.lag_trace(plan, dev.put(v), -1, phi_g)
+    cells = np.abs(phi_o.reshape(case.dim, -1)).max(axis=1) * np.array(case.vel_m)
+    print("trace far", case.name, "max displacement in velocity cells", cells, flush=True)
+    assert cells.max() > 4
+    assert relerr(dev.get(phi_g), phi_o) < TOL
