@@ -631,11 +631,13 @@ static int jacobian_assemble(lag_plan P, const float* v, const float* T, float* 
 // in half of the free device memory beside the old ones.  Block k of a row
 // lives at [k][...][slot] whatever the capacity, so only the value and cell
 // arrays are replaced; a captured PCG graph holding their old addresses is
-// dropped.  The caller's stream must be idle (hipFree waits for the device).
+// dropped.  The caller's stream must be idle (hipFree waits for the device);
+// the API lock keeps the allocation clear of another thread's graph capture.
 // Returns true if the capacity grew; on an allocation failure the old arrays
 // stay and the error is cleared.
 static bool jacobian_grow(lag_plan P, int need) {
   if (P->jac_k == 0 || need <= P->jac_k || need > 255) return false;
+  std::lock_guard<std::mutex> lk(api_lock());
   const int k = std::min(255, std::max(need, P->jac_k + (P->jac_k + 3) / 4));
   const int nv4 = P->geo.dim == 3 ? 6 : 2;
   const size_t vb = sizeof(float4) * (size_t)k * nv4 * (size_t)P->jac_slots;
