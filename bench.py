@@ -19,6 +19,8 @@ The JSON line also carries:
                  with HIP events on its own stream inside the timed region;
   cpu_baseline - the FP64 NumPy oracle's matvec on a sample of the
                  characteristics of the same problem, scaled to matvecs/s;
+                 with it ("solve"), a whole Gauss-Newton solve of the 2-D
+                 64^2 workload timed on the GPU and in the oracle;
   batch        - 80 uneven 2-D/3-D transport/continuity pairs solved one
                  after another on one stream against lag_batch_solve
                  (worker streams, graph-replayed PCG, autotuned bricks);
@@ -131,6 +133,50 @@ def cpu_baseline(w, v, p, nsample):
                       f"single-threaded NumPy float64"}
 
 
+def solve_comparison(L, torch):
+    """Whole Gauss-Newton solve of the 2-D 64^2 transport workload from v = 0
+    to |g| <= 1e-2 |g(0)|: the GPU solver (median wall time of five solves
+    after one untimed) against the oracle's solver timed once on one host
+    core, on the same T and R (R = T transported by the true velocity,
+    computed by the oracle)."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    from synthetic import workload
+    w = workload("2d64_transport")
+    P = O.Problem(dim=w.dim, img_m=w.img_m, vel_m=w.vel_m, nodes=w.nodes, model=w.model,
+                  reg=w.reg, nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma)
+    T = w.template().ravel()
+    R = O.objective(P, w.velocity_true(), T, np.zeros(P.n_points))["u"]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, hist = O.gn_solve(P, T, R, pcg_tol=w.pcg_tol, pcg_maxit=w.pcg_maxit)
+        t_oracle = time.perf_counter() - t0
+    plan = L.Plan(L.make_problem(w.dim, w.img_m, w.vel_m, nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma,
+                                 jac_blocks=8))
+    opts = L.lag_gn_default_options()
+    opts.pcg_tol, opts.pcg_maxit = w.pcg_tol, w.pcg_maxit
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()  # noqa: E731
+    Td, Rd = dev(T), dev(R)
+    times = []
+    for _ in range(6):
+        v = torch.zeros(plan.n_unknowns, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = L.lag_gn_solve(plan, Td, Rd, v, opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    plan.close()
+    gpu_ms = float(np.median(times[1:])) * 1e3
+    return {"workload": w.name, "stop": "|g| <= 1e-2 |g(0)|", "cores": 1,
+            "oracle_s": round(t_oracle, 3), "oracle_status": hist["status"],
+            "oracle_gn_iters": len(hist["pcg_iters"]), "oracle_pcg_iters": int(sum(hist["pcg_iters"])),
+            "oracle_J_reduction": round(1.0 - hist["J"][-1] / hist["J"][0], 4),
+            "gpu_ms": round(gpu_ms, 3), "gpu_converged": bool(info["converged"]),
+            "gpu_gn_iters": info["iters"], "gpu_pcg_iters": info["pcg_iters"],
+            "gpu_J_reduction": round(1.0 - info["J"] / info["J0"], 4),
+            "speedup": round(t_oracle * 1e3 / gpu_ms, 1)}
+
+
 def warm_start_measurement(args, L, torch):
     """Gauss-Newton solve time from v = 0 against the solve refined from the
     warm-start network's prediction, on held-out pairs.
@@ -208,13 +254,19 @@ def warm_start_measurement(args, L, torch):
     mean = lambda xs: float(np.mean(xs))  # noqa: E731
     plain_ms = mean([p["solve_s"] * 1e3 for p, _, _ in rows])
     warm_ms = mean([(q["solve_s"] + q["predict_s"]) * 1e3 for _, q, _ in rows])
+    median = lambda xs: round(float(np.median(xs)), 3)  # noqa: E731
     return {
         "metric": "Gauss-Newton solve time to |g| <= 1e-2 |g(0)|, learned warm start vs plain",
         "workload": we.name, "unit": "ms", "plain_ms": round(plain_ms, 3), "warm_ms": round(warm_ms, 3),
         "speedup": round(plain_ms / warm_ms, 3),
         "predict_ms": round(mean([q["predict_s"] * 1e3 for _, q, _ in rows]), 3),
+        "plain_ms_median": median([p["solve_s"] * 1e3 for p, _, _ in rows]),
+        "warm_ms_median": median([(q["solve_s"] + q["predict_s"]) * 1e3 for _, q, _ in rows]),
         "plain_gn_iters": mean([p["iters"] for p, _, _ in rows]),
         "warm_gn_iters": mean([q["iters"] for _, q, _ in rows]),
+        "plain_pcg_iters": mean([p["pcg_iters"] for p, _, _ in rows]),
+        "warm_pcg_iters": mean([q["pcg_iters"] for _, q, _ in rows]),
+        "objective_reduction_plain": round(mean([1.0 - p["J"] / p["J0"] for p, _, _ in rows]), 4),
         "all_converged": bool(all(p["converged"] and q["converged"] for p, q, _ in rows)),
         "objective_gap_closed_by_prediction": round(mean([(p["J0"] - Jp) / (p["J0"] - p["J"])
                                                           for p, _, Jp in rows]), 4),
@@ -445,6 +497,8 @@ def main():
         log(args, f"timing the oracle on {args.cpu_sample} characteristics ...")
         res["cpu_baseline"] = cpu_baseline(w, 0.5 * vt.astype(np.float64), p0.astype(np.float64),
                                            args.cpu_sample)
+        log(args, "timing the 2-D 64^2 solve on the GPU and in the oracle ...")
+        res["cpu_baseline"]["solve"] = solve_comparison(L, torch)
     print(json.dumps(res), flush=True)
 
 
