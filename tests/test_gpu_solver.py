@@ -248,3 +248,27 @@ def test_gradient_at_zero(case, torch, L):
     Jz, Jr = dev.get(oz), dev.get(orr)
     assert np.array_equal(Jz, Jr)
     assert abs(Jz[0] - obj_o["J"]) <= 1e-6 * abs(obj_o["J"])
+
+
+def test_gn_solve_reference_gradient(torch, L):
+    """The stopping reference |g(0)| is the same whether the solve starts at
+    v = 0 (taken from the first step's gradient) or elsewhere (untraced
+    gradient at zero), and equals the oracle's."""
+    case = SMALL_CASES[4]
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    plan = assembled_plan(L, case, k=8)
+    T = f32(case.template())
+    vt = case.velocity()
+    R = f32(O.objective(OP, vt, T, np.zeros(case.n_points))["u"])
+    Td, Rd = dev.put(T), dev.put(R)
+    opt = L.lag_gn_default_options()
+    opt.max_gn = 1
+    a = L.lag_gn_solve(plan, Td, Rd, torch.zeros(plan.n_unknowns, device="cuda"), opt)
+    b = L.lag_gn_solve(plan, Td, Rd, dev.put(0.5 * f32(vt)), opt)
+    g0o = np.linalg.norm(O.gradient(OP, np.zeros(OP.vel_shape), T, R)[0])
+    print("reference", a["g0"], b["g0"], g0o, flush=True)
+    assert abs(a["g0"] - b["g0"]) <= 1e-6 * g0o
+    assert abs(a["g0"] - g0o) <= 1e-5 * g0o
+    # the start at 0.5 v_true is closer: its first objective is lower
+    assert b["J0"] < a["J0"]
