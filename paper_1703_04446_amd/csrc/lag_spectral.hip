@@ -100,12 +100,86 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Quotient by a divisor that is fixed for the kernel, for the per-element
+// index loops (a runtime integer division costs tens of instructions).  With
+// m = floor((2^32 - 1) / d) + 1, m d = 2^32 + delta with 0 <= delta < d, so
+// floor(e m / 2^32) = floor(e / d) whenever e delta < 2^32: every e below
+// 2^32 / d (here e < 2^20, d <= 1024).
+struct DivBy {
+  unsigned d, m;
+  __device__ __forceinline__ explicit DivBy(int dd)
+      : d((unsigned)dd), m(dd > 1 ? 0xFFFFFFFFu / (unsigned)dd + 1u : 0u) {}
+  __device__ __forceinline__ int operator()(int e) const {
+    return d > 1 ? (int)__umulhi((unsigned)e, m) : e;
+  }
+};
+
+// Power-of-two lengths (radices 4 and 2 only): the same Stockham stages as
+// lds_fft with every index division a shift and every remainder a mask.  The
+// butterflies, twiddles and output positions are those of the general
+// routine, so the result is bitwise the same; the runtime divisions of the
+// general index arithmetic made a stage about five times as expensive.
+template <bool INV>
+__device__ float2* lds_fft_pow2(const FftLine& L, const float2* tw, int lines, int ls, float2* b0, float2* b1) {
+  const int ln = __ffs(L.n) - 1;  // log2 n
+  int lNs = 0;                     // log2 of the finished sub-transform length
+  for (int st = 0; st < L.nrad; ++st) {
+    const int R = L.rad[st];
+    const int lR = R == 4 ? 2 : 1;
+    const int lnb = ln - lR;            // n / R butterflies per line
+    const int lspan = ln - lNs - lR;    // twiddle stride n / (Ns R)
+    const int nbm = (1 << lnb) - 1, nsm = (1 << lNs) - 1;
+    for (int b = threadIdx.x; b < (lines << lnb); b += blockDim.x) {
+      const int line = b >> lnb, j = b & nbm;
+      const float2* src = b0 + line * ls;
+      float2* dst = b1 + line * ls;
+      const int k = j & nsm;
+      float2 v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r < R) {
+          float2 x = src[j + (r << lnb)];
+          float2 t = tw[(r * k) << lspan];
+          if (INV) t.y = -t.y;
+          v[r] = r ? cmul(x, t) : x;
+        }
+      }
+      float2 w[4];
+      if (R == 2) {
+        w[0] = make_float2(v[0].x + v[1].x, v[0].y + v[1].y);
+        w[1] = make_float2(v[0].x - v[1].x, v[0].y - v[1].y);
+      } else {
+        float2 a = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+        float2 bq = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+        float2 c = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+        float2 d = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+        float2 dj = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+        w[0] = make_float2(a.x + c.x, a.y + c.y);
+        w[2] = make_float2(a.x - c.x, a.y - c.y);
+        w[1] = make_float2(bq.x + dj.x, bq.y + dj.y);
+        w[3] = make_float2(bq.x - dj.x, bq.y - dj.y);
+      }
+      const int d0 = ((j >> lNs) << (lNs + lR)) + k;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < R) dst[d0 + (r << lNs)] = w[r];
+    }
+    __syncthreads();
+    float2* t = b0;
+    b0 = b1;
+    b1 = t;
+    lNs += lR;
+  }
+  return b0;
+}
+
 // In-LDS Stockham FFT of `lines` lines of length n (buffers [lines][ls],
 // line stride ls >= n), twiddles tw (the table of L staged in LDS).  Returns
 // the buffer holding the result.  INV selects exp(+2 pi i ...).
 template <bool INV>
 __device__ float2* lds_fft(const FftLine& L, const float2* tw, int lines, int ls, float2* b0, float2* b1) {
   const int n = L.n;
+  if ((n & (n - 1)) == 0) return lds_fft_pow2<INV>(L, tw, lines, ls, b0, b1);
   int Ns = 1;
   for (int st = 0; st < L.nrad; ++st) {
     const int R = L.rad[st];
@@ -220,8 +294,9 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
   const long long estride = axis == 1 ? (long long)m0 : (long long)m0 * m1;
   const int c1 = axis == 1 ? 0 : o;  // y of the lines (z pass)
   // load across lines (neighbouring x columns): contiguous runs of nlines
+  const DivBy by_lines(nlines), by_n(n);
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    const int i = e / nlines, l = e - i * nlines;
+    const int i = by_lines(e), l = e - i * nlines;
     b0[l * ls + i] = in[base + l + (long long)i * estride];
   }
   __syncthreads();
@@ -235,7 +310,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
     // divide by the symbol; the fused axis is the last one
     float2* other = (res == b0) ? b1 : b0;
     for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-      int l = e / n, i = e - (e / n) * n;
+      const int l = by_n(e), i = e - l * n;
       // x frequency across lines; in 2-D the fused axis is y, in 3-D z
       const int kx = x0 + l;
       const int ky = D == 2 ? i : c1;
@@ -253,7 +328,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
     res = lds_fft<true>(L, twl, nlines, ls, res, other);
   }
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    const int i = e / nlines, l = e - i * nlines;
+    const int i = by_lines(e), l = e - i * nlines;
     out[base + l + (long long)i * estride] = res[l * ls + i];
   }
 }
@@ -276,8 +351,9 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_r2c(Geo g, int lpb, FftLine L,
   const long long pr0 = (long long)blockIdx.x * lpb;
   if (pr0 >= pairs) return;
   const int nlines = (int)min((long long)lpb, pairs - pr0);
+  const DivBy by_n(n), by_cx(cx);
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    const int l = e / n, i = e - l * n;
+    const int l = by_n(e), i = e - l * n;
     const long long ra = 2 * (pr0 + l);
     const float a = in[ra * n + i];
     const float b = ra + 1 < rows ? in[(ra + 1) * n + i] : 0.f;
@@ -286,7 +362,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_r2c(Geo g, int lpb, FftLine L,
   __syncthreads();
   const float2* res = lds_fft<false>(L, twl, nlines, ls, b0, b1);
   for (int e = threadIdx.x; e < nlines * cx; e += blockDim.x) {
-    const int l = e / cx, k = e - l * cx;
+    const int l = by_cx(e), k = e - l * cx;
     const long long ra = 2 * (pr0 + l);
     const float2 z = res[l * ls + k], zm = res[l * ls + (k == 0 ? 0 : n - k)];
     out[ra * cx + k] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
@@ -311,8 +387,9 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_c2r(Geo g, int lpb, FftLine L,
   const long long pr0 = (long long)blockIdx.x * lpb;
   if (pr0 >= pairs) return;
   const int nlines = (int)min((long long)lpb, pairs - pr0);
+  const DivBy by_n(n);
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    const int l = e / n, i = e - l * n;
+    const int l = by_n(e), i = e - l * n;
     const long long ra = 2 * (pr0 + l);
     const bool direct = i < cx;
     const int k = direct ? i : n - i;
@@ -327,7 +404,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_c2r(Geo g, int lpb, FftLine L,
   __syncthreads();
   const float2* res = lds_fft<true>(L, twl, nlines, ls, b0, b1);
   for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    const int l = e / n, i = e - l * n;
+    const int l = by_n(e), i = e - l * n;
     const long long ra = 2 * (pr0 + l);
     const float2 v = res[l * ls + i];
     out[ra * n + i] = v.x;
@@ -352,6 +429,7 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_fwd(Geo g, FftLine Lx, F
   const int nx = Lx.n, ny = Ly.n, lsx = nx | 1, lsy = ny | 1;
   const int pairs = (ny + 1) / 2;
   const int cap = max(pairs * lsx, cx * lsy);
+  const DivBy by_nx(nx), by_cx(cx);
   float2* b0 = sh;
   float2* b1 = sh + cap;
   float2* twx = sh + 2 * cap;
@@ -361,7 +439,7 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_fwd(Geo g, FftLine Lx, F
   const long long plane = blockIdx.x;
   const float* src = in + plane * nx * ny;
   for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
-    const int l = e / nx, i = e - l * nx;
+    const int l = by_nx(e), i = e - l * nx;
     const int y = 2 * l;
     const float a = src[y * nx + i];
     const float b = y + 1 < ny ? src[(y + 1) * nx + i] : 0.f;
@@ -371,7 +449,7 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_fwd(Geo g, FftLine Lx, F
   float2* rx = lds_fft<false>(Lx, twx, pairs, lsx, b0, b1);
   float2* t = rx == b0 ? b1 : b0;
   for (int e = threadIdx.x; e < pairs * cx; e += blockDim.x) {
-    const int l = e / cx, k = e - l * cx;
+    const int l = by_cx(e), k = e - l * cx;
     const float2 z = rx[l * lsx + k], zm = rx[l * lsx + (k == 0 ? 0 : nx - k)];
     t[k * lsy + 2 * l] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
     if (2 * l + 1 < ny) t[k * lsy + 2 * l + 1] = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
@@ -380,7 +458,7 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_fwd(Geo g, FftLine Lx, F
   const float2* ry = lds_fft<false>(Ly, twy, cx, lsy, t, rx);
   float2* dst = out + plane * ny * cx;
   for (int e = threadIdx.x; e < ny * cx; e += blockDim.x) {
-    const int y = e / cx, k = e - y * cx;
+    const int y = by_cx(e), k = e - y * cx;
     dst[y * cx + k] = ry[k * lsy + y];
   }
 }
@@ -396,6 +474,7 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_inv(Geo g, FftLine Lx, F
   const int nx = Lx.n, ny = Ly.n, lsx = nx | 1, lsy = ny | 1;
   const int pairs = (ny + 1) / 2;
   const int cap = max(pairs * lsx, cx * lsy);
+  const DivBy by_nx(nx), by_cx(cx);
   float2* b0 = sh;
   float2* b1 = sh + cap;
   float2* twx = sh + 2 * cap;
@@ -405,14 +484,14 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_inv(Geo g, FftLine Lx, F
   const long long plane = blockIdx.x;
   const float2* src = in + plane * ny * cx;
   for (int e = threadIdx.x; e < ny * cx; e += blockDim.x) {
-    const int y = e / cx, k = e - y * cx;
+    const int y = by_cx(e), k = e - y * cx;
     b0[k * lsy + y] = src[y * cx + k];
   }
   __syncthreads();
   float2* ry = lds_fft<true>(Ly, twy, cx, lsy, b0, b1);
   float2* t = ry == b0 ? b1 : b0;
   for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
-    const int l = e / nx, i = e - l * nx;
+    const int l = by_nx(e), i = e - l * nx;
     const bool direct = i < cx;
     const int k = direct ? i : nx - i;
     float2 a = ry[k * lsy + 2 * l];
@@ -429,7 +508,7 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_inv(Geo g, FftLine Lx, F
   const float* rp = r ? r + plane * nx * ny : nullptr;
   double acc = 0.0;
   for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
-    const int l = e / nx, i = e - l * nx;
+    const int l = by_nx(e), i = e - l * nx;
     const float2 v = rx[l * lsx + i];
     dst[2 * l * nx + i] = v.x;
     if (rp) acc += (double)rp[2 * l * nx + i] * (double)v.x;
