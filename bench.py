@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--workload", default="3d128_transport")
     ap.add_argument("--cpu-sample", type=int, default=262144,
                     help="characteristics in the oracle's timed sample (0 = skip the CPU baseline)")
+    ap.add_argument("--op-timings", type=int, default=1,
+                    help="also time the individual entry points on the workload (1) or not (0)")
     ap.add_argument("--jac-blocks", type=int, default=8,
                     help="assembled-Jacobian capacity in cell blocks per characteristic")
     ap.add_argument("--matrix-free", action="store_true",
@@ -131,6 +133,67 @@ def cpu_baseline(w, v, p, nsample):
             "sample": f"{nsample} of {P.n_points} characteristics (uniform random, seed 12345); "
                       f"{dt:.2f} s measured, scaled by {P.n_points / nsample:.1f}; "
                       f"single-threaded NumPy float64"}
+
+
+def op_timings(L, torch, w, plan, Td, vtd, p):
+    """Per-call times of the hot-path entry points on the headline workload
+    (HIP events on the calling stream, after warm-up), with the algorithmic
+    bytes of the memory-bound ones: the assembled Hessian matvec at
+    v = v_true/2, v_true and 0 (the paper notes its nonzeros grow toward the
+    solution; at v = 0 nothing moves), the matrix-free matvec, and the
+    trace, transport, J dv, J^T w and preconditioner calls."""
+    n, nu = plan.n_points, plan.n_unknowns
+
+    def timed(fn, iters):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / iters
+
+    out = {}
+    Hp = torch.empty(nu, device="cuda")
+    for label, scale in (("v_true/2", 0.5), ("v_true", 1.0), ("0", 0.0)):
+        vv = scale * vtd
+        pl, extra = plan, None
+        if not L.lag_jacobian_assemble(pl, vv, Td):
+            # longer rows than the plan holds: a plan with room for them
+            bmax = L.lag_jacobian_info(pl)[1]
+            if bmax > 255:
+                out[f"gn_hessmat_assembled@{label}"] = {"stored": False}
+                continue
+            extra = pl = L.Plan(L.make_problem(w.dim, w.img_m, w.vel_m, nsteps=w.nsteps, alpha=w.alpha,
+                                               gamma=w.gamma, jac_blocks=bmax))
+            assert L.lag_jacobian_assemble(pl, vv, Td)
+        blocks, bmax, bpb = L.lag_jacobian_info(pl)
+        ms = timed(lambda: L.gn_hessmat_assembled(pl, None, p, Hp), 50)
+        out[f"gn_hessmat_assembled@{label}"] = {"ms": round(ms, 4), "matvecs_per_s": round(1e3 / ms, 1),
+                                                "jac_blocks": int(blocks), "blocks_per_row_max": int(bmax),
+                                                "alg_GB_per_s": round((blocks * bpb + n + 8 * nu) / ms / 1e6, 1)}
+        if extra is not None:
+            extra.close()
+    v = 0.5 * vtd
+    ms = timed(lambda: L.gn_hessmat(plan, v, Td, None, p, Hp), 10)
+    out["gn_hessmat_matrix_free@v_true/2"] = {"ms": round(ms, 4), "matvecs_per_s": round(1e3 / ms, 1)}
+    phi = torch.empty(w.dim * n, device="cuda")
+    u = torch.empty(n, device="cuda")
+    ms = timed(lambda: L.lag_trace(plan, v, -1, phi), 20)
+    out["lag_trace"] = {"ms": round(ms, 4)}
+    ms = timed(lambda: L.lag_transport(plan, Td, phi, u), 50)
+    byt = n * (4 * w.dim + 4)  # phi read, u written (T gathers counted once in L2)
+    out["lag_transport"] = {"ms": round(ms, 4), "alg_GB_per_s": round(byt / ms / 1e6, 1)}
+    ms = timed(lambda: L.lag_jvp(plan, v, Td, p, u), 10)
+    out["lag_jvp"] = {"ms": round(ms, 4)}
+    ms = timed(lambda: L.lag_vjp(plan, v, Td, u, Hp), 10)
+    out["lag_vjp"] = {"ms": round(ms, 4)}
+    z = torch.empty(nu, device="cuda")
+    ms = timed(lambda: L.spectral_precond_apply(plan, p, z), 50)
+    out["spectral_precond_apply"] = {"ms": round(ms, 4), "alg_GB_per_s": round(8 * nu / ms / 1e6, 1)}
+    return out
 
 
 def solve_comparison(L, torch):
@@ -488,6 +551,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if args.op_timings and plan.n_unknowns > 0 and w.model == "transport" and not args.matrix_free:
+        L.lag_profile_enable(plan, False)
+        res["ops"] = op_timings(L, torch, w, plan, Td, vtd, dev(p0))
     plan.close()
     if args.batch_pairs > 0:
         res["batch"] = batch_measurement(args, L, torch)
