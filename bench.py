@@ -57,8 +57,8 @@ MEASURED_TRAFFIC = {
     "source": "paper_1703_04446_amd/csrc/lag_lagrangian.hip",
     "sha256": "c9bec55efbb3d16ab31ae420ea98210fc5b7261624ad685d3e0809615a1e1dc8",
     "workload": "3d128_transport",
-    "fetch_kib": 226029.097, "fetch_scale": 1.999752,
-    "write_kib": 35784.045, "write_scale": 1.0,
+    "fetch_kib": 225988.84, "fetch_scale": 1.999748,
+    "write_kib": 35784.073, "write_scale": 1.0,
 }
 
 
