@@ -1596,6 +1596,8 @@ int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const R
   do {                                 \
     if (P->cover_max <= 3)             \
       LAG_REDUCE(DIM, 3, RG);          \
+    else if (P->cover_max <= 4)        \
+      LAG_REDUCE(DIM, 4, RG);          \
     else                               \
       LAG_REDUCE(DIM, 0, RG);          \
   } while (0)
