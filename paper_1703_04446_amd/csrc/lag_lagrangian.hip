@@ -465,18 +465,34 @@ __device__ __forceinline__ bool adjoint_pass(const Geo& g, const Stages& st,
 // adjoint_pass at v = 0: no characteristic moves, every stage point is the
 // start point and every step Jacobian the identity, so each step's stage
 // adjoints are the RK4 weights dt/6, dt/3, dt/3, dt/6 times the constant
-// adjoint.  The same scatters in the same order, without sampling v.
+// adjoint, all scattered at the start point.  For a stationary field they
+// are one contribution with the summed weights (zero_add: the same terms up
+// to the order of the float additions), merged in the caller's register
+// accumulator across the thread's characteristics, which start in the same
+// velocity cell for all phases of a region; a time-dependent field splits
+// every stage between its two nodes and keeps one scatter per stage.
+template <int D, class Acc>
+__device__ __forceinline__ void zero_add(const Geo& g, const Stages& st, const Start<D>& S, const float ybar[D],
+                                         Acc& acc, Merge<D, false>& mg) {
+  const float dt = st.dt;
+  const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
+  float wsum = 0.f;
+  for (int k = 0; k < g.nsteps; ++k) wsum += (c6 + c3) + (c3 + c6);
+  float phi[D], kb[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    phi[a] = 0.f;
+    kb[a] = wsum * ybar[a];
+  }
+  Loc<D> L;
+  locate_v<D>(g, S, phi, L);
+  mg.add(acc, st, L, 0, kb);
+}
+
 template <int D, bool NS, class Acc>
 __device__ __forceinline__ void zero_adjoint(const Geo& g, const Stages& st, const Start<D>& S, const float ybar[D],
                                              Acc& acc) {
   const float dt = st.dt;
-  constexpr bool MERGE = UseMerge<D, NS>::value;
-  Merge<D, NS> mg;
-  mg.reset();
-  auto scat = [&](const Loc<D>& L, int q, const float kb[D]) {
-    if constexpr (MERGE) mg.add(acc, st, L, q, kb);
-    else acc.add(L, q, kb);
-  };
   float phi[D], k6[D], k3[D];
   const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
 #pragma unroll
@@ -487,6 +503,13 @@ __device__ __forceinline__ void zero_adjoint(const Geo& g, const Stages& st, con
   }
   Loc<D> L;
   locate_v<D>(g, S, phi, L);
+  constexpr bool MERGE = UseMerge<D, NS>::value;
+  Merge<D, NS> mg;
+  mg.reset();
+  auto scat = [&](const Loc<D>& L, int q, const float kb[D]) {
+    if constexpr (MERGE) mg.add(acc, st, L, q, kb);
+    else acc.add(L, q, kb);
+  };
   for (int k = 0; k < g.nsteps; ++k) {
     const int q = 4 * k;
     scat(L, q, k6);
@@ -994,6 +1017,8 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
   const int fields = g.nodes * D;
   TileAcc<D, NS> acc = make_acc<D, NS>(lds, out, g, st, B, org, fields);
   bool bad = false;
+  Merge<D, false> zmg;  // ZERO with a stationary field: kept across the thread's points
+  zmg.reset();
   for_brick_points<D>(g, B, O, [&](const int idx[3]) {
     Start<D> S;
     make_start_idx<D>(g, idx, S);
@@ -1038,9 +1063,11 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
       for (int a = 0; a < D; ++a) s = fmaf(F[a][b], yN[a], s);
       y0[b] = s;
     }
-    if constexpr (ZERO) zero_adjoint<D, NS>(g, st, S, y0, acc);
+    if constexpr (ZERO && !NS) zero_add<D>(g, st, S, y0, acc, zmg);
+    else if constexpr (ZERO) zero_adjoint<D, NS>(g, st, S, y0, acc);
     else if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) bad = true;
   });
+  if constexpr (ZERO && !NS) zmg.flush(acc);
   if (bad) atomicOr(flags, 1);
   flush_tile<D, NS>(acc, fields, part, bid);
 }
