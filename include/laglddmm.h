@@ -353,9 +353,11 @@ int lag_gn_step(lag_plan plan, const float* T, const float* R, const float* v, f
  * direction from lag_pcg, Armijo backtracking by halving.  v is the start
  * value on entry and the solution on exit (velocity-shaped, device).
  * opt: host pointer or NULL for defaults; info: host pointer or NULL.
- * Each iteration is lag_gn_step.  Synchronises `stream` to read scalars.
- * Returns LAG_ELINESEARCH if the line search fails (v then holds the last
- * accepted iterate). */
+ * Each iteration is lag_gn_step.  The stopping test is
+ * |g| <= gtol |g(v = 0)|: the reference comes from lag_gradient_at_zero, or,
+ * when v is zero on entry, from the first step's own gradient.  Synchronises
+ * `stream` to read scalars.  Returns LAG_ELINESEARCH if the line search
+ * fails (v then holds the last accepted iterate). */
 int lag_gn_solve(lag_plan plan, const float* T, const float* R, float* v,
                  const lag_gn_options* opt, lag_gn_info* info, void* stream);
 
