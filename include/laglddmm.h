@@ -26,7 +26,9 @@
  *    unless stated otherwise.  The caller allocates and owns every buffer;
  *    the plan owns only its workspace.  Outputs must not alias inputs.
  *  - `stream` is a hipStream_t (NULL = the default stream).  The hot-path
- *    calls are asynchronous on that stream and allocate nothing.  Plan
+ *    calls are asynchronous on that stream and allocate nothing (the
+ *    Gauss-Newton step, and the solvers built on it, may grow the assembled
+ *    Jacobian's storage: see lag_gn_step).  Plan
  *    creation/destruction allocate/free and synchronise the device; the
  *    profiling reads, lag_pcg and lag_gn_solve synchronise (documented at
  *    each).
