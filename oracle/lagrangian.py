@@ -11,11 +11,13 @@ Follows Sec. 3.1 and Algorithm 1 of the paper:
   with hat width equal to the cell size, i.e. the transpose of linear
   interpolation at the forward end points (the special case the paper states
   right after eq. ukOMT, and the one its experiments use);
-* the Jacobian-vector product is Algorithm 1's forward derivative recursion
-  (D1..D4) applied to a direction dv; the vector-Jacobian product is the
-  exact reverse-mode adjoint of the same discrete map (this oracle keeps the
-  whole trajectory in memory for it; the memory-lean recursion of the paper
-  is what the GPU path implements).
+* RK4 is written as an explicit Runge-Kutta method given by its Butcher
+  tableau (stage offsets A, weights B, nodes C); the Jacobian-vector product
+  is the tangent-linear map of that discrete scheme (Sec. 3.2: the derivative
+  of the final state is obtained by differentiating the RK4 recursion), and
+  the vector-Jacobian product is the exact reverse-mode adjoint of the same
+  map (this oracle keeps the whole trajectory in memory for it; the memory-
+  lean recursion of the paper is what the GPU path implements).
 
 Readings:
 
@@ -40,8 +42,22 @@ def _direction(prob):
     return -1 if prob.model == "transport" else +1
 
 
-def _stage_times(t_k, dt):
-    return (t_k, t_k + 0.5 * dt, t_k + 0.5 * dt, t_k + dt)
+# Classical fourth-order Runge-Kutta method as a Butcher tableau: stage i is
+# evaluated at phi + dt * sum_j A[i][j] k_j and time t + C[i] dt; the step adds
+# dt * sum_i B[i] k_i.  (Algorithm 1 prints the last stage point with dt/2;
+# the classical full step dt is used, see the module readings.)
+RK4_A = ((), (0.5,), (0.0, 0.5), (0.0, 0.0, 1.0))
+RK4_B = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
+RK4_C = (0.0, 0.5, 0.5, 1.0)
+
+
+def _stage_point(phi, dt, row, ks):
+    """phi + dt * sum_j row[j] ks[j] (the stage offsets of one tableau row)."""
+    out = phi
+    for a, k in zip(row, ks):
+        if a != 0.0:
+            out = out + (dt * a) * k
+    return out
 
 
 class _GridVelocity:
@@ -103,12 +119,11 @@ def rk4_characteristics(sample, phi0, direction, nsteps, keep_path=False):
     phi = phi0.copy()
     path = [phi.copy()] if keep_path else None
     for k in range(nsteps):
-        t1, t2, t3, t4 = _stage_times(t0 + k * dt, dt)
-        k1 = sample(phi, t1)
-        k2 = sample(phi + 0.5 * dt * k1, t2)
-        k3 = sample(phi + 0.5 * dt * k2, t3)
-        k4 = sample(phi + dt * k3, t4)
-        phi = phi + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        tk = t0 + k * dt
+        ks = []
+        for row, c in zip(RK4_A, RK4_C):
+            ks.append(sample(_stage_point(phi, dt, row, ks), tk + c * dt))
+        phi = _stage_point(phi, dt, RK4_B, ks)
         if keep_path:
             path.append(phi.copy())
     return phi, path
@@ -178,8 +193,13 @@ def pushforward(prob, T, phi, points=None):
 
 
 def _tangent(prob, vel, dv, direction):
-    """Algorithm 1's derivative recursion applied to the direction dv.
+    """Tangent-linear RK4 map: the derivative of the discrete characteristic
+    along the velocity direction dv (Sec. 3.2, the derivative recursion that
+    accompanies Algorithm 1).
 
+    Differentiating a stage k_i = V(P_i, t_i) with P_i = phi + dt sum_j
+    A_ij k_j gives dk_i = V(dv; P_i, t_i) + grad_y V(P_i, t_i) dP_i with
+    dP_i = dphi + dt sum_j A_ij dk_j; the step gives dphi + dt sum_i B_i dk_i.
     Returns (phi_N, dphi_N) where dphi_N = (d_v y) dv.
     """
     n = vel.idx.shape[1]
@@ -188,17 +208,18 @@ def _tangent(prob, vel, dv, direction):
     phi = np.zeros((prob.dim, n))
     dphi = np.zeros((prob.dim, n))
     for k in range(prob.nsteps):
-        t1, t2, t3, t4 = _stage_times(t0 + k * dt, dt)
-        k1, g1, e1 = vel.sample(phi, t1, grad=True, dv=dv, track=(k > 0))
-        D1 = e1 + _matvec(g1, dphi)
-        k2, g2, e2 = vel.sample(phi + 0.5 * dt * k1, t2, grad=True, dv=dv)
-        D2 = e2 + _matvec(g2, dphi + 0.5 * dt * D1)
-        k3, g3, e3 = vel.sample(phi + 0.5 * dt * k2, t3, grad=True, dv=dv)
-        D3 = e3 + _matvec(g3, dphi + 0.5 * dt * D2)
-        k4, g4, e4 = vel.sample(phi + dt * k3, t4, grad=True, dv=dv)
-        D4 = e4 + _matvec(g4, dphi + dt * D3)
-        dphi = dphi + (dt / 6.0) * (D1 + 2.0 * D2 + 2.0 * D3 + D4)
-        phi = phi + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        tk = t0 + k * dt
+        ks, dks = [], []
+        for i, (row, c) in enumerate(zip(RK4_A, RK4_C)):
+            P = _stage_point(phi, dt, row, ks)
+            dP = _stage_point(dphi, dt, row, dks)
+            # the first sample of the first step sits at the fixed start point
+            val, grad, dval = vel.sample(P, tk + c * dt, grad=True, dv=dv,
+                                         track=not (k == 0 and i == 0))
+            ks.append(val)
+            dks.append(dval + _matvec(grad, dP))
+        phi = _stage_point(phi, dt, RK4_B, ks)
+        dphi = _stage_point(dphi, dt, RK4_B, dks)
     return phi, dphi
 
 
@@ -255,41 +276,29 @@ def vjp(prob, v, T, w, points=None):
     out = np.zeros((prob.nodes, prob.dim, prob.n_vel))
     dt = direction / prob.nsteps
     t0 = 0.0 if direction > 0 else 1.0
+    ns = len(RK4_B)
     for k in range(prob.nsteps - 1, -1, -1):
         phi = path[k]
-        t1, t2, t3, t4 = _stage_times(t0 + k * dt, dt)
-        # recompute the four stage points of step k
-        P1 = phi
-        k1, g1, _ = vel.sample(P1, t1, grad=True)
-        P2 = phi + 0.5 * dt * k1
-        k2, g2, _ = vel.sample(P2, t2, grad=True)
-        P3 = phi + 0.5 * dt * k2
-        k3, g3, _ = vel.sample(P3, t3, grad=True)
-        P4 = phi + dt * k3
-        _, g4, _ = vel.sample(P4, t4, grad=True)
-        # adjoint of phi_{k+1} = phi_k + dt/6 (k1 + 2 k2 + 2 k3 + k4)
-        kb1 = (dt / 6.0) * ybar
-        kb2 = (dt / 3.0) * ybar
-        kb3 = (dt / 3.0) * ybar
-        kb4 = (dt / 6.0) * ybar
+        tk = t0 + k * dt
+        # recompute the stage points, velocities and gradients of step k
+        P, ks, gs = [], [], []
+        for row, c in zip(RK4_A, RK4_C):
+            P.append(_stage_point(phi, dt, row, ks))
+            val, grad, _ = vel.sample(P[-1], tk + c * dt, grad=True)
+            ks.append(val)
+            gs.append(grad)
+        # adjoint of phi_{k+1} = phi_k + dt sum_i B_i k_i, stages in reverse:
+        # kbar_i collects dt B_i ybar and dt A_ji Pbar_j from later stages j;
+        # Pbar_i = grad_y V(P_i)^T kbar_i feeds phibar and the earlier stages,
+        # and kbar_i itself is scattered onto the velocity grid at P_i.
+        kbar = [(dt * b) * ybar for b in RK4_B]
         phib = ybar.copy()
-        # k4 = I(v, P4, t4), P4 = phi + dt k3
-        vel.scatter(out, P4, t4, kb4)
-        pb = _matTvec(g4, kb4)
-        phib += pb
-        kb3 = kb3 + dt * pb
-        # k3 = I(v, P3, t3), P3 = phi + dt/2 k2
-        vel.scatter(out, P3, t3, kb3)
-        pb = _matTvec(g3, kb3)
-        phib += pb
-        kb2 = kb2 + 0.5 * dt * pb
-        # k2 = I(v, P2, t2), P2 = phi + dt/2 k1
-        vel.scatter(out, P2, t2, kb2)
-        pb = _matTvec(g2, kb2)
-        phib += pb
-        kb1 = kb1 + 0.5 * dt * pb
-        # k1 = I(v, P1, t1)
-        vel.scatter(out, P1, t1, kb1)
-        phib += _matTvec(g1, kb1)
+        for i in range(ns - 1, -1, -1):
+            vel.scatter(out, P[i], tk + RK4_C[i] * dt, kbar[i])
+            pb = _matTvec(gs[i], kbar[i])
+            phib = phib + pb
+            for j, a in enumerate(RK4_A[i]):
+                if a != 0.0:
+                    kbar[j] = kbar[j] + (dt * a) * pb
         ybar = phib
     return out.reshape(prob.vel_shape)

@@ -469,6 +469,81 @@ def test_regularizer_energy_matches_gradient():
         assert abs(P.alpha * fd - np.sum(g * e)) <= 1e-8 * abs(P.alpha * fd)
 
 
+def _seminorm_form(P, x, y):
+    """h_v^d sum_c <x_c, A y_c> for stationary fields, computed without the
+    oracle's stencil: diffusion by summation by parts, h^d sum_a D_a^+ x . D_a^+ y
+    with forward differences; curvature through the DFT symbol of the
+    Laplacian, h^d sum_k lambda(k)^2 conj(x^) y^ / n (Parseval)."""
+    x = np.asarray(x, dtype=np.float64).reshape((P.dim,) + tuple(reversed(P.vel_m[: P.dim])))
+    y = np.asarray(y, dtype=np.float64).reshape(x.shape)
+    hv = P.h_vel
+    total = 0.0
+    for c in range(P.dim):
+        if P.reg == "diffusion":
+            for a in range(P.dim):
+                ax = P.dim - 1 - a
+                dx = (np.roll(x[c], -1, axis=ax) - x[c]) / hv[a]
+                dy = (np.roll(y[c], -1, axis=ax) - y[c]) / hv[a]
+                total += float(np.sum(dx * dy))
+        else:
+            shape = x[c].shape
+            lam = np.zeros(shape)
+            for a in range(P.dim):
+                ax = P.dim - 1 - a
+                k = np.arange(shape[ax]).reshape([-1 if i == ax else 1 for i in range(len(shape))])
+                lam = lam + 4.0 / hv[a] ** 2 * np.sin(np.pi * k / shape[ax]) ** 2
+            X, Y = np.fft.fftn(x[c]), np.fft.fftn(y[c])
+            total += float(np.real(np.sum(np.conj(X) * lam ** 2 * Y))) / x[c].size
+    return P.cell_vel * total
+
+
+@pytest.mark.parametrize("reg", ["diffusion", "curvature"])
+@pytest.mark.parametrize("nt", [1, 2, 3, 5])
+def test_time_quadrature_weights_trapezoid_error(reg, nt):
+    """The regulariser's time weights (node_weights) integrate a velocity that
+    is linear in time, v(t) = a + b t sampled at the n_t + 1 nodes, with the
+    composite trapezoid rule.  The integrand 1/2 <v(t), A v(t)> is quadratic
+    in t, so the exact integral is S = 1/2 (<a,a> + <a,b> + <b,b>/3) and the
+    trapezoid rule exceeds it by exactly <b,b> / (12 n_t^2).  Equal weights
+    1/n_t, or end weights that are not halved, miss this by O(1/n_t)."""
+    P = O.Problem(dim=2, img_m=(6, 5), vel_m=(6, 5), nodes=nt + 1, reg=reg, alpha=1.0,
+                  extent=(1.0, 1.3, 1.0))
+    Ps = O.Problem(dim=2, img_m=(6, 5), vel_m=(6, 5), nodes=1, reg=reg, alpha=1.0,
+                   extent=(1.0, 1.3, 1.0))
+    a = random_direction(Ps.vel_shape, 501)[0]
+    b = random_direction(Ps.vel_shape, 502)[0]
+    v = np.stack([a + b * (j / nt) for j in range(nt + 1)])
+    q = lambda x, y: _seminorm_form(Ps, x, y)  # noqa: E731
+    exact = 0.5 * (q(a, a) + q(a, b) + q(b, b) / 3.0)
+    expected = exact + q(b, b) / (12.0 * nt * nt)
+    got = O.regularizer_energy(P, v)
+    assert abs(got - expected) <= 1e-11 * abs(expected), (got, expected, exact)
+    # the pin has teeth: the two plausible misreadings miss it
+    assert abs(got - exact) > 1e-3 * abs(exact)
+    # a velocity constant in time gives the stationary energy 1/2 <a,a>
+    vc = np.stack([a] * (nt + 1))
+    assert abs(O.regularizer_energy(P, vc) - 0.5 * q(a, a)) <= 1e-11 * q(a, a)
+    assert abs(O.regularizer_energy(Ps, a[None]) - 0.5 * q(a, a)) <= 1e-11 * q(a, a)
+
+
+@pytest.mark.parametrize("plant", ["equal", "mean"])
+def test_time_quadrature_pin_rejects_misread_weights(plant, monkeypatch):
+    """Planting a misreading of the time weights in the oracle (every node
+    1/n_t, i.e. end weights not halved; or equal weights 1/(n_t + 1)) makes
+    the trapezoid pin fail."""
+    import importlib
+    OBJ = importlib.import_module("oracle.objective")
+
+    def bad(prob):
+        nt = prob.nodes - 1
+        if plant == "equal":       # every node weighted 1/n_t (ends not halved)
+            return np.full(prob.nodes, 1.0 / nt)
+        return np.full(prob.nodes, 1.0 / prob.nodes)   # equal weights summing to 1
+    monkeypatch.setattr(OBJ, "node_weights", bad)
+    with pytest.raises(AssertionError):
+        test_time_quadrature_weights_trapezoid_error("diffusion", 3)
+
+
 # --------------------------------------------------------------------- P13
 def test_pcg_solves_spd_system_like_cholesky():
     import scipy.linalg as sla
