@@ -125,6 +125,21 @@ int lag_plan_destroy(lag_plan plan);
 /* Copy of the plan's problem (host pointer). */
 int lag_plan_problem(lag_plan plan, lag_problem* out);
 
+/* Status bits the adjoint kernels (lag_vjp, gn_hessmat, the gradient, the
+ * Jacobian assembly) accumulate in the plan, read into *flags (host) after
+ * `stream` has finished; clear != 0 resets them.  Synchronises `stream`.
+ *   bit 0 (1): some characteristic's RK4 step Jacobians were close to
+ *              singular (product of their condition numbers above 100), so
+ *              its adjoint took the reverse sweep with recomputed step start
+ *              points instead of forward recovery (Sec. 3.2's derivative
+ *              recursion run backward; no matrix is inverted).  Informational:
+ *              the results are exact either way.
+ *   bit 1 (2): forward recovery met an exactly singular step Jacobian and
+ *              used the identity for it.  The guard above routes such
+ *              characteristics to the recomputed sweep first, so this bit
+ *              signals an internal error. */
+int lag_plan_flags(lag_plan plan, int32_t* flags, int32_t clear, void* stream);
+
 /* Kernel timing for measurement: when enabled, every launch of the
  * Gauss-Newton matvec's main kernel is bracketed by HIP events recorded on
  * the stream it runs on (up to 256 launches between reads).  Enabling

@@ -100,6 +100,7 @@ _SIGS = {
                              ctypes.POINTER(ctypes.c_int32)]),
     "lag_plan_destroy": (_I, [_P]),
     "lag_plan_problem": (_I, [_P, ctypes.POINTER(LagProblem)]),
+    "lag_plan_flags": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _P]),
     "lag_profile_enable": (_I, [_P, ctypes.c_int32]),
     "lag_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "lag_trace": (_I, [_P, _P, ctypes.c_int32, _P, _P]),
@@ -283,6 +284,13 @@ def lag_plan_create(prob):
 
 def lag_plan_destroy(plan):
     plan.close()
+
+
+def lag_plan_flags(plan, clear=True):
+    """Status bits of the plan's adjoint kernels (synchronises the stream)."""
+    f = ctypes.c_int32()
+    _check("lag_plan_flags", load().lag_plan_flags(plan.handle, ctypes.byref(f), int(bool(clear)), _stream()))
+    return f.value
 
 
 def lag_profile_enable(plan, enable=True):

@@ -455,6 +455,17 @@ int lag_plan_problem(lag_plan plan, lag_problem* out) {
   return LAG_OK;
 }
 
+int lag_plan_flags(lag_plan P, int32_t* flags, int32_t clear, void* stream) {
+  LAG_CHECK(P && flags);
+  const hipStream_t s = S(stream);
+  int host = 0;
+  LAG_HIP(hipMemcpyAsync(&host, P->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  if (clear) LAG_HIP(hipMemsetAsync(P->flags, 0, sizeof(int), s));
+  *flags = host;
+  return LAG_OK;
+}
+
 int lag_trace(lag_plan P, const float* v, int32_t dir, float* phi, void* stream) {
   LAG_CHECK(P && v && phi && (dir == 1 || dir == -1));
   int rc = launch_pack(P, v, P->pack_v, S(stream));

@@ -103,6 +103,39 @@ __device__ __forceinline__ bool solveT(const float M[2][2], const float b[2], fl
   return true;
 }
 
+// Frobenius condition number of a step Jacobian divided by the dimension:
+// 1 for a scaled rotation (the identity included), growing without bound as
+// M approaches a singular matrix (infinite when det M = 0).  Its product over
+// the steps bounds how much forward recovery (pass 2) can amplify rounding.
+__device__ __forceinline__ float step_cond(const float M[3][3]) {
+  float n2 = 0.f, a2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n2 = fmaf(M[i][j], M[i][j], n2);
+  const float c00 = M[1][1] * M[2][2] - M[1][2] * M[2][1], c01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+  const float c02 = M[1][0] * M[2][1] - M[1][1] * M[2][0], c10 = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+  const float c11 = M[0][0] * M[2][2] - M[0][2] * M[2][0], c12 = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+  const float c20 = M[0][1] * M[1][2] - M[0][2] * M[1][1], c21 = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+  const float c22 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  a2 = c00 * c00 + c01 * c01 + c02 * c02 + c10 * c10 + c11 * c11 + c12 * c12 + c20 * c20 + c21 * c21 + c22 * c22;
+  const float det = M[0][0] * c00 + M[0][1] * c01 + M[0][2] * c02;
+  return sqrtf(n2 * a2) / (3.f * fabsf(det));
+}
+__device__ __forceinline__ float step_cond(const float M[2][2]) {
+  // the adjugate of a 2 x 2 matrix has the same Frobenius norm as M
+  const float n2 = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[1][0] * M[1][0] + M[1][1] * M[1][1];
+  const float det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  return n2 / (2.f * fabsf(det));
+}
+
+// Forward recovery is used while the product of the step condition numbers
+// stays below this bound; beyond it (or if it is not finite) a characteristic
+// takes the recomputed reverse sweep instead, which inverts nothing.
+constexpr float kMaxRecoveryGrowth = 100.f;
+
+__device__ __forceinline__ bool recovery_ok(float growth) { return growth <= kMaxRecoveryGrowth; }
+
 // Stage positions and the state update, with explicit fmaf so that every
 // sweep rounds identically.
 template <int D>
@@ -134,6 +167,10 @@ __device__ __forceinline__ void matvec_acc(const float G[D][D], const float x[D]
   }
 }
 
+// Plan status bits written by the adjoint kernels (read by lag_plan_flags).
+constexpr int kFlagRecompute = 1;  // some characteristic took the recomputed reverse sweep
+constexpr int kFlagSingular = 2;   // forward recovery met a singular step (not expected: guarded)
+
 // ---------------------------------------------------------------------------
 // pass 1: positions, optional tangent (direction field dp) and flow Jacobian.
 template <int D, bool NS, bool TAN, bool FJ>
@@ -141,8 +178,9 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
                                              const typename VecT<D>::T* __restrict__ vp,
                                              const typename VecT<D>::T* __restrict__ dp,
                                              const Start<D>& S, float phi[D], float dphi[D],
-                                             float F[D][D]) {
+                                             float F[D][D], float* growth = nullptr) {
   constexpr bool GR = TAN || FJ;
+  if (FJ && growth) *growth = 1.f;
   const float dt = st.dt, hdt = 0.5f * dt;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -199,6 +237,7 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
     if (FJ) {
       float M[D][D], Fn[D][D];
       step_jacobian<D>(dt, G1, G2, G3, G4, M);
+      if (growth) *growth *= step_cond(M);
       matmul<D>(M, F, Fn);
 #pragma unroll
       for (int a = 0; a < D; ++a)
@@ -558,81 +597,145 @@ __device__ __forceinline__ void forward_record(const Geo& g, const Stages& st,
   }
 }
 
+// One step back of the exact reverse sweep of the RK4 map (eq. phiRK4): from
+// the step start point phi_k and lam = lambda_{k+1}, recompute the four
+// stages, form the stage adjoints (last to first), hand them to
+// scat(L, q, kb) last stage first, and return lambda_k in lam.
+template <int D, bool NS, class Scat>
+__device__ __forceinline__ void reverse_step(const Geo& g, const Stages& st,
+                                             const typename VecT<D>::T* __restrict__ vp, const Start<D>& S,
+                                             int k, const float phi[D], float lam[D], Scat scat) {
+  const float dt = st.dt, hdt = 0.5f * dt;
+  const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
+  const int q = 4 * k;
+  float k1[D], k2[D], k3[D], k4[D], P[D];
+  float G1[D][D], G2[D][D], G3[D][D], G4[D][D];
+  Loc<D> L1, L2, L3, L4;
+  locate_v<D>(g, S, phi, L1);
+  sample_vel<D, NS, true>(vp, g, st, q, L1, k1, G1);
+  stage_pos<D>(phi, hdt, k1, P);
+  locate_v<D>(g, S, P, L2);
+  sample_vel<D, NS, true>(vp, g, st, q + 1, L2, k2, G2);
+  stage_pos<D>(phi, hdt, k2, P);
+  locate_v<D>(g, S, P, L3);
+  sample_vel<D, NS, true>(vp, g, st, q + 2, L3, k3, G3);
+  stage_pos<D>(phi, dt, k3, P);
+  locate_v<D>(g, S, P, L4);
+  sample_vel<D, NS, true>(vp, g, st, q + 3, L4, k4, G4);
+  (void)k4;
+  float kb1[D], kb2[D], kb3[D], kb4[D], pb[D], sum[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) kb4[a] = c6 * lam[a];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float t = 0.f;
+#pragma unroll
+    for (int c = 0; c < D; ++c) t = fmaf(G4[c][a], kb4[c], t);
+    pb[a] = t;
+    sum[a] = t;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) kb3[a] = fmaf(dt, pb[a], c3 * lam[a]);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float t = 0.f;
+#pragma unroll
+    for (int c = 0; c < D; ++c) t = fmaf(G3[c][a], kb3[c], t);
+    pb[a] = t;
+    sum[a] += t;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) kb2[a] = fmaf(hdt, pb[a], c3 * lam[a]);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float t = 0.f;
+#pragma unroll
+    for (int c = 0; c < D; ++c) t = fmaf(G2[c][a], kb2[c], t);
+    pb[a] = t;
+    sum[a] += t;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) kb1[a] = fmaf(hdt, pb[a], c6 * lam[a]);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float t = 0.f;
+#pragma unroll
+    for (int c = 0; c < D; ++c) t = fmaf(G1[c][a], kb1[c], t);
+    sum[a] += t;
+  }
+  scat(L4, q + 3, kb4);
+  scat(L3, q + 2, kb3);
+  scat(L2, q + 1, kb2);
+  scat(L1, q, kb1);
+#pragma unroll
+  for (int a = 0; a < D; ++a) lam[a] += sum[a];
+}
+
 template <int D, class Acc>
 __device__ __forceinline__ void reverse_sweep(const Geo& g, const Stages& st,
                                               const typename VecT<D>::T* __restrict__ vp, const Start<D>& S,
                                               const float* traj, int ts, float lam[D], Acc& acc) {
-  const float dt = st.dt, hdt = 0.5f * dt;
-  const float c6 = dt * (1.f / 6.f), c3 = dt * (1.f / 3.f);
   Merge<D, false> mg;
   mg.reset();
   for (int k = g.nsteps - 1; k >= 0; --k) {
-    const int q = 4 * k;
-    float phi[D], k1[D], k2[D], k3[D], k4[D], P[D];
-    float G1[D][D], G2[D][D], G3[D][D], G4[D][D];
-    Loc<D> L1, L2, L3, L4;
+    float phi[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) phi[a] = traj[(k * D + a) * ts];
-    locate_v<D>(g, S, phi, L1);
-    sample_vel<D, false, true>(vp, g, st, q, L1, k1, G1);
-    stage_pos<D>(phi, hdt, k1, P);
-    locate_v<D>(g, S, P, L2);
-    sample_vel<D, false, true>(vp, g, st, q + 1, L2, k2, G2);
-    stage_pos<D>(phi, hdt, k2, P);
-    locate_v<D>(g, S, P, L3);
-    sample_vel<D, false, true>(vp, g, st, q + 2, L3, k3, G3);
-    stage_pos<D>(phi, dt, k3, P);
-    locate_v<D>(g, S, P, L4);
-    sample_vel<D, false, true>(vp, g, st, q + 3, L4, k4, G4);
-    (void)k4;
-    float kb1[D], kb2[D], kb3[D], kb4[D], pb[D], sum[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) kb4[a] = c6 * lam[a];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      float t = 0.f;
-#pragma unroll
-      for (int c = 0; c < D; ++c) t = fmaf(G4[c][a], kb4[c], t);
-      pb[a] = t;
-      sum[a] = t;
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) kb3[a] = fmaf(dt, pb[a], c3 * lam[a]);
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      float t = 0.f;
-#pragma unroll
-      for (int c = 0; c < D; ++c) t = fmaf(G3[c][a], kb3[c], t);
-      pb[a] = t;
-      sum[a] += t;
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) kb2[a] = fmaf(hdt, pb[a], c3 * lam[a]);
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      float t = 0.f;
-#pragma unroll
-      for (int c = 0; c < D; ++c) t = fmaf(G2[c][a], kb2[c], t);
-      pb[a] = t;
-      sum[a] += t;
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) kb1[a] = fmaf(hdt, pb[a], c6 * lam[a]);
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      float t = 0.f;
-#pragma unroll
-      for (int c = 0; c < D; ++c) t = fmaf(G1[c][a], kb1[c], t);
-      sum[a] += t;
-    }
-    mg.add(acc, st, L4, q + 3, kb4);
-    mg.add(acc, st, L3, q + 2, kb3);
-    mg.add(acc, st, L2, q + 1, kb2);
-    mg.add(acc, st, L1, q, kb1);
-#pragma unroll
-    for (int a = 0; a < D; ++a) lam[a] += sum[a];
+    reverse_step<D, false>(g, st, vp, S, k, phi, lam,
+                           [&](const Loc<D>& L, int q, const float kb[D]) { mg.add(acc, st, L, q, kb); });
   }
   mg.flush(acc);
+}
+
+// The same reverse sweep without stored step start points: phi_k is traced
+// again from the start point for every k (the operations of forward_pass,
+// so the cells are bitwise those of the forward pass).  O(N^2) samples and
+// O(1) state, no step Jacobian is inverted: the fallback of forward recovery
+// for characteristics whose step Jacobians are (nearly) singular.  lam is
+// lambda_N on entry.
+template <int D, bool NS>
+__device__ __forceinline__ void retrace(const Geo& g, const Stages& st,
+                                        const typename VecT<D>::T* __restrict__ vp, const Start<D>& S,
+                                        int ksteps, float phi[D]) {
+  const float dt = st.dt, hdt = 0.5f * dt;
+  float G[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) phi[a] = 0.f;
+  for (int k = 0; k < ksteps; ++k) {
+    const int q = 4 * k;
+    float k1[D], k2[D], k3[D], k4[D], P[D];
+    Loc<D> L;
+    locate_v<D>(g, S, phi, L);
+    sample_vel<D, NS, false>(vp, g, st, q, L, k1, G);
+    stage_pos<D>(phi, hdt, k1, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, NS, false>(vp, g, st, q + 1, L, k2, G);
+    stage_pos<D>(phi, hdt, k2, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, NS, false>(vp, g, st, q + 2, L, k3, G);
+    stage_pos<D>(phi, dt, k3, P);
+    locate_v<D>(g, S, P, L);
+    sample_vel<D, NS, false>(vp, g, st, q + 3, L, k4, G);
+    rk4_update<D>(phi, dt, k1, k2, k3, k4);
+  }
+}
+
+template <int D, bool NS, class Acc>
+__device__ __forceinline__ void reverse_recompute(const Geo& g, const Stages& st,
+                                                  const typename VecT<D>::T* __restrict__ vp, const Start<D>& S,
+                                                  float lam[D], Acc& acc) {
+  constexpr bool MERGE = UseMerge<D, NS>::value;
+  Merge<D, NS> mg;
+  mg.reset();
+  for (int k = g.nsteps - 1; k >= 0; --k) {
+    float phi[D];
+    retrace<D, NS>(g, st, vp, S, k, phi);
+    reverse_step<D, NS>(g, st, vp, S, k, phi, lam, [&](const Loc<D>& L, int q, const float kb[D]) {
+      if constexpr (MERGE) mg.add(acc, st, L, q, kb);
+      else acc.add(L, q, kb);
+    });
+  }
+  if constexpr (MERGE) mg.flush(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1016,7 +1119,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
   brick_origin<D>(g, B, bid, O, org);
   const int fields = g.nodes * D;
   TileAcc<D, NS> acc = make_acc<D, NS>(lds, out, g, st, B, org, fields);
-  bool bad = false;
+  int status = 0;  // kFlag* bits of this thread's characteristics
   Merge<D, false> zmg;  // ZERO with a stationary field: kept across the thread's points
   zmg.reset();
   for_brick_points<D>(g, B, O, [&](const int idx[3]) {
@@ -1025,6 +1128,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
     long long p = idx[0] + (long long)g.mi[0] * idx[1];
     if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
     float phi[D], dphi[D], F[D][D];
+    float growth = 1.f;
     if constexpr (ZERO) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -1033,7 +1137,7 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
         for (int b = 0; b < D; ++b) F[a][b] = a == b ? 1.f : 0.f;
       }
     } else {
-      forward_pass<D, NS, false, true>(g, st, vp, nullptr, S, phi, dphi, F);
+      forward_pass<D, NS, false, true>(g, st, vp, nullptr, S, phi, dphi, F, &growth);
     }
     Loc<D> L;
     locate_i<D>(g, S, phi, L);
@@ -1055,6 +1159,13 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
 #pragma unroll
     for (int a = 0; a < D; ++a) nz = nz || (yN[a] != 0.f);
     if (!nz) return;
+    if constexpr (!ZERO) {
+      if (!recovery_ok(growth)) {  // (nearly) singular step Jacobians
+        reverse_recompute<D, NS>(g, st, vp, S, yN, acc);
+        status |= kFlagRecompute;
+        return;
+      }
+    }
     float y0[D];
 #pragma unroll
     for (int b = 0; b < D; ++b) {
@@ -1065,10 +1176,10 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
     }
     if constexpr (ZERO && !NS) zero_add<D>(g, st, S, y0, acc, zmg);
     else if constexpr (ZERO) zero_adjoint<D, NS>(g, st, S, y0, acc);
-    else if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) bad = true;
+    else if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) status |= kFlagSingular;
   });
   if constexpr (ZERO && !NS) zmg.flush(acc);
-  if (bad) atomicOr(flags, 1);
+  if (status) atomicOr(flags, status);
   flush_tile<D, NS>(acc, fields, part, bid);
 }
 
@@ -1088,7 +1199,7 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
   brick_origin<D>(g, B, bid, O, org);
   const int fields = g.nodes * D;
   TileAcc<D, NS> acc = make_acc<D, NS>(lds, out, g, st, B, org, fields);
-  bool bad = false;
+  int status = 0;  // kFlag* bits of this thread's characteristics
   for_brick_points<D>(g, B, O, [&](const int idx[3]) {
     Start<D> S;
     make_start_idx<D>(g, idx, S);
@@ -1097,7 +1208,8 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
     float W = wvox ? wvox[p] : 1.f;
     if (W == 0.f) return;
     float phi[D], dphi[D], F[D][D];
-    forward_pass<D, NS, true, true>(g, st, vp, pp, S, phi, dphi, F);
+    float growth = 1.f;
+    forward_pass<D, NS, true, true>(g, st, vp, pp, S, phi, dphi, F, &growth);
     Loc<D> L;
     locate_i<D>(g, S, phi, L);
     float gT[D], val;
@@ -1110,6 +1222,11 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
     float yN[D], y0[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) yN[a] = s * gT[a];
+    if (!recovery_ok(growth)) {  // (nearly) singular step Jacobians
+      reverse_recompute<D, NS>(g, st, vp, S, yN, acc);
+      status |= kFlagRecompute;
+      return;
+    }
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       float t = 0.f;
@@ -1117,9 +1234,9 @@ __global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bri
       for (int a = 0; a < D; ++a) t = fmaf(F[a][b], yN[a], t);
       y0[b] = t;
     }
-    if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) bad = true;
+    if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) status |= kFlagSingular;
   });
-  if (bad) atomicOr(flags, 1);
+  if (status) atomicOr(flags, status);
   flush_tile<D, NS>(acc, fields, part, bid);
 }
 
@@ -1207,15 +1324,16 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
   const bool in = item_cell<D>(g, B, O, w, l, idx);
   const long long slot = bid * (long long)B.bdim[0] * B.bdim[1] * B.bdim[2] + (long long)w * 64 + lane;
   int count = 0;
-  bool bad = false;
+  bool bad = false, fallback = false;
   extern __shared__ float traj_lds[];  // STORED: [step][axis][thread]
   float* traj = traj_lds + threadIdx.x;
   if (in) {
     Start<D> S;
     make_start_idx<D>(g, idx, S);
     float phi[D], dphi[D], F[D][D];
+    float growth = 1.f;
     if constexpr (STORED) forward_record<D>(g, st, vp, S, phi, traj, kBlock);
-    else forward_pass<D, false, false, true>(g, st, vp, nullptr, S, phi, dphi, F);
+    else forward_pass<D, false, false, true>(g, st, vp, nullptr, S, phi, dphi, F, &growth);
     Loc<D> L;
     locate_i<D>(g, S, phi, L);
     float gT[D], val;
@@ -1251,8 +1369,16 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
       jw.count = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) jw.org[a] = org[a];
-      if constexpr (STORED) reverse_sweep<D>(g, st, vp, S, traj, kBlock, y0, jw);
-      else if (!adjoint_pass<D, false>(g, st, vp, S, y0, jw)) bad = true;
+      if constexpr (STORED) {
+        reverse_sweep<D>(g, st, vp, S, traj, kBlock, y0, jw);
+      } else if (!recovery_ok(growth)) {  // (nearly) singular step Jacobians
+#pragma unroll
+        for (int b = 0; b < D; ++b) y0[b] = gT[b];
+        reverse_recompute<D, false>(g, st, vp, S, y0, jw);
+        fallback = true;
+      } else if (!adjoint_pass<D, false>(g, st, vp, S, y0, jw)) {
+        bad = true;
+      }
       count = jw.count;
     }
   }
@@ -1264,11 +1390,11 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
     wmax = max(wmax, __shfl_xor(wmax, off, 64));
     wsum += __shfl_xor(wsum, off, 64);
   }
-  const bool wbad = __ballot(bad) != 0;
+  const int wflags = (__ballot(fallback) != 0 ? kFlagRecompute : 0) | (__ballot(bad) != 0 ? kFlagSingular : 0);
   if (lane == 0) {
     if (wmax > 0) atomicMax(maxcount, wmax);
     if (wsum > 0) atomicAdd(maxcount + 1, wsum);
-    if (wbad) atomicOr(flags, 1);
+    if (wflags) atomicOr(flags, wflags);
   }
 }
 

@@ -70,10 +70,17 @@ def gpu_problem(c: Case):
 
 
 def relerr(a, b):
+    """Parity error of ``a`` against the reference ``b``: the larger of the
+    relative 2-norm error |a - b| / |b| and the largest entry error
+    max|a - b| / max|b|.  The entry bound keeps a wrong entry in a small
+    region (a brick edge, a tile halo) from hiding under the norm."""
     a = np.asarray(a, dtype=np.float64).ravel()
     b = np.asarray(b, dtype=np.float64).ravel()
     nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    mb = np.abs(b).max() if b.size else 0.0
+    e2 = np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    einf = (np.abs(a - b).max() if b.size else 0.0) / (mb if mb > 0 else 1.0)
+    return float(max(e2, einf))
 
 
 # Cases small enough for the oracle to finish in seconds, chosen to cover

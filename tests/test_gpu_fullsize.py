@@ -10,7 +10,10 @@ sample of characteristics one by one:
   with weights supported on the sample (zero elsewhere), which the oracle
   evaluates exactly with ``points=sample``;
 * the regulariser and the preconditioner act on the velocity grid only and
-  are compared in full.
+  are compared in full;
+* with every characteristic weighted, identities that hold at any size (dot
+  test, energy, symmetry) and the agreement of the assembled and matrix-free
+  products cover the rows the sample leaves out.
 
 The 2-D 256^2 continuity workload (5 time nodes, N = 32) is small enough for
 a full comparison.
@@ -123,6 +126,55 @@ def test_transport_fullsize_sampled(name, nsample, torch, L):
         assert res[k] < TOL, (k, res[k])
     planD.close()
     plan.close()
+
+
+@pytest.mark.parametrize("name", ["3d128_transport", "3d256_transport"])
+def test_transport_fullsize_all_rows(name, torch, L):
+    """Every characteristic weighted (W = 1, no sample): properties that hold
+    at any size tie the full products to the sampled parity above.
+
+    * dot test <w, J p> = <J^T w, p> with w over all rows;
+    * energy identity <p, H_D p> = h^d |J p|^2 for the data term H_D;
+    * symmetry <q, H_D p> = <H_D q, p>;
+    * the assembled and the matrix-free Gauss-Newton products agree entry by
+      entry (two kernels with different accumulation structures)."""
+    w = workload(name)
+    dev = Dev(torch)
+    T = f32(w.template().ravel())
+    v = f32(0.5 * w.velocity_true())
+    p = f32(w.direction(0))
+    q = f32(w.direction(1))
+    planD = gplan(L, w, alpha=0.0, gamma=0.0)
+    n, nu = planD.n_points, planD.n_unknowns
+    hd = float(np.prod(1.0 / np.array(w.img_m, dtype=np.float64)))
+    Td, vd, pd, qd = dev.put(T), dev.put(v), dev.put(p), dev.put(q)
+    wimg = f32(w.image_direction(0).ravel())
+    Jp = dev.empty(n)
+    L.lag_jvp(planD, vd, Td, pd, Jp)
+    JTw = dev.empty(nu)
+    L.lag_vjp(planD, vd, Td, dev.put(wimg), JTw)
+    Jpg, JTwg = dev.get(Jp), dev.get(JTw)
+    lhs, rhs = float(wimg @ Jpg), float(JTwg.ravel() @ p.ravel())
+    scale = float(np.abs(wimg) @ np.abs(Jpg))
+    e_dot = abs(lhs - rhs) / scale
+    Hm = dev.empty(nu)
+    L.gn_hessmat(planD, vd, Td, None, pd, Hm)
+    Hq = dev.empty(nu)
+    L.gn_hessmat(planD, vd, Td, None, qd, Hq)
+    Hmg, Hqg = dev.get(Hm), dev.get(Hq)
+    energy = hd * float(Jpg @ Jpg)
+    e_energy = abs(float(p.ravel() @ Hmg.ravel()) - energy) / energy
+    a, b = float(q.ravel() @ Hmg.ravel()), float(Hqg.ravel() @ p.ravel())
+    e_sym = abs(a - b) / (float(np.abs(q.ravel()) @ np.abs(Hmg.ravel())) + 1e-300)
+    assert L.lag_jacobian_assemble(planD, vd, Td)
+    Ha = dev.empty(nu)
+    L.gn_hessmat_assembled(planD, None, pd, Ha)
+    e_am = relerr(dev.get(Ha), Hmg)
+    res = dict(dot=e_dot, energy=e_energy, symmetry=e_sym, assembled_vs_matfree=e_am)
+    print(name, "all rows", {k: f"{x:.2e}" for k, x in res.items()}, flush=True)
+    for k, x in res.items():
+        assert x < TOL, (k, x)
+    planD.close()
 
 
 def test_continuity_2d256_full(torch, L):
