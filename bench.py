@@ -44,7 +44,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32
+PEAK_FP32_VALU_TFLOPS = 157.3    # MI355X published FP32 vector peak (packed FP32 instructions)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz without packed FP32
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of the assembled matvec kernel on this workload, from two
@@ -81,6 +82,8 @@ def parse():
     ap.add_argument("--workload", default="3d128_transport")
     ap.add_argument("--cpu-sample", type=int, default=262144,
                     help="characteristics in the oracle's timed sample (0 = skip the CPU baseline)")
+    ap.add_argument("--cpu-gn-iteration", type=int, default=1,
+                    help="also time one whole Gauss-Newton iteration of the workload in the parallel oracle (1) or not (0)")
     ap.add_argument("--op-timings", type=int, default=1,
                     help="also time the individual entry points on the workload (1) or not (0)")
     ap.add_argument("--jac-blocks", type=int, default=8,
@@ -115,24 +118,182 @@ FLOP_PER_CHAR_STEP_3D = 2628
 FLOP_PER_CHAR_END_3D = 120
 
 
-def cpu_baseline(w, v, p, nsample):
-    """Oracle matvec on `nsample` characteristics, scaled to the full grid."""
+def cpu_cores():
+    """Host cores this process may use, capped at the 16 a one-GPU machine
+    shares out (os.cpu_count() may report the whole machine)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+# Worker processes of the parallel oracle: each holds the workload's problem
+# and template and evaluates the oracle over a contiguous range of
+# characteristics; the parent sums the velocity-grid partials in worker order.
+_ORACLE_WORKER = {}
+
+
+def _oracle_worker_init(name):
     import oracle as O
+    from synthetic import workload
+    w = workload(name)
+    P = O.Problem(dim=w.dim, img_m=w.img_m, vel_m=w.vel_m, nodes=w.nodes, model=w.model,
+                  reg=w.reg, nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma)
+    _ORACLE_WORKER.update(O=O, P=P, T=w.template().ravel())
+
+
+def _oracle_worker_run(task):
+    kind, lo, hi, v, x = task
+    O, P, T = _ORACLE_WORKER["O"], _ORACLE_WORKER["P"], _ORACLE_WORKER["T"]
+    pts = np.arange(lo, hi)
+    if kind == "hess":    # data term h^d J^T (J x) over the range
+        return P.cell_img * O.vjp(P, v, T, O.jvp(P, v, T, x, points=pts), points=pts)
+    if kind == "state":   # u1 on the range (transport)
+        return O.transport(P, T, O.trace(P, v, points=pts), points=pts)
+    if kind == "vjp":     # J^T x with x the range's image weights
+        return O.vjp(P, v, T, x, points=pts)
+    raise ValueError(kind)
+
+
+class ParallelOracle:
+    """The oracle's per-characteristic work split over worker processes
+    (transport model): characteristics in contiguous ranges, one per worker,
+    velocity-grid partial sums reduced in worker order."""
+
+    def __init__(self, w, workers):
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        import oracle as O
+        self.O = O
+        self.P = O.Problem(dim=w.dim, img_m=w.img_m, vel_m=w.vel_m, nodes=w.nodes, model=w.model,
+                           reg=w.reg, nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma)
+        self.workers = workers
+        edges = np.linspace(0, self.P.n_points, workers + 1).astype(np.int64)
+        self.ranges = list(zip(edges[:-1], edges[1:]))
+        saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+        for k in saved:
+            os.environ[k] = "1"   # one thread per worker process
+        try:
+            self.pool = ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"),
+                                            initializer=_oracle_worker_init, initargs=(w.name,))
+            list(self.pool.map(_oracle_worker_run, [("state", 0, 1, np.zeros(self.P.vel_shape), None)] * workers))
+        finally:
+            for k, val in saved.items():
+                if val is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = val
+
+    def _run(self, kind, v, xs):
+        tasks = [(kind, lo, hi, v, x) for (lo, hi), x in zip(self.ranges, xs)]
+        return list(self.pool.map(_oracle_worker_run, tasks))
+
+    def hessmat(self, v, p):
+        parts = self._run("hess", v, [p] * self.workers)
+        out = parts[0].copy()
+        for q in parts[1:]:
+            out += q
+        return out + self.O.regularizer_apply(self.P, p) + self.P.gamma * p
+
+    def state(self, v):
+        return np.concatenate(self._run("state", v, [None] * self.workers))
+
+    def objective(self, v, R):
+        D, res = self.O.ssd(self.P, self.state(v), R)
+        S = self.O.regularizer_energy(self.P, v)
+        return {"J": D + self.P.alpha * S, "D": D, "S": S, "res": res}
+
+    def gradient(self, v, R):
+        obj = self.objective(v, R)
+        w = self.P.cell_img * obj["res"]
+        parts = self._run("vjp", v, [w[lo:hi] for lo, hi in self.ranges])
+        g = parts[0].copy()
+        for q in parts[1:]:
+            g += q
+        return g + self.O.regularizer_apply(self.P, v), obj
+
+    def gn_iteration(self, v, R, pcg_tol, pcg_maxit, c1=1e-4, max_halvings=10):
+        """One inexact Gauss-Newton iteration as the oracle's solver takes it
+        (gradient, PCG with the spectral preconditioner, Armijo backtracking)."""
+        O = self.O
+        g, obj = self.gradient(v, R)
+        dv, info = O.pcg(lambda p: self.hessmat(v, p), -g, lambda r: O.spectral_precond_apply(self.P, r),
+                         tol=pcg_tol, maxit=pcg_maxit)
+        slope = float(np.vdot(g, dv))
+        mu, accepted = 1.0, False
+        for _ in range(max_halvings + 1):
+            Jt = self.objective(v + mu * dv, R)["J"]
+            if Jt <= obj["J"] + c1 * mu * slope:
+                accepted = True
+                break
+            mu *= 0.5
+        return {"J": obj["J"], "J_next": Jt, "mu": mu, "accepted": accepted, "pcg_iters": info["iters"],
+                "matvecs": info["matvecs"]}
+
+    def close(self):
+        self.pool.shutdown()
+
+
+def cpu_baseline(w, v, p, nsample, gn_iteration=True):
+    """The FP64 oracle on the host.  Headline value: one whole Gauss-Newton
+    matvec at v_true/2 over every characteristic, split over the host cores
+    in worker processes.  Beside it: the same matvec in one single-threaded
+    process on a uniform sample of the characteristics (scaled), and one
+    whole Gauss-Newton iteration of the workload in the parallel oracle."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
     P = O.Problem(dim=w.dim, img_m=w.img_m, vel_m=w.vel_m, nodes=w.nodes, model=w.model,
                   reg=w.reg, nsteps=w.nsteps, alpha=w.alpha, gamma=w.gamma)
     T = w.template().ravel()
     rng = np.random.default_rng(12345)
     pts = np.sort(rng.choice(P.n_points, nsample, replace=False))
-    from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         O.hessmat(P, v, T, p, points=pts)
-        dt = time.perf_counter() - t0
-    t_full = dt * P.n_points / nsample
-    return {"value": 1.0 / t_full, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsample} of {P.n_points} characteristics (uniform random, seed 12345); "
-                      f"{dt:.2f} s measured, scaled by {P.n_points / nsample:.1f}; "
-                      f"single-threaded NumPy float64"}
+        dt1 = time.perf_counter() - t0
+    single = {"value": nsample / (dt1 * P.n_points), "unit": "matvecs/s", "cores": 1,
+              "sample": f"{nsample} of {P.n_points} characteristics (uniform random, seed 12345); "
+                        f"{dt1:.2f} s measured, scaled by {P.n_points / nsample:.1f}; one process, "
+                        f"single-threaded NumPy float64"}
+    workers = cpu_cores()
+    par = ParallelOracle(w, workers)
+    try:
+        t0 = time.perf_counter()
+        par.hessmat(v, p)
+        dtp = time.perf_counter() - t0
+        out = {"value": 1.0 / dtp, "unit": "matvecs/s", "cores": workers, "kind": "oracle",
+               "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+               "sample": f"the whole matvec: all {P.n_points} characteristics at v_true/2, split into "
+                         f"{workers} contiguous ranges over {workers} single-threaded worker processes, "
+                         f"velocity-grid partials summed in worker order; {dtp:.2f} s",
+               "single_process": single}
+        if gn_iteration:
+            R = par.state(np.asarray(w.velocity_true(), dtype=np.float64))
+            t0 = time.perf_counter()
+            it = par.gn_iteration(v, R, w.pcg_tol, w.pcg_maxit)
+            dtg = time.perf_counter() - t0
+            out["gn_iteration"] = {"seconds": round(dtg, 2), "cores": workers, "iterate": "v_true/2",
+                                   "pcg_iters": it["pcg_iters"], "matvecs": it["matvecs"],
+                                   "J": it["J"], "J_next": it["J_next"], "mu": it["mu"],
+                                   "note": "gradient, PCG (spectral preconditioner, tol 0.1) and Armijo "
+                                           "line search of the oracle's solver, characteristics split "
+                                           "over the worker processes"}
+    finally:
+        par.close()
+    return out
 
 
 def op_timings(L, torch, w, plan, Td, vtd, p):
@@ -526,7 +687,8 @@ def main():
         roof = {"bound": "alu", "kernel": f"k_hess_transport<{w.dim},false>",
                 "achieved": round(achieved, 3) if kern_n > 0 else None,
                 "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4) if kern_n > 0 else None, "traffic": None}
+                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4) if kern_n > 0 else None, "traffic": None,
+                "frac_of_unpacked_fp32": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4) if kern_n > 0 else None}
     roof["kernel_ms"] = round(kern_avg_s * 1e3, 4) if kern_n > 0 else None
     roof["launches_timed"] = kern_n
     res = {
@@ -562,7 +724,7 @@ def main():
     if args.cpu_sample > 0:
         log(args, f"timing the oracle on {args.cpu_sample} characteristics ...")
         res["cpu_baseline"] = cpu_baseline(w, 0.5 * vt.astype(np.float64), p0.astype(np.float64),
-                                           args.cpu_sample)
+                                           args.cpu_sample, gn_iteration=bool(args.cpu_gn_iteration))
         log(args, "timing the 2-D 64^2 solve on the GPU and in the oracle ...")
         res["cpu_baseline"]["solve"] = solve_comparison(L, torch)
     print(json.dumps(res), flush=True)
