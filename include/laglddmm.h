@@ -54,7 +54,8 @@ enum {
     LAG_EHIP = 3,          /* a HIP runtime call or kernel launch failed      */
     LAG_ENOMEM = 4,        /* device allocation failed (allocating calls only)*/
     LAG_EBREAKDOWN = 5,    /* PCG met p^T H p <= 0                            */
-    LAG_ELINESEARCH = 6    /* Armijo line search found no acceptable step     */
+    LAG_ELINESEARCH = 6,   /* Armijo line search found no acceptable step     */
+    LAG_ETOOLARGE = 7      /* problem exceeds a fixed-size scratch buffer     */
 };
 
 enum { LAG_TRANSPORT = 0, LAG_CONTINUITY = 1 };   /* eq. transport / eq. continuity */
@@ -208,6 +209,24 @@ int gn_hessmat(lag_plan plan, const float* v, const float* T, const float* wvox,
  * prime factors are 2, 3 and 5; other sizes return LAG_EUNSUPPORTED.
  * alpha = gamma = 0 (no regulariser block to invert) returns LAG_EINVAL. */
 int spectral_precond_apply(lag_plan plan, const float* r, float* z, void* stream);
+
+/* ---- allocation-free variant ---------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * push-forward as lag_pushforward, without a plan.  Its binning scratch is a
+ * file-scope device array of LAG_NOALLOC_SCRATCH_BYTES that the loader
+ * places on every GPU the library runs on and that stays there until the
+ * process ends; the call itself allocates nothing and needs no plan.  The
+ * scratch holds 36 bytes per image cell in 2-D and 52 in 3-D (plus
+ * alignment), so problems up to about 1.8 M cells (2-D) or 1.2 M cells (3-D)
+ * fit; larger ones return LAG_ETOOLARGE.  All calls on one GPU share that
+ * GPU's scratch: calls that overlap on one GPU (concurrent streams or host
+ * threads) race and must be serialised by the caller.  The result is
+ * bitwise that of lag_pushforward.  T, u: image-shaped; phi: [dim][n_points]
+ * (device pointers); prob: host pointer. */
+#define LAG_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int lag_pushforward_noalloc(const lag_problem* prob, const float* T, const float* phi, float* u,
+                            void* stream);
 
 /* ---- assembled Jacobian (transport model, stationary velocity) ----------
  * The paper notes that the sparse derivative can be built explicitly to

@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblaglddmm.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "laglddmm.h")
 
-LAG_OK, LAG_EINVAL, LAG_EUNSUPPORTED, LAG_EHIP, LAG_ENOMEM, LAG_EBREAKDOWN, LAG_ELINESEARCH = range(7)
+LAG_OK, LAG_EINVAL, LAG_EUNSUPPORTED, LAG_EHIP, LAG_ENOMEM, LAG_EBREAKDOWN, LAG_ELINESEARCH, LAG_ETOOLARGE = range(8)
 LAG_TRANSPORT, LAG_CONTINUITY = 0, 1
 LAG_DIFFUSION, LAG_CURVATURE = 0, 1
 
@@ -106,6 +106,7 @@ _SIGS = {
     "lag_trace": (_I, [_P, _P, ctypes.c_int32, _P, _P]),
     "lag_transport": (_I, [_P, _P, _P, _P, _P]),
     "lag_pushforward": (_I, [_P, _P, _P, _P, _P]),
+    "lag_pushforward_noalloc": (_I, [ctypes.POINTER(LagProblem), _P, _P, _P, _P]),
     "lag_jvp": (_I, [_P, _P, _P, _P, _P, _P]),
     "lag_vjp": (_I, [_P, _P, _P, _P, _P, _P]),
     "gn_hessmat": (_I, [_P, _P, _P, _P, _P, _P, _P]),
@@ -319,6 +320,14 @@ def lag_pushforward(plan, T, phi, u):
     _check("lag_pushforward", load().lag_pushforward(plan.handle, _ptr(T, plan.n_points, "T"),
                                                      _ptr(phi, plan.prob.dim * plan.n_points, "phi"),
                                                      _ptr(u, plan.n_points, "u"), _stream()))
+
+
+def lag_pushforward_noalloc(prob, T, phi, u):
+    """lag_pushforward without a plan; the library allocates nothing (its
+    scratch is a fixed device array per GPU).  ``prob`` is a LagProblem."""
+    n, _ = lag_problem_sizes(prob)
+    _check("lag_pushforward_noalloc", load().lag_pushforward_noalloc(
+        ctypes.byref(prob), _ptr(T, n, "T"), _ptr(phi, prob.dim * n, "phi"), _ptr(u, n, "u"), _stream()))
 
 
 def lag_jvp(plan, v, T, dv, Jdv):

@@ -194,6 +194,40 @@ using namespace lag;
     if (!(cond)) return LAG_EINVAL; \
   } while (0)
 
+namespace lag {
+int make_geo(const lag_problem* prob, Geo& g) {
+  const int D = prob->dim;
+  g = Geo{};
+  g.dim = D;
+  g.nodes = prob->nt_nodes;
+  g.nsteps = prob->nsteps;
+  g.np = 1;
+  g.nv = 1;
+  double cell = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    g.mi[a] = a < D ? prob->img_m[a] : 1;
+    g.mv[a] = a < D ? prob->vel_m[a] : 1;
+    double L = a < D ? prob->extent[a] : 1.0;
+    g.inv_hi[a] = (float)(g.mi[a] / L);
+    g.inv_hv[a] = (float)(g.mv[a] / L);
+    g.ratio[a] = (double)g.mv[a] / (double)g.mi[a];
+    if (a < D) {
+      g.np *= g.mi[a];
+      g.nv *= g.mv[a];
+      cell *= L / g.mi[a];
+    }
+  }
+  g.cell_img = (float)cell;
+  g.nvp = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.pv[a] = a < D ? g.mv[a] + 1 : 1;
+    g.nvp *= g.pv[a];
+  }
+  if (g.nvp >= (1LL << 31)) return LAG_EUNSUPPORTED;  // packed-field offsets are 32-bit
+  return LAG_OK;
+}
+}  // namespace lag
+
 static inline hipStream_t S(void* s) { return (hipStream_t)s; }
 
 extern "C" {
@@ -207,6 +241,7 @@ const char* lag_strerror(int status) {
     case LAG_ENOMEM: return "device allocation failed";
     case LAG_EBREAKDOWN: return "PCG breakdown (p^T H p <= 0)";
     case LAG_ELINESEARCH: return "Armijo line search failed";
+    case LAG_ETOOLARGE: return "problem exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -292,36 +327,13 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
   HIPC(hipGetDevice(&P->device));
   const int D = prob->dim;
   Geo& g = P->geo;
-  g.dim = D;
-  g.nodes = prob->nt_nodes;
-  g.nsteps = prob->nsteps;
-  g.np = 1;
-  g.nv = 1;
-  double cell = 1.0, cellv = 1.0;
-  for (int a = 0; a < 3; ++a) {
-    g.mi[a] = a < D ? prob->img_m[a] : 1;
-    g.mv[a] = a < D ? prob->vel_m[a] : 1;
-    double L = a < D ? prob->extent[a] : 1.0;
-    g.inv_hi[a] = (float)(g.mi[a] / L);
-    g.inv_hv[a] = (float)(g.mv[a] / L);
-    g.ratio[a] = (double)g.mv[a] / (double)g.mi[a];
-    if (a < D) {
-      g.np *= g.mi[a];
-      g.nv *= g.mv[a];
-      cell *= L / g.mi[a];
-      cellv *= L / g.mv[a];
-    }
-  }
-  g.cell_img = (float)cell;
-  g.nvp = 1;
-  for (int a = 0; a < 3; ++a) {
-    g.pv[a] = a < D ? g.mv[a] + 1 : 1;
-    g.nvp *= g.pv[a];
-  }
-  if (g.nvp >= (1LL << 31)) {  // packed-field offsets are 32-bit
+  rc = make_geo(prob, g);
+  if (rc) {
     free_plan(P);
-    return LAG_EUNSUPPORTED;
+    return rc;
   }
+  double cellv = 1.0;
+  for (int a = 0; a < D; ++a) cellv *= prob->extent[a] / g.mv[a];
   P->fields = g.nodes * D;
   P->n_unknowns = (long long)P->fields * g.nv;
   choose_bricks(P, brick_target);

@@ -149,30 +149,27 @@ __global__ void __launch_bounds__(kBlock) k_bin_gather(Geo g, const int* __restr
   out[c] = acc;
 }
 
-int bin_and_gather(lag_plan P, float* out, hipStream_t s) {
-  const long long n = P->geo.np;
+int bin_and_gather(const Geo& g, const BinScratch& b, float* out, hipStream_t s) {
+  const long long n = g.np;
   const int nb = (int)((n + kScanTile - 1) / kScanTile);
   const unsigned g1 = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kBlock), 0, s, P->bin_count, P->bin_start, P->scan_blocks, n);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kBlock), 0, s, b.count, b.start, b.scan, n);
   LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, P->scan_blocks, nb);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, b.scan, nb);
   LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     P->bin_start, P->scan_blocks, n, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b.start,
+                     b.scan, n, nb);
   LAG_LAUNCH_CHECK();
-  int rc = launch_zero_i(P->bin_cursor, n, s);
+  int rc = launch_zero_i(b.cursor, n, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_bin_fill, dim3(g1), dim3(kBlock), 0, s, P->part_base, P->bin_start, P->bin_cursor,
-                     P->bin_items, n);
+  hipLaunchKernelGGL(k_bin_fill, dim3(g1), dim3(kBlock), 0, s, b.base, b.start, b.cursor, b.items, n);
   LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bin_sort, dim3(g1), dim3(kBlock), 0, s, P->bin_start, P->bin_items, n);
+  hipLaunchKernelGGL(k_bin_sort, dim3(g1), dim3(kBlock), 0, s, b.start, b.items, n);
   LAG_LAUNCH_CHECK();
-  if (P->geo.dim == 3)
-    hipLaunchKernelGGL(k_bin_gather<3>, dim3(g1), dim3(kBlock), 0, s, P->geo, P->bin_start, P->bin_items,
-                       P->part_vals, out);
+  if (g.dim == 3)
+    hipLaunchKernelGGL(k_bin_gather<3>, dim3(g1), dim3(kBlock), 0, s, g, b.start, b.items, b.vals, out);
   else
-    hipLaunchKernelGGL(k_bin_gather<2>, dim3(g1), dim3(kBlock), 0, s, P->geo, P->bin_start, P->bin_items,
-                       P->part_vals, out);
+    hipLaunchKernelGGL(k_bin_gather<2>, dim3(g1), dim3(kBlock), 0, s, g, b.start, b.items, b.vals, out);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }

@@ -112,8 +112,38 @@ void set_hip_error_text(const char* msg);  // records a message from another thr
 int launch_pack(lag_plan P, const float* v, void* dst, hipStream_t s);
 int launch_fill(float* x, long long n, float val, hipStream_t s);
 int launch_zero_i(int* x, long long n, hipStream_t s);
-// deterministic binned scatter of per-particle corner values (part_base/part_vals)
-int bin_and_gather(lag_plan P, float* out, hipStream_t s);
+// Scratch of the deterministic binned scatter: per particle its base cell
+// and 2^d corner values, per image cell a count, a bin start and a fill
+// cursor, the binned particle ids, and the scan's block sums.
+struct BinScratch {
+  int* base = nullptr;     // np
+  float* vals = nullptr;   // 2^d * np
+  int* count = nullptr;    // np + 1
+  int* start = nullptr;    // np + 1
+  int* cursor = nullptr;   // np
+  int* items = nullptr;    // np
+  int* scan = nullptr;     // scan_blocks(np) + 2
+};
+inline long long scan_blocks(long long np) { return (np + 1023) / 1024; }
+inline BinScratch plan_bins(lag_plan P) {
+  BinScratch b;
+  b.base = P->part_base;
+  b.vals = P->part_vals;
+  b.count = P->bin_count;
+  b.start = P->bin_start;
+  b.cursor = P->bin_cursor;
+  b.items = P->bin_items;
+  b.scan = P->scan_blocks;
+  return b;
+}
+// Launch geometry of a validated problem (host only); LAG_EUNSUPPORTED if
+// the packed velocity field needs offsets beyond 32 bits.
+int make_geo(const lag_problem* prob, Geo& g);
+// deterministic binned scatter of per-particle corner values (b.base/b.vals)
+int bin_and_gather(const Geo& g, const BinScratch& b, float* out, hipStream_t s);
+// push-forward through explicit binning scratch (the plan's, or a caller's)
+int launch_pushforward_bins(const Geo& g, const BinScratch& b, const float* T, const float* phi, float* u,
+                            hipStream_t s);
 int launch_trace(lag_plan P, const void* vpack, int dir, float* phi, hipStream_t s);
 int launch_transport(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s);
 int launch_pushforward(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s);

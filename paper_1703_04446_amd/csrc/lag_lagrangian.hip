@@ -1894,18 +1894,21 @@ int launch_transport(lag_plan P, const float* T, const float* phi, float* u, hip
 }
 
 
-int launch_pushforward(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s) {
-  int rc = launch_zero_i(P->bin_count, P->geo.np + 1, s);
+int launch_pushforward_bins(const Geo& g, const BinScratch& b, const float* T, const float* phi, float* u,
+                            hipStream_t s) {
+  int rc = launch_zero_i(b.count, g.np + 1, s);
   if (rc) return rc;
-  unsigned grid = grid_for((P->geo.np + kBlock - 1) / kBlock);
-  if (P->geo.dim == 3)
-    hipLaunchKernelGGL(k_push_prep<3>, dim3(grid), dim3(kBlock), 0, s, P->geo, T, phi, P->part_base,
-                       P->part_vals, P->bin_count);
+  const unsigned grid = grid_for((g.np + kBlock - 1) / kBlock);
+  if (g.dim == 3)
+    hipLaunchKernelGGL(k_push_prep<3>, dim3(grid), dim3(kBlock), 0, s, g, T, phi, b.base, b.vals, b.count);
   else
-    hipLaunchKernelGGL(k_push_prep<2>, dim3(grid), dim3(kBlock), 0, s, P->geo, T, phi, P->part_base,
-                       P->part_vals, P->bin_count);
+    hipLaunchKernelGGL(k_push_prep<2>, dim3(grid), dim3(kBlock), 0, s, g, T, phi, b.base, b.vals, b.count);
   LAG_LAUNCH_CHECK();
-  return bin_and_gather(P, u, s);
+  return bin_and_gather(g, b, u, s);
+}
+
+int launch_pushforward(lag_plan P, const float* T, const float* phi, float* u, hipStream_t s) {
+  return launch_pushforward_bins(P->geo, plan_bins(P), T, phi, u, s);
 }
 
 int launch_jvp(lag_plan P, const void* vpack, const void* dpack, const float* T, float* out, hipStream_t s) {
@@ -1949,7 +1952,7 @@ int launch_jvp(lag_plan P, const void* vpack, const void* dpack, const float* T,
                          (const float2*)vpack, (const float2*)dpack, T, P->part_base, P->part_vals, P->bin_count);
   }
   LAG_LAUNCH_CHECK();
-  return bin_and_gather(P, out, s);
+  return bin_and_gather(P->geo, plan_bins(P), out, s);
 }
 
 int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, float* out, hipStream_t s,

@@ -97,7 +97,22 @@ def test_cnn_config_validation_without_device(lib):
     assert lib.lag_cnn_destroy(nul) == L.LAG_OK
 
 
+def test_noalloc_rejects_problems_beyond_its_scratch_without_device(lib):
+    """The allocation-free push-forward refuses, on the host and before any
+    device call, a problem whose binning scratch exceeds the fixed array
+    (36 B per cell in 2-D, 52 B in 3-D, against 64 MiB), and null pointers."""
+    fake = ctypes.c_void_p(256)      # never dereferenced: the call returns first
+    assert lib.lag_pushforward_noalloc(None, fake, fake, fake, None) == L.LAG_EINVAL
+    big2 = L.make_problem(2, (1400, 1400), (700, 700), model="continuity")
+    assert lib.lag_pushforward_noalloc(ctypes.byref(big2), fake, fake, fake, None) == L.LAG_ETOOLARGE
+    big3 = L.make_problem(3, (112, 112, 112), (56, 56, 56), model="continuity")
+    assert lib.lag_pushforward_noalloc(ctypes.byref(big3), fake, fake, fake, None) == L.LAG_ETOOLARGE
+    bad = L.make_problem(3, (8, 8, 8), (4, 4, 4), nsteps=0)
+    assert lib.lag_pushforward_noalloc(ctypes.byref(bad), fake, fake, fake, None) == L.LAG_EINVAL
+    assert L.strerror(L.LAG_ETOOLARGE) != "unknown status"
+
+
 def test_strerror(lib):
-    for code in range(7):
+    for code in range(8):
         assert L.strerror(code)
     assert L.strerror(99) == "unknown status"
