@@ -168,7 +168,8 @@ static void free_plan(lag_plan P) {
                   P->fft_tw[0], P->fft_tw[1], P->fft_tw[2], P->fft_lam[0], P->fft_lam[1], P->fft_lam[2],
                   P->fft_mu1, P->flags, P->tile_part, P->cover_start[0], P->cover_start[1],
                   P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2], P->jac_vals,
-                  P->jac_cell, P->jac_cnt, P->jac_max, P->jac_fb};
+                  P->jac_cell, P->jac_cnt, P->jac_max, P->jac_fb, P->pg_vals, P->pg_cells, P->pg_rows,
+                  P->pg_npages, P->pg_order, P->pg_redo};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->ctl) (void)hipFree(P->ctl);
@@ -411,6 +412,17 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
     ALLOC(P->jac_max, sizeof(int) * 2);
     ALLOC(P->jac_fb, sizeof(float) * (size_t)P->n_unknowns);
     HIPC(hipMemset(P->jac_fb, 0, sizeof(float) * (size_t)P->n_unknowns));
+    P->pg_cap = jac_pages_per_brick(P, P->jac_k);
+    if (P->pg_cap > 0) {
+      const size_t chunks = (size_t)B.nbricks * (size_t)P->pg_cap;
+      ALLOC(P->pg_vals, sizeof(float4) * chunks * nv4 * 64);
+      ALLOC(P->pg_cells, sizeof(int) * chunks * 64);
+      ALLOC(P->pg_rows, sizeof(int) * chunks * 64);
+      ALLOC(P->pg_npages, sizeof(int) * (size_t)B.nbricks);
+      ALLOC(P->pg_order, sizeof(int) * (size_t)B.nbricks);
+      ALLOC(P->pg_redo, sizeof(int));
+      HIPC(hipMemset(P->pg_redo, 0, sizeof(int)));
+    }
   }
   rc = tiles_setup(P);
   if (rc) {
@@ -670,17 +682,45 @@ static bool jacobian_grow(lag_plan P, int need) {
     (void)hipGetLastError();
     return false;
   }
+  // the paged copy grows with the capacity (or is given up beyond 64 blocks
+  // per row, where the products read the [k][slot] layout directly)
+  const int pcap = jac_pages_per_brick(P, k);
+  const size_t chunks = (size_t)P->bricks.nbricks * (size_t)pcap;
+  const size_t pvb = sizeof(float4) * chunks * nv4 * 64, pcb = sizeof(int) * chunks * 64;
+  if (vb + cb + pvb + 2 * pcb > fr / 2) return false;
   float4* nvals = nullptr;
   int* ncell = nullptr;
-  if (hipMalloc(&nvals, vb) != hipSuccess || hipMalloc(&ncell, cb) != hipSuccess) {
-    if (nvals) (void)hipFree(nvals);
+  float4* npv = nullptr;
+  int *npc = nullptr, *npr = nullptr;
+  bool ok = hipMalloc(&nvals, vb) == hipSuccess && hipMalloc(&ncell, cb) == hipSuccess;
+  if (ok && pcap > 0)
+    ok = hipMalloc(&npv, pvb) == hipSuccess && hipMalloc(&npc, pcb) == hipSuccess && hipMalloc(&npr, pcb) == hipSuccess;
+  if (!ok) {
+    for (void* q : {(void*)nvals, (void*)ncell, (void*)npv, (void*)npc, (void*)npr})
+      if (q) (void)hipFree(q);
     (void)hipGetLastError();
     return false;
   }
   (void)hipFree(P->jac_vals);
   (void)hipFree(P->jac_cell);
+  for (void* q : {(void*)P->pg_vals, (void*)P->pg_cells, (void*)P->pg_rows})
+    if (q) (void)hipFree(q);
   P->jac_vals = nvals;
   P->jac_cell = ncell;
+  P->pg_vals = npv;
+  P->pg_cells = npc;
+  P->pg_rows = npr;
+  P->pg_cap = pcap;
+  if (pcap > 0 && (!P->pg_npages || !P->pg_order || !P->pg_redo)) {
+    const size_t nb = sizeof(int) * (size_t)P->bricks.nbricks;
+    if ((!P->pg_npages && hipMalloc(&P->pg_npages, nb) != hipSuccess) ||
+        (!P->pg_order && hipMalloc(&P->pg_order, nb) != hipSuccess) ||
+        (!P->pg_redo && (hipMalloc(&P->pg_redo, sizeof(int)) != hipSuccess ||
+                         hipMemset(P->pg_redo, 0, sizeof(int)) != hipSuccess))) {
+      (void)hipGetLastError();
+      P->pg_cap = 0;
+    }
+  }
   P->jac_k = k;
   if (P->pcg_exec) {
     (void)hipGraphExecDestroy(P->pcg_exec);

@@ -66,6 +66,16 @@ struct lag_plan_s {
   int jac_ready = 0;
   long long jac_blocks_stored = 0;
   int jac_max_seen = 0;
+  // paged copy of the assembled Jacobian (k_jac_pack): pg_cap pages of 128
+  // positions per brick; 0 = not used (the products read the [k][slot]
+  // layout directly)
+  int pg_cap = 0;
+  float4* pg_vals = nullptr;
+  int* pg_cells = nullptr;
+  int* pg_rows = nullptr;
+  int* pg_npages = nullptr;
+  int* pg_order = nullptr;     // launch order of the bricks (k_brick_order)
+  int* pg_redo = nullptr;      // count of bricks whose product pass was redone at the exact scale
   // per-brick partial velocity tiles and, per axis, the list of (brick,
   // tile offset) pairs covering each velocity index (fixed-order reduction)
   float* tile_part = nullptr;
@@ -157,6 +167,8 @@ int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, cons
                           const float* wvox, float* out, hipStream_t s);
 int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt);
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);
+// pages per brick of the paged copy for capacity kmax (0: layout not used)
+int jac_pages_per_brick(lag_plan P, int kmax);
 int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
                      hipStream_t s, const RegTail* rt);
 int tiles_setup(lag_plan P);       // partial-tile buffer + cover tables (plan creation)

@@ -1414,23 +1414,78 @@ __device__ __forceinline__ float jac_block_dot(const Geo& g, const int cell[D], 
     const unsigned sy = (unsigned)g.pv[0], sz = (unsigned)g.pv[0] * (unsigned)g.pv[1];
     const float4* c0 = pp + packed_corner(g, x0, y0, z0);
     const unsigned off[8] = {0u, 1u, sy, sy + 1u, sz, sz + 1u, sz + sy, sz + sy + 1u};
+    float4 q[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) q[o] = c0[off[o]];
+    // keep the eight gathers ahead of their first use: left to itself the
+    // scheduler sinks each load to its FMAs and waits for it alone, which
+    // makes the eight L2 trips of a block serial
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
-      float4 q = c0[off[o]];
-      s = fmaf(f[3 * o], q.x, s);
-      s = fmaf(f[3 * o + 1], q.y, s);
-      s = fmaf(f[3 * o + 2], q.z, s);
+      s = fmaf(f[3 * o], q[o].x, s);
+      s = fmaf(f[3 * o + 1], q[o].y, s);
+      s = fmaf(f[3 * o + 2], q[o].z, s);
     }
   } else {
     const int x0 = wrapi(cell[0], g.mv[0]), y0 = wrapi(cell[1], g.mv[1]);
     const unsigned sy = (unsigned)g.pv[0];
     const float2* c0 = pp + packed_corner(g, x0, y0, 0);
     const unsigned off[4] = {0u, 1u, sy, sy + 1u};
+    float2 q[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) q[o] = c0[off[o]];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
-      float2 q = c0[off[o]];
-      s = fmaf(f[2 * o], q.x, s);
-      s = fmaf(f[2 * o + 1], q.y, s);
+      s = fmaf(f[2 * o], q[o].x, s);
+      s = fmaf(f[2 * o + 1], q[o].y, s);
+    }
+  }
+  return s;
+}
+
+// jac_block_dot in two halves, so that other loads can be issued between
+// the gathers of p and their use.
+template <int D> struct PGather;
+template <> struct PGather<3> { float4 q[8]; };
+template <> struct PGather<2> { float2 q[4]; };
+
+template <int D>
+__device__ __forceinline__ void jac_block_gather(const Geo& g, const int cell[D],
+                                                 const typename VecT<D>::T* __restrict__ pp, PGather<D>& G) {
+  if constexpr (D == 3) {
+    const int x0 = wrapi(cell[0], g.mv[0]), y0 = wrapi(cell[1], g.mv[1]), z0 = wrapi(cell[2], g.mv[2]);
+    const unsigned sy = (unsigned)g.pv[0], sz = (unsigned)g.pv[0] * (unsigned)g.pv[1];
+    const float4* c0 = pp + packed_corner(g, x0, y0, z0);
+    const unsigned off[8] = {0u, 1u, sy, sy + 1u, sz, sz + 1u, sz + sy, sz + sy + 1u};
+#pragma unroll
+    for (int o = 0; o < 8; ++o) G.q[o] = c0[off[o]];
+  } else {
+    const int x0 = wrapi(cell[0], g.mv[0]), y0 = wrapi(cell[1], g.mv[1]);
+    const unsigned sy = (unsigned)g.pv[0];
+    const float2* c0 = pp + packed_corner(g, x0, y0, 0);
+    const unsigned off[4] = {0u, 1u, sy, sy + 1u};
+#pragma unroll
+    for (int o = 0; o < 4; ++o) G.q[o] = c0[off[o]];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ float jac_block_finish(const float* f, const PGather<D>& G) {
+  float s = 0.f;
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      s = fmaf(f[3 * o], G.q[o].x, s);
+      s = fmaf(f[3 * o + 1], G.q[o].y, s);
+      s = fmaf(f[3 * o + 2], G.q[o].z, s);
+    }
+  } else {
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      s = fmaf(f[2 * o], G.q[o].x, s);
+      s = fmaf(f[2 * o + 1], G.q[o].y, s);
     }
   }
   return s;
@@ -1619,6 +1674,411 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(Geo g, Bricks B, const flo
         jac_scatter<D>(g, B, org, tile, out, cell, f, s, e);
       }
     }
+  }
+  __syncthreads();
+  float* dst = part + bid * (long long)tot;
+  const float nan = __int_as_float(0x7fc00000);
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) dst[i] = finite ? ldexpf((float)tile[i], -e) : nan;
+}
+
+// ---------------------------------------------------------------------------
+// Paged layout of the assembled Jacobian.
+//
+// The assembly writes block k of a row at [k][...][slot]; rows carry 1, 2, 3
+// or more blocks, so a product that walks that layout level by level leaves
+// lanes idle at the higher levels and makes one dependent memory trip per
+// level.  After the assembly, k_jac_pack lays each brick's blocks out
+// densely, rows in slot order, in pages of 64 positions (one per lane): a
+// row never straddles a page (a row that does not fit the rest of a page
+// starts the next one), the first block of a row carries kJacHead in its
+// cell word, and unused positions hold the cell word -1, so a page's valid
+// positions are a prefix of it.  Layout: values [page][float4 j][64], cells
+// [page][64], and at a row's first position the row's slot within its brick
+// (for voxel weights and seeds).  Brick b owns pages [b * cap, (b + 1) * cap).
+constexpr int kJacHead = int(0x80000000u);
+constexpr int kPagePos = 64;
+
+// Pages a brick needs at most: every full page holds at least 65 - kmax
+// blocks (a row of at most kmax blocks that does not fit leaves fewer than
+// kmax positions unused), plus a partial last page.
+inline int jac_page_cap(long long brick_rows, int kmax) {
+  return (int)((brick_rows * kmax + (kPagePos + 1 - kmax) - 1) / (kPagePos + 1 - kmax)) + 1;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __restrict__ vals,
+                                                     const int* __restrict__ cells,
+                                                     const unsigned char* __restrict__ cnt, long long nslots,
+                                                     int cap, float4* __restrict__ pv, int* __restrict__ pc,
+                                                     int* __restrict__ prow, int* __restrict__ npages) {
+  constexpr int NV4 = JacLayout<D>::NV4;
+  // LDS: the rows that hold blocks (slot within the brick) and their first
+  // positions (increasing), then the counts of all rows
+  extern __shared__ int sh[];
+  __shared__ int s_rows, s_pos;
+  const long long bid = xcd_block(B.nbricks);
+  if (bid < 0) return;
+  const int rows = B.bdim[0] * B.bdim[1] * B.bdim[2];
+  const long long base = bid * (long long)rows;
+  const int r4 = (rows + 3) & ~3;
+  int* rl = sh;                      // [rows]
+  int* rs = sh + r4;                 // [rows]
+  unsigned char* cl = (unsigned char*)(sh + 2 * r4);   // [rows rounded up to 64], 16-byte aligned
+  const int rows64 = (rows + 63) & ~63;
+  for (int i = threadIdx.x; i < rows64; i += blockDim.x) cl[i] = i < rows ? cnt[base + i] : 0;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    // Greedy placement in slot order by wave 0, 64 rows at a time: a prefix
+    // sum places the rows as if none straddled a page; the rows before the
+    // first one that would straddle stand, that row starts the next page,
+    // and the scan resumes after it (about one straddling row per page).
+    const int lane = threadIdx.x;
+    int at = 0, nr = 0;
+    for (int i0 = 0; i0 < rows; i0 += 64) {
+      const int n = cl[i0 + lane];
+      int start = 0;
+      while (start < 64) {
+        const int x = lane >= start ? n : 0;
+        int incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
+        }
+        const int p = at + incl - x;
+        const bool straddle = lane >= start && n > 0 && (p & (kPagePos - 1)) + n > kPagePos;
+        const unsigned long long sm = __ballot(straddle);
+        const int first = sm ? __ffsll((long long)sm) - 1 : 64;
+        // rows start .. first - 1 are placed; compact the ones with blocks
+        const bool keep = lane >= start && lane < first && n > 0;
+        const unsigned long long km = __ballot(keep);
+        const int rank = __popcll(km & ((1ull << lane) - 1));
+        if (keep) {
+          rl[nr + rank] = i0 + lane;
+          rs[nr + rank] = p;
+        }
+        nr += __popcll(km);
+        if (first == 64) {
+          at += __shfl(incl, 63, 64);
+          break;
+        }
+        // the straddling row opens the next page
+        const int pf = __shfl(p, first, 64), nf = __shfl(n, first, 64);
+        const int page_at = (pf + kPagePos - 1) & ~(kPagePos - 1);
+        if (lane == 0) {
+          rl[nr] = i0 + first;
+          rs[nr] = page_at;
+        }
+        nr += 1;
+        at = page_at + nf;
+        start = first + 1;
+      }
+    }
+    if (lane == 0) {
+      s_rows = nr;
+      s_pos = at;
+      npages[bid] = (at + kPagePos - 1) / kPagePos;
+    }
+  }
+  __syncthreads();
+  const int nr = s_rows;
+  const int used = ((s_pos + kPagePos - 1) / kPagePos) * kPagePos;
+  const long long q0 = bid * (long long)cap * kPagePos;   // first position of the brick
+  // one thread per destination position: coalesced writes; the source row
+  // is the last row whose first position is at or before it
+  for (int q = threadIdx.x; q < used; q += blockDim.x) {
+    int lo = 0, hi = nr - 1;         // rs[lo] <= q (rs[0] = 0)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rs[mid] <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const int row = nr > 0 ? rl[lo] : 0;
+    const int k = q - (nr > 0 ? rs[lo] : 0);
+    const bool valid = nr > 0 && k < (int)cl[row];
+    const long long qq = q0 + q;     // = page * 64 + lane
+    const long long pg = qq >> 6;
+    const int j = (int)(qq & 63);
+    if (valid) {
+      const long long slot = base + row;
+      int cw = cells[(long long)k * nslots + slot];
+      if (k == 0) cw |= kJacHead;
+      pc[qq] = cw;
+      prow[qq] = k == 0 ? row : -1;
+#pragma unroll
+      for (int v = 0; v < NV4; ++v) pv[(pg * NV4 + v) * 64 + j] = vals[((long long)k * NV4 + v) * nslots + slot];
+    } else {
+      pc[qq] = -1;
+      prow[qq] = -1;
+    }
+  }
+}
+
+// Launch order of the bricks for the paged product: within each XCD's
+// contiguous range of logical blocks (xcd_block), bricks in decreasing
+// order of their page counts, ties by brick index.  The heaviest bricks then
+// start in the first generation of resident blocks and the lightest fill the
+// slots that free up, while every XCD keeps its compact set of bricks (and
+// its L2 working set).  One block; every brick's thread counts the bricks
+// of its range that go first (more pages, or as many and a lower index).
+__global__ void __launch_bounds__(1024) k_brick_order(const int* __restrict__ npages, int nbricks,
+                                                      int* __restrict__ order) {
+  const int per = (nbricks + kXcds - 1) / kXcds;
+  for (int b = threadIdx.x; b < nbricks; b += blockDim.x) {
+    const int lo = (b / per) * per, hi = min(nbricks, lo + per);
+    const int key = npages[b];
+    int rank = 0;                    // bricks of the range that go first
+    for (int c = lo; c < hi; ++c) {
+      const int kc = npages[c];
+      rank += kc > key || (kc == key && c < b);
+    }
+    order[lo + rank] = b;
+  }
+}
+
+// The same pointer with its origin hidden from the compiler: loads through
+// it may alias any memory, so an empty asm with a memory clobber orders
+// them (loads through __restrict__ read-only arguments may be moved across
+// such an asm).
+template <class T>
+__device__ __forceinline__ T* opaque(T* p) {
+  using G = __attribute__((address_space(1))) T*;   // global memory (kernel arguments point there)
+  G q = (G)p;
+  asm volatile("" : "+s"(q));
+  return (T*)q;
+}
+
+constexpr int kPgBlock = 512;   // 8 waves share a brick's tile (two blocks per CU)
+
+// Fixed-point scale of a brick's tile.  A stored block adds at most one
+// entry to each (node, component) of the tile, so no partial sum of the tile
+// exceeds Bt = sum_i |s_i| R_i (R_i = sum over the row's blocks of max
+// |J_ik|); a scale 2^e with Bt 2^e < 2^30 therefore never overflows 32-bit
+// integers, and integer sums do not depend on the order of the additions.
+// Bt is only known once every s_i is.  Each wave takes a contiguous run of
+// the brick's pages; after the first page of every wave (spread over the
+// brick) one barrier sums their exact share of Bt, which, scaled to the
+// brick's page count with 4x headroom, sets e; the waves then stream their
+// pages without synchronising, scattering round(s_i J_ik 2^e) and adding up
+// their exact shares of Bt.  At the end the exact Bt decides: if 2^e Bt
+// could have overflowed, or e lies more than three bits below the exact
+// scale, the brick is redone at the exact scale (a second pass over its
+// pages).  Every choice depends on the data only, so the result is the same
+// in every run.  With wseed == null, s_i = scale W_i J_i p (a row's blocks
+// are summed in position order, identically in every lane of the row);
+// otherwise s_i = scale wseed_i.
+template <int D, bool WS, bool WV>
+__global__ void __launch_bounds__(kPgBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __restrict__ pc,
+               const int* __restrict__ prow, const int* __restrict__ npages, const int* __restrict__ order,
+               int cap, const typename VecT<D>::T* __restrict__ pp,
+               const float* __restrict__ wvox, const float* __restrict__ wseed, float scale,
+               float* __restrict__ out, float* __restrict__ part, int* __restrict__ redo) {
+  if (halted(g.halt)) return;
+  extern __shared__ float lds[];
+  const long long lb = xcd_block(B.nbricks);
+  if (lb < 0) return;
+  const long long bid = order[lb];   // heaviest bricks of each XCD first
+  int O[3], org[3];
+  brick_origin<D>(g, B, bid, O, org);
+  const int tot = D * B.tvol;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int* tile = (int*)lds;             // [D][tvol] fixed-point sums
+  float* red = lds + tot;            // [2 * waves] bound shares
+  float* stage = red + 2 * nw + 64 * wave;   // this wave's 64 staging slots
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) tile[i] = 0;
+  constexpr int NV4 = JacLayout<D>::NV4;
+  constexpr bool ROW = WS || WV;     // the row's image index is needed
+  auto row_image = [&](int row) {
+    int l[3], idx[3];
+    lane_lattice(B, row & 63, l);
+    (void)item_cell<D>(g, B, O, row >> 6, l, idx);
+    long long pi = idx[0] + (long long)g.mi[0] * idx[1];
+    if (D == 3) pi += (long long)g.mi[0] * g.mi[1] * idx[2];
+    return pi;
+  };
+  // the lanes' terms summed in a fixed order: by eight lanes in groups of
+  // eight, then by lane 0 (through the wave's staging slots)
+  auto wave_total = [&](float x) {
+    __builtin_amdgcn_wave_barrier();
+    stage[lane] = x;
+    __builtin_amdgcn_wave_barrier();
+    float q = 0.f;
+    if (lane < 8) {
+      float y[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) y[k] = stage[8 * lane + k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) q += y[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 8) stage[lane] = q;
+    __builtin_amdgcn_wave_barrier();
+    float tsum = 0.f;
+    if (lane == 0) {
+      float y[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) y[k] = stage[k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) tsum += y[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    return tsum;                     // valid in lane 0
+  };
+  const int np = npages[bid];
+  const int per = (np + nw - 1) / nw;            // pages of each wave
+  const int p0 = min(np, wave * per), p1 = min(np, p0 + per);
+  const long long pg0 = bid * (long long)cap;
+  pv = opaque(pv);
+  pc = opaque(pc);
+  prow = opaque(prow);
+  pp = opaque(pp);
+  // Pages are double-buffered: while a page is gathered, summed and
+  // scattered, the next one is in flight.  Loads complete in issue order,
+  // so within a page everything it consumes (the row's weight or seed, the
+  // gathers of p) is issued before the next page's loads, and all of them are
+  // issued without branches (a page index past the wave's last page reads
+  // that last page and is marked empty).
+  auto load_page = [&](int page, float* ff, int& ww, int& rr) {
+    const long long pg = pg0 + min(page, max(p1 - 1, 0));
+    const int w0 = pc[pg * 64 + lane];
+    if (ROW) rr = prow[pg * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < NV4; ++j) {
+      const float4 a = pv[(pg * NV4 + j) * 64 + lane];
+      ff[4 * j] = a.x; ff[4 * j + 1] = a.y; ff[4 * j + 2] = a.z; ff[4 * j + 3] = a.w;
+    }
+    ww = page < p1 ? w0 : -1;
+  };
+  // s of this lane's position (and the cell of its block); the next page's
+  // loads go out in between
+  auto page_s = [&](int page, const float* f, int w, int rw, float* fn, int& wn, int& rwn, int* cl) {
+    const bool v = w != -1;
+    jac_block_cell<D>(w & ~kJacHead, org, cl);   // in range for any word (wrapped on use)
+    // segment [a, z) of this lane's position: rows are contiguous, heads mark
+    // their first positions, valid positions are a prefix of the page
+    const unsigned long long hm = __ballot(v && (w & kJacHead));
+    const int nvalid = __popcll(__ballot(v));
+    int a = 0, z = 0;
+    if (v) {
+      const unsigned long long below = hm & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+      a = 63 - __clzll((long long)below);
+      const unsigned long long above = lane == 63 ? 0ull : (hm & ~((2ull << lane) - 1));
+      z = above ? __ffsll((long long)above) - 1 : nvalid;
+    }
+    float sv = 0.f;
+    if constexpr (ROW) {
+      const int row = __shfl(rw, a, 64);   // the row's slot, from its first position
+      sv = WS ? wseed[v ? row_image(row) : 0] : wvox[v ? row_image(row) : 0];
+    }
+    PGather<D> G;
+    if constexpr (!WS) jac_block_gather<D>(g, cl, pp, G);
+    // gathers (and the weight) first, then the next page, then the use; an
+    // empty asm with a memory clobber keeps the compiler's passes from
+    // moving loads across these points, the scheduling barrier keeps the
+    // machine scheduler from doing so
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    load_page(page + 1, fn, wn, rwn);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    float t = 0.f;
+    if constexpr (!WS) {
+      // row sums through the wave's LDS staging slots (a wave's LDS accesses
+      // complete in order): every lane reads its row's products and adds
+      // them in position order, eight reads in flight at a time
+      stage[lane] = jac_block_finish<D>(f, G);
+      __builtin_amdgcn_wave_barrier();
+      for (int k0 = a; k0 < z; k0 += 8) {
+        float x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = k0 + k < z ? stage[k0 + k] : 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k0 + k < z) t += x[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    return v ? (WS ? scale * sv : t * scale * (WV ? sv : 1.f)) : 0.f;
+  };
+  auto block_max = [&](const float* f) {
+    float m = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4 * NV4; ++j) m = fmaxf(m, fabsf(f[j]));
+    return m;
+  };
+  // one pass over the wave's pages at scale e; the first page's products
+  // arrive already formed (s0, cl0, f0) when `first` is set
+  float fa[4 * NV4], fb[4 * NV4];
+  int wa = -1, wb = -1, ra = -1, rb = -1;
+  float bshare = 0.f;                // this lane's exact share of Bt
+  auto stream = [&](int from, int e, bool fin) {
+    for (int page = from; page < p1; page += 2) {
+      int cl[D];
+      float s = page_s(page, fa, wa, ra, fb, wb, rb, cl);
+      bshare += fabsf(s) * (wa != -1 ? block_max(fa) : 0.f);
+      if (fin && s != 0.f) jac_scatter<D>(g, B, org, tile, out, cl, fa, s, e);
+      if (page + 1 < p1) {
+        s = page_s(page + 1, fb, wb, rb, fa, wa, ra, cl);
+        bshare += fabsf(s) * (wb != -1 ? block_max(fb) : 0.f);
+        if (fin && s != 0.f) jac_scatter<D>(g, B, org, tile, out, cl, fb, s, e);
+      }
+    }
+  };
+  // ---- first page of every wave: the estimate of Bt
+  int cl0[D];
+  float s0 = 0.f;
+  if (p0 < p1) {
+    load_page(p0, fb, wb, rb);
+    s0 = page_s(p0, fb, wb, rb, fa, wa, ra, cl0);
+    bshare = fabsf(s0) * (wb != -1 ? block_max(fb) : 0.f);
+  }
+  {
+    const float bw = wave_total(bshare);
+    if (lane == 0) red[wave] = bw;
+  }
+  __syncthreads();
+  float b1 = 0.f;
+  int n1 = 0;
+  for (int q = 0; q < nw; ++q) {
+    b1 += red[q];
+    n1 += min(np, q * per) < min(np, q * per + per);
+  }
+  const float est = n1 > 0 ? 4.f * b1 * ((float)np / (float)n1) : 0.f;
+  int e = 0;
+  bool ok = est <= 3.0e38f;          // false for inf and NaN
+  if (ok && est > 0.f) {
+    int ex = 0;
+    (void)frexpf(est, &ex);
+    e = 30 - ex;                     // est * 2^e < 2^30
+  }
+  if (ok && s0 != 0.f) jac_scatter<D>(g, B, org, tile, out, cl0, fb, s0, e);
+  stream(p0 + 1, e, ok);
+  // ---- the exact bound decides whether the pass stands
+  {
+    const float bw = wave_total(bshare);
+    __syncthreads();                 // every wave has read red[] above
+    if (lane == 0) red[nw + wave] = bw;
+  }
+  __syncthreads();
+  float bt = 0.f;
+  for (int q = 0; q < nw; ++q) bt += red[nw + q];
+  const bool finite = bt <= 3.0e38f;
+  int ee = 0;
+  if (finite && bt > 0.f) {
+    int ex = 0;
+    (void)frexpf(bt, &ex);
+    ee = 30 - ex;                    // the exact scale
+  }
+  const bool again = finite && bt > 0.f && (!ok || e > ee || e < ee - 3);
+  if (again) {
+    if (threadIdx.x == 0) atomicAdd(redo, 1);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) tile[i] = 0;
+    __syncthreads();
+    bshare = 0.f;
+    if (p0 < p1) load_page(p0, fa, wa, ra);
+    stream(p0, ee, true);
+    e = ee;
   }
   __syncthreads();
   float* dst = part + bid * (long long)tot;
@@ -2038,7 +2498,28 @@ int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u,
   }
 #undef LAG_ASM
   LAG_LAUNCH_CHECK();
+  if (P->pg_cap > 0) {  // the paged copy the products read
+    const size_t prows = (size_t)B.bdim[0] * B.bdim[1] * B.bdim[2];
+    const size_t plds = 2 * sizeof(int) * ((prows + 3) & ~(size_t)3) + ((prows + 63) & ~(size_t)63);
+    unsigned pgrid = grid_for(B.nbricks);
+    if (P->geo.dim == 3)
+      hipLaunchKernelGGL(k_jac_pack<3>, dim3(pgrid), dim3(kBlock), plds, s, B, P->jac_vals, P->jac_cell, P->jac_cnt,
+                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages);
+    else
+      hipLaunchKernelGGL(k_jac_pack<2>, dim3(pgrid), dim3(kBlock), plds, s, B, P->jac_vals, P->jac_cell, P->jac_cnt,
+                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages);
+    LAG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_brick_order, dim3(1), dim3(1024), 0, s, P->pg_npages, B.nbricks, P->pg_order);
+    LAG_LAUNCH_CHECK();
+  }
   return LAG_OK;
+}
+
+int jac_pages_per_brick(lag_plan P, int kmax) {
+  const lag::Bricks& B = P->bricks;
+  const long long rows = (long long)B.bdim[0] * B.bdim[1] * B.bdim[2];
+  if (kmax < 1 || kmax > 64 || rows * (long long)(2 * sizeof(int) + 1) + 128 > 64 * 1024) return 0;
+  return jac_page_cap(rows, kmax);
 }
 
 int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
@@ -2047,14 +2528,31 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
   unsigned grid = grid_for(B.nbricks);
   const size_t lds = sizeof(float) * ((size_t)P->geo.dim * B.tvol + 2 * (kBlock / 64));
   if (!wseed) prof_begin(P, s);
-  if (P->geo.dim == 3)
+  if (P->pg_cap > 0) {
+    const size_t plds = sizeof(float) * ((size_t)P->geo.dim * B.tvol + 2 * (kPgBlock / 64) + kPgBlock);
+#define LAG_PG(DD, WS, WV, VT)                                                                                    \
+  hipLaunchKernelGGL((k_jac_apply_pg<DD, WS, WV>), dim3(grid), dim3(kPgBlock), plds, s, P->geo, B, P->pg_vals,     \
+                     P->pg_cells, P->pg_rows, P->pg_npages, P->pg_order, P->pg_cap, (const VT*)ppack,              \
+                     wvox, wseed, scale, P->jac_fb, P->tile_part, P->pg_redo)
+    if (P->geo.dim == 3) {
+      if (wseed) LAG_PG(3, true, false, float4);
+      else if (wvox) LAG_PG(3, false, true, float4);
+      else LAG_PG(3, false, false, float4);
+    } else {
+      if (wseed) LAG_PG(2, true, false, float2);
+      else if (wvox) LAG_PG(2, false, true, float2);
+      else LAG_PG(2, false, false, float2);
+    }
+#undef LAG_PG
+  } else if (P->geo.dim == 3) {
     hipLaunchKernelGGL(k_jac_apply<3>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
                        P->jac_cnt, P->jac_slots, (const float4*)ppack, wvox, wseed, scale, P->jac_fb,
                        P->tile_part);
-  else
+  } else {
     hipLaunchKernelGGL(k_jac_apply<2>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
                        P->jac_cnt, P->jac_slots, (const float2*)ppack, wvox, wseed, scale, P->jac_fb,
                        P->tile_part);
+  }
   if (!wseed) prof_end(P, s);
   LAG_LAUNCH_CHECK();
   return launch_tile_reduce(P, out, P->jac_fb, s, rt);  // assigns out
