@@ -1,0 +1,149 @@
+"""Gauss-Newton solves checked iterate by iterate against the oracle.
+
+The problem is non-convex and PCG is inexact, so the GPU's iterates are not
+the oracle's; instead, at every iterate v_k the GPU reaches (cast to float64
+for the oracle), the oracle's objective J(v_k), gradient g(v_k) and
+Gauss-Newton product H(v_k) p must match the GPU's to 1e-5 (largest entry
+and 2-norm, cases.relerr), kink-aware as in the parity tests: the gradient's
+data term is taken as J^T w with the oracle's residual weights w = h^d
+(u1 - R) on both sides and compared apart from the regulariser term (near
+convergence g is their small difference; the sum is bounded relative to the
+data term), and characteristics within 2e-5 cells of a grid
+line are masked (their weights zeroed for transport, their mass for
+continuity).  The solve itself must reach |g| <= 1e-2 |g(0)| with J
+decreasing at every step.
+
+Continuity solves with the cloud-in-cell push-forward have a piecewise
+smooth objective whose gradient jumps whenever a particle crosses a cell-
+centre line; the case below is one the oracle's own solver brings to the
+tolerance (in 14 iterations).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from cases import Case, gpu_problem, oracle_problem, relerr
+from synthetic import blob_image, fourier_velocity
+from test_gpu_parity import MASK_CELLS, Dev, f32
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1703_04446_amd as _L
+    _L.load()
+    return _L
+
+
+SOLVES = [
+    # 2-D 64^2 transport (the small workload), assembled Jacobian
+    dict(name="transport_2d64_assembled", case=Case("t", 2, (64, 64), (64, 64), nsteps=5, nblobs=8, kmax=4,
+                                                   amplitude=0.05, seed=1000), jac=8, pcg_maxit=20),
+    # the same, matrix-free products
+    dict(name="transport_2d64_matrix_free", case=Case("t", 2, (64, 64), (64, 64), nsteps=5, nblobs=8, kmax=4,
+                                                     amplitude=0.05, seed=1000), jac=0, pcg_maxit=20),
+    # 2-D 48^2 mass-preserving densities on a 24^2 velocity grid, curvature
+    # alpha = 1e-3, N = 10 (the batched-solve recipe for continuity pairs)
+    dict(name="continuity_2d48_curvature", case=Case("c", 2, (48, 48), (24, 24), model="continuity",
+                                                    reg="curvature", alpha=1e-3, nsteps=10, seed=4001),
+         jac=0, pcg_maxit=30, template=("blob", 8, 4001), velocity=(4, 0.05, 4002)),
+]
+
+
+@pytest.mark.parametrize("spec", SOLVES, ids=[s["name"] for s in SOLVES])
+def test_gn_iterates_match_oracle(spec, torch, L):
+    case = spec["case"]
+    dev = Dev(torch)
+    OP = oracle_problem(case)
+    import paper_1703_04446_amd as LL
+    prob = LL.make_problem(case.dim, case.img_m, case.vel_m, nt_nodes=case.nodes, model=case.model,
+                           reg=case.reg, nsteps=case.nsteps, alpha=case.alpha, gamma=case.gamma,
+                           jac_blocks=spec["jac"])
+    plan = L.Plan(prob)
+    n, nu = plan.n_points, plan.n_unknowns
+    if "template" in spec:
+        _, nb, ts = spec["template"]
+        T = f32(blob_image(case.img_m, nb, ts, density=case.model == "continuity").ravel())
+        K, A, vs = spec["velocity"]
+        vt = fourier_velocity(case.vel_m, K, A, vs)
+    else:
+        T = f32(case.template())
+        vt = case.velocity()
+    R = f32(O.objective(OP, vt, T, np.zeros(n))["u"])
+    Td, Rd = dev.put(T), dev.put(R)
+    p = f32(case.direction(5))
+    opt = L.lag_gn_default_options()
+    opt.pcg_maxit = spec["pcg_maxit"]
+    g0d = dev.empty(nu)
+    out3 = torch.empty(3, dtype=torch.float64, device="cuda")
+    L.lag_gradient_at_zero(plan, Td, Rd, g0d, out3)
+    g0 = float(np.linalg.norm(dev.get(g0d)))
+    v = torch.zeros(nu, device="cuda")
+    vn = torch.empty_like(v)
+    Js, worst = [], {}
+    converged = False
+    for k in range(30):
+        vk = dev.get(v).reshape(OP.vel_shape)
+        # --- the oracle at the GPU's iterate -------------------------------
+        obj = O.objective(OP, vk, T, R)
+        L.lag_objective(plan, v, Td, Rd, dev.empty(n), out3)
+        eJ = abs(float(out3[0]) - obj["J"]) / abs(obj["J"])
+        _, margin = O.jvp(OP, vk, T, np.zeros(OP.vel_shape), return_margin=True)
+        keep = margin >= MASK_CELLS
+        w = f32(OP.cell_img * obj["res"])
+        gd = dev.empty(nu)
+        Hp = dev.empty(nu)
+        reg = dev.empty(nu)
+        L.lag_reg_apply(plan, v, reg)
+        if case.model == "transport":
+            wm = w * keep
+            L.lag_vjp(plan, v, Td, dev.put(wm), gd)
+            g_o = O.vjp(OP, vk, T, wm) + O.regularizer_apply(OP, vk)
+            Wm = f32(keep.astype(np.float64))
+            L.gn_hessmat(plan, v, Td, dev.put(Wm), dev.put(p), Hp)
+            H_o = O.hessmat(OP, vk, T, p, wvox=Wm)
+        else:
+            Tm = T * keep
+            L.lag_vjp(plan, v, dev.put(Tm), dev.put(w), gd)
+            g_o = O.vjp(OP, vk, Tm, w) + O.regularizer_apply(OP, vk)
+            L.gn_hessmat(plan, v, dev.put(Tm), None, dev.put(p), Hp)
+            H_o = O.hessmat(OP, vk, Tm, p)
+        # at convergence g is the small difference of its data term and its
+        # regulariser term, so each term is compared on its own, and the sum
+        # relative to the data term
+        gdata_o = g_o - O.regularizer_apply(OP, vk)
+        eg_data = relerr(dev.get(gd), gdata_o)
+        eg_reg = relerr(dev.get(reg), O.regularizer_apply(OP, vk)) if case.alpha > 0 else 0.0
+        gsum = dev.get(gd) + dev.get(reg)
+        eg = float(np.abs(gsum - g_o).max() / np.abs(gdata_o).max())
+        eH = relerr(dev.get(Hp), H_o)
+        for key, e in (("J", eJ), ("g_data", eg_data), ("g_reg", eg_reg), ("g", eg), ("Hp", eH)):
+            worst[key] = max(worst.get(key, 0.0), e)
+        # --- the GPU's own step ----------------------------------------------
+        info = L.lag_gn_step(plan, Td, Rd, v, vn, opt, gstop=1e-2 * g0)
+        print(f"{spec['name']} it {k}: J {obj['J']:.6e} |g|/|g0| {info['gnorm'] / g0:.3e} "
+              f"pcg {info['pcg_iters']} mu {info['mu']} errs J {eJ:.1e} g {eg:.1e} Hp {eH:.1e}", flush=True)
+        assert abs(info["J"] - obj["J"]) <= TOL * abs(obj["J"])
+        if info["stopped"]:
+            converged = True
+            break
+        assert info["status"] == L.LAG_OK and info["accepted"]
+        Js.append((info["J"], info["J_next"]))
+        v.copy_(vn)
+    print(spec["name"], "worst iterate errors", {k: f"{e:.2e}" for k, e in worst.items()}, flush=True)
+    assert converged, "no convergence to |g| <= 1e-2 |g(0)| within 30 steps"
+    assert all(b < a for a, b in Js)
+    for key, e in worst.items():
+        assert e < TOL, (key, e)
+    plan.close()
