@@ -108,7 +108,10 @@ const char* lag_last_hip_error(void);
 /* Create a plan for `prob` on the current HIP device: validates the problem,
  * allocates the workspace (packed velocity copies, RK4 stage-time tables,
  * FFT twiddles, scratch) and uploads host-computed tables.  This is the
- * allocating call; it synchronises the device.  *out receives the plan. */
+ * allocating call; it synchronises the device.  *out receives the plan.
+ * LAG_EUNSUPPORTED if the 64-bit accumulation tile of one brick (8 bytes
+ * per velocity node of the tile and field) does not fit the device's LDS
+ * per block (only for very many time nodes). */
 int lag_plan_create(const lag_problem* prob, lag_plan* out);
 
 /* lag_plan_create with a chosen brick shape: brick_target[a] image cells per
@@ -138,8 +141,21 @@ int lag_plan_problem(lag_plan plan, lag_problem* out);
  *   bit 1 (2): forward recovery met an exactly singular step Jacobian and
  *              used the identity for it.  The guard above routes such
  *              characteristics to the recomputed sweep first, so this bit
- *              signals an internal error. */
+ *              signals an internal error.
+ *   bit 2 (4): a matrix-free adjoint value fell outside the accumulation
+ *              tile that the characteristic's forward cells had been checked
+ *              against, and was added by a float atomic (correct, but not
+ *              reproducible bit for bit).  Not expected: the reverse sweep
+ *              samples the cells of the forward pass. */
 int lag_plan_flags(lag_plan plan, int32_t* flags, int32_t clear, void* stream);
+
+/* Work counters of the last matrix-free adjoint product (lag_vjp,
+ * gn_hessmat, lag_gradient on the plan's stream): *deferred = number of
+ * characteristics whose samples left their brick's accumulation tile (summed
+ * apart in 64-bit fixed point), *redone = number of bricks whose first pass
+ * was redone at the exact fixed-point unit.  Either pointer may be NULL.
+ * Synchronises `stream`. */
+int lag_adjoint_stats(lag_plan plan, int32_t* deferred, int32_t* redone, void* stream);
 
 /* Kernel timing for measurement: when enabled, every launch of the
  * Gauss-Newton matvec's main kernel is bracketed by HIP events recorded on
@@ -183,8 +199,11 @@ int lag_jvp(lag_plan plan, const float* v, const float* T, const float* dv,
 
 /* Vector-Jacobian product JTw = (d_v u1)^T w (the data part of the gradient,
  * Sec. 3.2).  v, JTw: velocity-shaped; T, w: image-shaped.  Characteristics
- * are recomputed, never stored (memory independent of N).  The velocity-
- * grid sum uses float atomics, so the last bits may vary between runs. */
+ * are recomputed, never stored (memory independent of N).  Reproducible bit
+ * for bit: every velocity-grid sum is taken in integer fixed point (32-bit
+ * per brick tile, 64-bit for characteristics that leave their tile), whose
+ * value does not depend on the order of the additions, and the tiles are
+ * combined in a fixed order. */
 int lag_vjp(lag_plan plan, const float* v, const float* T, const float* w,
             float* JTw, void* stream);
 
@@ -195,7 +214,8 @@ int lag_vjp(lag_plan plan, const float* v, const float* T, const float* w,
  * A = -Laplace_h (diffusion) or Laplace_h^2 (curvature), periodic.
  * wvox: image-shaped voxel weights W, or NULL for W = 1.
  * v, p, Hp: velocity-shaped; T image-shaped.  Transport: one fused pass per
- * characteristic; continuity: J p on the image grid, then J^T. */
+ * characteristic; continuity: J p on the image grid, then J^T.  Reproducible
+ * bit for bit (the sums of lag_vjp). */
 int gn_hessmat(lag_plan plan, const float* v, const float* T, const float* wvox,
                const float* p, float* Hp, void* stream);
 

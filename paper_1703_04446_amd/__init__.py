@@ -11,7 +11,7 @@ from ._lib import (  # noqa: F401
     LAG_OK, LAG_EINVAL, LAG_EUNSUPPORTED, LAG_EHIP, LAG_ENOMEM, LAG_EBREAKDOWN, LAG_ELINESEARCH, LAG_ETOOLARGE,
     LAG_TRANSPORT, LAG_CONTINUITY, LAG_DIFFUSION, LAG_CURVATURE,
     LagProblem, LagError, Plan, make_problem, load, header_symbols, strerror,
-    lag_problem_check, lag_problem_sizes, lag_plan_create, lag_plan_destroy, lag_plan_flags,
+    lag_problem_check, lag_problem_sizes, lag_plan_create, lag_plan_destroy, lag_plan_flags, lag_adjoint_stats,
     lag_trace, lag_transport, lag_pushforward, lag_pushforward_noalloc, lag_jvp, lag_vjp, gn_hessmat,
     spectral_precond_apply, lag_reg_apply, lag_objective, lag_gradient, lag_gradient_at_zero, lag_dot,
     lag_pcg, lag_gn_default_options, lag_gn_solve, lag_profile_enable, lag_profile_read,

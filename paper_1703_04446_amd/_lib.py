@@ -101,6 +101,7 @@ _SIGS = {
     "lag_plan_destroy": (_I, [_P]),
     "lag_plan_problem": (_I, [_P, ctypes.POINTER(LagProblem)]),
     "lag_plan_flags": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _P]),
+    "lag_adjoint_stats": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _P]),
     "lag_profile_enable": (_I, [_P, ctypes.c_int32]),
     "lag_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "lag_trace": (_I, [_P, _P, ctypes.c_int32, _P, _P]),
@@ -292,6 +293,14 @@ def lag_plan_flags(plan, clear=True):
     f = ctypes.c_int32()
     _check("lag_plan_flags", load().lag_plan_flags(plan.handle, ctypes.byref(f), int(bool(clear)), _stream()))
     return f.value
+
+
+def lag_adjoint_stats(plan):
+    """(deferred characteristics, bricks redone) of the last matrix-free
+    adjoint product (synchronises the stream)."""
+    d, r = ctypes.c_int32(), ctypes.c_int32()
+    _check("lag_adjoint_stats", load().lag_adjoint_stats(plan.handle, ctypes.byref(d), ctypes.byref(r), _stream()))
+    return d.value, r.value
 
 
 def lag_profile_enable(plan, enable=True):

@@ -169,7 +169,7 @@ static void free_plan(lag_plan P) {
                   P->fft_mu1, P->flags, P->tile_part, P->cover_start[0], P->cover_start[1],
                   P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2], P->jac_vals,
                   P->jac_cell, P->jac_cnt, P->jac_max, P->jac_fb, P->pg_vals, P->pg_cells, P->pg_rows,
-                  P->pg_npages, P->pg_order, P->pg_redo};
+                  P->pg_npages, P->pg_order, P->pg_redo, P->dfr_list, P->dfr_hdr, P->dfr_acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->ctl) (void)hipFree(P->ctl);
@@ -338,6 +338,15 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
   P->fields = g.nodes * D;
   P->n_unknowns = (long long)P->fields * g.nv;
   choose_bricks(P, brick_target);
+  {
+    // the matrix-free adjoint kernels hold a 64-bit tile of the brick in LDS
+    int max_lds = 0;
+    HIPC(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
+    if (adjoint_lds_bytes(P) > (size_t)max_lds) {
+      free_plan(P);
+      return LAG_EUNSUPPORTED;
+    }
+  }
 
   // time-node quadrature weights (trapezoid; 1 for a stationary field)
   const int nt = g.nodes - 1;
@@ -401,6 +410,11 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
   for (int i = 0; i < 10; ++i) ALLOC(P->vec[i], sizeof(float) * P->n_unknowns);
   ALLOC(P->flags, sizeof(int) * 4);
   HIPC(hipMemset(P->flags, 0, sizeof(int) * 4));
+  ALLOC(P->dfr_list, sizeof(int) * g.np);
+  ALLOC(P->dfr_hdr, sizeof(int) * 4);
+  HIPC(hipMemset(P->dfr_hdr, 0, sizeof(int) * 4));
+  ALLOC(P->dfr_acc, sizeof(unsigned long long) * (size_t)P->n_unknowns);
+  HIPC(hipMemset(P->dfr_acc, 0, sizeof(unsigned long long) * (size_t)P->n_unknowns));
   if (prob->jac_blocks > 0 && prob->model == LAG_TRANSPORT && g.nodes == 1) {
     const lag::Bricks& B = P->bricks;
     P->jac_k = prob->jac_blocks;
@@ -476,6 +490,17 @@ int lag_profile_read(lag_plan P, double* ms_total, int32_t* launches) {
 int lag_plan_problem(lag_plan plan, lag_problem* out) {
   LAG_CHECK(plan && out);
   *out = plan->prob;
+  return LAG_OK;
+}
+
+int lag_adjoint_stats(lag_plan P, int32_t* deferred, int32_t* redone, void* stream) {
+  LAG_CHECK(P);
+  hipStream_t s = S(stream);
+  int host[4] = {0, 0, 0, 0};
+  LAG_HIP(hipMemcpyAsync(host, P->dfr_hdr, sizeof(host), hipMemcpyDeviceToHost, s));
+  LAG_HIP(hipStreamSynchronize(s));
+  if (deferred) *deferred = host[0];
+  if (redone) *redone = host[2];
   return LAG_OK;
 }
 

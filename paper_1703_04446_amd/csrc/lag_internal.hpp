@@ -85,7 +85,12 @@ struct lag_plan_s {
   // assembled matvec: out-of-tile contributions (float atomics), added and
   // cleared by the tile reduction, so outputs need no fill beforehand
   float* jac_fb = nullptr;
-  // status flags written by kernels (bit 0: singular RK4 step Jacobian)
+  // matrix-free adjoint products: characteristics whose cells leave their
+  // brick's tile, handled apart in a 64-bit fixed-point buffer
+  int* dfr_list = nullptr;               // np image cell indices
+  int* dfr_hdr = nullptr;                // [0] count, [1] largest magnitude sum (float bits), [2] bricks redone
+  unsigned long long* dfr_acc = nullptr; // fields * nv, zero between calls
+  // status flags written by kernels (kFlag* bits)
   int* flags = nullptr;
   // PCG control: device control block, pinned host mirrors (two slots, read
   // one iteration late), their copy events, the capture stream and the
@@ -165,7 +170,9 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
                hipStream_t s, bool zero = false);
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
-int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt);
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred = false);
+// LDS of the matrix-free adjoint kernel (64-bit tile of the plan's bricks)
+size_t adjoint_lds_bytes(lag_plan P);
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);
 // pages per brick of the paged copy for capacity kmax (0: layout not used)
 int jac_pages_per_brick(lag_plan P, int kmax);

@@ -170,6 +170,29 @@ __device__ __forceinline__ void matvec_acc(const float G[D][D], const float x[D]
 // Plan status bits written by the adjoint kernels (read by lag_plan_flags).
 constexpr int kFlagRecompute = 1;  // some characteristic took the recomputed reverse sweep
 constexpr int kFlagSingular = 2;   // forward recovery met a singular step (not expected: guarded)
+constexpr int kFlagSpill = 4;      // an adjoint value left its tile: added by float atomics (order not fixed)
+
+// Whether every sample of one characteristic falls in a brick's tile (with
+// the cell's upper corners): origin and last usable cell offset are uniform
+// across the block, so only the flag takes a register per lane.
+template <int D>
+struct CellBox {
+  int org[D];
+  int last[D];   // tile size - 2
+  bool in;
+  __device__ __forceinline__ void reset(const int o[3], const int td[3]) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      org[a] = o[a];
+      last[a] = td[a] - 2;
+    }
+    in = true;
+  }
+  __device__ __forceinline__ void take(const Loc<D>& L) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) in = in && (unsigned)(L.c[a] - org[a]) <= (unsigned)last[a];
+  }
+};
 
 // ---------------------------------------------------------------------------
 // pass 1: positions, optional tangent (direction field dp) and flow Jacobian.
@@ -178,7 +201,8 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
                                              const typename VecT<D>::T* __restrict__ vp,
                                              const typename VecT<D>::T* __restrict__ dp,
                                              const Start<D>& S, float phi[D], float dphi[D],
-                                             float F[D][D], float* growth = nullptr) {
+                                             float F[D][D], float* growth = nullptr,
+                                             CellBox<D>* box = nullptr) {
   constexpr bool GR = TAN || FJ;
   if (FJ && growth) *growth = 1.f;
   const float dt = st.dt, hdt = 0.5f * dt;
@@ -197,6 +221,7 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
     Loc<D> L;
     // stage 1 at phi
     locate_v<D>(g, S, phi, L);
+    if (box) box->take(L);
     sample_vel<D, NS, GR>(vp, g, st, q, L, k1, G1);
     if (TAN) {
       sample_vel<D, NS, false>(dp, g, st, q, L, e, dummy);
@@ -207,6 +232,7 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
     // stage 2 at phi + dt/2 k1
     stage_pos<D>(phi, hdt, k1, P);
     locate_v<D>(g, S, P, L);
+    if (box) box->take(L);
     sample_vel<D, NS, GR>(vp, g, st, q + 1, L, k2, G2);
     if (TAN) {
       sample_vel<D, NS, false>(dp, g, st, q + 1, L, e, dummy);
@@ -217,6 +243,7 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
     // stage 3 at phi + dt/2 k2
     stage_pos<D>(phi, hdt, k2, P);
     locate_v<D>(g, S, P, L);
+    if (box) box->take(L);
     sample_vel<D, NS, GR>(vp, g, st, q + 2, L, k3, G3);
     if (TAN) {
       sample_vel<D, NS, false>(dp, g, st, q + 2, L, e, dummy);
@@ -227,6 +254,7 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
     // stage 4 at phi + dt k3
     stage_pos<D>(phi, dt, k3, P);
     locate_v<D>(g, S, P, L);
+    if (box) box->take(L);
     sample_vel<D, NS, GR>(vp, g, st, q + 3, L, k4, G4);
     if (TAN) {
       sample_vel<D, NS, false>(dp, g, st, q + 3, L, e, dummy);
@@ -249,10 +277,34 @@ __device__ __forceinline__ void forward_pass(const Geo& g, const Stages& st,
 }
 
 // ---------------------------------------------------------------------------
-// Velocity-grid accumulator: LDS tile of a brick with global fallback.
+// v 2^e rounded to the nearest integer, as a two's-complement 64-bit word,
+// for |v| 2^e < 2^62, in float arithmetic: t = v 2^(e-32) splits exactly
+// into floor(t) (an int32) and the fraction t - floor(t), whose scaling by
+// 2^32 is exact and is rounded to the nearest integer (at most 2^32 - 256).
+__device__ __forceinline__ unsigned long long fix64(float v, int e) {
+  const float t = ldexpf(v, e - 32);
+  const float hi = floorf(t);
+  const unsigned lo = __float2uint_rn(ldexpf(t - hi, 32));
+  return ((unsigned long long)(long long)(int)hi << 32) + lo;
+}
+
+// ---------------------------------------------------------------------------
+// Velocity-grid accumulators of the matrix-free adjoint products.  A scatter
+// hands over one sample (add: corner weights times a stage adjoint, split
+// between two time nodes for a time-dependent field) or one register-merged
+// cell (add_block: 2^d corners x d components per time slot); the three
+// accumulators differ only in where the values go.
+//
+// AdjTile: the brick's LDS tile in 64-bit fixed point with unit 2^-e.  An
+// integer sum does not depend on the order of its additions, so the tile is
+// the same bit for bit on every run; sabs sums the magnitudes the thread
+// added (their block-wide sum bounds every partial sum of the tile).  Cells
+// outside the tile do not occur for a characteristic whose forward cells
+// passed CellBox::inside (the adjoint replay samples the same cells); should
+// one occur, its values go to the output by float atomics and `spill` is set.
 template <int D, bool NS>
-struct TileAcc {
-  float* lds;
+struct AdjTile {
+  unsigned long long* tile;
   float* gout;
   const int* j0;
   const float* th;
@@ -261,8 +313,42 @@ struct TileAcc {
   int mv[3];
   int tvol;
   long long nv;
+  int e;
+  float sabs;
+  bool spill;
 
-  __device__ __forceinline__ void add(const Loc<D>& L, int q, const float kb[D]) const {
+  __device__ __forceinline__ bool base_of(const int c[D], int& base) const {
+    bool in = true;
+    int t[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      t[a] = c[a] - org[a];
+      in = in && (t[a] >= 0) && (t[a] + 1 < td[a]);
+    }
+    base = (t[2] * td[1] + t[1]) * td[0] + t[0];
+    return in;
+  }
+  __device__ __forceinline__ int corner_off(int base, int o) const {
+    int off = base + (o & 1) + ((o >> 1) & 1) * td[0];
+    if (D == 3) off += ((o >> 2) & 1) * td[0] * td[1];
+    return off;
+  }
+  __device__ __forceinline__ void put(int i, float v) {
+    atomicAdd(&tile[i], fix64(v, e));
+    sabs += fabsf(v);
+  }
+  __device__ __forceinline__ void spill_put(const int c[D], int o, int field, float v) {
+    Loc<D> L;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      L.c[a] = c[a];
+      L.f[a] = 0.f;
+    }
+    unsafeAtomicAdd(&gout[(long long)field * nv + corner_index<D>(L, mv, o)], v);
+    spill = true;
+  }
+
+  __device__ __forceinline__ void add(const Loc<D>& L, int q, const float kb[D]) {
     float w[1 << D];
     corner_weights<D>(L, w);
     int jA = 0;
@@ -272,78 +358,148 @@ struct TileAcc {
       wB = th[q];
       wA = 1.f - wB;
     }
-    bool in = true;
-    int t[3] = {0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      t[a] = L.c[a] - org[a];
-      in = in && (t[a] >= 0) && (t[a] + 1 < td[a]);
-    }
-    if (in) {
-      int base = (t[2] * td[1] + t[1]) * td[0] + t[0];
+    int base;
+    if (base_of(L.c, base)) {
 #pragma unroll
       for (int o = 0; o < (1 << D); ++o) {
-        int off = base + (o & 1) + ((o >> 1) & 1) * td[0];
-        if (D == 3) off += ((o >> 2) & 1) * td[0] * td[1];
+        const int off = corner_off(base, o);
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-          float val = w[o] * kb[c];
-          atomicAdd(&lds[(jA * D + c) * tvol + off], wA * val);
-          if (NS) atomicAdd(&lds[((jA + 1) * D + c) * tvol + off], wB * val);
+          const float val = w[o] * kb[c];
+          put((jA * D + c) * tvol + off, wA * val);
+          if (NS) put(((jA + 1) * D + c) * tvol + off, wB * val);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
 #pragma unroll
-      for (int o = 0; o < (1 << D); ++o) {
-        long long gi = corner_index<D>(L, mv, o);
+      for (int o = 0; o < (1 << D); ++o)
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-          float val = w[o] * kb[c];
-          unsafeAtomicAdd(&gout[(long long)(jA * D + c) * nv + gi], wA * val);
-          if (NS) unsafeAtomicAdd(&gout[(long long)((jA + 1) * D + c) * nv + gi], wB * val);
+          const float val = w[o] * kb[c];
+          spill_put(L.c, o, jA * D + c, wA * val);
+          if (NS) spill_put(L.c, o, (jA + 1) * D + c, wB * val);
         }
+    }
+  }
+
+  template <int NSLOT>
+  __device__ __forceinline__ void add_block(const int cell[D], int jA, const float a[NSLOT][1 << D][D]) {
+    int base;
+    if (base_of(cell, base)) {
+#pragma unroll
+      for (int o = 0; o < (1 << D); ++o) {
+        const int off = corner_off(base, o);
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+          for (int c = 0; c < D; ++c) put(((jA + s) * D + c) * tvol + off, a[s][o][c]);
+        // one corner's conversions at a time (they would otherwise be
+        // hoisted ahead of the atomics, each holding a register)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int o = 0; o < (1 << D); ++o)
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+          for (int c = 0; c < D; ++c) spill_put(cell, o, (jA + s) * D + c, a[s][o][c]);
+    }
+  }
+};
+
+// AdjBound: the magnitude sum of what a characteristic scatters, with no
+// memory traffic (the same values as the other accumulators).
+template <int D, bool NS>
+struct AdjBound {
+  const int* j0;
+  const float* th;
+  float sabs;
+
+  __device__ __forceinline__ void add(const Loc<D>& L, int q, const float kb[D]) {
+    float w[1 << D];
+    corner_weights<D>(L, w);
+    float wA = 1.f, wB = 0.f;
+    if (NS) {
+      wB = th[q];
+      wA = 1.f - wB;
+    }
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o)
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const float val = w[o] * kb[c];
+        sabs += fabsf(wA * val);
+        if (NS) sabs += fabsf(wB * val);
+      }
+  }
+
+  template <int NSLOT>
+  __device__ __forceinline__ void add_block(const int*, int, const float a[NSLOT][1 << D][D]) {
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o)
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+        for (int c = 0; c < D; ++c) sabs += fabsf(a[s][o][c]);
+  }
+};
+
+// AdjWide: 64-bit fixed point with unit 2^-e in a grid-sized buffer (the
+// characteristics that leave their tile); integer atomics, so the sum does
+// not depend on the order either.
+template <int D, bool NS>
+struct AdjWide {
+  unsigned long long* acc;
+  const int* j0;
+  const float* th;
+  int mv[3];
+  long long nv;
+  int e;
+
+  __device__ __forceinline__ void put(long long gi, int field, float v) {
+    const long long q = __double2ll_rn(ldexp((double)v, e));
+    atomicAdd(&acc[(long long)field * nv + gi], (unsigned long long)q);
+  }
+
+  __device__ __forceinline__ void add(const Loc<D>& L, int q, const float kb[D]) {
+    float w[1 << D];
+    corner_weights<D>(L, w);
+    int jA = 0;
+    float wA = 1.f, wB = 0.f;
+    if (NS) {
+      jA = j0[q];
+      wB = th[q];
+      wA = 1.f - wB;
+    }
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o) {
+      const long long gi = corner_index<D>(L, mv, o);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const float val = w[o] * kb[c];
+        put(gi, jA * D + c, wA * val);
+        if (NS) put(gi, (jA + 1) * D + c, wB * val);
       }
     }
   }
 
-  // Add pre-merged corner values a[slot][o][c] of one cell (slot 1 is the
-  // second time node of a time-dependent field).
   template <int NSLOT>
-  __device__ __forceinline__ void add_block(const int cell[D], int jA, const float a[NSLOT][1 << D][D]) const {
-    bool in = true;
-    int t[3] = {0, 0, 0};
+  __device__ __forceinline__ void add_block(const int cell[D], int jA, const float a[NSLOT][1 << D][D]) {
+    Loc<D> L;
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-      t[ax] = cell[ax] - org[ax];
-      in = in && (t[ax] >= 0) && (t[ax] + 1 < td[ax]);
+      L.c[ax] = cell[ax];
+      L.f[ax] = 0.f;
     }
-    if (in) {
-      int base = (t[2] * td[1] + t[1]) * td[0] + t[0];
 #pragma unroll
-      for (int o = 0; o < (1 << D); ++o) {
-        int off = base + (o & 1) + ((o >> 1) & 1) * td[0];
-        if (D == 3) off += ((o >> 2) & 1) * td[0] * td[1];
+    for (int o = 0; o < (1 << D); ++o) {
+      const long long gi = corner_index<D>(L, mv, o);
 #pragma unroll
-        for (int s = 0; s < NSLOT; ++s)
+      for (int s = 0; s < NSLOT; ++s)
 #pragma unroll
-          for (int c = 0; c < D; ++c) atomicAdd(&lds[((jA + s) * D + c) * tvol + off], a[s][o][c]);
-      }
-    } else {
-      Loc<D> L;
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax) {
-        L.c[ax] = cell[ax];
-        L.f[ax] = 0.f;
-      }
-#pragma unroll
-      for (int o = 0; o < (1 << D); ++o) {
-        long long gi = corner_index<D>(L, mv, o);
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s)
-#pragma unroll
-          for (int c = 0; c < D; ++c)
-            unsafeAtomicAdd(&gout[(long long)((jA + s) * D + c) * nv + gi], a[s][o][c]);
-      }
+        for (int c = 0; c < D; ++c) put(gi, (jA + s) * D + c, a[s][o][c]);
     }
   }
 };
@@ -1071,64 +1227,55 @@ __global__ void __launch_bounds__(kBlock) k_trace_tile(Geo g, Stages st, Bricks 
   });
 }
 
-// Write the block's tile to its slot of the partial-tile buffer; a separate
-// kernel sums the overlapping tiles per velocity node in a fixed order.
-template <int D, bool NS>
-__device__ __forceinline__ void flush_tile(const TileAcc<D, NS>& acc, int fields, float* __restrict__ part,
-                                           long long bid) {
-  __syncthreads();
-  const int tot = fields * acc.tvol;
-  float* dst = part + bid * (long long)tot;
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) dst[i] = acc.lds[i];
-}
+// ---------------------------------------------------------------------------
+// Matrix-free adjoint products (J^T w and the transport Gauss-Newton data
+// term), one characteristic at a time, seeded at its end point y_N:
+//   MODE 0  transport, J^T w:   seed w_i grad T(y_i)
+//   MODE 1  continuity, J^T w:  seed T_j grad I(w)(y_j)
+//   MODE 2  transport, h^d J^T W J p:  seed h^d W_i (grad T(y_i) . dy_i) grad T(y_i)
+// ZERO: at v = 0 (vp unused), y = x and a unit flow Jacobian.
+struct AdjArgs {
+  const void* vp;      // packed velocity
+  const void* pp;      // packed direction (MODE 2)
+  const float* T;      // template (MODE 0, 2), masses (MODE 1)
+  const float* w;      // image-grid weights (MODE 0, 1)
+  const float* wvox;   // per-voxel weights or null (MODE 2)
+};
 
-template <int D, bool NS>
-__device__ __forceinline__ TileAcc<D, NS> make_acc(float* lds, float* gout, const Geo& g, const Stages& st,
-                                                   const Bricks& B, const int org[3], int fields) {
-  TileAcc<D, NS> acc;
-  acc.lds = lds;
-  acc.gout = gout;
-  acc.tvol = B.tvol;
-  acc.nv = g.nv;
-  acc.j0 = st.j0;
-  acc.th = st.th;
+template <int D>
+struct AdjItem {
+  Start<D> S;
+  float yN[D];    // seed at t = 1
+  float y0[D];    // F^T yN, the forward-recovery start at t = 0
+  float growth;   // conditioning product of the step Jacobians
+};
+
+// Trace and seed the characteristic of image cell idx; false for a zero seed.
+template <int D, bool NS, int MODE, bool ZERO>
+__device__ __forceinline__ bool adj_prepare(const Geo& g, const Stages& st, const AdjArgs& A, const int idx[3],
+                                            AdjItem<D>& it, CellBox<D>* box) {
+  using VT = typename VecT<D>::T;
+  make_start_idx<D>(g, idx, it.S);
+  long long p = idx[0] + (long long)g.mi[0] * idx[1];
+  if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
+  float phi[D], dphi[D], F[D][D];
+  it.growth = 1.f;
+  Loc<D> L;
+  if constexpr (MODE == 2) {
+    const float W = A.wvox ? A.wvox[p] : 1.f;
+    if (W == 0.f) return false;
+    forward_pass<D, NS, true, true>(g, st, (const VT*)A.vp, (const VT*)A.pp, it.S, phi, dphi, F, &it.growth, box);
+    locate_i<D>(g, it.S, phi, L);
+    float gT[D], val;
+    sample_img<D, false, true>(A.T, g, L, val, gT);
+    float Jp = 0.f;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    acc.org[a] = org[a];
-    acc.td[a] = B.tdim[a];
-    acc.mv[a] = g.mv[a];
-  }
-  for (int i = threadIdx.x; i < fields * B.tvol; i += blockDim.x) lds[i] = 0.f;
-  __syncthreads();
-  return acc;
-}
-
-// VJP: MODEL 0 = transport (seed w_i grad T(y_i)),
-//      MODEL 1 = continuity (seed T_j grad I(w)(y_j)).
-// ZERO: at v = 0 (vp unused): y = x and a unit flow Jacobian, zero_adjoint.
-template <int D, bool NS, int MODEL, bool ZERO>
-__global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, const typename VecT<D>::T* __restrict__ vp,
-                                                const float* __restrict__ T, const float* __restrict__ w,
-                                                float* __restrict__ out, float* __restrict__ part,
-                                                int* __restrict__ flags) {
-  if (halted(g.halt)) return;
-  extern __shared__ float lds[];
-  long long bid = xcd_block(B.nbricks);
-  if (bid < 0) return;
-  int O[3], org[3];
-  brick_origin<D>(g, B, bid, O, org);
-  const int fields = g.nodes * D;
-  TileAcc<D, NS> acc = make_acc<D, NS>(lds, out, g, st, B, org, fields);
-  int status = 0;  // kFlag* bits of this thread's characteristics
-  Merge<D, false> zmg;  // ZERO with a stationary field: kept across the thread's points
-  zmg.reset();
-  for_brick_points<D>(g, B, O, [&](const int idx[3]) {
-    Start<D> S;
-    make_start_idx<D>(g, idx, S);
-    long long p = idx[0] + (long long)g.mi[0] * idx[1];
-    if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
-    float phi[D], dphi[D], F[D][D];
-    float growth = 1.f;
+    for (int a = 0; a < D; ++a) Jp = fmaf(gT[a], dphi[a], Jp);
+    const float s = g.cell_img * W * Jp;
+    if (s == 0.f) return false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) it.yN[a] = s * gT[a];
+  } else {
     if constexpr (ZERO) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -1137,107 +1284,287 @@ __global__ void __launch_bounds__(kBlock) k_vjp(Geo g, Stages st, Bricks B, cons
         for (int b = 0; b < D; ++b) F[a][b] = a == b ? 1.f : 0.f;
       }
     } else {
-      forward_pass<D, NS, false, true>(g, st, vp, nullptr, S, phi, dphi, F, &growth);
+      forward_pass<D, NS, false, true>(g, st, (const VT*)A.vp, nullptr, it.S, phi, dphi, F, &it.growth, box);
     }
-    Loc<D> L;
-    locate_i<D>(g, S, phi, L);
-    float yN[D], val;
-    if (MODEL == 0) {
-      float gT[D];
-      sample_img<D, false, true>(T, g, L, val, gT);
-      const float wi = w[p];
+    locate_i<D>(g, it.S, phi, L);
+    float gr[D], val;
+    if (MODE == 0) {
+      sample_img<D, false, true>(A.T, g, L, val, gr);
+      const float wi = A.w[p];
 #pragma unroll
-      for (int a = 0; a < D; ++a) yN[a] = wi * gT[a];
+      for (int a = 0; a < D; ++a) it.yN[a] = wi * gr[a];
     } else {
-      float gw[D];
-      sample_img<D, false, true>(w, g, L, val, gw);
-      const float m = T[p];
+      sample_img<D, false, true>(A.w, g, L, val, gr);
+      const float m = A.T[p];
 #pragma unroll
-      for (int a = 0; a < D; ++a) yN[a] = m * gw[a];
+      for (int a = 0; a < D; ++a) it.yN[a] = m * gr[a];
     }
     bool nz = false;
 #pragma unroll
-    for (int a = 0; a < D; ++a) nz = nz || (yN[a] != 0.f);
-    if (!nz) return;
-    if constexpr (!ZERO) {
-      if (!recovery_ok(growth)) {  // (nearly) singular step Jacobians
-        reverse_recompute<D, NS>(g, st, vp, S, yN, acc);
-        status |= kFlagRecompute;
-        return;
-      }
-    }
-    float y0[D];
+    for (int a = 0; a < D; ++a) nz = nz || (it.yN[a] != 0.f);
+    if (!nz) return false;
+  }
 #pragma unroll
-    for (int b = 0; b < D; ++b) {
-      float s = 0.f;
+  for (int b = 0; b < D; ++b) {
+    float s = 0.f;
 #pragma unroll
-      for (int a = 0; a < D; ++a) s = fmaf(F[a][b], yN[a], s);
-      y0[b] = s;
-    }
-    if constexpr (ZERO && !NS) zero_add<D>(g, st, S, y0, acc, zmg);
-    else if constexpr (ZERO) zero_adjoint<D, NS>(g, st, S, y0, acc);
-    else if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) status |= kFlagSingular;
-  });
-  if constexpr (ZERO && !NS) zmg.flush(acc);
-  if (status) atomicOr(flags, status);
-  flush_tile<D, NS>(acc, fields, part, bid);
+    for (int a = 0; a < D; ++a) s = fmaf(F[a][b], it.yN[a], s);
+    it.y0[b] = s;
+  }
+  return true;
 }
 
-// Fused transport Gauss-Newton data term: out += h^d J^T (W (J p)).
+// Magnitude estimate of a characteristic's scatter, without tracing it: the
+// seed formed at the start point x (as if v were 0, with dy = p(x) for
+// MODE 2), times the time span; the stage adjoints of a step sum to about
+// |dt| times the step's adjoint, which runs from y_0 = F^T y_N to y_N.
+template <int D, bool NS, int MODE>
+__device__ __forceinline__ float adj_guess(const Geo& g, const Stages& st, const AdjArgs& A, const int idx[3]) {
+  using VT = typename VecT<D>::T;
+  Start<D> S;
+  make_start_idx<D>(g, idx, S);
+  long long p = idx[0] + (long long)g.mi[0] * idx[1];
+  if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
+  float zero[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) zero[a] = 0.f;
+  Loc<D> L;
+  locate_i<D>(g, S, zero, L);
+  float gr[D], val;
+  sample_img<D, false, true>(MODE == 1 ? A.w : A.T, g, L, val, gr);
+  float n1 = 0.f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) n1 += fabsf(gr[a]);
+  float s;
+  if constexpr (MODE == 0) {
+    s = fabsf(A.w[p]);
+  } else if constexpr (MODE == 1) {
+    s = fabsf(A.T[p]);
+  } else {
+    const float W = A.wvox ? A.wvox[p] : 1.f;
+    Loc<D> Lv;
+    locate_v<D>(g, S, zero, Lv);
+    float pv[D], dummy[D][D];
+    sample_vel<D, NS, false>((const VT*)A.pp, g, st, 0, Lv, pv, dummy);
+    float Jp = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) Jp = fmaf(gr[a], pv[a], Jp);
+    s = fabsf(g.cell_img * W * Jp);
+  }
+  return fabsf((float)g.nsteps * st.dt) * s * n1;
+}
+
+// The reverse sweep of a prepared characteristic into acc; returns kFlag*
+// bits.  Forward recovery unless the step Jacobians are ill-conditioned.
+template <int D, bool NS, bool ZERO, class Acc>
+__device__ __forceinline__ int adj_scatter(const Geo& g, const Stages& st, const void* vpv, AdjItem<D>& it, Acc& acc,
+                                           Merge<D, false>& zmg) {
+  using VT = typename VecT<D>::T;
+  const VT* vp = (const VT*)vpv;
+  if constexpr (ZERO) {
+    if constexpr (!NS) zero_add<D>(g, st, it.S, it.y0, acc, zmg);
+    else zero_adjoint<D, NS>(g, st, it.S, it.y0, acc);
+    return 0;
+  } else {
+    if (!recovery_ok(it.growth)) {
+      reverse_recompute<D, NS>(g, st, vp, it.S, it.yN, acc);
+      return kFlagRecompute;
+    }
+    return adjoint_pass<D, NS>(g, st, vp, it.S, it.y0, acc) ? 0 : kFlagSingular;
+  }
+}
+
+// Block-wide float sum in a fixed order (butterflies within each wave, then
+// the wave totals in wave order); every thread calls it and gets the total.
+// red holds one float per wave.
+__device__ __forceinline__ float block_sum_fixed(float v, float* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float t = 0.f;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+// Exponent e with bound 2^e in [2^(top-1), 2^top), bound > 0.
+__device__ __forceinline__ int fix_unit(float bound, int top) {
+  int x;
+  frexpf(bound, &x);
+  return top - x;
+}
+
+// Unit of the deferred buffer: n characteristics, each scattering at most
+// smax in magnitude, keep every partial sum below 2^61 units.
+__device__ __forceinline__ int deferred_unit(int n, float smax) {
+  int x;
+  frexp((double)n * (double)smax, &x);
+  return 61 - x;
+}
+
+// Adjoint products through the brick's LDS tile; the brick's tile goes to
+// its slot of `part` (k_tile_reduce sums the overlapping tiles per node in a
+// fixed order).  The tile is 64-bit fixed point with a per-brick unit 2^-e,
+// so the brick's sums do not depend on the order of the additions.  Each
+// wave takes a contiguous run of the brick's items, and before anything is
+// scattered the magnitude estimates (adj_guess) of the waves' first items,
+// scaled by items / first items, set e so that the estimate is about 2^45
+// units.  The exact magnitude sum S of the pass then decides: the pass
+// stands if every partial sum provably stays below 2^62 units (S < 2^62
+// units) and the unit is fine enough (S >= 2^36 units: a unit of at most
+// 2^-36 S, far below float rounding of the sums), otherwise the whole block
+// redoes the brick at the unit S sets (S about 2^60 units).  32 bits would
+// not do: with weights of both signs S can exceed the largest output entry a
+// thousandfold, and a unit of S 2^-28 is then visible at 1e-5.  A
+// characteristic whose forward cells leave the tile is not scattered here
+// but appended to the deferred list (once, on the first pass) for
+// k_adjoint_deferred.
+struct Deferred {
+  int* list;                // deferred characteristics (image cell index); room for every point
+  int* hdr;                 // [0] count, [1] largest magnitude sum (float bits), [2] bricks redone (this call)
+  unsigned long long* acc;  // fields * nv, 64-bit fixed point, cleared by k_tile_reduce
+};
+
+// Stationary 3-D bricks hold 32 or more 64-row items: eight waves share the
+// brick's tile (two per SIMD on one LDS tile of up to 104 KB).  2-D bricks
+// hold few items, and time-dependent 3-D fields need more registers than two
+// waves per SIMD leave: four waves.
 template <int D, bool NS>
-__global__ void __launch_bounds__(kBlock) k_hess_transport(Geo g, Stages st, Bricks B,
-                                                           const typename VecT<D>::T* __restrict__ vp,
-                                                           const typename VecT<D>::T* __restrict__ pp,
-                                                           const float* __restrict__ T, const float* __restrict__ wvox,
-                                                           float* __restrict__ out, float* __restrict__ part,
-                                                           int* __restrict__ flags) {
+struct AdjBlock {
+  static constexpr int threads = (D == 3 && !NS) ? 512 : 256;
+};
+
+template <int D, bool NS, int MODE, bool ZERO>
+__global__ void __launch_bounds__((AdjBlock<D, NS>::threads)) k_adjoint(Geo g, Stages st, Bricks B, AdjArgs A, float* __restrict__ out,
+                                                    float* __restrict__ part, int* __restrict__ flags, Deferred dq) {
   if (halted(g.halt)) return;
-  extern __shared__ float lds[];
-  long long bid = xcd_block(B.nbricks);
+  extern __shared__ unsigned long long ldsq[];
+  const long long bid = xcd_block(B.nbricks);
   if (bid < 0) return;
   int O[3], org[3];
   brick_origin<D>(g, B, bid, O, org);
-  const int fields = g.nodes * D;
-  TileAcc<D, NS> acc = make_acc<D, NS>(lds, out, g, st, B, org, fields);
-  int status = 0;  // kFlag* bits of this thread's characteristics
-  for_brick_points<D>(g, B, O, [&](const int idx[3]) {
-    Start<D> S;
-    make_start_idx<D>(g, idx, S);
-    long long p = idx[0] + (long long)g.mi[0] * idx[1];
-    if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
-    float W = wvox ? wvox[p] : 1.f;
-    if (W == 0.f) return;
-    float phi[D], dphi[D], F[D][D];
-    float growth = 1.f;
-    forward_pass<D, NS, true, true>(g, st, vp, pp, S, phi, dphi, F, &growth);
-    Loc<D> L;
-    locate_i<D>(g, S, phi, L);
-    float gT[D], val;
-    sample_img<D, false, true>(T, g, L, val, gT);
-    float Jp = 0.f;
+  const int tot = g.nodes * D * B.tvol;
+  float* red = reinterpret_cast<float*>(ldsq + tot);
+  AdjTile<D, NS> acc;
+  acc.tile = ldsq;
+  acc.gout = out;
+  acc.j0 = st.j0;
+  acc.th = st.th;
 #pragma unroll
-    for (int a = 0; a < D; ++a) Jp = fmaf(gT[a], dphi[a], Jp);
-    const float s = g.cell_img * W * Jp;
-    if (s == 0.f) return;
-    float yN[D], y0[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) yN[a] = s * gT[a];
-    if (!recovery_ok(growth)) {  // (nearly) singular step Jacobians
-      reverse_recompute<D, NS>(g, st, vp, S, yN, acc);
-      status |= kFlagRecompute;
-      return;
+  for (int a = 0; a < 3; ++a) {
+    acc.org[a] = org[a];
+    acc.td[a] = B.tdim[a];
+    acc.mv[a] = g.mv[a];
+  }
+  acc.tvol = B.tvol;
+  acc.nv = g.nv;
+  acc.e = 0;
+  acc.sabs = 0.f;
+  acc.spill = false;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) ldsq[i] = 0ull;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int l[3];
+  lane_lattice(B, lane, l);
+  const int items = brick_items(B);
+  const int run = (items + nw - 1) / nw;
+  const int w0 = wave * run, w1 = min(items, w0 + run);
+  int status = 0;
+  Merge<D, false> zmg;  // ZERO with a stationary field: kept across the thread's points
+  zmg.reset();
+  // trace item w's characteristic; false when it scatters nothing here
+  auto prepare = [&](int w, AdjItem<D>& it, bool first) -> bool {
+    int idx[3];
+    if (!item_cell<D>(g, B, O, w, l, idx)) return false;
+    if constexpr (ZERO) {
+      return adj_prepare<D, NS, MODE, true>(g, st, A, idx, it, nullptr);
+    } else {
+      CellBox<D> box;
+      box.reset(org, B.tdim);
+      if (!adj_prepare<D, NS, MODE, false>(g, st, A, idx, it, &box)) return false;
+      if (box.in) return true;
+      if (first) {
+        long long p = idx[0] + (long long)g.mi[0] * idx[1];
+        if (D == 3) p += (long long)g.mi[0] * g.mi[1] * idx[2];
+        dq.list[atomicAdd(dq.hdr, 1)] = (int)p;
+      }
+      return false;
     }
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      float t = 0.f;
-#pragma unroll
-      for (int a = 0; a < D; ++a) t = fmaf(F[a][b], yN[a], t);
-      y0[b] = t;
+  };
+  // pass 0 at the estimated unit; pass 1 (rare) redoes the brick at the exact one
+  for (int pass = 0;; ++pass) {
+    const bool first = pass == 0;
+    if (first) {
+      int idx[3];
+      const bool cur = w0 < w1 && item_cell<D>(g, B, O, w0, l, idx);
+      float est = block_sum_fixed(cur ? adj_guess<D, NS, MODE>(g, st, A, idx) : 0.f, red);  // also orders the tile clear
+      est *= (float)items / (float)((items + run - 1) / run);
+      acc.e = est > 0.f ? fix_unit(est, 46) : 0;
     }
-    if (!adjoint_pass<D, NS>(g, st, vp, S, y0, acc)) status |= kFlagSingular;
-  });
+    for (int w = w0; w < w1; ++w) {
+      AdjItem<D> it;
+      if (prepare(w, it, first)) status |= adj_scatter<D, NS, ZERO>(g, st, A.vp, it, acc, zmg);
+    }
+    if constexpr (ZERO && !NS) zmg.flush(acc);
+    const float sb = block_sum_fixed(acc.sabs, red);
+    const double m = ldexp((double)sb, acc.e);
+    if (!first || !(sb > 0.f) || (m < 0x1p62 && m >= 0x1p36)) break;  // the same in every thread
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) ldsq[i] = 0ull;
+    __syncthreads();
+    acc.e = fix_unit(sb, 61);
+    acc.sabs = 0.f;
+    zmg.reset();
+    if (threadIdx.x == 0) atomicAdd(dq.hdr + 2, 1);
+  }
+  if (acc.spill) status |= kFlagSpill;
   if (status) atomicOr(flags, status);
-  flush_tile<D, NS>(acc, fields, part, bid);
+  __syncthreads();
+  float* dst = part + bid * (long long)tot;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) dst[i] = (float)ldexp((double)(long long)ldsq[i], -acc.e);
+}
+
+// The deferred characteristics, grid-stride: PASS 0 finds the largest
+// magnitude sum of one characteristic's scatter (an order-free maximum),
+// PASS 1 scatters them into the 64-bit buffer at the unit that bound fixes.
+template <int D, bool NS, int MODE, int PASS>
+__global__ void __launch_bounds__(kBlock) k_adjoint_deferred(Geo g, Stages st, AdjArgs A, Deferred dq,
+                                                             int* __restrict__ flags) {
+  if (halted(g.halt)) return;
+  const int n = dq.hdr[0];
+  if (n == 0) return;
+  const float smax = __int_as_float(dq.hdr[1]);
+  if (PASS == 1 && !(smax > 0.f)) return;
+  const int e = PASS == 1 ? deferred_unit(n, smax) : 0;
+  int status = 0;
+  Merge<D, false> zmg;
+  zmg.reset();
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long p = dq.list[i];
+    int idx[3];
+    idx[0] = (int)(p % g.mi[0]);
+    idx[1] = (int)((p / g.mi[0]) % g.mi[1]);
+    idx[2] = D == 3 ? (int)(p / ((long long)g.mi[0] * g.mi[1])) : 0;
+    AdjItem<D> it;
+    if (!adj_prepare<D, NS, MODE, false>(g, st, A, idx, it, nullptr)) continue;
+    if constexpr (PASS == 0) {
+      AdjBound<D, NS> acc{st.j0, st.th, 0.f};
+      adj_scatter<D, NS, false>(g, st, A.vp, it, acc, zmg);
+      atomicMax(reinterpret_cast<unsigned*>(dq.hdr + 1), __float_as_uint(acc.sabs));
+    } else {
+      AdjWide<D, NS> acc;
+      acc.acc = dq.acc;
+      acc.j0 = st.j0;
+      acc.th = st.th;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc.mv[a] = g.mv[a];
+      acc.nv = g.nv;
+      acc.e = e;
+      status |= adj_scatter<D, NS, false>(g, st, A.vp, it, acc, zmg);
+    }
+  }
+  if (status) atomicOr(flags, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -2163,7 +2490,8 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
                                                         const int* __restrict__ cs0, const int2* __restrict__ ce0,
                                                         const int* __restrict__ cs1, const int2* __restrict__ ce1,
                                                         const int* __restrict__ cs2, const int2* __restrict__ ce2,
-                                                        float* __restrict__ fb, float* __restrict__ out, RegTail rt) {
+                                                        float* __restrict__ fb, float* __restrict__ out, RegTail rt,
+                                                        Deferred dq) {
   if (halted(g.halt)) return;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < g.nv * fields;
@@ -2176,6 +2504,14 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
       fb[i] = 0.f;
     } else {
       t = out[i] + sum;
+    }
+    if (dq.hdr) {  // the deferred characteristics' 64-bit sums (uniform branch)
+      const int n = dq.hdr[0];
+      const float smax = __int_as_float(dq.hdr[1]);
+      if (n > 0 && smax > 0.f) {
+        t += (float)ldexp((double)(long long)dq.acc[i], -deferred_unit(n, smax));
+        dq.acc[i] = 0ull;
+      }
     }
     if constexpr (REG != 0) {
       val = reg_value<D, REG == 2>(g, rt.p, rt.scale, rt.gamma, rt.ih2, i);
@@ -2195,16 +2531,18 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
   }
 }
 
-int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt) {
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred) {
   const long long tot = P->geo.nv * P->fields;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
   const RegTail none;
   const RegTail& r = rt ? *rt : none;
+  Deferred dq{nullptr, nullptr, nullptr};
+  if (deferred) dq = Deferred{P->dfr_list, P->dfr_hdr, P->dfr_acc};
   const int reg = r.p ? (r.curv ? 2 : 1) : 0;
 #define LAG_REDUCE(DIM, K, RG)                                                                                   \
   hipLaunchKernelGGL((k_tile_reduce<DIM, K, RG>), dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields,  \
                      P->tile_part, P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1],       \
-                     P->cover_start[2], P->cover_ent[2], fb, out, r)
+                     P->cover_start[2], P->cover_ent[2], fb, out, r, dq)
 #define LAG_REDUCE_K(DIM, RG)          \
   do {                                 \
     if (P->cover_max <= 3)             \
@@ -2415,63 +2753,63 @@ int launch_jvp(lag_plan P, const void* vpack, const void* dpack, const float* T,
   return bin_and_gather(P->geo, plan_bins(P), out, s);
 }
 
+size_t adjoint_lds_bytes(lag_plan P) {
+  return sizeof(unsigned long long) * (size_t)P->fields * P->bricks.tvol + sizeof(float) * (512 / 64);
+}
+
+// Matrix-free adjoint product: the tile pass, then (when some characteristic
+// left its tile) the two passes over the deferred list, then the fixed-order
+// reduction of the tiles plus the deferred sums.  out must hold zeros (the
+// tile pass's float fallback adds into it).
+template <int D, bool NS, int MODE, bool ZERO>
+static int launch_adjoint_t(lag_plan P, const AdjArgs& A, const Stages& st, float* out, hipStream_t s, bool prof) {
+  const lag::Bricks& B = P->bricks;
+  const Deferred dq{P->dfr_list, P->dfr_hdr, P->dfr_acc};
+  int rc = launch_zero_i(P->dfr_hdr, 3, s);
+  if (rc) return rc;
+  const size_t lds = adjoint_lds_bytes(P);
+  if (prof) prof_begin(P, s);
+  hipLaunchKernelGGL((k_adjoint<D, NS, MODE, ZERO>), dim3(grid_for(B.nbricks)), dim3(AdjBlock<D, NS>::threads), lds, s,
+                     P->geo, st, B, A, out, P->tile_part, P->flags, dq);
+  if (prof) prof_end(P, s);
+  LAG_LAUNCH_CHECK();
+  if constexpr (!ZERO) {
+    const unsigned dgrid = (unsigned)std::min<long long>((P->geo.np + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL((k_adjoint_deferred<D, NS, MODE, 0>), dim3(dgrid), dim3(kBlock), 0, s, P->geo, st, A, dq,
+                       P->flags);
+    hipLaunchKernelGGL((k_adjoint_deferred<D, NS, MODE, 1>), dim3(dgrid), dim3(kBlock), 0, s, P->geo, st, A, dq,
+                       P->flags);
+    LAG_LAUNCH_CHECK();
+  }
+  return launch_tile_reduce(P, out, nullptr, s, nullptr, !ZERO);
+}
+
+template <int MODE, bool ZERO>
+static int launch_adjoint(lag_plan P, const AdjArgs& A, const Stages& st, float* out, hipStream_t s, bool prof) {
+  const bool ns = P->geo.nodes > 1;
+  if (P->geo.dim == 3)
+    return ns ? launch_adjoint_t<3, true, MODE, ZERO>(P, A, st, out, s, prof)
+              : launch_adjoint_t<3, false, MODE, ZERO>(P, A, st, out, s, prof);
+  return ns ? launch_adjoint_t<2, true, MODE, ZERO>(P, A, st, out, s, prof)
+            : launch_adjoint_t<2, false, MODE, ZERO>(P, A, st, out, s, prof);
+}
+
 int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, float* out, hipStream_t s,
                bool zero) {
   int rc = launch_fill(out, P->n_unknowns, 0.f, s);
   if (rc) return rc;
-  const int dir = model_dir(P);
-  Stages st = stages_for(P, dir);
-  const lag::Bricks& B = P->bricks;
-  unsigned grid = grid_for(B.nbricks);
-  size_t lds = sizeof(float) * (size_t)P->fields * B.tvol;
-  const bool ns = P->geo.nodes > 1;
-  const bool tr = P->prob.model == LAG_TRANSPORT;
-#define LAG_VJP(DD, NSV, MM, VT)                                                                       \
-  do {                                                                                                 \
-    if (zero)                                                                                          \
-      hipLaunchKernelGGL((k_vjp<DD, NSV, MM, true>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,  \
-                         (const VT*)nullptr, T, w, out, P->tile_part, P->flags);                       \
-    else                                                                                               \
-      hipLaunchKernelGGL((k_vjp<DD, NSV, MM, false>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B, \
-                         (const VT*)vpack, T, w, out, P->tile_part, P->flags);                         \
-  } while (0)
-  if (P->geo.dim == 3) {
-    if (ns) { if (tr) LAG_VJP(3, true, 0, float4); else LAG_VJP(3, true, 1, float4); }
-    else { if (tr) LAG_VJP(3, false, 0, float4); else LAG_VJP(3, false, 1, float4); }
-  } else {
-    if (ns) { if (tr) LAG_VJP(2, true, 0, float2); else LAG_VJP(2, true, 1, float2); }
-    else { if (tr) LAG_VJP(2, false, 0, float2); else LAG_VJP(2, false, 1, float2); }
-  }
-#undef LAG_VJP
-  LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, nullptr, s, nullptr);
+  const Stages st = stages_for(P, model_dir(P));
+  const AdjArgs A{zero ? nullptr : vpack, nullptr, T, w, nullptr};
+  if (P->prob.model == LAG_TRANSPORT)
+    return zero ? launch_adjoint<0, true>(P, A, st, out, s, false) : launch_adjoint<0, false>(P, A, st, out, s, false);
+  return zero ? launch_adjoint<1, true>(P, A, st, out, s, false) : launch_adjoint<1, false>(P, A, st, out, s, false);
 }
 
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T, const float* wvox,
                           float* out, hipStream_t s) {
-  Stages st = stages_for(P, -1);
-  const lag::Bricks& B = P->bricks;
-  unsigned grid = grid_for(B.nbricks);
-  size_t lds = sizeof(float) * (size_t)P->fields * B.tvol;
-  prof_begin(P, s);
-  if (P->geo.dim == 3) {
-    if (P->geo.nodes > 1)
-      hipLaunchKernelGGL((k_hess_transport<3, true>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->tile_part, P->flags);
-    else
-      hipLaunchKernelGGL((k_hess_transport<3, false>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float4*)vpack, (const float4*)ppack, T, wvox, out, P->tile_part, P->flags);
-  } else {
-    if (P->geo.nodes > 1)
-      hipLaunchKernelGGL((k_hess_transport<2, true>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->tile_part, P->flags);
-    else
-      hipLaunchKernelGGL((k_hess_transport<2, false>), dim3(grid), dim3(kBlock), lds, s, P->geo, st, B,
-                         (const float2*)vpack, (const float2*)ppack, T, wvox, out, P->tile_part, P->flags);
-  }
-  prof_end(P, s);
-  LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, nullptr, s, nullptr);
+  const Stages st = stages_for(P, -1);
+  const AdjArgs A{vpack, ppack, T, nullptr, wvox};
+  return launch_adjoint<2, false>(P, A, st, out, s, true);
 }
 
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s) {
