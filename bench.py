@@ -507,9 +507,9 @@ def warm_start_measurement(args, L, torch):
 def batch_pairs(npairs):
     """The batched-solve workload: pair j (seed 4000 + j); the first 80 % are
     2-D with sides drawn from {96, 128, 192, 256}, the rest 3-D with sides
-    from {64, 80, 96}; even j transport, odd j continuity; stationary
-    velocity on the grid with half the cells per axis; N = 5, diffusion
-    alpha = 1e-2."""
+    from {64, 80, 96}; even j transport (diffusion, alpha = 1e-2), odd j
+    continuity (curvature, alpha = 1e-3); stationary velocity on the grid
+    with half the cells per axis; N = 10."""
     rng = np.random.default_rng(4000)
     n2 = (npairs * 4) // 5
     out = []
@@ -525,25 +525,29 @@ def batch_pairs(npairs):
 
 def batch_measurement(args, L, torch):
     """Wall time of solving the batch one pair after another (one stream,
-    host-driven PCG, one plan per distinct problem) against lag_batch_solve
-    (worker streams, PCG replayed as captured graphs, autotuned bricks)."""
+    host-driven PCG, one plan per distinct problem), on worker streams
+    (lag_batch_solve: PCG replayed as captured graphs per pair, autotuned
+    bricks) and in lockstep with the PCG iterations of all pairs in one
+    captured graph (lag_batch_solve_graph, the same autotuned bricks)."""
     from synthetic import blob_image, fourier_velocity
     specs = batch_pairs(args.batch_pairs)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda()  # noqa: E731
     probs, Ts, Rs = [], [], []
     for dim, img, vel, model, seed in specs:
-        prob = L.make_problem(dim, img, vel, model=model, nsteps=5, alpha=1e-2,
-                              jac_blocks=8 if model == "transport" else 0)
+        tr = model == "transport"
+        prob = L.make_problem(dim, img, vel, model=model, nsteps=10, reg="diffusion" if tr else "curvature",
+                              alpha=1e-2 if tr else 1e-3, jac_blocks=8 if tr else 0)
         plan = L.Plan(prob)
-        T = dev(blob_image(img, 8 if dim == 2 else 24, seed, density=(model == "continuity")))
+        T = dev(blob_image(img, 8 if dim == 2 else 24, seed, density=not tr))
         phi = torch.empty(dim * plan.n_points, device="cuda")
         R = torch.empty(plan.n_points, device="cuda")
-        L.lag_trace(plan, dev(fourier_velocity(vel, 4, 0.05, seed + 1)), -1 if model == "transport" else 1, phi)
-        (L.lag_transport if model == "transport" else L.lag_pushforward)(plan, T, phi, R)
+        L.lag_trace(plan, dev(fourier_velocity(vel, 4, 0.05, seed + 1)), -1 if tr else 1, phi)
+        (L.lag_transport if tr else L.lag_pushforward)(plan, T, phi, R)
         plan.close()
         probs.append(prob), Ts.append(T), Rs.append(R)
+    max_gn, pcg_maxit = 50, 30
     opts = L.lag_gn_default_options()
-    opts.pcg_maxit, opts.max_gn = 30, 20
+    opts.pcg_maxit, opts.max_gn = pcg_maxit, max_gn
     # sequential reference (plans cached per distinct problem, created before timing)
     plans, key = {}, lambda p: bytes(p)  # noqa: E731
     for p in probs:
@@ -557,38 +561,52 @@ def batch_measurement(args, L, torch):
     t_seq = time.perf_counter() - t0
     for pl in plans.values():
         pl.close()
-    # autotuning (one-time cost per distinct problem), then the batch
+    log(args, f"batch: sequential {t_seq:.2f} s, {sum(i['converged'] for i in seq)} of {len(seq)} converged")
+    # autotuning (one-time cost per distinct problem)
     t0 = time.perf_counter()
     kinds = {}
     for p in probs:
         if key(p) not in kinds:
             kinds[key(p)] = L.lag_autotune_bricks(p)
     t_tune = time.perf_counter() - t0
+    bricks = [kinds[key(p)][0] for p in probs]
     bo = L.lag_gn_default_options()
-    bo.pcg_maxit, bo.max_gn, bo.graph_iters = 30, 20, 4
-    vb = [torch.zeros_like(v) for v in vs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos, st = L.lag_batch_solve(probs, Ts, Rs, vb, bo, workers=args.batch_workers,
-                                  bricks=[kinds[key(p)][0] for p in probs])
-    torch.cuda.synchronize()
-    t_batch_net = time.perf_counter() - t0
-    t_batch = t_batch_net + t_tune
+    bo.pcg_maxit, bo.max_gn, bo.graph_iters = pcg_maxit, max_gn, 4
+    runs = {}
+    for name, workers in (("workers", args.batch_workers), ("graph", 0)):
+        vb = [torch.zeros_like(v) for v in vs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, st = L.lag_batch_solve(probs, Ts, Rs, vb, bo, workers=workers, bricks=bricks)
+        torch.cuda.synchronize()
+        runs[name] = (time.perf_counter() - t0, infos, st)
+        log(args, f"batch {name}: {runs[name][0]:.2f} s, {sum(i['converged'] for i in infos)} converged")
+    t_graph, infos, st = runs["graph"]
+    t_work, infos_w, _ = runs["workers"]
     n2 = sum(1 for s_ in specs if s_[0] == 2)
-    log(args, f"batch: {len(specs)} pairs, sequential {t_seq:.2f} s, batched {t_batch:.2f} s "
-              f"(incl. {t_tune:.2f} s autotuning)")
+    cont = [i for i, s_ in enumerate(specs) if s_[3] == "continuity"]
     return {
         "metric": "batched Gauss-Newton solves of uneven pairs, pairs/s",
+        "path": "lag_batch_solve_graph: one host thread, all pairs in lockstep, the PCG iterations of all "
+                "pairs replayed as one captured HIP graph",
         "pairs": len(specs), "pairs_2d": n2, "pairs_3d": len(specs) - n2,
-        "sequential_s": round(t_seq, 3), "batched_s": round(t_batch_net, 3), "autotune_s": round(t_tune, 3),
+        "recipe": "N=10; transport: diffusion alpha=1e-2; continuity: curvature alpha=1e-3; gtol 1e-2, "
+                  f"max_gn {max_gn}, pcg_maxit {pcg_maxit}, pcg_tol 0.1",
+        "sequential_s": round(t_seq, 3), "batched_s": round(t_graph, 3), "workers_s": round(t_work, 3),
+        "autotune_s": round(t_tune, 3),
         "sequential_pairs_per_s": round(len(specs) / t_seq, 2),
-        "batched_pairs_per_s": round(len(specs) / t_batch_net, 2),
-        "speedup": round(t_seq / t_batch_net, 3),
+        "batched_pairs_per_s": round(len(specs) / t_graph, 2),
+        "workers_pairs_per_s": round(len(specs) / t_work, 2),
+        "speedup": round(t_seq / t_graph, 3),
         "workers": args.batch_workers, "graph_iters": 4,
         "converged_sequential": int(sum(i["converged"] for i in seq)),
         "converged_batched": int(sum(i["converged"] for i in infos)),
+        "converged_workers": int(sum(i["converged"] for i in infos_w)),
+        "converged_continuity_batched": int(sum(infos[i]["converged"] for i in cont)),
+        "line_search_failures_batched": int(sum(1 for x in st if x == L.LAG_ELINESEARCH)),
         "gn_iters_sequential": int(sum(i["iters"] for i in seq)),
         "gn_iters_batched": int(sum(i["iters"] for i in infos)),
+        "worst_grad_ratio_batched": round(max(i["gnorm"] / i["g0"] for i in infos if i["g0"] > 0), 4),
         "bricks": {f"{p.dim}d {list(p.img_m)[:p.dim]} {'transport' if p.model == 0 else 'continuity'}": kinds[key(p)][0]
                    for p in probs},
     }

@@ -488,6 +488,25 @@ int lag_batch_solve(int32_t npairs, const lag_problem* probs, const float* const
                     float* const* v, const lag_gn_options* opt, int32_t workers, const int32_t* bricks,
                     int32_t autotune, lag_gn_info* infos, int32_t* status);
 
+/* The batch in lockstep from one host thread, with the PCG iterations of all
+ * pairs in one captured HIP graph.  Every pair has its own plan (brick
+ * shape from `bricks`, host npairs x 3, or the default if NULL).  Each
+ * Gauss-Newton iteration (Sec. 3.2, as lag_gn_step) takes the gradients of
+ * all running pairs on four HIP streams, starts their PCG solves, replays
+ * the batch graph (opt->graph_iters PCG iterations of every pair per
+ * replay, 4 if 0) until every pair's device-side stopping test has halted
+ * it, then runs the Armijo line search of all pairs round by round (one
+ * synchronisation per halving round).  A pair that has stopped keeps its
+ * place in the graph with its PCG halted (its kernels return at entry).
+ * The graph is captured again only when some running pair changes its
+ * operator (assembled or matrix-free) or its Jacobian storage grows.  The
+ * stopping test and its reference |g(v = 0)| are those of lag_gn_solve;
+ * infos (host, npairs, may be NULL) and status (host, npairs: LAG_OK or
+ * LAG_ELINESEARCH) as in lag_batch_solve.  Allocating and synchronising. */
+int lag_batch_solve_graph(int32_t npairs, const lag_problem* probs, const float* const* T, const float* const* R,
+                          float* const* v, const lag_gn_options* opt, const int32_t* bricks, lag_gn_info* infos,
+                          int32_t* status);
+
 /* ---- learned warm start: a 3-D U-Net on the MFMA units --------------------
  * Maps the template and reference, resampled to a cubic grid of side `size`
  * (the velocity grid), to a stationary velocity [3][size^3] that starts the

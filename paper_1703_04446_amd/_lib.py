@@ -98,6 +98,10 @@ _SIGS = {
                              ctypes.POINTER(_P), ctypes.POINTER(LagGnOptions), ctypes.c_int32,
                              ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(LagGnInfo),
                              ctypes.POINTER(ctypes.c_int32)]),
+    "lag_batch_solve_graph": (_I, [ctypes.c_int32, ctypes.POINTER(LagProblem), ctypes.POINTER(_P),
+                                   ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(LagGnOptions),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(LagGnInfo),
+                                   ctypes.POINTER(ctypes.c_int32)]),
     "lag_plan_destroy": (_I, [_P]),
     "lag_plan_problem": (_I, [_P, ctypes.POINTER(LagProblem)]),
     "lag_plan_flags": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _P]),
@@ -641,7 +645,9 @@ def lag_autotune_bricks(prob):
 
 def lag_batch_solve(probs, Ts, Rs, vs, options=None, workers=4, autotune=True, bricks=None):
     """Solve len(probs) independent problems; returns (infos, statuses).
-    ``bricks``: per pair a 3-list of brick targets (overrides autotune)."""
+    ``bricks``: per pair a 3-list of brick targets (overrides autotune).
+    ``workers=0`` calls lag_batch_solve_graph (lockstep, the PCG iterations of
+    all pairs in one captured graph; autotune is then ignored)."""
     n = len(probs)
     if not (len(Ts) == len(Rs) == len(vs) == n):
         raise ValueError("probs, Ts, Rs and vs must have the same length")
@@ -664,10 +670,13 @@ def lag_batch_solve(probs, Ts, Rs, vs, options=None, workers=4, autotune=True, b
         if len(flat) != 3 * n:
             raise ValueError("bricks: one 3-list per pair")
         bp = (ctypes.c_int32 * (3 * n))(*flat)
-    rc = load().lag_batch_solve(n, arr, T, R, V, ctypes.byref(o), int(workers), bp, int(bool(autotune)), infos,
-                                st)
+    if workers == 0:   # lockstep, PCG of all pairs in one captured graph
+        rc = load().lag_batch_solve_graph(n, arr, T, R, V, ctypes.byref(o), bp, infos, st)
+    else:
+        rc = load().lag_batch_solve(n, arr, T, R, V, ctypes.byref(o), int(workers), bp, int(bool(autotune)),
+                                    infos, st)
     if rc not in (LAG_OK, LAG_ELINESEARCH):
-        _check("lag_batch_solve", rc)
+        _check("lag_batch_solve_graph" if workers == 0 else "lag_batch_solve", rc)
     out = []
     for i in range(n):
         d = {f: getattr(infos[i], f) for f, _ in LagGnInfo._fields_}

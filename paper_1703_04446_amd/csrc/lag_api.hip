@@ -1305,3 +1305,415 @@ int lag_gn_solve(lag_plan P, const float* T, const float* R, float* v, const lag
 }
 
 }  // extern "C"
+
+// ---- many pairs in lockstep, PCG of the whole batch as one graph ----------
+
+namespace lag {
+
+// Word 0 (the halt flag) of many plans' PCG control blocks, gathered.
+__global__ void k_gather_ctl(const int* const* ctl, int n, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ctl[i][0];
+}
+
+// Halt a plan's PCG: its iterations in a replayed graph return at entry.
+__global__ void k_halt_ctl(int* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl[0] = 3;
+}
+
+}  // namespace lag
+
+namespace {
+
+constexpr int kBatchStreams = 4;  // hardware queues HIP gives one process
+
+// The Gauss-Newton operator of one pair, assembled or matrix-free.
+struct BatchOp {
+  lag_plan P;
+  const float* v;
+  const float* T;
+  int assembled;
+  int operator()(const float* p, float* Hp, hipStream_t s, double* part) const {
+    return assembled ? hessmat_assembled(P, nullptr, p, Hp, part, s) : hessmat_free(P, v, T, nullptr, p, Hp, part, s);
+  }
+};
+
+struct BatchPair {
+  lag_plan P = nullptr;
+  int active = 1;
+  int in_graph = 0;      // has iterations in the current batch graph
+  int stored = 0;        // this step's gradient and operator use the assembled Jacobian
+  int graph_mode = -1;   // operator captured in the batch graph (-1: none)
+  int graph_gen = -1;    // Jacobian storage generation captured
+  int gen = 0;           // bumped when the Jacobian storage is reallocated
+  bool from_zero = true;
+  double gstop = 0.0, slope = 0.0, mu = 1.0;
+  int status = LAG_OK;
+  lag_gn_info info{};
+};
+
+}  // namespace
+
+extern "C" {
+
+int lag_batch_solve_graph(int32_t npairs, const lag_problem* probs, const float* const* T, const float* const* R,
+                          float* const* v, const lag_gn_options* opt, const int32_t* bricks, lag_gn_info* infos,
+                          int32_t* status) {
+  if (npairs < 0 || (npairs > 0 && (!probs || !T || !R || !v || !status))) return LAG_EINVAL;
+  lag_gn_options o;
+  lag_gn_default_options(&o);
+  if (opt) o = *opt;
+  if (o.max_gn < 0 || o.pcg_maxit < 0 || o.max_halvings < 0 || o.gtol < 0.0 || o.graph_iters < 0 ||
+      o.graph_iters > 64)
+    return LAG_EINVAL;
+  for (int i = 0; i < npairs; ++i) {
+    const int rc = lag_problem_check(&probs[i]);
+    if (rc) return rc;
+    if (!T[i] || !R[i] || !v[i]) return LAG_EINVAL;
+    status[i] = LAG_OK;
+  }
+  if (npairs == 0) return LAG_OK;
+  constexpr int kSc = 24;  // host copy of scalars 0..23 per pair
+  const int per_graph = o.graph_iters > 0 ? o.graph_iters : 4;
+  std::vector<BatchPair> pr(npairs);
+  hipStream_t es[kBatchStreams] = {};
+  hipEvent_t ev_es[kBatchStreams] = {};
+  hipStream_t s0 = nullptr;
+  hipEvent_t ev0 = nullptr, ev_state[2] = {nullptr, nullptr};
+  int** d_ctl = nullptr;
+  int* d_state = nullptr;
+  int* h_state = nullptr;   // pinned, 2 x npairs halt flags
+  double* h_sc = nullptr;   // pinned, kSc per pair
+  int* h_ctl = nullptr;     // pinned, 4 per pair (PCG control block)
+  int* h_mx = nullptr;      // pinned, 2 per pair (longest row, blocks stored)
+  hipGraphExec_t exec = nullptr;
+  int ng = 0;                    // pairs in the current graph
+  int captures = 0, replays = 0;
+  auto cleanup = [&]() {
+    if (s0) (void)hipStreamSynchronize(s0);
+    for (hipStream_t s : es)
+      if (s) (void)hipStreamSynchronize(s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (auto& p : pr)
+      if (p.P) lag_plan_destroy(p.P);
+    for (int k = 0; k < kBatchStreams; ++k) {
+      if (es[k]) (void)hipStreamDestroy(es[k]);
+      if (ev_es[k]) (void)hipEventDestroy(ev_es[k]);
+    }
+    if (s0) (void)hipStreamDestroy(s0);
+    for (hipEvent_t e : {ev0, ev_state[0], ev_state[1]})
+      if (e) (void)hipEventDestroy(e);
+    for (void* q : {(void*)d_ctl, (void*)d_state})
+      if (q) (void)hipFree(q);
+    for (void* q : {(void*)h_state, (void*)h_sc, (void*)h_ctl, (void*)h_mx})
+      if (q) (void)hipHostFree(q);
+  };
+  auto fail = [&](int rc) {
+    const std::string msg = lag_last_hip_error();
+    cleanup();
+    if (!msg.empty()) set_hip_error_text(msg.c_str());
+    return rc;
+  };
+#define BTRY(expr)               \
+  do {                           \
+    const int _r = (expr);       \
+    if (_r) return fail(_r);     \
+  } while (0)
+#define BHIP(call)                                          \
+  do {                                                      \
+    const hipError_t _e = (call);                           \
+    if (_e != hipSuccess) return fail(set_hip_error(_e));   \
+  } while (0)
+  for (int i = 0; i < npairs; ++i) {
+    BTRY(lag_plan_create_tuned(&probs[i], bricks ? bricks + 3 * i : nullptr, &pr[i].P));
+    BTRY(ensure_pcg_ctl(pr[i].P));
+  }
+  for (int k = 0; k < kBatchStreams; ++k) {
+    BHIP(hipStreamCreateWithFlags(&es[k], hipStreamNonBlocking));
+    BHIP(hipEventCreateWithFlags(&ev_es[k], hipEventDisableTiming));
+  }
+  BHIP(hipStreamCreateWithFlags(&s0, hipStreamNonBlocking));
+  BHIP(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
+  for (auto& e : ev_state) BHIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  BHIP(hipMalloc((void**)&d_ctl, sizeof(int*) * npairs));
+  BHIP(hipMalloc((void**)&d_state, sizeof(int) * npairs));
+  BHIP(hipHostMalloc((void**)&h_state, sizeof(int) * 2 * npairs, hipHostMallocDefault));
+  BHIP(hipHostMalloc((void**)&h_sc, sizeof(double) * kSc * npairs, hipHostMallocDefault));
+  BHIP(hipHostMalloc((void**)&h_ctl, sizeof(int) * 4 * npairs, hipHostMallocDefault));
+  BHIP(hipHostMalloc((void**)&h_mx, sizeof(int) * 2 * npairs, hipHostMallocDefault));
+  {
+    std::vector<int*> ctl(npairs);
+    for (int i = 0; i < npairs; ++i) ctl[i] = pr[i].P->ctl;
+    BHIP(hipMemcpy(d_ctl, ctl.data(), sizeof(int*) * npairs, hipMemcpyHostToDevice));
+  }
+  auto st = [&](int i) { return es[i % kBatchStreams]; };
+  auto sync_all = [&]() -> int {
+    for (hipStream_t s : es) LAG_HIP(hipStreamSynchronize(s));
+    return LAG_OK;
+  };
+  auto sc = [&](int i, int k) { return h_sc[(size_t)kSc * i + k]; };
+  auto copy_sc = [&](int i, int off, int cnt) -> int {
+    LAG_HIP(hipMemcpyAsync(h_sc + (size_t)kSc * i + off, pr[i].P->scalars + off, sizeof(double) * cnt,
+                           hipMemcpyDeviceToHost, st(i)));
+    return LAG_OK;
+  };
+  // gradient of pair i at v[i] into vec[0]; J, D, S and |g|^2 into scalars 8..11
+  auto gradient = [&](int i, bool assembled) -> int {
+    lag_plan P = pr[i].P;
+    hipStream_t s = st(i);
+    int r;
+    if (assembled) {
+      if ((r = jacobian_assemble_launch(P, v[i], T[i], P->img_a, s))) return r;
+      if ((r = gradient_assembled(P, v[i], T[i], R[i], P->img_a, P->vec[0], P->scalars + 8, s))) return r;
+      LAG_HIP(hipMemcpyAsync(h_mx + 2 * i, P->jac_max, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    } else if ((r = lag_gradient(P, v[i], T[i], R[i], P->vec[0], P->scalars + 8, s))) {
+      return r;
+    }
+    if ((r = launch_dot(P, P->n_unknowns, P->vec[0], P->vec[0], P->scalars + 11, s))) return r;
+    return copy_sc(i, 8, 4);
+  };
+  // objective of pair i at v + mu dv (into vec[7]), J into scalar 13
+  auto trial = [&](int i, double mu) -> int {
+    lag_plan P = pr[i].P;
+    hipStream_t s = st(i);
+    int r;
+    if ((r = launch_axpby(P->n_unknowns, 1.f, v[i], (float)mu, P->vec[2], P->vec[7], s))) return r;
+    if ((r = objective_full(P, P->vec[7], T[i], R[i], nullptr, nullptr, P->scalars + 13, s))) return r;
+    return copy_sc(i, 12, 2);
+  };
+
+  // reference gradient norm: |g(v = 0)| for a start away from zero, else
+  // the first gradient's (as lag_gn_solve)
+  for (int i = 0; i < npairs; ++i) {
+    lag_plan P = pr[i].P;
+    BTRY(launch_dot(P, P->n_unknowns, v[i], v[i], P->scalars + 16, st(i)));
+    BTRY(copy_sc(i, 16, 1));
+  }
+  BTRY(sync_all());
+  bool any_start = false;
+  for (int i = 0; i < npairs; ++i) {
+    pr[i].from_zero = sc(i, 16) == 0.0;
+    if (pr[i].from_zero) continue;
+    any_start = true;
+    lag_plan P = pr[i].P;
+    BTRY(gradient_at_zero(P, T[i], R[i], P->vec[0], P->scalars + 8, st(i)));
+    BTRY(launch_dot(P, P->n_unknowns, P->vec[0], P->vec[0], P->scalars + 11, st(i)));
+    BTRY(copy_sc(i, 8, 4));
+  }
+  if (any_start) BTRY(sync_all());
+  for (int i = 0; i < npairs; ++i)
+    if (!pr[i].from_zero) {
+      pr[i].info.g0 = sqrt(sc(i, 11));
+      pr[i].gstop = o.gtol * pr[i].info.g0;
+    }
+
+  for (int it = 0; it <= o.max_gn; ++it) {
+    // ---- gradients (assembled where the plan stores J), all pairs at once
+    int nact = 0;
+    for (int i = 0; i < npairs; ++i)
+      if (pr[i].active) BTRY(gradient(i, pr[i].P->jac_k > 0));
+    BTRY(sync_all());
+    for (int i = 0; i < npairs; ++i) {
+      BatchPair& b = pr[i];
+      if (!b.active) continue;
+      lag_plan P = b.P;
+      b.stored = 0;
+      if (P->jac_k > 0) {
+        b.stored = jacobian_assembled(P, h_mx + 2 * i);
+        if (!b.stored) {  // over capacity: grow once and assemble again, else matrix-free
+          if (jacobian_grow(P, h_mx[2 * i])) {
+            ++b.gen;
+            BTRY(gradient(i, true));
+            BTRY(sync_all());
+            b.stored = jacobian_assembled(P, h_mx + 2 * i);
+          }
+          if (!b.stored) {
+            BTRY(gradient(i, false));
+            BTRY(sync_all());
+          }
+        }
+      }
+      const double J = sc(i, 8), gn = sqrt(sc(i, 11));
+      if (it == 0) {
+        b.info.J0 = J;
+        if (b.from_zero) {
+          b.info.g0 = gn;
+          b.gstop = o.gtol * gn;
+        }
+      }
+      b.info.J = J;
+      b.info.gnorm = gn;
+      if (gn <= b.gstop) {
+        b.info.converged = 1;
+        b.active = 0;
+      } else if (it == o.max_gn) {
+        b.active = 0;
+      } else {
+        ++nact;
+      }
+    }
+    if (nact == 0) break;
+
+    // ---- PCG: starts on the pairs' streams, iterations in one graph
+    for (int i = 0; i < npairs; ++i) {
+      BatchPair& b = pr[i];
+      lag_plan P = b.P;
+      if (!b.active) {
+        if (b.in_graph) {
+          hipLaunchKernelGGL(lag::k_halt_ctl, dim3(1), dim3(64), 0, st(i), P->ctl);
+          BHIP(hipGetLastError());
+        }
+        continue;
+      }
+      BTRY(launch_axpby(P->n_unknowns, -1.f, P->vec[0], 0.f, nullptr, P->vec[1], st(i)));
+      PcgExtra ex;
+      ex.bb = sc(i, 11);  // rhs = -g: rhs . rhs = g . g
+      double nb = 0.0;
+      BTRY(pcg_start(P, P->vec[1], P->vec[2], o.pcg_tol, o.pcg_maxit, &nb, st(i), &ex));
+    }
+    // the graph holds the pairs running when it was captured; it is captured
+    // again when a running pair changes its operator or storage, or once
+    // half of the pairs in it have stopped (their halted iterations still
+    // cost a dispatch each)
+    int in_graph = 0;
+    bool same = exec != nullptr;
+    for (int i = 0; i < npairs; ++i) {
+      in_graph += pr[i].in_graph;
+      if (pr[i].active)
+        same = same && pr[i].in_graph && pr[i].graph_mode == pr[i].stored && pr[i].graph_gen == pr[i].gen;
+    }
+    same = same && 2 * nact > in_graph;
+    if (!same) {
+      // capture the running pairs' `per_graph` PCG iterations, the k-th
+      // of them on branch k mod kBatchStreams
+      BTRY(sync_all());
+      std::lock_guard<std::mutex> lk(api_lock());
+      if (exec) {
+        (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+      }
+      BHIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+      int crc = hipEventRecord(ev0, s0) == hipSuccess ? LAG_OK : LAG_EHIP;
+      for (int k = 0; k < kBatchStreams && crc == LAG_OK; ++k)
+        if (hipStreamWaitEvent(es[k], ev0, 0) != hipSuccess) crc = LAG_EHIP;
+      std::vector<int*> ctl;
+      for (int i = 0; i < npairs && crc == LAG_OK; ++i) {
+        BatchPair& b = pr[i];
+        b.in_graph = b.active;
+        if (!b.active) continue;
+        lag_plan P = b.P;
+        b.graph_mode = b.stored;
+        b.graph_gen = b.gen;
+        BatchOp H{P, v[i], T[i], b.graph_mode == 1};
+        const hipStream_t br = es[ctl.size() % kBatchStreams];
+        ctl.push_back(P->ctl);
+        P->geo.halt = P->ctl;
+        P->capturing = 1;
+        for (int u = 0; u < per_graph && crc == LAG_OK; ++u) crc = pcg_iteration(P, H, P->vec[2], br);
+        P->geo.halt = nullptr;
+        P->capturing = 0;
+      }
+      ng = (int)ctl.size();
+      for (int k = 0; k < kBatchStreams && crc == LAG_OK; ++k)
+        if (hipEventRecord(ev_es[k], es[k]) != hipSuccess || hipStreamWaitEvent(s0, ev_es[k], 0) != hipSuccess)
+          crc = LAG_EHIP;
+      hipGraph_t graph = nullptr;
+      const hipError_t ce = hipStreamEndCapture(s0, &graph);
+      if (crc != LAG_OK || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(crc != LAG_OK ? crc : set_hip_error(ce));
+      }
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        exec = nullptr;
+        return fail(set_hip_error(ie));
+      }
+      BHIP(hipMemcpy(d_ctl, ctl.data(), sizeof(int*) * ng, hipMemcpyHostToDevice));
+      ++captures;
+    }
+    // the starts must be done before the graph runs
+    for (int k = 0; k < kBatchStreams; ++k) {
+      BHIP(hipEventRecord(ev_es[k], es[k]));
+      BHIP(hipStreamWaitEvent(s0, ev_es[k], 0));
+    }
+    // replay until every pair's PCG has stopped; as in pcg_graph_impl the
+    // flags of replay l are read after replay l + 1 is enqueued
+    const int launches = (o.pcg_maxit + per_graph - 1) / per_graph;
+    for (int l = 0; l < launches; ++l) {
+      const int slot = l & 1;
+      BHIP(hipGraphLaunch(exec, s0));
+      hipLaunchKernelGGL(lag::k_gather_ctl, dim3((ng + 255) / 256), dim3(256), 0, s0, d_ctl, ng, d_state);
+      BHIP(hipGetLastError());
+      BHIP(hipMemcpyAsync(h_state + slot * npairs, d_state, sizeof(int) * ng, hipMemcpyDeviceToHost, s0));
+      BHIP(hipEventRecord(ev_state[slot], s0));
+      ++replays;
+      if (l > 0) {
+        BHIP(hipEventSynchronize(ev_state[slot ^ 1]));
+        bool all = true;
+        for (int k = 0; k < ng && all; ++k) all = h_state[(slot ^ 1) * npairs + k] != 0;
+        if (all) break;
+      }
+    }
+    BHIP(hipEventRecord(ev0, s0));
+    for (int k = 0; k < kBatchStreams; ++k) BHIP(hipStreamWaitEvent(es[k], ev0, 0));
+
+    // ---- PCG results, slope g . dv and the first trial (mu = 1)
+    for (int i = 0; i < npairs; ++i) {
+      BatchPair& b = pr[i];
+      if (!b.active) continue;
+      lag_plan P = b.P;
+      BHIP(hipMemcpyAsync(h_ctl + 4 * i, P->ctl, sizeof(int) * 4, hipMemcpyDeviceToHost, st(i)));
+      BTRY(launch_dot(P, P->n_unknowns, P->vec[0], P->vec[2], P->scalars + 12, st(i)));
+      b.mu = 1.0;
+      BTRY(trial(i, 1.0));
+    }
+    BTRY(sync_all());
+    std::vector<int> pending;
+    for (int i = 0; i < npairs; ++i) {
+      BatchPair& b = pr[i];
+      if (!b.active) continue;
+      const int iters = h_ctl[4 * i + 1];
+      b.info.iters += 1;
+      b.info.pcg_iters += iters;
+      b.info.matvecs += iters + (h_ctl[4 * i] == 2 ? 1 : 0);
+      b.slope = sc(i, 12);
+      pending.push_back(i);
+    }
+    // ---- Armijo backtracking by halving, all pending pairs per round
+    for (int k = 0;; ++k) {
+      std::vector<int> next;
+      for (int i : pending) {
+        BatchPair& b = pr[i];
+        const double Jt = sc(i, 13);
+        if (Jt <= b.info.J + o.armijo_c1 * b.mu * b.slope) {
+          b.info.J = Jt;
+          BTRY(launch_axpby(b.P->n_unknowns, 1.f, b.P->vec[7], 0.f, nullptr, v[i], st(i)));
+        } else if (k < o.max_halvings) {
+          b.mu *= 0.5;
+          next.push_back(i);
+        } else {
+          b.status = LAG_ELINESEARCH;
+          b.active = 0;
+        }
+      }
+      if (next.empty()) break;
+      for (int i : next) BTRY(trial(i, pr[i].mu));
+      BTRY(sync_all());
+      pending.swap(next);
+    }
+  }
+  BTRY(sync_all());
+#undef BTRY
+#undef BHIP
+  (void)captures;
+  (void)replays;
+  for (int i = 0; i < npairs; ++i) {
+    status[i] = pr[i].status;
+    if (infos) infos[i] = pr[i].info;
+  }
+  cleanup();
+  return LAG_OK;
+}
+
+}  // extern "C"

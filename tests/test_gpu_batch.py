@@ -3,14 +3,14 @@ brick-shape autotuner.
 
 Per pair, the batch must honour the solve's contract: a pair reported as
 converged meets |g| <= gtol |g(v = 0)|, and the oracle's objective at the
-batch's solution equals the GPU's (iterate-wise parity, 1e-5).  Transport
-pairs use the assembled operator, which is deterministic: without
-autotuning they reproduce the sequential solve (same iterations, same
-solution to 1e-6); with autotuned bricks only the order of sums changes
-(objective to 1e-4).  The matrix-free continuity solves sum with float
-atomics and their Gauss-Newton path is not reproducible from run to run
-(measured: 6, 12 and 18 iterations for one pair), so for them only the
-contract is checked.
+batch's solution equals the GPU's (iterate-wise parity, 1e-5).  Every
+operator sums in integer fixed point with fixed reduction orders (the
+assembled transport products and the matrix-free continuity ones alike),
+so a batch with the default bricks reproduces the sequential solve of each
+pair bit for bit: the same iterations and the same solution, whether the
+batch runs on worker streams or in lockstep with the PCG iterations of all
+pairs in one captured graph.  With autotuned bricks only the order of sums
+changes (objective to 1e-4).
 """
 
 import numpy as np
@@ -106,12 +106,46 @@ def test_batch_solve(autotune, torch, L):
         if ib["converged"]:
             assert ib["gnorm"] <= bo.gtol * ib["g0"] * (1 + 1e-12)
         assert abs(Jo - ib["J"]) <= 1e-5 * abs(Jo)
-        if spec[2] == "transport":
-            assert ib["converged"] == i1["converged"]
-            if autotune:
+        if autotune:
+            if spec[2] == "transport":
+                assert ib["converged"] == i1["converged"]
                 assert abs(ib["J"] - i1["J"]) <= 1e-4 * abs(i1["J"])
-            else:
-                assert ib["iters"] == i1["iters"] and e <= 1e-6
+        else:
+            assert ib["iters"] == i1["iters"] and ib["pcg_iters"] == i1["pcg_iters"]
+            assert torch.equal(vb, v1), (spec, e)
+
+
+@pytest.mark.parametrize("per_graph", [3, 4])
+def test_batch_solve_graph(per_graph, torch, L):
+    """Lockstep batch, PCG of all pairs in one graph: each pair's solve is
+    the sequential one, bit for bit, whatever the replay length."""
+    pairs = [make_pair(torch, L, *p) for p in PAIRS]
+    opts = L.lag_gn_default_options()
+    opts.pcg_maxit, opts.max_gn = 30, 20
+    seq = sequential(torch, L, pairs, opts)
+    bo = L.lag_gn_default_options()
+    bo.pcg_maxit, bo.max_gn, bo.graph_iters = 30, 20, per_graph
+    vs = [torch.zeros_like(v) for _, v in seq]
+    infos, st = L.lag_batch_solve([p[0] for p in pairs], [p[1] for p in pairs], [p[2] for p in pairs], vs,
+                                  bo, workers=0)
+    assert all(x in (L.LAG_OK, L.LAG_ELINESEARCH) for x in st), st
+    for spec, (prob, T, R), (i1, v1), ib, vb in zip(PAIRS, pairs, seq, infos, vs):
+        print(spec, "seq", i1["iters"], i1["pcg_iters"], "%.6e" % i1["J"], i1["converged"],
+              "graph batch", ib["iters"], ib["pcg_iters"], "%.6e" % ib["J"], ib["converged"], flush=True)
+        for key in ("iters", "pcg_iters", "matvecs", "converged"):
+            assert ib[key] == i1[key], (spec, key)
+        assert ib["J"] == i1["J"] and ib["gnorm"] == i1["gnorm"] and ib["g0"] == i1["g0"]
+        assert torch.equal(vb, v1), spec
+    # a start away from zero takes its reference from |g(v = 0)|, as lag_gn_solve
+    prob, T, R = pairs[0]
+    plan = L.Plan(prob)
+    v0 = 0.5 * seq[0][1]
+    va = v0.clone()
+    ia = L.lag_gn_solve(plan, T, R, va, opts)
+    plan.close()
+    vb = [v0.clone()]
+    ib, st = L.lag_batch_solve([prob], [T], [R], vb, bo, workers=0)
+    assert ib[0]["g0"] == ia["g0"] and ib[0]["iters"] == ia["iters"] and torch.equal(vb[0], va)
 
 
 def test_autotuned_plan_matches_default(torch, L):

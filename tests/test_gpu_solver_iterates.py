@@ -122,9 +122,11 @@ def test_gn_iterates_match_oracle(spec, torch, L):
         # at convergence g is the small difference of its data term and its
         # regulariser term, so each term is compared on its own, and the sum
         # relative to the data term
-        gdata_o = g_o - O.regularizer_apply(OP, vk)
+        reg_o = np.asarray(O.regularizer_apply(OP, vk)).ravel()
+        g_o = np.asarray(g_o).ravel()
+        gdata_o = g_o - reg_o
         eg_data = relerr(dev.get(gd), gdata_o)
-        eg_reg = relerr(dev.get(reg), O.regularizer_apply(OP, vk)) if case.alpha > 0 else 0.0
+        eg_reg = relerr(dev.get(reg), reg_o) if case.alpha > 0 else 0.0
         gsum = dev.get(gd) + dev.get(reg)
         eg = float(np.abs(gsum - g_o).max() / np.abs(gdata_o).max())
         eH = relerr(dev.get(Hp), H_o)
