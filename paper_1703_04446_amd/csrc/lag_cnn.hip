@@ -60,135 +60,368 @@ __device__ __forceinline__ int nbr(int v, int s, int dz, int dy, int dx) {
 }
 
 // ---------------------------------------------------------------------------
-// forward convolution: one wave computes 64 voxels x (16*NT) output channels
-template <int NT>
-__global__ void __launch_bounds__(256) k_conv_fwd(const unsigned short* __restrict__ in, int in_cs, int in_co,
-                                                  int cin, int s, const unsigned short* __restrict__ wf,
-                                                  const float* __restrict__ bias, int cout,
-                                                  float* __restrict__ pre, unsigned short* __restrict__ act,
-                                                  int act_cs, int act_co, int co_base) {
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int V = s * s * s;
-  const int v0 = wave * 64;
-  if (v0 >= V) return;
-  const int r = lane & 15, q = lane >> 4;
+// Convolutions on gfx950's double-K matrix cores, v_mfma_f32_16x16x32_bf16:
+// A 16 x 32 with A[i][k] in lane i + 16 (k / 8), element k % 8; B 32 x 16
+// with B[k][n] in lane n + 16 (k / 8), element k % 8; C 16 x 16 with C[m][n]
+// in lane n + 16 (m / 4), element m % 4.
+//
+// A block computes an output tile of TX x TY x TZ voxels (x fastest; 8 x 8 x
+// 4 on grids of side >= 8, 4 x 4 x 4 on a side of 4), 64 voxels per wave
+// (four 16-voxel row tiles), for 16 NT channels.  The contraction runs over
+// (tap, channel) in chunks of 16 channels: the chunk's input tile with a
+// one-voxel periodic halo, (TX+2)(TY+2)(TZ+2) rows of 16 bf16 (rows padded
+// to 24 for the banks), is staged in LDS, and the 27 x 16 = 432 products of
+// the chunk take 14 MFMA steps of K = 32: step q, lane group g covers tap
+// 2q + g/2 and channels 8 (g % 2) .. +8 (the last half step is tap 27,
+// whose weights are zero).  The chunk's weights for the block's 16 NT
+// output channels, [28 taps][16 NT][16], are staged in LDS beside the input
+// tile (a weight load per K step from L2 would stall every step on its
+// latency); the A operand of a row tile and the B operand of a column tile
+// are then one 16-byte LDS read per lane each.
+//   forward      out[v][co] = sum_{t,ci} x[v + o_t][ci] W[t][ci][co]
+//   backward-in  gx[v][ci]  = sum_{t,co} g[v - o_t][co] W[t][ci][co]
+// (the backward reads the halo at the mirrored tap and the transposed weights).
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+constexpr int kTaps = 28;      // 27 taps and a zero tap that pads the last K step
+constexpr int kRow = 24;       // LDS row of a staged voxel: 16 channels + 8 padding (bf16)
+
+struct ConvTile {
+  int lx, ly, lz;              // log2 of the tile extents
+};
+
+__host__ __device__ inline ConvTile conv_tile(int s) {
+  ConvTile t;
+  if (s % 8 == 0) {
+    t.lx = 3; t.ly = 3; t.lz = 2;
+  } else {
+    t.lx = 2; t.ly = 2; t.lz = 2;   // sides that are multiples of 4 only
+  }
+  return t;
+}
+
+// halo offset of tap t (t = 27: offset 0, any valid row)
+__device__ __forceinline__ int tap_off(int t, int hx, int hy) {
+  if (t >= 27) return 0;
+  const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+  return (dz * hy + dy) * hx + dx;
+}
+
+// Split over the contraction (small grids, few blocks): blockIdx.z takes
+// chunks z, z + gridDim.z, ... and, with gridDim.z > 1, writes its raw sums
+// to kpart[z][v][out_cs] for k_conv_finish.
+template <bool BWD, int NT>
+__global__ void __launch_bounds__(256) k_conv_mfma(const unsigned short* __restrict__ in, int in_cs, int in_co,
+                                                   int kch, int s, ConvTile T,
+                                                   const unsigned short* __restrict__ w, int wn, int wk,
+                                                   const float* __restrict__ bias, float* __restrict__ out,
+                                                   int out_cs, unsigned short* __restrict__ act, int act_cs,
+                                                   int act_co, float* __restrict__ kpart) {
+  extern __shared__ uint4 smem[];
+  unsigned short* wt = reinterpret_cast<unsigned short*>(smem);         // [kTaps][16 NT][16]
+  unsigned short* tile = wt + kTaps * 16 * NT * 16;                     // [H][kRow]
+  const int TX = 1 << T.lx, TY = 1 << T.ly, TZ = 1 << T.lz;
+  const int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, H = HX * HY * HZ;
+  const int ntx = s >> T.lx, nty = s >> T.ly;
+  const int b = blockIdx.x;
+  const int x0 = (b % ntx) << T.lx, y0 = ((b / ntx) % nty) << T.ly, z0 = (b / (ntx * nty)) << T.lz;
+  const int n_base = blockIdx.y * 16 * NT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, grp = lane >> 4;
+  // halo row of this lane's voxel in row tile i (tap offset added per step)
+  int hb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int u = 64 * wave + 16 * i + m;
+    const int x = u & (TX - 1), y = (u >> T.lx) & (TY - 1), z = u >> (T.lx + T.ly);
+    hb[i] = (z * HY + y) * HX + x;
+  }
   f32x4 acc[4][NT];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int t = 0; t < 27; ++t) {
-    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-    int nb[4];
+    for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ci0 = 8 * (grp & 1);
+  const int kz = gridDim.z;
+  for (int c = 16 * blockIdx.z; c < kch; c += 16 * kz) {
+    __syncthreads();   // the previous chunk's reads are done
+    for (int q = threadIdx.x; q < 2 * H; q += blockDim.x) {
+      const int r = q >> 1, half = q & 1;
+      const int hx = r % HX, hy = (r / HX) % HY, hz = r / (HX * HY);
+      int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+      gx = gx < 0 ? gx + s : (gx >= s ? gx - s : gx);
+      gy = gy < 0 ? gy + s : (gy >= s ? gy - s : gy);
+      gz = gz < 0 ? gz + s : (gz >= s ? gz - s : gz);
+      const long long v = ((long long)gz * s + gy) * s + gx;
+      const uint4 val = *reinterpret_cast<const uint4*>(in + v * in_cs + in_co + c + 8 * half);
+      *reinterpret_cast<uint4*>(tile + r * kRow + 8 * half) = val;
+    }
+    for (int q = threadIdx.x; q < kTaps * 16 * NT * 2; q += blockDim.x) {
+      const int row = q >> 1, half = q & 1;   // row = t * 16 NT + n
+      const int t = row / (16 * NT), n = row - t * 16 * NT;
+      const uint4 val = *reinterpret_cast<const uint4*>(w + ((long long)t * wn + n_base + n) * wk + c + 8 * half);
+      *reinterpret_cast<uint4*>(wt + row * 16 + 8 * half) = val;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) nb[mt] = nbr(v0 + 16 * mt + r, s, dz, dy, dx);
-    for (int c0 = 0; c0 < cin; c0 += 16) {
-      i16x4 a[4], b[NT];
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        a[mt] = *(const i16x4*)(in + (long long)nb[mt] * in_cs + in_co + c0 + 4 * q);
+    for (int q = 0; q < 14; ++q) {
+      const int t = 2 * q + (grp >> 1);
+      const int off = tap_off(BWD ? (t >= 27 ? 27 : 26 - t) : t, HX, HY);
+      bf16x8 bv[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
-        b[nt] = *(const i16x4*)(wf + ((long long)t * cout + co_base + 16 * nt + r) * cin + c0 + 4 * q);
+        bv[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(wt + ((t * 16 * NT) + 16 * nt + m) * 16 + ci0));
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
+      for (int i = 0; i < 4; ++i) {
+        const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(tile + (hb[i] + off) * kRow + ci0));
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[i][nt], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int v = v0 + 16 * mt + 4 * q + j;
-        const int co = co_base + 16 * nt + r;
-        const float val = acc[mt][nt][j] + bias[co];
-        pre[(long long)v * cout + co] = val;
-        act[(long long)v * act_cs + act_co + co] = f2bf(fmaxf(val, 0.f));
-      }
-}
-
-// backward to the input: gx[v][ci] = sum_{t,co} g[v - o_t][co] W[t][ci][co]
-template <int NT>
-__global__ void __launch_bounds__(256) k_conv_bwd_data(const unsigned short* __restrict__ g, int cout, int s,
-                                                       const unsigned short* __restrict__ wb, int cin,
-                                                       float* __restrict__ gx, int ci_base) {
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int V = s * s * s;
-  const int v0 = wave * 64;
-  if (v0 >= V) return;
-  const int r = lane & 15, q = lane >> 4;
-  f32x4 acc[4][NT];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int t = 0; t < 27; ++t) {
-    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-    int nb[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) nb[mt] = nbr(v0 + 16 * mt + r, s, -dz, -dy, -dx);
-    for (int c0 = 0; c0 < cout; c0 += 16) {
-      i16x4 a[4], b[NT];
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) a[mt] = *(const i16x4*)(g + (long long)nb[mt] * cout + c0 + 4 * q);
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        b[nt] = *(const i16x4*)(wb + ((long long)t * cin + ci_base + 16 * nt + r) * cout + c0 + 4 * q);
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int v = v0 + 16 * mt + 4 * q + j;
-        gx[(long long)v * cin + ci_base + 16 * nt + r] = acc[mt][nt][j];
-      }
-}
-
-// weight gradient: gW[t][ci][co] += sum over a voxel range of x[v+o_t][ci] g[v][co]
-// grid: (voxel ranges, 27 taps, ci tiles * co tiles); one wave per block
-__global__ void __launch_bounds__(64) k_conv_bwd_weight(const unsigned short* __restrict__ in, int in_cs, int in_co,
-                                                        int cin, int cin_store, int s,
-                                                        const unsigned short* __restrict__ g, int cout, int range,
-                                                        float* __restrict__ gw) {
-  const int lane = threadIdx.x;
-  const int r = lane & 15, q = lane >> 4;
-  const int t = blockIdx.y;
-  const int nco = cout / 16;
-  const int ct = blockIdx.z / nco, ot = blockIdx.z % nco;
-  const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-  const int V = s * s * s;
-  const int vb = blockIdx.x * range, ve = min(V, vb + range);
-  const int ci = 16 * ct + r, co = 16 * ot + r;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = vb; k0 < ve; k0 += 16) {
-    i16x4 a, b;
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int v = k0 + 4 * q + j;   // ve - vb is a multiple of 16
-      a[j] = (short)in[(long long)nbr(v, s, dz, dy, dx) * in_cs + in_co + ci];
-      b[j] = (short)g[(long long)v * cout + co];
+      const int u = 64 * wave + 16 * i + 4 * grp + j;
+      const int x = x0 + (u & (TX - 1)), y = y0 + ((u >> T.lx) & (TY - 1)), z = z0 + (u >> (T.lx + T.ly));
+      const long long v = ((long long)z * s + y) * s + x;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = n_base + 16 * nt + m;
+        if (kz > 1) {
+          kpart[((long long)blockIdx.z * s * s * s + v) * out_cs + n] = acc[i][nt][j];
+        } else if constexpr (BWD) {
+          out[v * out_cs + n] = acc[i][nt][j];
+        } else {
+          const float val = acc[i][nt][j] + bias[n];
+          out[v * out_cs + n] = val;
+          act[v * act_cs + act_co + n] = f2bf(fmaxf(val, 0.f));
+        }
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+}
+
+// Sum of the split contraction in order of z, then the epilogue: forward
+// (bias) -> pre-activation, bf16 relu activation; backward -> gx.
+template <bool BWD>
+__global__ void k_conv_finish(const float* __restrict__ kpart, int kz, long long V, int nch,
+                              const float* __restrict__ bias, float* __restrict__ out, unsigned short* __restrict__ act,
+                              int act_cs, int act_co) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V * nch) return;
+  float sum = 0.f;
+  for (int z = 0; z < kz; ++z) sum += kpart[z * V * nch + i];
+  if constexpr (BWD) {
+    out[i] = sum;
+  } else {
+    const int n = (int)(i % nch);
+    const long long v = i / nch;
+    const float val = sum + bias[n];
+    out[i] = val;
+    act[v * act_cs + act_co + n] = f2bf(fmaxf(val, 0.f));
+  }
+}
+
+// Weight gradient, one block per (voxel range r, 16-channel input slice):
+//   part[r][t][ci][co] = sum over the range's tiles of x[v + o_t][ci] g[v][co]
+// with M = ci, N = co, K = voxels: the tile's gradient is staged transposed,
+// gT[co][u] (u = tile voxel, x fastest), and its input slice with the halo
+// transposed, xT[ci][hz][hy][16] (rows of 16 bf16, HX <= 10 used), so that
+// 8 voxels consecutive in x are one 16-byte read; the three taps of a tap
+// row (dz, dy) share two aligned reads, from which byte alignment takes the
+// x shifts dx = 0, 1, 2.  Wave w owns the tap rows w, w + 4, w + 8; a K
+// step reads its B operands once for all of them and covers 4 rows of 8 x
+// (tile side 8) or 8 rows of 4 x (side 4, element reads).  Fixed-order sum
+// over r later.
+// Four rows of 8 bf16 (r[k] = row k) written transposed: dst[e * stride + k]
+// = r[k][e] for e < 8, as eight 8-byte stores.
+__device__ __forceinline__ void transpose_4x8(const uint4 r[4], unsigned short* dst, int stride) {
+  const unsigned int* w0 = reinterpret_cast<const unsigned int*>(&r[0]);
+  const unsigned int* w1 = reinterpret_cast<const unsigned int*>(&r[1]);
+  const unsigned int* w2 = reinterpret_cast<const unsigned int*>(&r[2]);
+  const unsigned int* w3 = reinterpret_cast<const unsigned int*>(&r[3]);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    // elements 2d (low halves) and 2d + 1 (high halves) of the four rows
+    const unsigned int lo01 = (w0[d] & 0xffffu) | (w1[d] << 16), lo23 = (w2[d] & 0xffffu) | (w3[d] << 16);
+    const unsigned int hi01 = (w0[d] >> 16) | (w1[d] & 0xffff0000u), hi23 = (w2[d] >> 16) | (w3[d] & 0xffff0000u);
+    *reinterpret_cast<uint2*>(dst + (2 * d) * stride) = make_uint2(lo01, lo23);
+    *reinterpret_cast<uint2*>(dst + (2 * d + 1) * stride) = make_uint2(hi01, hi23);
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_wgrad(const unsigned short* __restrict__ in, int in_cs, int in_co,
+                                                    int s, ConvTile T, const unsigned short* __restrict__ g, int cout,
+                                                    int tiles_per_range, int cin_pad, float* __restrict__ part) {
+  extern __shared__ uint4 smem[];
+  const int TX = 1 << T.lx, TY = 1 << T.ly, TZ = 1 << T.lz;
+  const int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+  const int NV = TX * TY * TZ;
+  unsigned short* gT = reinterpret_cast<unsigned short*>(smem);                 // [cout][NV]
+  unsigned short* xT = gT + (size_t)cout * NV;                                   // [16][HZ][HY][16]
+  const int ntx = s >> T.lx, nty = s >> T.ly, ntiles = ntx * nty * (s >> T.lz);
+  const int r = blockIdx.x, cs = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int m = lane & 15, grp = lane >> 4;
+  constexpr int kMaxRows = 3;   // tap rows (dz, dy) per wave: w, w + 4, w + 8 (< 9)
+  f32x4 acc[kMaxRows][3][NT];
+#pragma unroll
+  for (int k = 0; k < kMaxRows; ++k)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[k][dx][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int tb = r * tiles_per_range, te = min(ntiles, tb + tiles_per_range);
+  for (int b = tb; b < te; ++b) {
+    const int x0 = (b % ntx) << T.lx, y0 = ((b / ntx) % nty) << T.ly, z0 = (b / (ntx * nty)) << T.lz;
+    __syncthreads();
+    // gT: runs of 4 voxels (consecutive in x) x 8 channels per thread,
+    // transposed in registers and written as 8-byte runs of gT[co][u]
+    for (int q = threadIdx.x; q < (NV / 4) * (cout / 8); q += blockDim.x) {
+      const int u4 = q % (NV / 4), c8 = q / (NV / 4);
+      const int u = 4 * u4;
+      const int x = x0 + (u & (TX - 1)), y = y0 + ((u >> T.lx) & (TY - 1)), z = z0 + (u >> (T.lx + T.ly));
+      const long long v = ((long long)z * s + y) * s + x;
+      uint4 r4[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r4[k] = *reinterpret_cast<const uint4*>(g + (v + k) * cout + 8 * c8);
+      transpose_4x8(r4, gT + (8 * c8) * NV + u, NV);
+    }
+    // xT: the 16-channel slice with the halo, runs of 4 halo voxels along x
+    // (rows of 16; positions HX .. 15 hold copies, never read)
+    const int nrun = (HX + 3) >> 2;   // runs of 4 covering the HX halo positions of a row
+    for (int q = threadIdx.x; q < 2 * nrun * HY * HZ; q += blockDim.x) {
+      const int half = q & 1, xr = (q >> 1) % nrun, rr = (q >> 1) / nrun;   // rr = hz * HY + hy
+      const int hy = rr % HY, hz = rr / HY;
+      int gy = y0 + hy - 1, gz = z0 + hz - 1;
+      gy = gy < 0 ? gy + s : (gy >= s ? gy - s : gy);
+      gz = gz < 0 ? gz + s : (gz >= s ? gz - s : gz);
+      const long long vrow = ((long long)gz * s + gy) * s;
+      uint4 r4[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        // positions HX .. 15 of the row are never read: load the last halo
+        // voxel there, so that gx stays within one period of the grid
+        int gx = x0 + min(4 * xr + k, HX - 1) - 1;
+        gx = gx < 0 ? gx + s : (gx >= s ? gx - s : gx);
+        r4[k] = *reinterpret_cast<const uint4*>(in + (vrow + gx) * in_cs + in_co + 16 * cs + 8 * half);
+      }
+      transpose_4x8(r4, xT + ((8 * half) * HZ * HY + rr) * 16 + 4 * xr, HZ * HY * 16);
+    }
+    __syncthreads();
+    for (int q = 0; q < NV / 32; ++q) {
+      // lane group grp: voxels u = 32 q + 8 grp .. +8; B once per step
+      const int u0 = 32 * q + 8 * grp;
+      bf16x8 bv[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) bv[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(gT + (16 * nt + m) * NV + u0));
+#pragma unroll
+      for (int k = 0; k < kMaxRows; ++k) {
+        const int j = wave + nw * k;   // tap row (dz, dy); taps 3 j + dx
+        if (j >= 9) continue;
+        const int dz = j / 3, dy = j % 3;
+        if (TX == 8) {
+          const int y = (u0 >> 3) & (TY - 1), z = u0 >> (3 + T.ly);
+          const unsigned short* row = xT + ((m * HZ + z + dz) * HY + y + dy) * 16;
+          const uint4 lo = *reinterpret_cast<const uint4*>(row);
+          const uint4 hi = *reinterpret_cast<const uint4*>(row + 8);
+          const bf16x8 a0 = as_bf16x8(lo);
+          const bf16x8 a1 = as_bf16x8(make_uint4(__builtin_amdgcn_alignbyte(lo.y, lo.x, 2),
+                                                 __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
+                                                 __builtin_amdgcn_alignbyte(lo.w, lo.z, 2),
+                                                 __builtin_amdgcn_alignbyte(hi.x, lo.w, 2)));
+          const bf16x8 a2 = as_bf16x8(make_uint4(lo.y, lo.z, lo.w, hi.x));
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            acc[k][0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv[nt], acc[k][0][nt], 0, 0, 0);
+            acc[k][1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv[nt], acc[k][1][nt], 0, 0, 0);
+            acc[k][2][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bv[nt], acc[k][2][nt], 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            unsigned int w4[4];
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+              unsigned int pair = 0;
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int u = u0 + 2 * k2 + h;
+                const int x = u & (TX - 1), y = (u >> T.lx) & (TY - 1), z = u >> (T.lx + T.ly);
+                pair |= (unsigned int)xT[((m * HZ + z + dz) * HY + y + dy) * 16 + x + dx] << (16 * h);
+              }
+              w4[k2] = pair;
+            }
+            const bf16x8 av = as_bf16x8(make_uint4(w4[0], w4[1], w4[2], w4[3]));
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              acc[k][dx][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[k][dx][nt], 0, 0, 0);
+          }
+        }
+      }
+    }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int cij = 16 * ct + 4 * q + j;   // padded input channels are not stored
-    if (cij < cin_store) unsafeAtomicAdd(&gw[((long long)t * cin_store + cij) * cout + 16 * ot + r], acc[j]);
+  for (int k = 0; k < kMaxRows; ++k) {
+    const int jr = wave + nw * k;
+    if (jr >= 9) continue;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int t = 3 * jr + dx;
+          const int ci = 16 * cs + 4 * grp + j;
+          part[(((long long)r * 27 + t) * cin_pad + ci) * cout + 16 * nt + m] = acc[k][dx][nt][j];
+        }
   }
+}
+
+// G[t][ci][co] += sum over r of part[r][t][ci][co], ci < cin, in a fixed
+// order: a block takes 32 consecutive outputs; its 8 lane rows sum the
+// ranges r = row, row + 8, ... and the 8 row sums are added in a fixed tree.
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, int nr, int cin, int cin_pad,
+                                                      int cout, float* __restrict__ gw) {
+  __shared__ float sh[8][32];
+  const long long n = 27LL * cin * cout;
+  const int o = threadIdx.x & 31, row = threadIdx.x >> 5;
+  const long long i = (long long)blockIdx.x * 32 + o;
+  float s = 0.f;
+  if (i < n) {
+    const int co = (int)(i % cout);
+    const int ci = (int)((i / cout) % cin);
+    const int t = (int)(i / ((long long)cout * cin));
+    const long long stride = 27LL * cin_pad * cout;
+    const float* p = part + ((long long)t * cin_pad + ci) * cout + co;
+    for (int r = row; r < nr; r += 8) s += p[r * stride];
+  }
+  sh[row][o] = s;
+  __syncthreads();
+  if (row == 0 && i < n)
+    gw[i] += ((sh[0][o] + sh[1][o]) + (sh[2][o] + sh[3][o])) + ((sh[4][o] + sh[5][o]) + (sh[6][o] + sh[7][o]));
+}
+
+// out[k] += sum over the rows b < nb of part[b][k]: one block per k, rows
+// taken by the threads in a fixed pattern and added in a fixed tree
+__global__ void __launch_bounds__(256) k_rows_reduce(const float* __restrict__ part, int nb, int nk,
+                                                     float* __restrict__ out) {
+  __shared__ float sh[256];
+  const int k = blockIdx.x;
+  float s = 0.f;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(long long)b * nk + k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] += sh[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -222,40 +455,46 @@ __global__ void k_pool(const unsigned short* __restrict__ in, int in_cs, int in_
   out[i] = f2bf(0.125f * sum);
 }
 
-// up: out view (size s) channel slice [0, c) = copy of the parent in `in` (size s/2)
+// up: out view (size s) channel slice [0, c) = copy of the parent in `in`
+// (size s/2); 8 channels (16 bytes) per thread
 __global__ void k_up(const unsigned short* __restrict__ in, int c, int s, unsigned short* __restrict__ out,
                      int out_cs) {
+  const int c8 = c / 8;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)s * s * s * c) return;
-  const int ch = (int)(i % c);
-  const int v = (int)(i / c);
+  if (i >= (long long)s * s * s * c8) return;
+  const int ch = 8 * (int)(i % c8);
+  const int v = (int)(i / c8);
   const int x = v % s, y = (v / s) % s, z = v / (s * s);
   const int h = s / 2;
   const int pv = ((z >> 1) * h + (y >> 1)) * h + (x >> 1);
-  out[(long long)v * out_cs + ch] = in[(long long)pv * c + ch];
+  *reinterpret_cast<uint4*>(out + (long long)v * out_cs + ch) =
+      *reinterpret_cast<const uint4*>(in + (long long)pv * c + ch);
 }
 
 // gpre = g (float, view of width gcs at offset goff) masked by pre > 0;
-// writes the bf16 copy and accumulates the bias gradient
+// writes the bf16 copy and the block's bias-gradient partials part[block][c]
+// (summed in block order by k_partial_reduce)
 __global__ void k_relu_back(const float* __restrict__ g, int gcs, int goff, const float* __restrict__ pre, int c,
-                            int V, unsigned short* __restrict__ gb, float* __restrict__ gbias) {
+                            int V, unsigned short* __restrict__ gb, float* __restrict__ part) {
   __shared__ float sh[256];
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // grid-stride: the stride is a multiple of 256, so a thread keeps its
+  // channel (c divides 256 for c in {16, 32, 64}) and sums in a fixed order
   float val = 0.f;
-  int ch = 0;
-  if (i < (long long)V * c) {
-    ch = (int)(i % c);
+  const long long n = (long long)V * c;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c);
     const long long v = i / c;
-    val = pre[i] > 0.f ? g[v * gcs + goff + ch] : 0.f;
-    gb[i] = f2bf(val);
+    const float gi = pre[i] > 0.f ? g[v * gcs + goff + ch] : 0.f;
+    gb[i] = f2bf(gi);
+    val += gi;
   }
-  // block partial sums per channel (c divides 256 for c in {16, 32, 64})
+  // block partial sums per channel
   sh[threadIdx.x] = val;
   __syncthreads();
   if ((int)threadIdx.x < c) {
     float s = 0.f;
     for (int k = threadIdx.x; k < 256; k += c) s += sh[k];
-    unsafeAtomicAdd(&gbias[threadIdx.x], s);
+    part[(long long)blockIdx.x * c + threadIdx.x] = s;
   }
 }
 
@@ -338,63 +577,93 @@ __global__ void k_mse(const float* __restrict__ v, const float* __restrict__ tgt
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_mse_final(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = scale * s;
+__global__ void __launch_bounds__(256) k_mse_final(const double* __restrict__ part, int n, double scale,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = scale * sh[0];
 }
 
-// head backward: gd0[vox][c] = sum_k go[k][vox] Wh[c][k]; gWh, gbh by block partial sums
-__global__ void k_head_bwd(const unsigned short* __restrict__ d0, int c, int V, const float* __restrict__ wh,
-                           const float* __restrict__ go, float* __restrict__ gd0, float* __restrict__ gwh,
-                           float* __restrict__ gbh) {
-  __shared__ float sh[256];
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+// head backward: gd0[vox][c] = sum_k go[k][vox] Wh[c][k]; the block's
+// partials of gWh[c][3] and gbh[3] go to part[block][3 c + 3] (wave sums by
+// butterflies, then the four waves in order)
+__global__ void __launch_bounds__(256) k_head_bwd(const unsigned short* __restrict__ d0, int c, int V,
+                                                  const float* __restrict__ wh, const float* __restrict__ go,
+                                                  float* __restrict__ gd0, float* __restrict__ part) {
+  __shared__ float sh[4][3 * 64 + 3];
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float g[3] = {0.f, 0.f, 0.f};
   if (v < V) {
-    g0 = go[v];
-    g1 = go[V + v];
-    g2 = go[2 * V + v];
+    g[0] = go[v];
+    g[1] = go[V + v];
+    g[2] = go[2 * V + v];
     for (int ch = 0; ch < c; ++ch)
-      gd0[(long long)v * c + ch] = g0 * wh[ch * 3] + g1 * wh[ch * 3 + 1] + g2 * wh[ch * 3 + 2];
+      gd0[(long long)v * c + ch] = g[0] * wh[ch * 3] + g[1] * wh[ch * 3 + 1] + g[2] * wh[ch * 3 + 2];
   }
-  // weight gradient: gwh[ch][k] += sum_v d0[v][ch] g_k[v]
-  for (int ch = 0; ch < c; ++ch) {
-    float a = v < V ? bf2f(d0[(long long)v * c + ch]) : 0.f;
-    for (int k = 0; k < 3; ++k) {
-      sh[threadIdx.x] = a * (k == 0 ? g0 : (k == 1 ? g1 : g2));
-      __syncthreads();
-      for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
+  auto wave_sum = [](float x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+  };
+  for (int c8 = 0; c8 < c; c8 += 8) {
+    uint4 row = make_uint4(0u, 0u, 0u, 0u);
+    if (v < V) row = *reinterpret_cast<const uint4*>(d0 + (long long)v * c + c8);
+    const unsigned short* e = reinterpret_cast<const unsigned short*>(&row);
+#pragma unroll
+    for (int k8 = 0; k8 < 8; ++k8) {
+      const float a = bf2f(e[k8]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float t = wave_sum(a * g[k]);
+        if (lane == 0) sh[wave][(c8 + k8) * 3 + k] = t;
       }
-      if (threadIdx.x == 0) unsafeAtomicAdd(&gwh[ch * 3 + k], sh[0]);
-      __syncthreads();
     }
   }
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    sh[threadIdx.x] = k == 0 ? g0 : (k == 1 ? g1 : g2);
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) unsafeAtomicAdd(&gbh[k], sh[0]);
-    __syncthreads();
+    const float t = wave_sum(g[k]);
+    if (lane == 0) sh[wave][3 * c + k] = t;
   }
+  __syncthreads();
+  const int nk = 3 * c + 3;
+  for (int k = threadIdx.x; k < nk; k += blockDim.x)
+    part[(long long)blockIdx.x * nk + k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
 }
 
-// bf16 weight copies: wf[t][co][ci_pad], wb[t][ci_pad][co] from w[t][ci][co]
-__global__ void k_wcopy(const float* __restrict__ w, int taps, int cin, int cin_pad, int cout,
-                        unsigned short* __restrict__ wf, unsigned short* __restrict__ wb) {
+// bf16 weight copies of every convolution in one launch: layer l covers
+// threads [start[l], start[l + 1]); wf[t][co][ci_pad], wb[t][ci_pad][co]
+// from w[t][ci][co], t < kTaps (tap 27 and the padded channels are zero)
+struct WcopyArgs {
+  const float* w[kLayers - 1];
+  unsigned short* wf[kLayers - 1];
+  unsigned short* wb[kLayers - 1];
+  int cin[kLayers - 1], cinp[kLayers - 1], cout[kLayers - 1];
+  long long start[kLayers];
+};
+
+__global__ void k_wcopy(WcopyArgs A) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)taps * cin_pad * cout) return;
+  if (i >= A.start[kLayers - 1]) return;
+  int l = 0;
+  while (i >= A.start[l + 1]) ++l;
+  i -= A.start[l];
+  const float* __restrict__ w = A.w[l];
+  unsigned short* __restrict__ wf = A.wf[l];
+  unsigned short* __restrict__ wb = A.wb[l];
+  const int cin = A.cin[l], cin_pad = A.cinp[l], cout = A.cout[l];
   const int co = (int)(i % cout);
   const int ci = (int)((i / cout) % cin_pad);
   const int t = (int)(i / ((long long)cout * cin_pad));
-  const unsigned short val = ci < cin ? f2bf(w[((long long)t * cin + ci) * cout + co]) : (unsigned short)0;
+  const unsigned short val =
+      (ci < cin && t < 27) ? f2bf(w[((long long)t * cin + ci) * cout + co]) : (unsigned short)0;
   wb[((long long)t * cin_pad + ci) * cout + co] = val;
   wf[((long long)t * cout + co) * cin_pad + ci] = val;
 }
@@ -445,10 +714,38 @@ struct lag_cnn_s {
   unsigned short* gb16 = nullptr;    // bf16 gradient of a pre-activation (largest)
   float* gout = nullptr;             // 3 x S^3
   double* part = nullptr;
+  float* wpart = nullptr;            // weight-gradient partials per voxel range
+  float* kpart = nullptr;            // split-contraction partials of the convolutions
+  float* bpart = nullptr;            // bias / head gradient partials per block
   int adam_t = 0;
 };
 
 static int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// output tiles of a grid of side s, and the voxel ranges of the weight gradient
+static int conv_tiles(int s) {
+  const ConvTile t = conv_tile(s);
+  return (s >> t.lx) * (s >> t.ly) * (s >> t.lz);
+}
+static int wgrad_per_range(int s) { return ceil_div(conv_tiles(s), 512); }
+static int wgrad_ranges(int s) { return ceil_div(conv_tiles(s), wgrad_per_range(s)); }
+
+// 16-channel output tiles per block: up to 4 on grids of side >= 32, else 1
+// (more blocks on the small grids)
+static int conv_nt(int s, int n16) {
+  if (s < 32) return 1;
+  for (int nt = 4; nt > 1; --nt)
+    if (n16 % nt == 0) return nt;
+  return 1;
+}
+
+// Split of the contraction over blockIdx.z when a layer has fewer than 512
+// blocks: each block then takes every kz-th 16-channel chunk.
+static int conv_split(int s, int nout, int kch) {
+  const int blocks = conv_tiles(s) * (nout / (16 * conv_nt(s, nout / 16)));
+  if (blocks >= 512) return 1;
+  return std::max(1, std::min(kch / 16, ceil_div(512, blocks)));
+}
 
 extern "C" {
 
@@ -468,7 +765,7 @@ int lag_cnn_destroy(lag_cnn n) {
   if (!n) return LAG_OK;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {n->P, n->G, n->M1, n->M2, n->x0, n->p0, n->p1, n->p2, n->cat2, n->cat1, n->cat0,
-                  n->gb16, n->gout, n->part};
+                  n->gb16, n->gout, n->part, n->wpart, n->bpart, n->kpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int l = 0; l < kLayers; ++l) {
@@ -548,10 +845,15 @@ int lag_cnn_create(const lag_cnn_config* cfg, lag_cnn* out) {
     (void)hipMemset(n->M1, 0, sizeof(float) * off);
     (void)hipMemset(n->M2, 0, sizeof(float) * off);
   }
+  size_t wpart = 0, kpart = 0;
   for (int l = 0; l < HEAD; ++l) {
-    const size_t wn = (size_t)27 * n->cinp[l] * n->cout[l];
+    const size_t Vl = (size_t)sz[l] * sz[l] * sz[l];
+    kpart = std::max(kpart, (size_t)conv_split(sz[l], n->cout[l], n->cinp[l]) * Vl * n->cout[l]);
+    kpart = std::max(kpart, (size_t)conv_split(sz[l], n->cinp[l], n->cout[l]) * Vl * n->cinp[l]);
+    const size_t wn = (size_t)kTaps * n->cinp[l] * n->cout[l];
     CNN_ALLOC(n->wf[l], 2 * wn);
     CNN_ALLOC(n->wb[l], 2 * wn);
+    wpart = std::max(wpart, (size_t)wgrad_ranges(sz[l]) * 27 * n->cinp[l] * n->cout[l]);
     const long long V = (long long)sz[l] * sz[l] * sz[l];
     CNN_ALLOC(n->pre[l], sizeof(float) * V * n->cout[l]);
   }
@@ -583,6 +885,10 @@ int lag_cnn_create(const lag_cnn_config* cfg, lag_cnn* out) {
   CNN_ALLOC(n->gb16, 2 * V0 * 64);
   CNN_ALLOC(n->gout, sizeof(float) * 3 * V0);
   CNN_ALLOC(n->part, sizeof(double) * 1024);
+  CNN_ALLOC(n->wpart, sizeof(float) * wpart);
+  CNN_ALLOC(n->kpart, sizeof(float) * kpart);
+  // bias partials: one row of c per 256 (voxel, channel) pairs; head: 3 c + 3 per 256 voxels
+  CNN_ALLOC(n->bpart, sizeof(float) * std::max<long long>(1024 * 64, (V0 / 256 + 1) * (3 * 64 + 3)));
   *out = n;
   return LAG_OK;
 }
@@ -618,25 +924,42 @@ int lag_cnn_get_grads(lag_cnn n, float* host) {
 
 // ---- launch helpers ----------------------------------------------------------
 
-static int conv_fwd(lag_cnn n, int l, const unsigned short* in, int in_cs, int in_co, unsigned short* act, int act_cs,
-                    int act_co, hipStream_t s) {
-  const int sz = n->lsize[l], cout = n->cout[l];
-  const long long V = (long long)sz * sz * sz;
-  const int waves = ceil_div(V, 64);
-  const dim3 grid(ceil_div(waves, 4));
-  const float* bias = n->P + n->boff[l];
-  // output channels in groups of up to 64 (NT = 4 tiles of 16)
-  for (int cb = 0; cb < cout; cb += 64) {
-    const int nt = std::min(4, (cout - cb) / 16);
-    switch (nt) {
-      case 1: hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, in, in_cs, in_co, n->cinp[l], sz, n->wf[l], bias, cout, n->pre[l], act, act_cs, act_co, cb); break;
-      case 2: hipLaunchKernelGGL(k_conv_fwd<2>, grid, dim3(256), 0, s, in, in_cs, in_co, n->cinp[l], sz, n->wf[l], bias, cout, n->pre[l], act, act_cs, act_co, cb); break;
-      case 3: hipLaunchKernelGGL(k_conv_fwd<3>, grid, dim3(256), 0, s, in, in_cs, in_co, n->cinp[l], sz, n->wf[l], bias, cout, n->pre[l], act, act_cs, act_co, cb); break;
-      default: hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), 0, s, in, in_cs, in_co, n->cinp[l], sz, n->wf[l], bias, cout, n->pre[l], act, act_cs, act_co, cb); break;
-    }
+static size_t conv_lds(ConvTile T, int nt);
+
+template <bool BWD>
+static int launch_conv(lag_cnn n, int s, int nout, const unsigned short* in, int in_cs, int in_co, int kch,
+                       const unsigned short* w, int wn, int wk, const float* bias, float* out, unsigned short* act,
+                       int act_cs, int act_co, hipStream_t st) {
+  const ConvTile T = conv_tile(s);
+  const int nt = conv_nt(s, nout / 16), kz = conv_split(s, nout, kch);
+  const dim3 grid(conv_tiles(s), nout / (16 * nt), kz), block(1 << (T.lx + T.ly + T.lz));
+  const size_t lds = conv_lds(T, nt);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((k_conv_mfma<BWD, 1>), grid, block, lds, st, in, in_cs, in_co, kch, s, T, w, wn, wk, bias, out, nout, act, act_cs, act_co, n->kpart); break;
+    case 2: hipLaunchKernelGGL((k_conv_mfma<BWD, 2>), grid, block, lds, st, in, in_cs, in_co, kch, s, T, w, wn, wk, bias, out, nout, act, act_cs, act_co, n->kpart); break;
+    case 3: hipLaunchKernelGGL((k_conv_mfma<BWD, 3>), grid, block, lds, st, in, in_cs, in_co, kch, s, T, w, wn, wk, bias, out, nout, act, act_cs, act_co, n->kpart); break;
+    default: hipLaunchKernelGGL((k_conv_mfma<BWD, 4>), grid, block, lds, st, in, in_cs, in_co, kch, s, T, w, wn, wk, bias, out, nout, act, act_cs, act_co, n->kpart); break;
+  }
+  LAG_LAUNCH_CHECK();
+  if (kz > 1) {
+    const long long V = (long long)s * s * s;
+    hipLaunchKernelGGL((k_conv_finish<BWD>), dim3(ceil_div(V * nout, 256)), dim3(256), 0, st, n->kpart, kz, V, nout,
+                       bias, out, act, act_cs, act_co);
     LAG_LAUNCH_CHECK();
   }
   return LAG_OK;
+}
+
+static size_t conv_lds(ConvTile T, int nt) {
+  return sizeof(unsigned short) * (kRow * (size_t)(((1 << T.lx) + 2) * ((1 << T.ly) + 2) * ((1 << T.lz) + 2)) +
+                                   (size_t)kTaps * 16 * nt * 16);
+}
+
+static int conv_fwd(lag_cnn n, int l, const unsigned short* in, int in_cs, int in_co, unsigned short* act, int act_cs,
+                    int act_co, hipStream_t s) {
+  const int sz = n->lsize[l], cout = n->cout[l];
+  return launch_conv<false>(n, sz, cout, in, in_cs, in_co, n->cinp[l], n->wf[l], cout, n->cinp[l],
+                            n->P + n->boff[l], n->pre[l], act, act_cs, act_co, s);
 }
 
 // backward through relu + conv l: g (float view of the layer output gradient)
@@ -645,39 +968,50 @@ static int conv_bwd(lag_cnn n, int l, const float* g, int gcs, int goff, const u
                     int in_co, float* gx, hipStream_t s) {
   const int sz = n->lsize[l], cout = n->cout[l], cin = n->cinp[l];
   const long long V = (long long)sz * sz * sz;
-  hipLaunchKernelGGL(k_relu_back, dim3(ceil_div(V * cout, 256)), dim3(256), 0, s, g, gcs, goff, n->pre[l], cout,
-                     (int)V, n->gb16, n->G + n->boff[l]);
+  const int nb = std::min(ceil_div(V * cout, 256), 1024);
+  hipLaunchKernelGGL(k_relu_back, dim3(nb), dim3(256), 0, s, g, gcs, goff, n->pre[l], cout, (int)V, n->gb16,
+                     n->bpart);
   LAG_LAUNCH_CHECK();
-  // weight gradient (accumulated into G, which the caller zeroes)
-  const int range = V >= 4096 ? 4096 : (int)V;
-  dim3 grid(ceil_div(V, range), 27, (cin / 16) * (cout / 16));
-  hipLaunchKernelGGL(k_conv_bwd_weight, grid, dim3(64), 0, s, in, in_cs, in_co, cin, n->cin[l], sz, n->gb16, cout,
-                     range, n->G + n->woff[l]);
+  hipLaunchKernelGGL(k_rows_reduce, dim3(cout), dim3(256), 0, s, n->bpart, nb, cout, n->G + n->boff[l]);
+  LAG_LAUNCH_CHECK();
+  // weight gradient: partials per voxel range, then their fixed-order sum into G
+  const ConvTile T = conv_tile(sz);
+  const int NV = 1 << (T.lx + T.ly + T.lz);
+  const int tpr = wgrad_per_range(sz), nr = wgrad_ranges(sz);
+  const size_t lds = sizeof(unsigned short) * ((size_t)cout * NV +
+                                               16 * 16 * (size_t)(((1 << T.ly) + 2) * ((1 << T.lz) + 2)));
+  const dim3 wg(nr, cin / 16);
+  switch (cout / 16) {
+    case 1: hipLaunchKernelGGL(k_conv_wgrad<1>, wg, dim3(256), lds, s, in, in_cs, in_co, sz, T, n->gb16, cout, tpr, cin, n->wpart); break;
+    case 2: hipLaunchKernelGGL(k_conv_wgrad<2>, wg, dim3(256), lds, s, in, in_cs, in_co, sz, T, n->gb16, cout, tpr, cin, n->wpart); break;
+    default: hipLaunchKernelGGL(k_conv_wgrad<4>, wg, dim3(256), lds, s, in, in_cs, in_co, sz, T, n->gb16, cout, tpr, cin, n->wpart); break;
+  }
+  LAG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(27LL * n->cin[l] * cout, 32)), dim3(256), 0, s, n->wpart, nr,
+                     n->cin[l], cin, cout, n->G + n->woff[l]);
   LAG_LAUNCH_CHECK();
   if (gx) {
-    const int waves = ceil_div(V, 64);
-    const dim3 g2(ceil_div(waves, 4));
-    for (int cb = 0; cb < cin; cb += 64) {
-      const int nt = std::min(4, (cin - cb) / 16);
-      switch (nt) {
-        case 1: hipLaunchKernelGGL(k_conv_bwd_data<1>, g2, dim3(256), 0, s, n->gb16, cout, sz, n->wb[l], cin, gx, cb); break;
-        case 2: hipLaunchKernelGGL(k_conv_bwd_data<2>, g2, dim3(256), 0, s, n->gb16, cout, sz, n->wb[l], cin, gx, cb); break;
-        case 3: hipLaunchKernelGGL(k_conv_bwd_data<3>, g2, dim3(256), 0, s, n->gb16, cout, sz, n->wb[l], cin, gx, cb); break;
-        default: hipLaunchKernelGGL(k_conv_bwd_data<4>, g2, dim3(256), 0, s, n->gb16, cout, sz, n->wb[l], cin, gx, cb); break;
-      }
-      LAG_LAUNCH_CHECK();
-    }
+    const int rc = launch_conv<true>(n, sz, cin, n->gb16, cout, 0, cout, n->wb[l], cin, cout, nullptr, gx, nullptr, 0,
+                                     0, s);
+    if (rc) return rc;
   }
   return LAG_OK;
 }
 
 static int refresh_weights(lag_cnn n, hipStream_t s) {
+  WcopyArgs A;
+  A.start[0] = 0;
   for (int l = 0; l < HEAD; ++l) {
-    const long long cnt = 27LL * n->cinp[l] * n->cout[l];
-    hipLaunchKernelGGL(k_wcopy, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, n->P + n->woff[l], 27, n->cin[l],
-                       n->cinp[l], n->cout[l], n->wf[l], n->wb[l]);
-    LAG_LAUNCH_CHECK();
+    A.w[l] = n->P + n->woff[l];
+    A.wf[l] = n->wf[l];
+    A.wb[l] = n->wb[l];
+    A.cin[l] = n->cin[l];
+    A.cinp[l] = n->cinp[l];
+    A.cout[l] = n->cout[l];
+    A.start[l + 1] = A.start[l] + (long long)kTaps * n->cinp[l] * n->cout[l];
   }
+  hipLaunchKernelGGL(k_wcopy, dim3(ceil_div(A.start[HEAD], 256)), dim3(256), 0, s, A);
+  LAG_LAUNCH_CHECK();
   return LAG_OK;
 }
 
@@ -705,13 +1039,13 @@ static int forward_impl(lag_cnn n, const float* T, const float* R, float* v, hip
   if ((rc = conv_fwd(n, MA, n->p2, c2, 0, n->a[MA], c3, 0, s))) return rc;
   if ((rc = conv_fwd(n, MB, n->a[MA], c3, 0, n->a[MB], c3, 0, s))) return rc;
   // decoder
-  hipLaunchKernelGGL(k_up, dim3(ceil_div(V2 * c3, 256)), dim3(256), 0, s, n->a[MB], c3, S / 4, n->cat2, w2);
+  hipLaunchKernelGGL(k_up, dim3(ceil_div(V2 * c3 / 8, 256)), dim3(256), 0, s, n->a[MB], c3, S / 4, n->cat2, w2);
   LAG_LAUNCH_CHECK();
   if ((rc = conv_fwd(n, D2, n->cat2, w2, 0, n->a[D2], c2, 0, s))) return rc;
-  hipLaunchKernelGGL(k_up, dim3(ceil_div(V1 * c2, 256)), dim3(256), 0, s, n->a[D2], c2, S / 2, n->cat1, w1);
+  hipLaunchKernelGGL(k_up, dim3(ceil_div(V1 * c2 / 8, 256)), dim3(256), 0, s, n->a[D2], c2, S / 2, n->cat1, w1);
   LAG_LAUNCH_CHECK();
   if ((rc = conv_fwd(n, D1, n->cat1, w1, 0, n->a[D1], c1, 0, s))) return rc;
-  hipLaunchKernelGGL(k_up, dim3(ceil_div(V0 * c1, 256)), dim3(256), 0, s, n->a[D1], c1, S, n->cat0, w0);
+  hipLaunchKernelGGL(k_up, dim3(ceil_div(V0 * c1 / 8, 256)), dim3(256), 0, s, n->a[D1], c1, S, n->cat0, w0);
   LAG_LAUNCH_CHECK();
   if ((rc = conv_fwd(n, D0, n->cat0, w0, 0, n->a[D0], c0, 0, s))) return rc;
   hipLaunchKernelGGL(k_head_fwd, dim3(ceil_div(V0, 256)), dim3(256), 0, s, n->a[D0], c0, (int)V0,
@@ -743,11 +1077,15 @@ int lag_cnn_backward(lag_cnn n, const float* T, const float* R, const float* tar
   // gout = d loss / d (head's linear output) = out_scale (v - target) / n
   hipLaunchKernelGGL(k_mse, dim3(1024), dim3(256), 0, s, v, target, nv, gscale, n->gout, n->part);
   LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, n->part, 1024, 0.5 / (double)nv, loss);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, s, n->part, 1024, 0.5 / (double)nv, loss);
   LAG_LAUNCH_CHECK();
   float* gd0 = n->gbuf[0];
   hipLaunchKernelGGL(k_head_bwd, dim3(ceil_div(V0, 256)), dim3(256), 0, s, n->a[D0], c0, (int)V0,
-                     n->P + n->woff[HEAD], n->gout, gd0, n->G + n->woff[HEAD], n->G + n->boff[HEAD]);
+                     n->P + n->woff[HEAD], n->gout, gd0, n->bpart);
+  LAG_LAUNCH_CHECK();
+  // gWh[c][3] and gbh[3] are contiguous in G
+  hipLaunchKernelGGL(k_rows_reduce, dim3(3 * c0 + 3), dim3(256), 0, s, n->bpart, ceil_div(V0, 256), 3 * c0 + 3,
+                     n->G + n->woff[HEAD]);
   LAG_LAUNCH_CHECK();
   // decoder
   if ((rc = conv_bwd(n, D0, gd0, c0, 0, n->cat0, w0, 0, n->gcat[0], s))) return rc;
