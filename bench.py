@@ -545,7 +545,7 @@ def batch_measurement(args, L, torch):
         (L.lag_transport if tr else L.lag_pushforward)(plan, T, phi, R)
         plan.close()
         probs.append(prob), Ts.append(T), Rs.append(R)
-    max_gn, pcg_maxit = 50, 30
+    max_gn, pcg_maxit = 50, 50   # Sec. 4 caps the Krylov iterations at 50
     opts = L.lag_gn_default_options()
     opts.pcg_maxit, opts.max_gn = pcg_maxit, max_gn
     # sequential reference (plans cached per distinct problem, created before timing)

@@ -15,8 +15,10 @@ decreasing at every step.
 
 Continuity solves with the cloud-in-cell push-forward have a piecewise
 smooth objective whose gradient jumps whenever a particle crosses a cell-
-centre line; the case below is one the oracle's own solver brings to the
-tolerance (in 14 iterations).
+centre line, so not every pair reaches the tolerance (the oracle's own
+solver stalls on some); the stationary case below is one the oracle brings
+to the tolerance in 14 iterations, the time-dependent one a pair the GPU
+solver brings there in 15.
 """
 
 import numpy as np
@@ -58,6 +60,14 @@ SOLVES = [
     dict(name="continuity_2d48_curvature", case=Case("c", 2, (48, 48), (24, 24), model="continuity",
                                                     reg="curvature", alpha=1e-3, nsteps=10, seed=4001),
          jac=0, pcg_maxit=30, template=("blob", 8, 4001), velocity=(4, 0.05, 4002)),
+    # mass-preserving registration with a time-dependent velocity: 4 time
+    # intervals (5 nodes), 8 RK4 steps each, |k| <= 6 and amplitude 0.08,
+    # curvature alpha = 1e-3, at most 50 PCG iterations (Sec. 4 caps Krylov
+    # iterations at 50); a 40^2 density on a 20^2 velocity grid
+    dict(name="continuity_2d40_nonstationary", case=Case("c2", 2, (40, 40), (20, 20), nodes=5, model="continuity",
+                                                        reg="curvature", alpha=1e-3, nsteps=32, nblobs=8, kmax=6,
+                                                        amplitude=0.08, seed=2005),
+         jac=0, pcg_maxit=50),
 ]
 
 
@@ -126,11 +136,16 @@ def test_gn_iterates_match_oracle(spec, torch, L):
         g_o = np.asarray(g_o).ravel()
         gdata_o = g_o - reg_o
         eg_data = relerr(dev.get(gd), gdata_o)
-        eg_reg = relerr(dev.get(reg), reg_o) if case.alpha > 0 else 0.0
+        # at v = 0 (and for alpha = 0) the regulariser term is exactly zero
+        eg_reg = relerr(dev.get(reg), reg_o) if np.any(reg_o) else float(np.abs(dev.get(reg)).max())
         gsum = dev.get(gd) + dev.get(reg)
-        eg = float(np.abs(gsum - g_o).max() / np.abs(gdata_o).max())
+        # (at v = 0 every characteristic ends on a node, the kink mask keeps
+        # no cell and both data terms are exactly zero)
+        mdata = float(np.abs(gdata_o).max())
+        eg = float(np.abs(gsum - g_o).max() / (mdata if mdata > 0 else 1.0))
         eH = relerr(dev.get(Hp), H_o)
         for key, e in (("J", eJ), ("g_data", eg_data), ("g_reg", eg_reg), ("g", eg), ("Hp", eH)):
+            assert np.isfinite(e), (key, k)
             worst[key] = max(worst.get(key, 0.0), e)
         # --- the GPU's own step ----------------------------------------------
         info = L.lag_gn_step(plan, Td, Rd, v, vn, opt, gstop=1e-2 * g0)
