@@ -75,6 +75,7 @@ struct lag_plan_s {
   int* pg_rows = nullptr;
   int* pg_npages = nullptr;
   int* pg_order = nullptr;     // launch order of the bricks (k_brick_order)
+  int4* pg_box = nullptr;      // per brick: tile nodes its stored blocks touch (k_jac_pack)
   int* pg_redo = nullptr;      // count of bricks whose product pass was redone at the exact scale
   // per-brick partial velocity tiles and, per axis, the list of (brick,
   // tile offset) pairs covering each velocity index (fixed-order reduction)
@@ -170,7 +171,10 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
                hipStream_t s, bool zero = false);
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
-int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred = false);
+// box (may be null): per brick, the tile nodes its partial tile holds; the
+// other nodes of its tile are not read (they count as zero)
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred = false,
+                       const int4* box = nullptr);
 // LDS of the matrix-free adjoint kernel (64-bit tile of the plan's bricks)
 size_t adjoint_lds_bytes(lag_plan P);
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);

@@ -2037,14 +2037,17 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
                                                      const int* __restrict__ cells,
                                                      const unsigned char* __restrict__ cnt, long long nslots,
                                                      int cap, float4* __restrict__ pv, int* __restrict__ pc,
-                                                     int* __restrict__ prow, int* __restrict__ npages) {
+                                                     int* __restrict__ prow, int* __restrict__ npages,
+                                                     int4* __restrict__ box) {
   constexpr int NV4 = JacLayout<D>::NV4;
   // LDS: the rows that hold blocks (slot within the brick) and their first
   // positions (increasing), then the counts of all rows
   extern __shared__ int sh[];
   __shared__ int s_rows, s_pos;
+  __shared__ int s_box[6];           // per axis: lowest and highest tile node touched
   const long long bid = xcd_block(B.nbricks);
   if (bid < 0) return;
+  if (threadIdx.x < 6) s_box[threadIdx.x] = threadIdx.x < 3 ? 0x7fff : -1;
   const int rows = B.bdim[0] * B.bdim[1] * B.bdim[2];
   const long long base = bid * (long long)rows;
   const int r4 = (rows + 3) & ~3;
@@ -2111,6 +2114,9 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
   const int nr = s_rows;
   const int used = ((s_pos + kPagePos - 1) / kPagePos) * kPagePos;
   const long long q0 = bid * (long long)cap * kPagePos;   // first position of the brick
+  // tile nodes touched by the blocks that scatter into the tile (their cell
+  // and the next node along each axis)
+  int blo[3] = {0x7fff, 0x7fff, 0x7fff}, bhi[3] = {-1, -1, -1};
   // one thread per destination position: coalesced writes; the source row
   // is the last row whose first position is at or before it
   for (int q = threadIdx.x; q < used; q += blockDim.x) {
@@ -2129,6 +2135,22 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
     if (valid) {
       const long long slot = base + row;
       int cw = cells[(long long)k * nslots + slot];
+      {
+        int t[3] = {0, 0, 0};
+        bool tin = true;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+          t[ax] = ((cw >> (10 * ax)) & 1023) - 512;
+          tin = tin && t[ax] >= 0 && t[ax] + 1 < B.tdim[ax];
+        }
+        if (tin) {
+#pragma unroll
+          for (int ax = 0; ax < D; ++ax) {
+            blo[ax] = min(blo[ax], t[ax]);
+            bhi[ax] = max(bhi[ax], t[ax] + 1);
+          }
+        }
+      }
       if (k == 0) cw |= kJacHead;
       pc[qq] = cw;
       prow[qq] = k == 0 ? row : -1;
@@ -2138,6 +2160,32 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
       pc[qq] = -1;
       prow[qq] = -1;
     }
+  }
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      blo[ax] = min(blo[ax], __shfl_xor(blo[ax], off, 64));
+      bhi[ax] = max(bhi[ax], __shfl_xor(bhi[ax], off, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      atomicMin(&s_box[ax], blo[ax]);
+      atomicMax(&s_box[3 + ax], bhi[ax]);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // packed per axis as lo | hi << 16; an empty box has lo > hi; the axes
+    // beyond D span the single tile node 0
+    int w[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      const int lo = ax < D ? s_box[ax] : 0, hi = ax < D ? s_box[3 + ax] : 0;
+      w[ax] = lo <= hi ? (lo | (hi << 16)) : 1;
+    }
+    box[bid] = make_int4(w[0], w[1], w[2], 0);
   }
 }
 
@@ -2200,7 +2248,8 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
                const int* __restrict__ prow, const int* __restrict__ npages, const int* __restrict__ order,
                int cap, const typename VecT<D>::T* __restrict__ pp,
                const float* __restrict__ wvox, const float* __restrict__ wseed, float scale,
-               float* __restrict__ out, float* __restrict__ part, int* __restrict__ redo) {
+               float* __restrict__ out, float* __restrict__ part, int* __restrict__ redo,
+               const int4* __restrict__ box) {
   if (halted(g.halt)) return;
   extern __shared__ float lds[];
   const long long lb = xcd_block(B.nbricks);
@@ -2408,9 +2457,24 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
     e = ee;
   }
   __syncthreads();
+  // Only the tile nodes the brick's blocks touch (the box k_jac_pack
+  // recorded) are read by the tile reduction: write the box's planes, each
+  // as the contiguous run of its rows y0 .. y1 (whole rows along x).
   float* dst = part + bid * (long long)tot;
   const float nan = __int_as_float(0x7fc00000);
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) dst[i] = finite ? ldexpf((float)tile[i], -e) : nan;
+  const int4 bx = box[bid];
+  const int y0 = bx.y & 0xffff, z0 = bx.z & 0xffff;
+  const int run = ((bx.y >> 16) - y0 + 1) * B.tdim[0];     // values per plane
+  const int nz = (bx.z >> 16) - z0 + 1;
+  if (run > 0 && nz > 0 && (bx.x >> 16) >= (bx.x & 0xffff)) {
+    const int per = nz * run;
+    for (int i = threadIdx.x; i < D * per; i += blockDim.x) {
+      const int f = i / per, r = i - f * per;
+      const int z = r / run, j = r - z * run;
+      const int t = f * B.tvol + ((z0 + z) * B.tdim[1] + y0) * B.tdim[0] + j;
+      dst[t] = finite ? ldexpf((float)tile[t], -e) : nan;
+    }
+  }
 }
 
 // Sum the partial tiles into the velocity-grid output in a fixed order:
@@ -2419,11 +2483,18 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
 // out-of-tile atomics, so out needs no fill beforehand).  With
 // K > 0 (at most K covering bricks per axis) all loads are issued before the
 // sum, which adds the same terms in the same order as the generic loops.
+// Tile node (x, y, z) lies in the packed box q (lo | hi << 16 per axis).
+__device__ __forceinline__ bool in_box(const int4 q, int x, int y, int z) {
+  return x >= (q.x & 0xffff) && x <= (q.x >> 16) && y >= (q.y & 0xffff) && y <= (q.y >> 16) &&
+         z >= (q.z & 0xffff) && z <= (q.z >> 16);
+}
+
 template <int D, int K>
 __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fields, const float* __restrict__ part,
                                           const int* __restrict__ cs0, const int2* __restrict__ ce0,
                                           const int* __restrict__ cs1, const int2* __restrict__ ce1,
-                                          const int* __restrict__ cs2, const int2* __restrict__ ce2, long long i) {
+                                          const int* __restrict__ cs2, const int2* __restrict__ ce2,
+                                          const int4* __restrict__ box, long long i) {
   const long long f = i / g.nv, r = i - f * g.nv;
   const int X = (int)(r % g.mv[0]);
   const int Y = (int)((r / g.mv[0]) % g.mv[1]);
@@ -2453,7 +2524,7 @@ __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fie
           if (kz < nz && ky < ny && kx < nx) {
             const long long b = cx[kx].x + (long long)B.nb[0] * (cy[ky].x + B.nb[1] * cz[kz].x);
             const int t = cx[kx].y + B.tdim[0] * (cy[ky].y + B.tdim[1] * cz[kz].y);
-            v[kz][ky][kx] = pf[b * tsz + t];
+            if (!box || in_box(box[b], cx[kx].y, cy[ky].y, cz[kz].y)) v[kz][ky][kx] = pf[b * tsz + t];
           }
         }
 #pragma unroll
@@ -2474,7 +2545,7 @@ __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fie
           const int2 cx = ce0[ex];
           const long long b = cx.x + (long long)B.nb[0] * bzy;
           const int t = cx.y + B.tdim[0] * tzy;
-          sum += pf[b * tsz + t];
+          if (!box || in_box(box[b], cx.y, cy.y, cz.y)) sum += pf[b * tsz + t];
         }
       }
     }
@@ -2491,13 +2562,13 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
                                                         const int* __restrict__ cs1, const int2* __restrict__ ce1,
                                                         const int* __restrict__ cs2, const int2* __restrict__ ce2,
                                                         float* __restrict__ fb, float* __restrict__ out, RegTail rt,
-                                                        Deferred dq) {
+                                                        Deferred dq, const int4* __restrict__ box) {
   if (halted(g.halt)) return;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < g.nv * fields;
   float val = 0.f;
   if (valid) {
-    const float sum = tile_sum<D, K>(g, B, fields, part, cs0, ce0, cs1, ce1, cs2, ce2, i);
+    const float sum = tile_sum<D, K>(g, B, fields, part, cs0, ce0, cs1, ce1, cs2, ce2, box, i);
     float t;
     if (fb) {
       t = sum + fb[i];
@@ -2531,7 +2602,8 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
   }
 }
 
-int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred) {
+int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred,
+                       const int4* box) {
   const long long tot = P->geo.nv * P->fields;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
   const RegTail none;
@@ -2542,7 +2614,7 @@ int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const R
 #define LAG_REDUCE(DIM, K, RG)                                                                                   \
   hipLaunchKernelGGL((k_tile_reduce<DIM, K, RG>), dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields,  \
                      P->tile_part, P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1],       \
-                     P->cover_start[2], P->cover_ent[2], fb, out, r, dq)
+                     P->cover_start[2], P->cover_ent[2], fb, out, r, dq, box)
 #define LAG_REDUCE_K(DIM, RG)          \
   do {                                 \
     if (P->cover_max <= 3)             \
@@ -2842,10 +2914,10 @@ int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u,
     unsigned pgrid = grid_for(B.nbricks);
     if (P->geo.dim == 3)
       hipLaunchKernelGGL(k_jac_pack<3>, dim3(pgrid), dim3(kBlock), plds, s, B, P->jac_vals, P->jac_cell, P->jac_cnt,
-                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages);
+                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages, P->pg_box);
     else
       hipLaunchKernelGGL(k_jac_pack<2>, dim3(pgrid), dim3(kBlock), plds, s, B, P->jac_vals, P->jac_cell, P->jac_cnt,
-                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages);
+                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages, P->pg_box);
     LAG_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_brick_order, dim3(1), dim3(1024), 0, s, P->pg_npages, B.nbricks, P->pg_order);
     LAG_LAUNCH_CHECK();
@@ -2871,7 +2943,7 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
 #define LAG_PG(DD, WS, WV, VT)                                                                                    \
   hipLaunchKernelGGL((k_jac_apply_pg<DD, WS, WV>), dim3(grid), dim3(kPgBlock), plds, s, P->geo, B, P->pg_vals,     \
                      P->pg_cells, P->pg_rows, P->pg_npages, P->pg_order, P->pg_cap, (const VT*)ppack,              \
-                     wvox, wseed, scale, P->jac_fb, P->tile_part, P->pg_redo)
+                     wvox, wseed, scale, P->jac_fb, P->tile_part, P->pg_redo, P->pg_box)
     if (P->geo.dim == 3) {
       if (wseed) LAG_PG(3, true, false, float4);
       else if (wvox) LAG_PG(3, false, true, float4);
@@ -2893,7 +2965,8 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
   }
   if (!wseed) prof_end(P, s);
   LAG_LAUNCH_CHECK();
-  return launch_tile_reduce(P, out, P->jac_fb, s, rt);  // assigns out
+  // assigns out; the paged product wrote only each brick's box
+  return launch_tile_reduce(P, out, P->jac_fb, s, rt, false, P->pg_cap > 0 ? P->pg_box : nullptr);
 }
 
 }  // namespace lag
