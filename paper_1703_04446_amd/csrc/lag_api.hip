@@ -169,7 +169,9 @@ static void free_plan(lag_plan P) {
                   P->fft_mu1, P->flags, P->tile_part, P->cover_start[0], P->cover_start[1],
                   P->cover_start[2], P->cover_ent[0], P->cover_ent[1], P->cover_ent[2], P->jac_vals,
                   P->jac_cell, P->jac_cnt, P->jac_max, P->jac_fb, P->pg_vals, P->pg_cells, P->pg_rows,
-                  P->pg_npages, P->pg_order, P->pg_box, P->pg_redo, P->dfr_list, P->dfr_hdr, P->dfr_acc};
+                  P->pg_npages, P->pg_order, P->pg_redo, P->dfr_list, P->dfr_hdr, P->dfr_acc, P->pg_axbox,
+                  P->pgc_start[0], P->pgc_start[1], P->pgc_start[2], P->pgc_ent[0], P->pgc_ent[1],
+                  P->pgc_ent[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->ctl) (void)hipFree(P->ctl);
@@ -434,7 +436,6 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
       ALLOC(P->pg_rows, sizeof(int) * chunks * 64);
       ALLOC(P->pg_npages, sizeof(int) * (size_t)B.nbricks);
       ALLOC(P->pg_order, sizeof(int) * (size_t)B.nbricks);
-      ALLOC(P->pg_box, sizeof(int4) * (size_t)B.nbricks);
       ALLOC(P->pg_redo, sizeof(int));
       HIPC(hipMemset(P->pg_redo, 0, sizeof(int)));
     }
@@ -737,11 +738,10 @@ static bool jacobian_grow(lag_plan P, int need) {
   P->pg_cells = npc;
   P->pg_rows = npr;
   P->pg_cap = pcap;
-  if (pcap > 0 && (!P->pg_npages || !P->pg_order || !P->pg_box || !P->pg_redo)) {
+  if (pcap > 0 && (!P->pg_npages || !P->pg_order || !P->pg_redo)) {
     const size_t nb = sizeof(int) * (size_t)P->bricks.nbricks;
     if ((!P->pg_npages && hipMalloc(&P->pg_npages, nb) != hipSuccess) ||
         (!P->pg_order && hipMalloc(&P->pg_order, nb) != hipSuccess) ||
-        (!P->pg_box && hipMalloc(&P->pg_box, 4 * nb) != hipSuccess) ||
         (!P->pg_redo && (hipMalloc(&P->pg_redo, sizeof(int)) != hipSuccess ||
                          hipMemset(P->pg_redo, 0, sizeof(int)) != hipSuccess))) {
       (void)hipGetLastError();

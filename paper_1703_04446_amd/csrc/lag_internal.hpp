@@ -75,7 +75,6 @@ struct lag_plan_s {
   int* pg_rows = nullptr;
   int* pg_npages = nullptr;
   int* pg_order = nullptr;     // launch order of the bricks (k_brick_order)
-  int4* pg_box = nullptr;      // per brick: tile nodes its stored blocks touch (k_jac_pack)
   int* pg_redo = nullptr;      // count of bricks whose product pass was redone at the exact scale
   // per-brick partial velocity tiles and, per axis, the list of (brick,
   // tile offset) pairs covering each velocity index (fixed-order reduction)
@@ -83,6 +82,14 @@ struct lag_plan_s {
   int* cover_start[3] = {nullptr, nullptr, nullptr};
   int2* cover_ent[3] = {nullptr, nullptr, nullptr};
   int cover_max = 0;  // most covering bricks of a node along one axis
+  // the paged product writes, per brick, only the tile nodes that the bricks
+  // sharing its index along each axis touch: per axis and brick index the
+  // lowest and highest tile node (lo at [off[a] + i], hi at [nb_sum + off[a]
+  // + i], off = 0, nb[0], nb[0] + nb[1]), and the cover lists restricted to
+  // those nodes (k_jac_pack, k_cover_filter, once per assembly)
+  int* pg_axbox = nullptr;
+  int* pgc_start[3] = {nullptr, nullptr, nullptr};
+  int2* pgc_ent[3] = {nullptr, nullptr, nullptr};
   // assembled matvec: out-of-tile contributions (float atomics), added and
   // cleared by the tile reduction, so outputs need no fill beforehand
   float* jac_fb = nullptr;
@@ -171,10 +178,10 @@ int launch_vjp(lag_plan P, const void* vpack, const float* T, const float* w, fl
                hipStream_t s, bool zero = false);
 int launch_hess_transport(lag_plan P, const void* vpack, const void* ppack, const float* T,
                           const float* wvox, float* out, hipStream_t s);
-// box (may be null): per brick, the tile nodes its partial tile holds; the
-// other nodes of its tile are not read (they count as zero)
+// paged: the partial tiles of the paged product, read through the
+// restricted cover lists (the nodes they leave out count as zero)
 int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred = false,
-                       const int4* box = nullptr);
+                       bool paged = false);
 // LDS of the matrix-free adjoint kernel (64-bit tile of the plan's bricks)
 size_t adjoint_lds_bytes(lag_plan P);
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);

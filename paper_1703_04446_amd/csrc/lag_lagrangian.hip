@@ -2038,7 +2038,7 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
                                                      const unsigned char* __restrict__ cnt, long long nslots,
                                                      int cap, float4* __restrict__ pv, int* __restrict__ pc,
                                                      int* __restrict__ prow, int* __restrict__ npages,
-                                                     int4* __restrict__ box) {
+                                                     int* __restrict__ axbox) {
   constexpr int NV4 = JacLayout<D>::NV4;
   // LDS: the rows that hold blocks (slot within the brick) and their first
   // positions (increasing), then the counts of all rows
@@ -2177,16 +2177,75 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // packed per axis as lo | hi << 16; an empty box has lo > hi; the axes
-    // beyond D span the single tile node 0
-    int w[3];
-    for (int ax = 0; ax < 3; ++ax) {
-      const int lo = ax < D ? s_box[ax] : 0, hi = ax < D ? s_box[3 + ax] : 0;
-      w[ax] = lo <= hi ? (lo | (hi << 16)) : 1;
+  if (threadIdx.x == 0 && s_box[0] <= s_box[3]) {
+    // into the box of every brick index of this brick along each axis
+    const int bi[3] = {(int)(bid % B.nb[0]), (int)((bid / B.nb[0]) % B.nb[1]), (int)(bid / ((long long)B.nb[0] * B.nb[1]))};
+    const int off[3] = {0, B.nb[0], B.nb[0] + B.nb[1]}, nbs = B.nb[0] + B.nb[1] + B.nb[2];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      atomicMin(&axbox[off[ax] + bi[ax]], s_box[ax]);
+      atomicMax(&axbox[nbs + off[ax] + bi[ax]], s_box[3 + ax]);
     }
-    box[bid] = make_int4(w[0], w[1], w[2], 0);
   }
+}
+
+// Empty axis boxes (lo above hi) before the pack fills them.
+__global__ void k_axbox_init(int* __restrict__ axbox, int nbs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 2 * nbs) axbox[i] = i < nbs ? 0x7fff : -1;
+}
+
+// The cover lists of the paged product: per axis a and velocity index X,
+// the (brick index, tile node) entries of the full lists whose node lies in
+// that brick index's axis box, in the same order.  One block per axis
+// (axes beyond the dimension keep their lists); a block-wide scan in chunks
+// of blockDim places them.
+__global__ void __launch_bounds__(1024) k_cover_filter(int D, int3 mv, int3 nb, const int* __restrict__ axbox,
+                                                      const int* __restrict__ cs0, const int2* __restrict__ ce0,
+                                                      const int* __restrict__ cs1, const int2* __restrict__ ce1,
+                                                      const int* __restrict__ cs2, const int2* __restrict__ ce2,
+                                                      int* __restrict__ os0, int2* __restrict__ oe0,
+                                                      int* __restrict__ os1, int2* __restrict__ oe1,
+                                                      int* __restrict__ os2, int2* __restrict__ oe2) {
+  __shared__ int sh[1024];
+  __shared__ int carry;
+  const int a = blockIdx.x;
+  const int m = a == 0 ? mv.x : (a == 1 ? mv.y : mv.z);
+  const int* cs = a == 0 ? cs0 : (a == 1 ? cs1 : cs2);
+  const int2* ce = a == 0 ? ce0 : (a == 1 ? ce1 : ce2);
+  int* os = a == 0 ? os0 : (a == 1 ? os1 : os2);
+  int2* oe = a == 0 ? oe0 : (a == 1 ? oe1 : oe2);
+  const int off = a == 0 ? 0 : (a == 1 ? nb.x : nb.x + nb.y), nbs = nb.x + nb.y + nb.z;
+  auto keep = [&](int2 e) {
+    return a >= D || (e.y >= axbox[off + e.x] && e.y <= axbox[nbs + off + e.x]);
+  };
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int X0 = 0; X0 < m; X0 += blockDim.x) {
+    const int X = X0 + threadIdx.x;
+    int n = 0;
+    if (X < m)
+      for (int e = cs[X]; e < cs[X + 1]; ++e) n += keep(ce[e]);
+    sh[threadIdx.x] = n;
+    __syncthreads();
+    for (int d = 1; d < (int)blockDim.x; d <<= 1) {   // inclusive scan
+      const int t = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const int base = carry + sh[threadIdx.x] - n;
+    if (X < m) {
+      os[X] = base;
+      int k = base;
+      for (int e = cs[X]; e < cs[X + 1]; ++e)
+        if (keep(ce[e])) oe[k++] = ce[e];
+    }
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) carry = base + n;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) os[m] = carry;
 }
 
 // Launch order of the bricks for the paged product: within each XCD's
@@ -2249,7 +2308,7 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
                int cap, const typename VecT<D>::T* __restrict__ pp,
                const float* __restrict__ wvox, const float* __restrict__ wseed, float scale,
                float* __restrict__ out, float* __restrict__ part, int* __restrict__ redo,
-               const int4* __restrict__ box) {
+               const int* __restrict__ axbox) {
   if (halted(g.halt)) return;
   extern __shared__ float lds[];
   const long long lb = xcd_block(B.nbricks);
@@ -2457,16 +2516,20 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
     e = ee;
   }
   __syncthreads();
-  // Only the tile nodes the brick's blocks touch (the box k_jac_pack
-  // recorded) are read by the tile reduction: write the box's planes, each
-  // as the contiguous run of its rows y0 .. y1 (whole rows along x).
+  // The tile reduction reads only the nodes inside the axis boxes of the
+  // brick's indices (k_jac_pack, k_cover_filter): write the planes z0 .. z1
+  // of those, each as the contiguous run of its rows y0 .. y1 (whole rows
+  // along x).
   float* dst = part + bid * (long long)tot;
   const float nan = __int_as_float(0x7fc00000);
-  const int4 bx = box[bid];
-  const int y0 = bx.y & 0xffff, z0 = bx.z & 0xffff;
-  const int run = ((bx.y >> 16) - y0 + 1) * B.tdim[0];     // values per plane
-  const int nz = (bx.z >> 16) - z0 + 1;
-  if (run > 0 && nz > 0 && (bx.x >> 16) >= (bx.x & 0xffff)) {
+  const int nbs = B.nb[0] + B.nb[1] + B.nb[2];
+  const int by = (int)((bid / B.nb[0]) % B.nb[1]), bz = (int)(bid / ((long long)B.nb[0] * B.nb[1]));
+  const int y0 = axbox[B.nb[0] + by], y1 = axbox[nbs + B.nb[0] + by];
+  const int z0 = D == 3 ? axbox[B.nb[0] + B.nb[1] + bz] : 0;
+  const int z1 = D == 3 ? axbox[nbs + B.nb[0] + B.nb[1] + bz] : 0;
+  const int run = (y1 - y0 + 1) * B.tdim[0];     // values per plane
+  const int nz = z1 - z0 + 1;
+  if (run > 0 && nz > 0) {
     const int per = nz * run;
     for (int i = threadIdx.x; i < D * per; i += blockDim.x) {
       const int f = i / per, r = i - f * per;
@@ -2483,18 +2546,11 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
 // out-of-tile atomics, so out needs no fill beforehand).  With
 // K > 0 (at most K covering bricks per axis) all loads are issued before the
 // sum, which adds the same terms in the same order as the generic loops.
-// Tile node (x, y, z) lies in the packed box q (lo | hi << 16 per axis).
-__device__ __forceinline__ bool in_box(const int4 q, int x, int y, int z) {
-  return x >= (q.x & 0xffff) && x <= (q.x >> 16) && y >= (q.y & 0xffff) && y <= (q.y >> 16) &&
-         z >= (q.z & 0xffff) && z <= (q.z >> 16);
-}
-
 template <int D, int K>
 __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fields, const float* __restrict__ part,
                                           const int* __restrict__ cs0, const int2* __restrict__ ce0,
                                           const int* __restrict__ cs1, const int2* __restrict__ ce1,
-                                          const int* __restrict__ cs2, const int2* __restrict__ ce2,
-                                          const int4* __restrict__ box, long long i) {
+                                          const int* __restrict__ cs2, const int2* __restrict__ ce2, long long i) {
   const long long f = i / g.nv, r = i - f * g.nv;
   const int X = (int)(r % g.mv[0]);
   const int Y = (int)((r / g.mv[0]) % g.mv[1]);
@@ -2524,7 +2580,7 @@ __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fie
           if (kz < nz && ky < ny && kx < nx) {
             const long long b = cx[kx].x + (long long)B.nb[0] * (cy[ky].x + B.nb[1] * cz[kz].x);
             const int t = cx[kx].y + B.tdim[0] * (cy[ky].y + B.tdim[1] * cz[kz].y);
-            if (!box || in_box(box[b], cx[kx].y, cy[ky].y, cz[kz].y)) v[kz][ky][kx] = pf[b * tsz + t];
+            v[kz][ky][kx] = pf[b * tsz + t];
           }
         }
 #pragma unroll
@@ -2545,7 +2601,7 @@ __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fie
           const int2 cx = ce0[ex];
           const long long b = cx.x + (long long)B.nb[0] * bzy;
           const int t = cx.y + B.tdim[0] * tzy;
-          if (!box || in_box(box[b], cx.y, cy.y, cz.y)) sum += pf[b * tsz + t];
+          sum += pf[b * tsz + t];
         }
       }
     }
@@ -2562,13 +2618,13 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
                                                         const int* __restrict__ cs1, const int2* __restrict__ ce1,
                                                         const int* __restrict__ cs2, const int2* __restrict__ ce2,
                                                         float* __restrict__ fb, float* __restrict__ out, RegTail rt,
-                                                        Deferred dq, const int4* __restrict__ box) {
+                                                        Deferred dq) {
   if (halted(g.halt)) return;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < g.nv * fields;
   float val = 0.f;
   if (valid) {
-    const float sum = tile_sum<D, K>(g, B, fields, part, cs0, ce0, cs1, ce1, cs2, ce2, box, i);
+    const float sum = tile_sum<D, K>(g, B, fields, part, cs0, ce0, cs1, ce1, cs2, ce2, i);
     float t;
     if (fb) {
       t = sum + fb[i];
@@ -2603,7 +2659,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
 }
 
 int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const RegTail* rt, bool deferred,
-                       const int4* box) {
+                       bool paged) {
   const long long tot = P->geo.nv * P->fields;
   unsigned grid = (unsigned)((tot + kBlock - 1) / kBlock);
   const RegTail none;
@@ -2611,10 +2667,11 @@ int launch_tile_reduce(lag_plan P, float* out, float* fb, hipStream_t s, const R
   Deferred dq{nullptr, nullptr, nullptr};
   if (deferred) dq = Deferred{P->dfr_list, P->dfr_hdr, P->dfr_acc};
   const int reg = r.p ? (r.curv ? 2 : 1) : 0;
+  int* const* cs = paged ? P->pgc_start : P->cover_start;
+  int2* const* ce = paged ? P->pgc_ent : P->cover_ent;
 #define LAG_REDUCE(DIM, K, RG)                                                                                   \
   hipLaunchKernelGGL((k_tile_reduce<DIM, K, RG>), dim3(grid), dim3(kBlock), 0, s, P->geo, P->bricks, P->fields,  \
-                     P->tile_part, P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1],       \
-                     P->cover_start[2], P->cover_ent[2], fb, out, r, dq, box)
+                     P->tile_part, cs[0], ce[0], cs[1], ce[1], cs[2], ce[2], fb, out, r, dq)
 #define LAG_REDUCE_K(DIM, RG)          \
   do {                                 \
     if (P->cover_max <= 3)             \
@@ -2670,7 +2727,11 @@ int tiles_setup(lag_plan P) {
     LAG_HIP(hipMalloc(&P->cover_ent[a], sizeof(int2) * std::max<size_t>(ent.size(), 1)));
     LAG_HIP(hipMemcpy(P->cover_start[a], start.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice));
     LAG_HIP(hipMemcpy(P->cover_ent[a], ent.data(), sizeof(int2) * ent.size(), hipMemcpyHostToDevice));
+    // the paged product's restricted lists (filled after each assembly)
+    LAG_HIP(hipMalloc(&P->pgc_start[a], sizeof(int) * (m + 1)));
+    LAG_HIP(hipMalloc(&P->pgc_ent[a], sizeof(int2) * std::max<size_t>(ent.size(), 1)));
   }
+  LAG_HIP(hipMalloc(&P->pg_axbox, sizeof(int) * 2 * (size_t)(B.nb[0] + B.nb[1] + B.nb[2])));
   return LAG_OK;
 }
 
@@ -2912,12 +2973,21 @@ int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u,
     const size_t prows = (size_t)B.bdim[0] * B.bdim[1] * B.bdim[2];
     const size_t plds = 2 * sizeof(int) * ((prows + 3) & ~(size_t)3) + ((prows + 63) & ~(size_t)63);
     unsigned pgrid = grid_for(B.nbricks);
+    const int nbs = B.nb[0] + B.nb[1] + B.nb[2];
+    hipLaunchKernelGGL(k_axbox_init, dim3((2 * nbs + 255) / 256), dim3(256), 0, s, P->pg_axbox, nbs);
+    LAG_LAUNCH_CHECK();
     if (P->geo.dim == 3)
       hipLaunchKernelGGL(k_jac_pack<3>, dim3(pgrid), dim3(kBlock), plds, s, B, P->jac_vals, P->jac_cell, P->jac_cnt,
-                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages, P->pg_box);
+                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages, P->pg_axbox);
     else
       hipLaunchKernelGGL(k_jac_pack<2>, dim3(pgrid), dim3(kBlock), plds, s, B, P->jac_vals, P->jac_cell, P->jac_cnt,
-                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages, P->pg_box);
+                         P->jac_slots, P->pg_cap, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages, P->pg_axbox);
+    LAG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cover_filter, dim3(3), dim3(1024), 0, s, P->geo.dim,
+                       make_int3(P->geo.mv[0], P->geo.mv[1], P->geo.mv[2]), make_int3(B.nb[0], B.nb[1], B.nb[2]),
+                       P->pg_axbox, P->cover_start[0], P->cover_ent[0], P->cover_start[1], P->cover_ent[1],
+                       P->cover_start[2], P->cover_ent[2], P->pgc_start[0], P->pgc_ent[0], P->pgc_start[1],
+                       P->pgc_ent[1], P->pgc_start[2], P->pgc_ent[2]);
     LAG_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_brick_order, dim3(1), dim3(1024), 0, s, P->pg_npages, B.nbricks, P->pg_order);
     LAG_LAUNCH_CHECK();
@@ -2943,7 +3013,7 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
 #define LAG_PG(DD, WS, WV, VT)                                                                                    \
   hipLaunchKernelGGL((k_jac_apply_pg<DD, WS, WV>), dim3(grid), dim3(kPgBlock), plds, s, P->geo, B, P->pg_vals,     \
                      P->pg_cells, P->pg_rows, P->pg_npages, P->pg_order, P->pg_cap, (const VT*)ppack,              \
-                     wvox, wseed, scale, P->jac_fb, P->tile_part, P->pg_redo, P->pg_box)
+                     wvox, wseed, scale, P->jac_fb, P->tile_part, P->pg_redo, P->pg_axbox)
     if (P->geo.dim == 3) {
       if (wseed) LAG_PG(3, true, false, float4);
       else if (wvox) LAG_PG(3, false, true, float4);
@@ -2965,8 +3035,8 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
   }
   if (!wseed) prof_end(P, s);
   LAG_LAUNCH_CHECK();
-  // assigns out; the paged product wrote only each brick's box
-  return launch_tile_reduce(P, out, P->jac_fb, s, rt, false, P->pg_cap > 0 ? P->pg_box : nullptr);
+  // assigns out; the paged product wrote only the nodes its cover lists read
+  return launch_tile_reduce(P, out, P->jac_fb, s, rt, false, P->pg_cap > 0);
 }
 
 }  // namespace lag
