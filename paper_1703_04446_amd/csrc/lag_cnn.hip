@@ -11,15 +11,20 @@
 //   out  = scale * (dec0 @ Wh + bh)                                 (1x1 head)
 // Convolutions are 3x3x3 with periodic padding.  Activations are channel-
 // last bfloat16 (a convolution input row of 16 channels is one 32-byte
-// segment), pre-activations and gradients float32, master weights float32
-// with bfloat16 copies for the matrix cores.
+// segment), gradients float32, master weights float32 with bfloat16 copies
+// for the matrix cores.  No pre-activation is kept: the relu backward masks
+// with the stored bfloat16 activation, which is non-zero exactly where the
+// pre-activation is positive (down to 2^-133).
 //
-// Every 3x3x3 convolution is an implicit GEMM on the MFMA units
-// (v_mfma_f32_16x16x16_bf16: A 16x16 in lanes as A[l%16][4(l/16)+j],
-// B as B[4(l/16)+j][l%16], C as C[4(l/16)+j][l%16], j = 0..3):
+// Every 3x3x3 convolution is an implicit GEMM on the double-K MFMA
+// (v_mfma_f32_16x16x32_bf16: A[i][k] in lane i + 16 (k / 8), element k % 8;
+// B[k][n] in lane n + 16 (k / 8), element k % 8; C[m][n] in lane n + 16
+// (m / 4), element m % 4), with the halo tile and the weights staged in LDS:
 //   forward      out[v][co]  = sum_{t,ci} x[v+o_t][ci] W[t][ci][co]     (M=v,  N=co, K=t,ci)
 //   backward-in  gx[v][ci]   = sum_{t,co} g[v-o_t][co] W[t][ci][co]     (M=v,  N=ci, K=t,co)
 //   backward-W   gW[t][ci][co] = sum_v x[v+o_t][ci] g[v][co]            (M=ci, N=co, K=v)
+// Every gradient reduction (weights, biases, head) sums in a fixed order,
+// so a training step gives the same bits in every run.
 // Concatenation is never materialised by a copy: producers write into
 // channel slices of the concatenated buffer ("views": base, channel stride,
 // channel offset).
@@ -198,7 +203,7 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const unsigned short* __restr
           out[v * out_cs + n] = acc[i][nt][j];
         } else {
           const float val = acc[i][nt][j] + bias[n];
-          out[v * out_cs + n] = val;
+          if (out) out[v * out_cs + n] = val;
           act[v * act_cs + act_co + n] = f2bf(fmaxf(val, 0.f));
         }
       }
@@ -206,7 +211,8 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const unsigned short* __restr
 }
 
 // Sum of the split contraction in order of z, then the epilogue: forward
-// (bias) -> pre-activation, bf16 relu activation; backward -> gx.
+// (bias) -> bf16 relu activation (and the pre-activation if out != null);
+// backward -> gx.
 template <bool BWD>
 __global__ void k_conv_finish(const float* __restrict__ kpart, int kz, long long V, int nch,
                               const float* __restrict__ bias, float* __restrict__ out, unsigned short* __restrict__ act,
@@ -221,7 +227,7 @@ __global__ void k_conv_finish(const float* __restrict__ kpart, int kz, long long
     const int n = (int)(i % nch);
     const long long v = i / nch;
     const float val = sum + bias[n];
-    out[i] = val;
+    if (out) out[i] = val;
     act[v * act_cs + act_co + n] = f2bf(fmaxf(val, 0.f));
   }
 }
@@ -383,28 +389,52 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const unsigned short* __rest
   }
 }
 
-// G[t][ci][co] += sum over r of part[r][t][ci][co], ci < cin, in a fixed
-// order: a block takes 32 consecutive outputs; its 8 lane rows sum the
-// ranges r = row, row + 8, ... and the 8 row sums are added in a fixed tree.
+// G[t][ci][co] += sum over r of part[r][t][ci][co] (ci < cin) and, for the
+// outputs after those, gb[co] += sum over the blocks b < nb of
+// bpart[b][co], in a fixed order: a block takes OW consecutive outputs
+// (32: 128-byte rows for many outputs; 8: more blocks and more rows in
+// flight for few); its RW = 256 / OW lane rows sum the rows r = row, row +
+// RW, ... (four running sums, taking every fourth of them, added pairwise),
+// and the RW row sums are added in order.
+template <int OW>
 __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, int nr, int cin, int cin_pad,
-                                                      int cout, float* __restrict__ gw) {
-  __shared__ float sh[8][32];
-  const long long n = 27LL * cin * cout;
-  const int o = threadIdx.x & 31, row = threadIdx.x >> 5;
-  const long long i = (long long)blockIdx.x * 32 + o;
-  float s = 0.f;
-  if (i < n) {
+                                                      int cout, float* __restrict__ gw, const float* __restrict__ bpart,
+                                                      int nb, float* __restrict__ gb) {
+  constexpr int RW = 256 / OW;
+  __shared__ float sh[RW][OW];
+  const long long nw = 27LL * cin * cout;
+  const int o = threadIdx.x % OW, row = threadIdx.x / OW;
+  const long long i = (long long)blockIdx.x * OW + o;
+  float s4[4] = {0.f, 0.f, 0.f, 0.f};
+  const float* p = nullptr;
+  long long stride = 0;
+  int rows = 0;
+  if (i < nw) {
     const int co = (int)(i % cout);
     const int ci = (int)((i / cout) % cin);
     const int t = (int)(i / ((long long)cout * cin));
-    const long long stride = 27LL * cin_pad * cout;
-    const float* p = part + ((long long)t * cin_pad + ci) * cout + co;
-    for (int r = row; r < nr; r += 8) s += p[r * stride];
+    stride = 27LL * cin_pad * cout;
+    p = part + ((long long)t * cin_pad + ci) * cout + co;
+    rows = nr;
+  } else if (i < nw + cout) {
+    stride = cout;
+    p = bpart + (i - nw);
+    rows = nb;
   }
-  sh[row][o] = s;
+  int r = row;
+  for (; r + 3 * RW < rows; r += 4 * RW) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s4[k] += p[(r + RW * k) * stride];
+  }
+  for (int k = 0; r < rows; r += RW, ++k) s4[k] += p[r * stride];
+  sh[row][o] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   __syncthreads();
-  if (row == 0 && i < n)
-    gw[i] += ((sh[0][o] + sh[1][o]) + (sh[2][o] + sh[3][o])) + ((sh[4][o] + sh[5][o]) + (sh[6][o] + sh[7][o]));
+  if (row == 0) {
+    float tot = 0.f;
+    for (int q = 0; q < RW; ++q) tot += sh[q][o];
+    if (i < nw) gw[i] += tot;
+    else if (i < nw + cout) gb[i - nw] += tot;
+  }
 }
 
 // out[k] += sum over the rows b < nb of part[b][k]: one block per k, rows
@@ -471,11 +501,14 @@ __global__ void k_up(const unsigned short* __restrict__ in, int c, int s, unsign
       *reinterpret_cast<const uint4*>(in + (long long)pv * c + ch);
 }
 
-// gpre = g (float, view of width gcs at offset goff) masked by pre > 0;
-// writes the bf16 copy and the block's bias-gradient partials part[block][c]
-// (summed in block order by k_partial_reduce)
-__global__ void k_relu_back(const float* __restrict__ g, int gcs, int goff, const float* __restrict__ pre, int c,
-                            int V, unsigned short* __restrict__ gb, float* __restrict__ part) {
+// gpre = g (float, view of width gcs at offset goff) masked by the layer's
+// relu (its bf16 activation, view of width acs at offset aco, is non-zero
+// exactly where the pre-activation is positive); writes the bf16 copy and
+// the block's bias-gradient partials part[block][c] (summed in block order
+// by k_wgrad_reduce)
+__global__ void k_relu_back(const float* __restrict__ g, int gcs, int goff, const unsigned short* __restrict__ act,
+                            int acs, int aco, int c, int V, unsigned short* __restrict__ gb,
+                            float* __restrict__ part) {
   __shared__ float sh[256];
   // grid-stride: the stride is a multiple of 256, so a thread keeps its
   // channel (c divides 256 for c in {16, 32, 64}) and sums in a fixed order
@@ -484,7 +517,7 @@ __global__ void k_relu_back(const float* __restrict__ g, int gcs, int goff, cons
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const int ch = (int)(i % c);
     const long long v = i / c;
-    const float gi = pre[i] > 0.f ? g[v * gcs + goff + ch] : 0.f;
+    const float gi = (act[v * acs + aco + ch] & 0x7fff) != 0 ? g[v * gcs + goff + ch] : 0.f;
     gb[i] = f2bf(gi);
     val += gi;
   }
@@ -701,10 +734,11 @@ struct lag_cnn_s {
   float *P = nullptr, *G = nullptr, *M1 = nullptr, *M2 = nullptr;   // params, grads, Adam moments
   unsigned short* wf[kLayers] = {nullptr};
   unsigned short* wb[kLayers] = {nullptr};
-  // activations (bf16) and pre-activations (fp32)
+  // activations (bf16); per layer, the view its forward wrote its output to
   unsigned short* x0 = nullptr;      // S^3 x 16
   unsigned short* a[kLayers] = {nullptr};
-  float* pre[kLayers] = {nullptr};
+  unsigned short* actp[kLayers] = {nullptr};
+  int acs[kLayers] = {0}, aco[kLayers] = {0};
   unsigned short *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;   // pooled
   unsigned short *cat2 = nullptr, *cat1 = nullptr, *cat0 = nullptr;
   // gradients
@@ -727,8 +761,11 @@ static int conv_tiles(int s) {
   const ConvTile t = conv_tile(s);
   return (s >> t.lx) * (s >> t.ly) * (s >> t.lz);
 }
-static int wgrad_per_range(int s) { return ceil_div(conv_tiles(s), 512); }
-static int wgrad_ranges(int s) { return ceil_div(conv_tiles(s), wgrad_per_range(s)); }
+// tiles per voxel range of the weight gradient: about 512 blocks over the
+// ranges and the 16-channel input slices (fewer ranges for wide inputs keep
+// the partials, ranges x 27 x cin x cout floats, small)
+static int wgrad_per_range(int s, int cinp) { return ceil_div((long long)conv_tiles(s) * (cinp / 16), 512); }
+static int wgrad_ranges(int s, int cinp) { return ceil_div(conv_tiles(s), wgrad_per_range(s, cinp)); }
 
 // 16-channel output tiles per block: up to 4 on grids of side >= 32, else 1
 // (more blocks on the small grids)
@@ -772,7 +809,6 @@ int lag_cnn_destroy(lag_cnn n) {
     if (n->wf[l]) (void)hipFree(n->wf[l]);
     if (n->wb[l]) (void)hipFree(n->wb[l]);
     if (n->a[l]) (void)hipFree(n->a[l]);
-    if (n->pre[l]) (void)hipFree(n->pre[l]);
   }
   for (int i = 0; i < 4; ++i) {
     if (n->gbuf[i]) (void)hipFree(n->gbuf[i]);
@@ -853,9 +889,7 @@ int lag_cnn_create(const lag_cnn_config* cfg, lag_cnn* out) {
     const size_t wn = (size_t)kTaps * n->cinp[l] * n->cout[l];
     CNN_ALLOC(n->wf[l], 2 * wn);
     CNN_ALLOC(n->wb[l], 2 * wn);
-    wpart = std::max(wpart, (size_t)wgrad_ranges(sz[l]) * 27 * n->cinp[l] * n->cout[l]);
-    const long long V = (long long)sz[l] * sz[l] * sz[l];
-    CNN_ALLOC(n->pre[l], sizeof(float) * V * n->cout[l]);
+    wpart = std::max(wpart, (size_t)wgrad_ranges(sz[l], n->cinp[l]) * 27 * n->cinp[l] * n->cout[l]);
   }
   const long long V0 = (long long)S * S * S, V1 = V0 / 8, V2 = V1 / 8, V3 = V2 / 8;
   CNN_ALLOC(n->x0, 2 * V0 * 16);
@@ -958,8 +992,11 @@ static size_t conv_lds(ConvTile T, int nt) {
 static int conv_fwd(lag_cnn n, int l, const unsigned short* in, int in_cs, int in_co, unsigned short* act, int act_cs,
                     int act_co, hipStream_t s) {
   const int sz = n->lsize[l], cout = n->cout[l];
+  n->actp[l] = act;   // where the backward finds the relu mask
+  n->acs[l] = act_cs;
+  n->aco[l] = act_co;
   return launch_conv<false>(n, sz, cout, in, in_cs, in_co, n->cinp[l], n->wf[l], cout, n->cinp[l],
-                            n->P + n->boff[l], n->pre[l], act, act_cs, act_co, s);
+                            n->P + n->boff[l], nullptr, act, act_cs, act_co, s);
 }
 
 // backward through relu + conv l: g (float view of the layer output gradient)
@@ -969,15 +1006,13 @@ static int conv_bwd(lag_cnn n, int l, const float* g, int gcs, int goff, const u
   const int sz = n->lsize[l], cout = n->cout[l], cin = n->cinp[l];
   const long long V = (long long)sz * sz * sz;
   const int nb = std::min(ceil_div(V * cout, 256), 1024);
-  hipLaunchKernelGGL(k_relu_back, dim3(nb), dim3(256), 0, s, g, gcs, goff, n->pre[l], cout, (int)V, n->gb16,
-                     n->bpart);
-  LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_rows_reduce, dim3(cout), dim3(256), 0, s, n->bpart, nb, cout, n->G + n->boff[l]);
+  hipLaunchKernelGGL(k_relu_back, dim3(nb), dim3(256), 0, s, g, gcs, goff, n->actp[l], n->acs[l], n->aco[l], cout,
+                     (int)V, n->gb16, n->bpart);
   LAG_LAUNCH_CHECK();
   // weight gradient: partials per voxel range, then their fixed-order sum into G
   const ConvTile T = conv_tile(sz);
   const int NV = 1 << (T.lx + T.ly + T.lz);
-  const int tpr = wgrad_per_range(sz), nr = wgrad_ranges(sz);
+  const int tpr = wgrad_per_range(sz, cin), nr = wgrad_ranges(sz, cin);
   const size_t lds = sizeof(unsigned short) * ((size_t)cout * NV +
                                                16 * 16 * (size_t)(((1 << T.ly) + 2) * ((1 << T.lz) + 2)));
   const dim3 wg(nr, cin / 16);
@@ -987,8 +1022,14 @@ static int conv_bwd(lag_cnn n, int l, const float* g, int gcs, int goff, const u
     default: hipLaunchKernelGGL(k_conv_wgrad<4>, wg, dim3(256), lds, s, in, in_cs, in_co, sz, T, n->gb16, cout, tpr, cin, n->wpart); break;
   }
   LAG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(27LL * n->cin[l] * cout, 32)), dim3(256), 0, s, n->wpart, nr,
-                     n->cin[l], cin, cout, n->G + n->woff[l]);
+  // weight and bias gradients: fixed-order sums of the partials
+  const long long nout = 27LL * n->cin[l] * cout + cout;
+  if (ceil_div(nout, 32) >= 1024)
+    hipLaunchKernelGGL(k_wgrad_reduce<32>, dim3(ceil_div(nout, 32)), dim3(256), 0, s, n->wpart, nr, n->cin[l], cin,
+                       cout, n->G + n->woff[l], n->bpart, nb, n->G + n->boff[l]);
+  else
+    hipLaunchKernelGGL(k_wgrad_reduce<8>, dim3(ceil_div(nout, 8)), dim3(256), 0, s, n->wpart, nr, n->cin[l], cin,
+                       cout, n->G + n->woff[l], n->bpart, nb, n->G + n->boff[l]);
   LAG_LAUNCH_CHECK();
   if (gx) {
     const int rc = launch_conv<true>(n, sz, cin, n->gb16, cout, 0, cout, n->wb[l], cin, cout, nullptr, gx, nullptr, 0,
