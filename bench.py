@@ -24,6 +24,8 @@ The JSON line also carries:
   batch        - 80 uneven 2-D/3-D transport/continuity pairs solved one
                  after another on one stream against lag_batch_solve
                  (worker streams, graph-replayed PCG, autotuned bricks);
+  warm_start_kernels - forward and training-step TFLOP/s of the warm-start
+                 network's MFMA kernels at 64^3 (HIP events);
   warm_start   - the second headline figure: wall time of a full
                  Gauss-Newton solve from v = 0 against the solve refined
                  from the warm-start network's prediction on 10 held-out
@@ -96,6 +98,8 @@ def parse():
     ap.add_argument("--warm-start-steps", type=int, default=4000,
                     help="training steps of the warm-start network (0 = skip the warm-start measurement)")
     ap.add_argument("--ws-pairs", type=int, default=2000, help="warm-start training pairs")
+    ap.add_argument("--cnn-timing-steps", type=int, default=20,
+                    help="timed forward and training steps of the warm-start network's kernels (0 = skip)")
     ap.add_argument("--ws-templates", type=int, default=50, help="distinct templates among the training pairs")
     ap.add_argument("--ws-lr", type=float, default=5e-4, help="Adam learning rate of the warm-start network")
     ap.add_argument("--batch-pairs", type=int, default=80,
@@ -399,6 +403,52 @@ def solve_comparison(L, torch):
             "gpu_gn_iters": info["iters"], "gpu_pcg_iters": info["pcg_iters"],
             "gpu_J_reduction": round(1.0 - info["J"] / info["J0"], 4),
             "speedup": round(t_oracle * 1e3 / gpu_ms, 1)}
+
+
+def cnn_throughput(args, L, torch):
+    """Throughput of the warm-start network's kernels at its training size
+    (the 64^3 velocity grid, channels of the default configuration):
+    forward, and a training step (forward, loss, backward with every weight
+    and bias gradient and every input gradient but the first layer's), on
+    random inputs, timed with HIP events on the stream the kernels run on.
+    FLOPs count the 3x3x3 convolutions with their true input widths (2 for
+    the first layer)."""
+    cfg = L.lag_cnn_default_config()
+    S = cfg.size = 64
+    c0, c1, c2, c3 = (int(cfg.channels[i]) for i in range(4))
+    io = [(2, c0, S), (c0, c0, S), (c0, c1, S // 2), (c1, c1, S // 2), (c1, c2, S // 4), (c2, c2, S // 4),
+          (c2, c3, S // 8), (c3, c3, S // 8), (c3 + c2, c2, S // 4), (c2 + c1, c1, S // 2), (c1 + c0, c0, S)]
+    fwd = sum(2 * 27 * ci * co * s ** 3 for ci, co, s in io)
+    train = 3 * fwd - 2 * 27 * 2 * c0 * S ** 3
+    net = L.Cnn(cfg)
+    rng = np.random.default_rng(7)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()  # noqa: E731
+    T, R = dev(rng.random(S ** 3)), dev(rng.random(S ** 3))
+    tgt = dev(0.05 * rng.standard_normal(3 * S ** 3))
+    v = torch.empty(3 * S ** 3, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        L.lag_cnn_forward(net, T, R, v)
+        L.lag_cnn_backward(net, T, R, tgt, v, loss)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k = args.cnn_timing_steps
+    out = {}
+    for name, fn, flop in (("forward", lambda: L.lag_cnn_forward(net, T, R, v), fwd),
+                           ("training_step", lambda: L.lag_cnn_backward(net, T, R, tgt, v, loss), train)):
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        out[name] = {"ms": round(ms, 4), "gflop": round(flop / 1e9, 2), "tflop_s": round(flop / ms / 1e9, 1)}
+    net.close()
+    log(args, f"warm-start network {S}^3 {[c0, c1, c2, c3]}: forward {out['forward']['ms']} ms "
+              f"({out['forward']['tflop_s']} TFLOP/s), training step {out['training_step']['ms']} ms "
+              f"({out['training_step']['tflop_s']} TFLOP/s)")
+    return {"size": S, "channels": [c0, c1, c2, c3], "dtype": "bf16 MFMA, fp32 accum", "steps": k,
+            "peak_tflop_s": 2500.0, **out}
 
 
 def warm_start_measurement(args, L, torch):
@@ -737,6 +787,8 @@ def main():
     plan.close()
     if args.batch_pairs > 0:
         res["batch"] = batch_measurement(args, L, torch)
+    if args.cnn_timing_steps > 0:
+        res["warm_start_kernels"] = cnn_throughput(args, L, torch)
     if args.warm_start_steps > 0:
         res["warm_start"] = warm_start_measurement(args, L, torch)
     if args.cpu_sample > 0:
