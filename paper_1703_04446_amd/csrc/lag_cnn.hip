@@ -467,6 +467,86 @@ __global__ void k_input(const float* __restrict__ T, const float* __restrict__ R
   x[(long long)v * 16 + 1] = f2bf(scale * R[v]);
 }
 
+// First convolution (2 input channels: the template and the reference, each
+// scaled and rounded to bf16 exactly as k_input stores them).  The general
+// kernel would pad the 2 channels to 16; here K runs over (tap, channel)
+// pairs, k = 2 tap + ci, 54 of them padded to 64: two double-K MFMA steps.
+// A block takes an 8 x 8 x 4 tile (side a multiple of 8); its halo sits in
+// LDS as one 32-bit word per voxel (the bf16 pair of T and R), so a lane's
+// A operand (taps 16 s + 4 grp .. + 3 of its voxel, both channels) is four
+// word reads, and the B operand of each 16-channel output tile stays in
+// registers for the whole block.  Writes the bf16 relu activation
+// act[v][co] (view act_cs, act_co); wf is the forward weight copy
+// [tap][co][wk].
+__global__ void __launch_bounds__(256) k_conv_in2(const float* __restrict__ T, const float* __restrict__ R,
+                                                  float scale, int s, const unsigned short* __restrict__ wf,
+                                                  int wk, int cout, const float* __restrict__ bias,
+                                                  unsigned short* __restrict__ act, int act_cs, int act_co) {
+  __shared__ unsigned int hx[10 * 10 * 6];
+  const int ntx = s >> 3, nty = s >> 3;
+  const int b = blockIdx.x;
+  const int x0 = (b % ntx) << 3, y0 = ((b / ntx) % nty) << 3, z0 = (b / (ntx * nty)) << 2;
+  for (int q = threadIdx.x; q < 600; q += blockDim.x) {
+    const int hx_ = q % 10, hy = (q / 10) % 10, hz = q / 100;
+    int gx = x0 + hx_ - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+    gx = gx < 0 ? gx + s : (gx >= s ? gx - s : gx);
+    gy = gy < 0 ? gy + s : (gy >= s ? gy - s : gy);
+    gz = gz < 0 ? gz + s : (gz >= s ? gz - s : gz);
+    const long long v = ((long long)gz * s + gy) * s + gx;
+    hx[q] = (unsigned int)f2bf(scale * T[v]) | ((unsigned int)f2bf(scale * R[v]) << 16);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, grp = lane >> 4;
+  // A operands of the wave's four 16-voxel row tiles, both K steps
+  bf16x8 av[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int u = 64 * wave + 16 * i + m;
+    const int x = u & 7, y = (u >> 3) & 7, z = u >> 6;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      unsigned int w4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = 16 * st + 4 * grp + j;
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        w4[j] = t < 27 ? hx[((z + dz) * 10 + y + dy) * 10 + x + dx] : 0u;
+      }
+      av[i][st] = as_bf16x8(make_uint4(w4[0], w4[1], w4[2], w4[3]));
+    }
+  }
+  for (int nt = 0; nt < cout / 16; ++nt) {
+    const int co = 16 * nt + m;
+    bf16x8 bw[2];
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      unsigned int w4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = 16 * st + 4 * grp + j;
+        w4[j] = t < 27 ? (unsigned int)wf[((long long)t * cout + co) * wk] |
+                             ((unsigned int)wf[((long long)t * cout + co) * wk + 1] << 16)
+                       : 0u;
+      }
+      bw[st] = as_bf16x8(make_uint4(w4[0], w4[1], w4[2], w4[3]));
+    }
+    const float bco = bias[co];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i][0], bw[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i][1], bw[1], acc, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int u = 64 * wave + 16 * i + 4 * grp + j;
+        const long long v = ((long long)(z0 + (u >> 6)) * s + y0 + ((u >> 3) & 7)) * s + x0 + (u & 7);
+        act[v * act_cs + act_co + co] = f2bf(fmaxf(acc[j] + bco, 0.f));
+      }
+    }
+  }
+}
+
 // pool: out (size s/2) = mean of the 2x2x2 children of `in` (size s)
 __global__ void k_pool(const unsigned short* __restrict__ in, int in_cs, int in_co, int c, int s,
                        unsigned short* __restrict__ out) {
@@ -1056,16 +1136,24 @@ static int refresh_weights(lag_cnn n, hipStream_t s) {
   return LAG_OK;
 }
 
-static int forward_impl(lag_cnn n, const float* T, const float* R, float* v, hipStream_t s) {
+static int forward_impl(lag_cnn n, const float* T, const float* R, float* v, hipStream_t s, bool train = false) {
   const int S = n->S, c0 = n->c[0], c1 = n->c[1], c2 = n->c[2], c3 = n->c[3];
   const long long V0 = (long long)S * S * S, V1 = V0 / 8, V2 = V1 / 8, V3 = V2 / 8;
   int rc;
   if ((rc = refresh_weights(n, s))) return rc;
-  hipLaunchKernelGGL(k_input, dim3(ceil_div(V0, 256)), dim3(256), 0, s, T, R, n->cfg.in_scale, (int)V0, n->x0);
-  LAG_LAUNCH_CHECK();
+  if (train) {  // the first layer's weight gradient reads the stored input
+    hipLaunchKernelGGL(k_input, dim3(ceil_div(V0, 256)), dim3(256), 0, s, T, R, n->cfg.in_scale, (int)V0, n->x0);
+    LAG_LAUNCH_CHECK();
+  }
   const int w0 = c1 + c0, w1 = c2 + c1, w2 = c3 + c2;
   // encoder; enc0/enc1/enc2 are written into their concatenation slices
-  if ((rc = conv_fwd(n, E0A, n->x0, 16, 0, n->a[E0A], c0, 0, s))) return rc;
+  // first layer (2 input channels) on the vector ALUs
+  n->actp[E0A] = n->a[E0A];
+  n->acs[E0A] = c0;
+  n->aco[E0A] = 0;
+  hipLaunchKernelGGL(k_conv_in2, dim3(conv_tiles(S)), dim3(256), 0, s, T, R, n->cfg.in_scale, S, n->wf[E0A],
+                     n->cinp[E0A], c0, n->P + n->boff[E0A], n->a[E0A], c0, 0);
+  LAG_LAUNCH_CHECK();
   if ((rc = conv_fwd(n, E0B, n->a[E0A], c0, 0, n->cat0, w0, c1, s))) return rc;
   hipLaunchKernelGGL(k_pool, dim3(ceil_div(V1 * c0, 256)), dim3(256), 0, s, n->cat0, w0, c1, c0, S, n->p0);
   LAG_LAUNCH_CHECK();
@@ -1106,7 +1194,7 @@ int lag_cnn_backward(lag_cnn n, const float* T, const float* R, const float* tar
                      void* stream) {
   if (!n || !T || !R || !target || !v || !loss) return LAG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  int rc = forward_impl(n, T, R, v, s);
+  int rc = forward_impl(n, T, R, v, s, true);
   if (rc) return rc;
   const int S = n->S, c0 = n->c[0], c1 = n->c[1], c2 = n->c[2], c3 = n->c[3];
   const long long V0 = (long long)S * S * S, V1 = V0 / 8, V2 = V1 / 8, V3 = V2 / 8;
