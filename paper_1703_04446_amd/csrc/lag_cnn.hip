@@ -585,28 +585,43 @@ __global__ void k_up(const unsigned short* __restrict__ in, int c, int s, unsign
 // relu (its bf16 activation, view of width acs at offset aco, is non-zero
 // exactly where the pre-activation is positive); writes the bf16 copy and
 // the block's bias-gradient partials part[block][c] (summed in block order
-// by k_wgrad_reduce)
+// by k_wgrad_reduce).  8 channels per thread (16-byte loads and stores).
 __global__ void k_relu_back(const float* __restrict__ g, int gcs, int goff, const unsigned short* __restrict__ act,
                             int acs, int aco, int c, int V, unsigned short* __restrict__ gb,
                             float* __restrict__ part) {
-  __shared__ float sh[256];
-  // grid-stride: the stride is a multiple of 256, so a thread keeps its
-  // channel (c divides 256 for c in {16, 32, 64}) and sums in a fixed order
-  float val = 0.f;
-  const long long n = (long long)V * c;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const int ch = (int)(i % c);
-    const long long v = i / c;
-    const float gi = (act[v * acs + aco + ch] & 0x7fff) != 0 ? g[v * gcs + goff + ch] : 0.f;
-    gb[i] = f2bf(gi);
-    val += gi;
+  __shared__ float sh[256][9];
+  // grid-stride over groups of 8 channels: the stride is a multiple of 256
+  // and c / 8 divides 256, so a thread keeps its channel group and sums in a
+  // fixed order
+  const int c8 = c >> 3;
+  float val[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const long long n8 = (long long)V * c8;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = 8 * (int)(i % c8);
+    const long long v = i / c8;
+    const float4 g0 = *reinterpret_cast<const float4*>(g + v * gcs + goff + ch);
+    const float4 g1 = *reinterpret_cast<const float4*>(g + v * gcs + goff + ch + 4);
+    const uint4 a = *reinterpret_cast<const uint4*>(act + v * acs + aco + ch);
+    const float gi[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+    const unsigned int aw[4] = {a.x, a.y, a.z, a.w};
+    unsigned int pk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float lo = (aw[q] & 0x7fffu) != 0u ? gi[2 * q] : 0.f;
+      const float hi = (aw[q] & 0x7fff0000u) != 0u ? gi[2 * q + 1] : 0.f;
+      val[2 * q] += lo;
+      val[2 * q + 1] += hi;
+      pk[q] = (unsigned int)f2bf(lo) | ((unsigned int)f2bf(hi) << 16);
+    }
+    *reinterpret_cast<uint4*>(gb + 8 * i) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
   }
-  // block partial sums per channel
-  sh[threadIdx.x] = val;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) sh[threadIdx.x][e] = val[e];
   __syncthreads();
   if ((int)threadIdx.x < c) {
+    const int grp = threadIdx.x >> 3, e = threadIdx.x & 7;
     float s = 0.f;
-    for (int k = threadIdx.x; k < 256; k += c) s += sh[k];
+    for (int k = grp; k < 256; k += c8) s += sh[k][e];
     part[(long long)blockIdx.x * c + threadIdx.x] = s;
   }
 }
@@ -704,51 +719,81 @@ __global__ void __launch_bounds__(256) k_mse_final(const double* __restrict__ pa
   if (threadIdx.x == 0) *out = scale * sh[0];
 }
 
-// head backward: gd0[vox][c] = sum_k go[k][vox] Wh[c][k]; the block's
-// partials of gWh[c][3] and gbh[3] go to part[block][3 c + 3] (wave sums by
-// butterflies, then the four waves in order)
+// Head backward (1x1, 3 outputs): gd0[v][ch] = sum_k go[k][v] Wh[ch][k]
+// (float4 stores), and the block's partials of the head gradients,
+// part[block][3 ch + k] = sum_v d0[v][ch] go[k][v] and part[block][3 c + k]
+// = sum_v go[k][v].  Grid-stride over voxels with the sums in registers, 16
+// channels at a time; a wave adds its lanes in a fixed butterfly and the
+// block its four waves in order.
 __global__ void __launch_bounds__(256) k_head_bwd(const unsigned short* __restrict__ d0, int c, int V,
                                                   const float* __restrict__ wh, const float* __restrict__ go,
                                                   float* __restrict__ gd0, float* __restrict__ part) {
-  __shared__ float sh[4][3 * 64 + 3];
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float sh[4][51];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float g[3] = {0.f, 0.f, 0.f};
-  if (v < V) {
-    g[0] = go[v];
-    g[1] = go[V + v];
-    g[2] = go[2 * V + v];
-    for (int ch = 0; ch < c; ++ch)
-      gd0[(long long)v * c + ch] = g[0] * wh[ch * 3] + g[1] * wh[ch * 3 + 1] + g[2] * wh[ch * 3 + 2];
-  }
+  const int nk = 3 * c + 3;
   auto wave_sum = [](float x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
     return x;
   };
-  for (int c8 = 0; c8 < c; c8 += 8) {
-    uint4 row = make_uint4(0u, 0u, 0u, 0u);
-    if (v < V) row = *reinterpret_cast<const uint4*>(d0 + (long long)v * c + c8);
-    const unsigned short* e = reinterpret_cast<const unsigned short*>(&row);
+  for (int c16 = 0; c16 < c; c16 += 16) {
+    float acc[16][3], ab[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k8 = 0; k8 < 8; ++k8) {
-      const float a = bf2f(e[k8]);
+    for (int e = 0; e < 16; ++e) acc[e][0] = acc[e][1] = acc[e][2] = 0.f;
+    float w[16][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float t = wave_sum(a * g[k]);
-        if (lane == 0) sh[wave][(c8 + k8) * 3 + k] = t;
+    for (int e = 0; e < 16; ++e) {
+      w[e][0] = wh[(c16 + e) * 3];
+      w[e][1] = wh[(c16 + e) * 3 + 1];
+      w[e][2] = wh[(c16 + e) * 3 + 2];
+    }
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) {
+      const float g[3] = {go[v], go[V + v], go[2 * V + v]};
+      const uint4 r0 = *reinterpret_cast<const uint4*>(d0 + (long long)v * c + c16);
+      const uint4 r1 = *reinterpret_cast<const uint4*>(d0 + (long long)v * c + c16 + 8);
+      const unsigned int rw[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const float a = __uint_as_float((e & 1) ? (rw[e >> 1] & 0xffff0000u) : (rw[e >> 1] << 16));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[e][k] = fmaf(a, g[k], acc[e][k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ab[k] += g[k];
+      float4* dst = reinterpret_cast<float4*>(gd0 + (long long)v * c + c16);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float o[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int e = 4 * q + t;
+          o[t] = g[0] * w[e][0] + g[1] * w[e][1] + g[2] * w[e][2];
+        }
+        dst[q] = make_float4(o[0], o[1], o[2], o[3]);
       }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float t = wave_sum(g[k]);
-    if (lane == 0) sh[wave][3 * c + k] = t;
+    for (int e = 0; e < 16; ++e)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float t = wave_sum(acc[e][k]);
+        if (lane == 0) sh[wave][e * 3 + k] = t;
+      }
+    if (c16 == 0) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float t = wave_sum(ab[k]);
+        if (lane == 0) sh[wave][48 + k] = t;
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 51; k += blockDim.x) {
+      const float t = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
+      if (k < 48) part[(long long)blockIdx.x * nk + 3 * c16 + k] = t;
+      else if (c16 == 0) part[(long long)blockIdx.x * nk + 3 * c + (k - 48)] = t;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int nk = 3 * c + 3;
-  for (int k = threadIdx.x; k < nk; k += blockDim.x)
-    part[(long long)blockIdx.x * nk + k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
 }
 
 // bf16 weight copies of every convolution in one launch: layer l covers
@@ -1085,7 +1130,7 @@ static int conv_bwd(lag_cnn n, int l, const float* g, int gcs, int goff, const u
                     int in_co, float* gx, hipStream_t s) {
   const int sz = n->lsize[l], cout = n->cout[l], cin = n->cinp[l];
   const long long V = (long long)sz * sz * sz;
-  const int nb = std::min(ceil_div(V * cout, 256), 1024);
+  const int nb = std::min(ceil_div(V * cout / 8, 256), 1024);
   hipLaunchKernelGGL(k_relu_back, dim3(nb), dim3(256), 0, s, g, gcs, goff, n->actp[l], n->acs[l], n->aco[l], cout,
                      (int)V, n->gb16, n->bpart);
   LAG_LAUNCH_CHECK();
@@ -1209,11 +1254,12 @@ int lag_cnn_backward(lag_cnn n, const float* T, const float* R, const float* tar
   hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, s, n->part, 1024, 0.5 / (double)nv, loss);
   LAG_LAUNCH_CHECK();
   float* gd0 = n->gbuf[0];
-  hipLaunchKernelGGL(k_head_bwd, dim3(ceil_div(V0, 256)), dim3(256), 0, s, n->a[D0], c0, (int)V0,
-                     n->P + n->woff[HEAD], n->gout, gd0, n->bpart);
+  const int hb = std::min(ceil_div(V0, 256), 256);   // head blocks (grid-stride)
+  hipLaunchKernelGGL(k_head_bwd, dim3(hb), dim3(256), 0, s, n->a[D0], c0, (int)V0, n->P + n->woff[HEAD], n->gout,
+                     gd0, n->bpart);
   LAG_LAUNCH_CHECK();
   // gWh[c][3] and gbh[3] are contiguous in G
-  hipLaunchKernelGGL(k_rows_reduce, dim3(3 * c0 + 3), dim3(256), 0, s, n->bpart, ceil_div(V0, 256), 3 * c0 + 3,
+  hipLaunchKernelGGL(k_rows_reduce, dim3(3 * c0 + 3), dim3(256), 0, s, n->bpart, hb, 3 * c0 + 3,
                      n->G + n->woff[HEAD]);
   LAG_LAUNCH_CHECK();
   // decoder
