@@ -161,10 +161,15 @@ def test_gn_solve_2d(torch, L, k):
     assert abs(J0o - info["J0"]) <= 1e-5 * abs(J0o)
     g0o = np.linalg.norm(O.gradient(OP, np.zeros(OP.vel_shape), T, R)[0])
     assert abs(g0o - info["g0"]) <= 1e-4 * g0o
-    # the oracle's own solve reaches a comparable objective
+    # the oracle's own solve from v = 0 (its own FP64 trajectory) converges
+    # in as many Gauss-Newton steps to the same objective, within 1e-3
+    # (measured: 1.1e-5; the Krylov solves part by an iteration)
     vo, hist = O.gn_solve(OP, T, R, pcg_maxit=20)
+    print("oracle", hist["status"], len(hist["J"]) - 1, "steps, J", hist["J"][-1], "GPU", info["iters"], info["J"],
+          flush=True)
     assert hist["status"] == "converged"
-    assert info["J"] <= 1.5 * hist["J"][-1]
+    assert len(hist["J"]) - 1 == info["iters"]
+    assert abs(info["J"] - hist["J"][-1]) <= 1e-3 * hist["J"][-1]
 
 
 def test_gn_step_monotone(torch, L):
