@@ -752,7 +752,7 @@ def main():
     else:
         flops = n * (w.nsteps * FLOP_PER_CHAR_STEP_3D + FLOP_PER_CHAR_END_3D)
         achieved = flops / kern_avg_s / 1e12
-        roof = {"bound": "alu", "kernel": f"k_hess_transport<{w.dim},false>",
+        roof = {"bound": "alu", "kernel": f"k_adjoint<{w.dim}, stationary, Gauss-Newton mode>",
                 "achieved": round(achieved, 3) if kern_n > 0 else None,
                 "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4) if kern_n > 0 else None, "traffic": None,

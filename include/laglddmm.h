@@ -158,8 +158,9 @@ int lag_plan_flags(lag_plan plan, int32_t* flags, int32_t clear, void* stream);
 int lag_adjoint_stats(lag_plan plan, int32_t* deferred, int32_t* redone, void* stream);
 
 /* Kernel timing for measurement: when enabled, every launch of the
- * Gauss-Newton matvec's main kernel is bracketed by HIP events recorded on
- * the stream it runs on (up to 256 launches between reads).  Enabling
+ * Gauss-Newton matvec's main kernel carries a pair of HIP events that the
+ * dispatch on its stream stamps at the kernel's start and end (so the time
+ * excludes the gap before the dispatch; up to 256 launches between reads).  Enabling
  * creates the events (host call, once per plan).  lag_profile_read
  * synchronises on the recorded events, returns the summed kernel time in
  * milliseconds and the number of timed launches (host pointers), and resets

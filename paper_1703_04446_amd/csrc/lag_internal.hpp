@@ -2,6 +2,7 @@
 // the launchers each translation unit exports to the C-ABI layer.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -213,13 +214,15 @@ int launch_pcg_p(lag_plan P, float* p, const float* z, hipStream_t s);
 int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s);
 int launch_pcg_check(lag_plan P, hipStream_t s);
 
-// profiling brackets around the dominant matvec kernel (no-ops unless enabled)
-inline void prof_begin(lag_plan P, hipStream_t s) {
-  if (P->prof_on && !P->capturing && P->prof_n < 256) (void)hipEventRecord(P->prof_ev[2 * P->prof_n], s);
-}
-inline void prof_end(lag_plan P, hipStream_t s) {
+// Timing of the dominant matvec kernel (off unless enabled): the next pair
+// of events, which the launch itself stamps at the kernel's start and end
+// (hipExtLaunchKernelGGL), so the time excludes the gap before the dispatch;
+// both null when not timing (or while a graph is captured).
+inline void prof_events(lag_plan P, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
   if (P->prof_on && !P->capturing && P->prof_n < 256) {
-    (void)hipEventRecord(P->prof_ev[2 * P->prof_n + 1], s);
+    *start = P->prof_ev[2 * P->prof_n];
+    *stop = P->prof_ev[2 * P->prof_n + 1];
     ++P->prof_n;
   }
 }

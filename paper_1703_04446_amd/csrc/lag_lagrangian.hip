@@ -2901,10 +2901,14 @@ static int launch_adjoint_t(lag_plan P, const AdjArgs& A, const Stages& st, floa
   int rc = launch_zero_i(P->dfr_hdr, 3, s);
   if (rc) return rc;
   const size_t lds = adjoint_lds_bytes(P);
-  if (prof) prof_begin(P, s);
-  hipLaunchKernelGGL((k_adjoint<D, NS, MODE, ZERO>), dim3(grid_for(B.nbricks)), dim3(AdjBlock<D, NS>::threads), lds, s,
-                     P->geo, st, B, A, out, P->tile_part, P->flags, dq);
-  if (prof) prof_end(P, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof) prof_events(P, &e0, &e1);
+  if (e0)
+    hipExtLaunchKernelGGL((k_adjoint<D, NS, MODE, ZERO>), dim3(grid_for(B.nbricks)), dim3(AdjBlock<D, NS>::threads),
+                          lds, s, e0, e1, 0, P->geo, st, B, A, out, P->tile_part, P->flags, dq);
+  else
+    hipLaunchKernelGGL((k_adjoint<D, NS, MODE, ZERO>), dim3(grid_for(B.nbricks)), dim3(AdjBlock<D, NS>::threads), lds,
+                       s, P->geo, st, B, A, out, P->tile_part, P->flags, dq);
   LAG_LAUNCH_CHECK();
   if constexpr (!ZERO) {
     const unsigned dgrid = (unsigned)std::min<long long>((P->geo.np + kBlock - 1) / kBlock, 1024);
@@ -3007,13 +3011,22 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
   const lag::Bricks& B = P->bricks;
   unsigned grid = grid_for(B.nbricks);
   const size_t lds = sizeof(float) * ((size_t)P->geo.dim * B.tvol + 2 * (kBlock / 64));
-  if (!wseed) prof_begin(P, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!wseed) prof_events(P, &e0, &e1);
   if (P->pg_cap > 0) {
     const size_t plds = sizeof(float) * ((size_t)P->geo.dim * B.tvol + 2 * (kPgBlock / 64) + kPgBlock);
 #define LAG_PG(DD, WS, WV, VT)                                                                                    \
-  hipLaunchKernelGGL((k_jac_apply_pg<DD, WS, WV>), dim3(grid), dim3(kPgBlock), plds, s, P->geo, B, P->pg_vals,     \
-                     P->pg_cells, P->pg_rows, P->pg_npages, P->pg_order, P->pg_cap, (const VT*)ppack,              \
-                     wvox, wseed, scale, P->jac_fb, P->tile_part, P->pg_redo, P->pg_axbox)
+  do {                                                                                                            \
+    if (e0)                                                                                                       \
+      hipExtLaunchKernelGGL((k_jac_apply_pg<DD, WS, WV>), dim3(grid), dim3(kPgBlock), plds, s, e0, e1, 0, P->geo,  \
+                            B, P->pg_vals, P->pg_cells, P->pg_rows, P->pg_npages, P->pg_order, P->pg_cap,          \
+                            (const VT*)ppack, wvox, wseed, scale, P->jac_fb, P->tile_part, P->pg_redo,             \
+                            P->pg_axbox);                                                                         \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_jac_apply_pg<DD, WS, WV>), dim3(grid), dim3(kPgBlock), plds, s, P->geo, B, P->pg_vals, \
+                         P->pg_cells, P->pg_rows, P->pg_npages, P->pg_order, P->pg_cap, (const VT*)ppack, wvox,    \
+                         wseed, scale, P->jac_fb, P->tile_part, P->pg_redo, P->pg_axbox);                          \
+  } while (0)
     if (P->geo.dim == 3) {
       if (wseed) LAG_PG(3, true, false, float4);
       else if (wvox) LAG_PG(3, false, true, float4);
@@ -3025,15 +3038,24 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
     }
 #undef LAG_PG
   } else if (P->geo.dim == 3) {
-    hipLaunchKernelGGL(k_jac_apply<3>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
-                       P->jac_cnt, P->jac_slots, (const float4*)ppack, wvox, wseed, scale, P->jac_fb,
-                       P->tile_part);
+    if (e0)
+      hipExtLaunchKernelGGL(k_jac_apply<3>, dim3(grid), dim3(kBlock), lds, s, e0, e1, 0, P->geo, B, P->jac_vals,
+                            P->jac_cell, P->jac_cnt, P->jac_slots, (const float4*)ppack, wvox, wseed, scale,
+                            P->jac_fb, P->tile_part);
+    else
+      hipLaunchKernelGGL(k_jac_apply<3>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
+                         P->jac_cnt, P->jac_slots, (const float4*)ppack, wvox, wseed, scale, P->jac_fb,
+                         P->tile_part);
   } else {
-    hipLaunchKernelGGL(k_jac_apply<2>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
-                       P->jac_cnt, P->jac_slots, (const float2*)ppack, wvox, wseed, scale, P->jac_fb,
-                       P->tile_part);
+    if (e0)
+      hipExtLaunchKernelGGL(k_jac_apply<2>, dim3(grid), dim3(kBlock), lds, s, e0, e1, 0, P->geo, B, P->jac_vals,
+                            P->jac_cell, P->jac_cnt, P->jac_slots, (const float2*)ppack, wvox, wseed, scale,
+                            P->jac_fb, P->tile_part);
+    else
+      hipLaunchKernelGGL(k_jac_apply<2>, dim3(grid), dim3(kBlock), lds, s, P->geo, B, P->jac_vals, P->jac_cell,
+                         P->jac_cnt, P->jac_slots, (const float2*)ppack, wvox, wseed, scale, P->jac_fb,
+                         P->tile_part);
   }
-  if (!wseed) prof_end(P, s);
   LAG_LAUNCH_CHECK();
   // assigns out; the paged product wrote only the nodes its cover lists read
   return launch_tile_reduce(P, out, P->jac_fb, s, rt, false, P->pg_cap > 0);
