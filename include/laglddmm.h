@@ -543,7 +543,8 @@ int lag_cnn_get_grads(lag_cnn net, float* host);
 /* Inference: T, R are size^3 images (x fastest); v receives [3][size^3]. */
 int lag_cnn_forward(lag_cnn net, const float* T, const float* R, float* v, void* stream);
 /* Forward, loss = 1/2 mean (v - target)^2 written to *loss (device double),
- * and the gradient of every parameter (kept in the net). */
+ * and the gradient of every parameter (kept in the net).  Every gradient sum
+ * runs in a fixed order, so repeated calls give the same bits. */
 int lag_cnn_backward(lag_cnn net, const float* T, const float* R, const float* target, float* v,
                      double* loss, void* stream);
 /* One Adam update of the parameters with the last gradients. */
