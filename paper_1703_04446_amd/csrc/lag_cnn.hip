@@ -870,7 +870,14 @@ struct lag_cnn_s {
   float* gbuf[4] = {nullptr};        // scratch per level (largest widths)
   float* gcat[3] = {nullptr};        // g of cat0 / cat1 / cat2
   float* gtmp[4] = {nullptr};
-  unsigned short* gb16 = nullptr;    // bf16 gradient of a pre-activation (largest)
+  // per layer: the bf16 gradient of its pre-activation and its bias
+  // partials (the weight gradient reads them on the side stream while the
+  // next layers' backward runs on the caller's)
+  unsigned short* gbl[kLayers] = {nullptr};
+  float* bpl[kLayers] = {nullptr};
+  hipStream_t side = nullptr;        // weight gradients (default priority)
+  hipEvent_t fork[kLayers] = {nullptr};
+  hipEvent_t join = nullptr;
   float* gout = nullptr;             // 3 x S^3
   double* part = nullptr;
   float* wpart = nullptr;            // weight-gradient partials per voxel range
@@ -927,14 +934,19 @@ int lag_cnn_destroy(lag_cnn n) {
   if (!n) return LAG_OK;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {n->P, n->G, n->M1, n->M2, n->x0, n->p0, n->p1, n->p2, n->cat2, n->cat1, n->cat0,
-                  n->gb16, n->gout, n->part, n->wpart, n->bpart, n->kpart};
+                  n->gout, n->part, n->wpart, n->bpart, n->kpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int l = 0; l < kLayers; ++l) {
     if (n->wf[l]) (void)hipFree(n->wf[l]);
     if (n->wb[l]) (void)hipFree(n->wb[l]);
     if (n->a[l]) (void)hipFree(n->a[l]);
+    if (n->gbl[l]) (void)hipFree(n->gbl[l]);
+    if (n->bpl[l]) (void)hipFree(n->bpl[l]);
+    if (n->fork[l]) (void)hipEventDestroy(n->fork[l]);
   }
+  if (n->join) (void)hipEventDestroy(n->join);
+  if (n->side) (void)hipStreamDestroy(n->side);
   for (int i = 0; i < 4; ++i) {
     if (n->gbuf[i]) (void)hipFree(n->gbuf[i]);
     if (n->gtmp[i]) (void)hipFree(n->gtmp[i]);
@@ -1041,7 +1053,22 @@ int lag_cnn_create(const lag_cnn_config* cfg, lag_cnn* out) {
     CNN_ALLOC(n->gbuf[i], sizeof(float) * Vs[i] * 64);
     CNN_ALLOC(n->gtmp[i], sizeof(float) * Vs[i] * 64);
   }
-  CNN_ALLOC(n->gb16, 2 * V0 * 64);
+  for (int l = 0; l < HEAD; ++l) {
+    const long long Vl = (long long)sz[l] * sz[l] * sz[l];
+    CNN_ALLOC(n->gbl[l], 2 * Vl * n->cout[l]);
+    CNN_ALLOC(n->bpl[l], sizeof(float) * 1024 * n->cout[l]);
+    if (hipEventCreateWithFlags(&n->fork[l], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      lag_cnn_destroy(n);
+      return LAG_EHIP;
+    }
+  }
+  if (hipEventCreateWithFlags(&n->join, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    lag_cnn_destroy(n);
+    return LAG_EHIP;
+  }
   CNN_ALLOC(n->gout, sizeof(float) * 3 * V0);
   CNN_ALLOC(n->part, sizeof(double) * 1024);
   CNN_ALLOC(n->wpart, sizeof(float) * wpart);
@@ -1060,6 +1087,7 @@ int lag_cnn_param_count(lag_cnn n, int64_t* count) {
 
 int lag_cnn_get_params(lag_cnn n, float* host) {
   if (!n || !host) return LAG_EINVAL;
+  LAG_HIP(hipDeviceSynchronize());
   LAG_HIP(hipMemcpy(host, n->P, sizeof(float) * n->nparams, hipMemcpyDeviceToHost));
   return LAG_OK;
 }
@@ -1075,6 +1103,7 @@ int lag_cnn_set_params(lag_cnn n, const float* host) {
 
 int lag_cnn_get_grads(lag_cnn n, float* host) {
   if (!n || !host) return LAG_EINVAL;
+  LAG_HIP(hipDeviceSynchronize());   // every stream's work, the side stream's included
   LAG_HIP(hipMemcpy(host, n->G, sizeof(float) * n->nparams, hipMemcpyDeviceToHost));
   return LAG_OK;
 }
@@ -1132,8 +1161,13 @@ static int conv_bwd(lag_cnn n, int l, const float* g, int gcs, int goff, const u
   const long long V = (long long)sz * sz * sz;
   const int nb = std::min(ceil_div(V * cout / 8, 256), 1024);
   hipLaunchKernelGGL(k_relu_back, dim3(nb), dim3(256), 0, s, g, gcs, goff, n->actp[l], n->acs[l], n->aco[l], cout,
-                     (int)V, n->gb16, n->bpart);
+                     (int)V, n->gbl[l], n->bpl[l]);
   LAG_LAUNCH_CHECK();
+  // weight gradient on the side stream, after the relu backward; the input
+  // gradient below goes on on the caller's stream meanwhile
+  LAG_HIP(hipEventRecord(n->fork[l], s));
+  LAG_HIP(hipStreamWaitEvent(n->side, n->fork[l], 0));
+  const hipStream_t ws = n->side;
   // weight gradient: partials per voxel range, then their fixed-order sum into G
   const ConvTile T = conv_tile(sz);
   const int NV = 1 << (T.lx + T.ly + T.lz);
@@ -1142,22 +1176,22 @@ static int conv_bwd(lag_cnn n, int l, const float* g, int gcs, int goff, const u
                                                16 * 16 * (size_t)(((1 << T.ly) + 2) * ((1 << T.lz) + 2)));
   const dim3 wg(nr, cin / 16);
   switch (cout / 16) {
-    case 1: hipLaunchKernelGGL(k_conv_wgrad<1>, wg, dim3(256), lds, s, in, in_cs, in_co, sz, T, n->gb16, cout, tpr, cin, n->wpart); break;
-    case 2: hipLaunchKernelGGL(k_conv_wgrad<2>, wg, dim3(256), lds, s, in, in_cs, in_co, sz, T, n->gb16, cout, tpr, cin, n->wpart); break;
-    default: hipLaunchKernelGGL(k_conv_wgrad<4>, wg, dim3(256), lds, s, in, in_cs, in_co, sz, T, n->gb16, cout, tpr, cin, n->wpart); break;
+    case 1: hipLaunchKernelGGL(k_conv_wgrad<1>, wg, dim3(256), lds, ws, in, in_cs, in_co, sz, T, n->gbl[l], cout, tpr, cin, n->wpart); break;
+    case 2: hipLaunchKernelGGL(k_conv_wgrad<2>, wg, dim3(256), lds, ws, in, in_cs, in_co, sz, T, n->gbl[l], cout, tpr, cin, n->wpart); break;
+    default: hipLaunchKernelGGL(k_conv_wgrad<4>, wg, dim3(256), lds, ws, in, in_cs, in_co, sz, T, n->gbl[l], cout, tpr, cin, n->wpart); break;
   }
   LAG_LAUNCH_CHECK();
   // weight and bias gradients: fixed-order sums of the partials
   const long long nout = 27LL * n->cin[l] * cout + cout;
   if (ceil_div(nout, 32) >= 1024)
-    hipLaunchKernelGGL(k_wgrad_reduce<32>, dim3(ceil_div(nout, 32)), dim3(256), 0, s, n->wpart, nr, n->cin[l], cin,
-                       cout, n->G + n->woff[l], n->bpart, nb, n->G + n->boff[l]);
+    hipLaunchKernelGGL(k_wgrad_reduce<32>, dim3(ceil_div(nout, 32)), dim3(256), 0, ws, n->wpart, nr, n->cin[l], cin,
+                       cout, n->G + n->woff[l], n->bpl[l], nb, n->G + n->boff[l]);
   else
-    hipLaunchKernelGGL(k_wgrad_reduce<8>, dim3(ceil_div(nout, 8)), dim3(256), 0, s, n->wpart, nr, n->cin[l], cin,
-                       cout, n->G + n->woff[l], n->bpart, nb, n->G + n->boff[l]);
+    hipLaunchKernelGGL(k_wgrad_reduce<8>, dim3(ceil_div(nout, 8)), dim3(256), 0, ws, n->wpart, nr, n->cin[l], cin,
+                       cout, n->G + n->woff[l], n->bpl[l], nb, n->G + n->boff[l]);
   LAG_LAUNCH_CHECK();
   if (gx) {
-    const int rc = launch_conv<true>(n, sz, cin, n->gb16, cout, 0, cout, n->wb[l], cin, cout, nullptr, gx, nullptr, 0,
+    const int rc = launch_conv<true>(n, sz, cin, n->gbl[l], cout, 0, cout, n->wb[l], cin, cout, nullptr, gx, nullptr, 0,
                                      0, s);
     if (rc) return rc;
   }
@@ -1291,6 +1325,9 @@ int lag_cnn_backward(lag_cnn n, const float* T, const float* R, const float* tar
   LAG_LAUNCH_CHECK();
   if ((rc = conv_bwd(n, E0B, n->gcat[0], w0, c1, n->a[E0A], c0, 0, n->gtmp[0], s))) return rc;
   if ((rc = conv_bwd(n, E0A, n->gtmp[0], c0, 0, n->x0, 16, 0, nullptr, s))) return rc;
+  // the weight gradients are complete before the caller's stream goes on
+  LAG_HIP(hipEventRecord(n->join, n->side));
+  LAG_HIP(hipStreamWaitEvent(s, n->join, 0));
   return LAG_OK;
 }
 
