@@ -409,8 +409,9 @@ def cnn_throughput(args, L, torch):
     """Throughput of the warm-start network's kernels at its training size
     (the 64^3 velocity grid, channels of the default configuration):
     forward, and a training step (forward, loss, backward with every weight
-    and bias gradient and every input gradient but the first layer's), on
-    random inputs, timed with HIP events on the stream the kernels run on.
+    and bias gradient and every input gradient but the first layer's, Adam
+    update), on random inputs, timed with HIP events on the stream the
+    kernels run on.
     FLOPs count the 3x3x3 convolutions with their true input widths (2 for
     the first layer)."""
     cfg = L.lag_cnn_default_config()
@@ -433,8 +434,15 @@ def cnn_throughput(args, L, torch):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     k = args.cnn_timing_steps
     out = {}
+    def train_step():
+        # a full step: forward, loss, backward, Adam (at learning rate 0, so
+        # that the timed steps see the same weights; the update and the next
+        # pass's bf16 weight copy run as in training)
+        L.lag_cnn_backward(net, T, R, tgt, v, loss)
+        L.lag_cnn_adam_step(net, 0.0)
+
     for name, fn, flop in (("forward", lambda: L.lag_cnn_forward(net, T, R, v), fwd),
-                           ("training_step", lambda: L.lag_cnn_backward(net, T, R, tgt, v, loss), train)):
+                           ("training_step", train_step, train)):
         torch.cuda.synchronize()
         e0.record()
         for _ in range(k):

@@ -516,7 +516,8 @@ int lag_batch_solve_graph(int32_t npairs, const lag_problem* probs, const float*
  * 2x average pooling, nearest-neighbour upsampling with skip
  * concatenation, and a 1x1 output head scaled by out_scale.  Convolutions
  * run as implicit GEMMs on bf16 MFMA with float32 accumulation; weights are
- * kept in float32 for Adam and copied to bf16 for every pass.  Parameters
+ * kept in float32 for Adam and copied to bf16 by the first pass after they
+ * change (creation, lag_cnn_set_params, lag_cnn_adam_step).  Parameters
  * are stored flat, layer by layer (e0a e0b e1a e1b e2a e2b ma mb d2 d1 d0
  * head), each as W[taps][cin][cout] followed by b[cout] (taps = 27, 1 for
  * the head; the first layer has cin = 2). */

@@ -884,6 +884,7 @@ struct lag_cnn_s {
   float* kpart = nullptr;            // split-contraction partials of the convolutions
   float* bpart = nullptr;            // bias / head gradient partials per block
   int adam_t = 0;
+  bool wdirty = true;                // master weights changed since the last bf16 copy
 };
 
 static int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -1095,6 +1096,7 @@ int lag_cnn_get_params(lag_cnn n, float* host) {
 int lag_cnn_set_params(lag_cnn n, const float* host) {
   if (!n || !host) return LAG_EINVAL;
   LAG_HIP(hipMemcpy(n->P, host, sizeof(float) * n->nparams, hipMemcpyHostToDevice));
+  n->wdirty = true;
   n->adam_t = 0;
   LAG_HIP(hipMemset(n->M1, 0, sizeof(float) * n->nparams));
   LAG_HIP(hipMemset(n->M2, 0, sizeof(float) * n->nparams));
@@ -1219,7 +1221,10 @@ static int forward_impl(lag_cnn n, const float* T, const float* R, float* v, hip
   const int S = n->S, c0 = n->c[0], c1 = n->c[1], c2 = n->c[2], c3 = n->c[3];
   const long long V0 = (long long)S * S * S, V1 = V0 / 8, V2 = V1 / 8, V3 = V2 / 8;
   int rc;
-  if ((rc = refresh_weights(n, s))) return rc;
+  if (n->wdirty) {  // bf16 copies of the weights, once per change of the master weights
+    if ((rc = refresh_weights(n, s))) return rc;
+    n->wdirty = false;
+  }
   if (train) {  // the first layer's weight gradient reads the stored input
     hipLaunchKernelGGL(k_input, dim3(ceil_div(V0, 256)), dim3(256), 0, s, T, R, n->cfg.in_scale, (int)V0, n->x0);
     LAG_LAUNCH_CHECK();
@@ -1338,6 +1343,7 @@ int lag_cnn_adam_step(lag_cnn n, float lr, float beta1, float beta2, float eps, 
   hipLaunchKernelGGL(k_adam, dim3(ceil_div(n->nparams, 256)), dim3(256), 0, (hipStream_t)stream, n->P, n->G, n->M1,
                      n->M2, n->nparams, lr, beta1, beta2, eps, c1, c2);
   LAG_LAUNCH_CHECK();
+  n->wdirty = true;
   return LAG_OK;
 }
 
