@@ -1168,8 +1168,12 @@ __device__ __forceinline__ void sample_tile(const typename VecT<D>::T* __restric
   }
 }
 
+// 512 threads (8 waves) share a brick's tile: the 52 KB tile lets three
+// blocks onto a CU, so the waves per CU are set by the block size.
+constexpr int kTraceBlock = 512;
+
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_trace_tile(Geo g, Stages st, Bricks B,
+__global__ void __launch_bounds__(kTraceBlock) k_trace_tile(Geo g, Stages st, Bricks B,
                                                        const typename VecT<D>::T* __restrict__ vp,
                                                        float* __restrict__ phi_out) {
   extern __shared__ float vtile[];
@@ -2792,9 +2796,11 @@ int launch_trace(lag_plan P, const void* vpack, int dir, float* phi, hipStream_t
   if (P->geo.nodes == 1 && tile <= 64 * 1024) {  // LDS-staged velocity tile per brick
     unsigned grid = grid_for(B.nbricks);
     if (P->geo.dim == 3)
-      hipLaunchKernelGGL(k_trace_tile<3>, dim3(grid), dim3(kBlock), tile, s, P->geo, st, B, (const float4*)vpack, phi);
+      hipLaunchKernelGGL(k_trace_tile<3>, dim3(grid), dim3(kTraceBlock), tile, s, P->geo, st, B, (const float4*)vpack,
+                         phi);
     else
-      hipLaunchKernelGGL(k_trace_tile<2>, dim3(grid), dim3(kBlock), tile, s, P->geo, st, B, (const float2*)vpack, phi);
+      hipLaunchKernelGGL(k_trace_tile<2>, dim3(grid), dim3(kTraceBlock), tile, s, P->geo, st, B, (const float2*)vpack,
+                         phi);
     LAG_LAUNCH_CHECK();
     return LAG_OK;
   }
