@@ -2325,7 +2325,12 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
   int* tile = (int*)lds;             // [D][tvol] fixed-point sums
   float* red = lds + tot;            // [2 * waves] bound shares
   float* stage = red + 2 * nw + 64 * wave;   // this wave's 64 staging slots
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) tile[i] = 0;
+  auto zero_tile = [&]() {           // 16-byte LDS writes (the tile starts the LDS block)
+    int4* t4 = (int4*)tile;
+    for (int i = threadIdx.x; i < tot / 4; i += blockDim.x) t4[i] = make_int4(0, 0, 0, 0);
+    for (int i = 4 * (tot / 4) + threadIdx.x; i < tot; i += blockDim.x) tile[i] = 0;
+  };
+  zero_tile();
   constexpr int NV4 = JacLayout<D>::NV4;
   constexpr bool ROW = WS || WV;     // the row's image index is needed
   auto row_image = [&](int row) {
@@ -2512,7 +2517,7 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
   const bool again = finite && bt > 0.f && (!ok || e > ee || e < ee - 3);
   if (again) {
     if (threadIdx.x == 0) atomicAdd(redo, 1);
-    for (int i = threadIdx.x; i < tot; i += blockDim.x) tile[i] = 0;
+    zero_tile();
     __syncthreads();
     bshare = 0.f;
     if (p0 < p1) load_page(p0, fa, wa, ra);
@@ -2534,13 +2539,24 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
   const int run = (y1 - y0 + 1) * B.tdim[0];     // values per plane
   const int nz = z1 - z0 + 1;
   if (run > 0 && nz > 0) {
-    const int per = nz * run;
-    for (int i = threadIdx.x; i < D * per; i += blockDim.x) {
-      const int f = i / per, r = i - f * per;
-      const int z = r / run, j = r - z * run;
-      const int t = f * B.tvol + ((z0 + z) * B.tdim[1] + y0) * B.tdim[0] + j;
-      dst[t] = finite ? ldexpf((float)tile[t], -e) : nan;
-    }
+    // a wave per plane, the plane's run across the lanes with four LDS
+    // reads in flight (no index division per value)
+    for (int f = 0; f < D; ++f)
+      for (int z = wave; z < nz; z += nw) {
+        const int base = f * B.tvol + ((z0 + z) * B.tdim[1] + y0) * B.tdim[0];
+        for (int j0 = 0; j0 < run; j0 += 256) {
+          int v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            v[k] = tile[base + min(j0 + 64 * k + lane, run - 1)];   // unconditional: in flight together
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int j = j0 + 64 * k + lane;
+            if (j < run) dst[base + j] = finite ? ldexpf((float)v[k], -e) : nan;
+          }
+        }
+      }
   }
 }
 
