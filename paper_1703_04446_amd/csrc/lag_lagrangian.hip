@@ -2036,6 +2036,38 @@ inline int jac_page_cap(long long brick_rows, int kmax) {
   return (int)((brick_rows * kmax + (kPagePos + 1 - kmax) - 1) / (kPagePos + 1 - kmax)) + 1;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active) on
+// DPP: shifts by 1, 2, 4 and 8 within each row of 16 lanes (zero from
+// outside the row), then each row's total broadcast into the rows above.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  int v = x;
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);    // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);    // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);    // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);    // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1 and 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// A brick's block counts into LDS, zero past its rows (16-byte loads when
+// the brick's counts are 16-byte aligned; a byte loop would wait on one HBM
+// trip per iteration).
+__device__ __forceinline__ void load_counts(const unsigned char* __restrict__ cnt, long long base, int rows,
+                                            unsigned char* cl) {
+  const int rows64 = (rows + 63) & ~63;
+  int done = 0;
+  if (((base | (long long)(size_t)cnt) & 15) == 0) {
+    const uint4* src = reinterpret_cast<const uint4*>(cnt + base);
+    uint4* dst = reinterpret_cast<uint4*>(cl);
+    const int full = rows >> 4;      // 16-byte groups inside the brick
+#pragma unroll 4
+    for (int i = threadIdx.x; i < full; i += blockDim.x) dst[i] = src[i];
+    done = 16 * full;
+  }
+  for (int i = done + threadIdx.x; i < rows64; i += blockDim.x) cl[i] = i < rows ? cnt[base + i] : 0;
+}
+
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __restrict__ vals,
                                                      const int* __restrict__ cells,
@@ -2059,7 +2091,7 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
   int* rs = sh + r4;                 // [rows]
   unsigned char* cl = (unsigned char*)(sh + 2 * r4);   // [rows rounded up to 64], 16-byte aligned
   const int rows64 = (rows + 63) & ~63;
-  for (int i = threadIdx.x; i < rows64; i += blockDim.x) cl[i] = i < rows ? cnt[base + i] : 0;
+  load_counts(cnt, base, rows, cl);
   __syncthreads();
   if (threadIdx.x < 64) {
     // Greedy placement in slot order by wave 0, 64 rows at a time: a prefix
@@ -2073,12 +2105,7 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
       int start = 0;
       while (start < 64) {
         const int x = lane >= start ? n : 0;
-        int incl = x;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const int y = __shfl_up(incl, off, 64);
-          if (lane >= off) incl += y;
-        }
+        const int incl = wave_incl_scan(x);
         const int p = at + incl - x;
         const bool straddle = lane >= start && n > 0 && (p & (kPagePos - 1)) + n > kPagePos;
         const unsigned long long sm = __ballot(straddle);
@@ -2093,11 +2120,11 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
         }
         nr += __popcll(km);
         if (first == 64) {
-          at += __shfl(incl, 63, 64);
+          at += __builtin_amdgcn_readlane(incl, 63);
           break;
         }
         // the straddling row opens the next page
-        const int pf = __shfl(p, first, 64), nf = __shfl(n, first, 64);
+        const int pf = __builtin_amdgcn_readlane(p, first), nf = __builtin_amdgcn_readlane(n, first);
         const int page_at = (pf + kPagePos - 1) & ~(kPagePos - 1);
         if (lane == 0) {
           rl[nr] = i0 + first;
