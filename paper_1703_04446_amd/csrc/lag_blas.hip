@@ -15,8 +15,20 @@ __global__ void __launch_bounds__(kBlock) k_dot_partial(const float* __restrict_
   if (halted(halt)) return;
   __shared__ double sh[kBlock];
   double s = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    s += (double)x[i] * (double)y[i];
+  const long long st = (long long)gridDim.x * blockDim.x;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += 4 * st) {   // four elements' loads in flight (clamped), terms added in index order
+    float xa[4], ya[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long k = min(i + u * st, n - 1);
+      xa[u] = x[k];
+      ya[u] = y[k];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * st < n) s += (double)xa[u] * (double)ya[u];
+  }
   double t = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -27,10 +39,22 @@ __global__ void __launch_bounds__(kBlock) k_ssd_partial(const float* __restrict_
                                                          double* __restrict__ part) {
   __shared__ double sh[kBlock];
   double s = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    float r = u[i] - R[i];
-    s += (double)r * (double)r;
-    if (wres) wres[i] = scale * r;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += 4 * st) {
+    float ua[4], ra[4];              // four elements' loads in flight (clamped), terms added in index order
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long k = min(i + q * st, n - 1);
+      ua[q] = u[k];
+      ra[q] = R[k];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (i + q * st >= n) break;
+      const float r = ua[q] - ra[q];
+      s += (double)r * (double)r;
+      if (wres) wres[i + q * st] = scale * r;
+    }
   }
   double t = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -38,9 +62,20 @@ __global__ void __launch_bounds__(kBlock) k_ssd_partial(const float* __restrict_
 
 // Sum of the block partials of a reduction, in the same order in every block
 // of kBlock threads (so consumers can take it without a separate launch).
+// Four loads are issued before the first add, in the same order of addition
+// as a plain strided loop.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nparts, double* sh) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+  const int bs = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 3 * bs < nparts; i += 4 * bs) {
+    const double a = part[i], b = part[i + bs], c = part[i + 2 * bs], d = part[i + 3 * bs];
+    s += a;
+    s += b;
+    s += c;
+    s += d;
+  }
+  for (; i < nparts; i += bs) s += part[i];
   return block_sum(s, sh);
 }
 
@@ -175,14 +210,29 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restric
   }
   const float a = ok ? (float)(sc[0] / pHp) : 0.f;
   double s = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    float ri = r[i];
-    if (ok) {
-      x[i] = fmaf(a, p[i], x[i]);
-      ri = fmaf(-a, Hp[i], ri);
-      r[i] = ri;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += 4 * st) {   // four elements' loads in flight (clamped), terms added in index order
+    float ra[4], pa[4], xa[4], ha[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long k = min(i + u * st, n - 1);
+      ra[u] = r[k];
+      pa[u] = p[k];
+      xa[u] = x[k];
+      ha[u] = Hp[k];
     }
-    s += (double)ri * (double)ri;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i + u * st >= n) break;
+      float ri = ra[u];
+      if (ok) {
+        x[i + u * st] = fmaf(a, pa[u], xa[u]);
+        ri = fmaf(-a, ha[u], ri);
+        r[i + u * st] = ri;
+      }
+      s += (double)ri * (double)ri;
+    }
   }
   __syncthreads();  // every thread has read sh[0] of the first sum
   const double t = block_sum(s, sh);

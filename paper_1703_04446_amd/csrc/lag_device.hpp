@@ -193,15 +193,36 @@ __device__ __forceinline__ float lap_at(const float* __restrict__ f, const int m
   return s;
 }
 
+// Field f and node r (with its x, y, z on the velocity grid) of the flat
+// index i = f nv + r: 32-bit divisions where the indices fit (the 64-bit
+// ones expand into long branchy sequences), else 64-bit.
+__device__ __forceinline__ void split_index(const Geo& g, long long i, long long& f, long long& r, int& x, int& y,
+                                            int& z) {
+  if (i < 0x7fffffffLL && g.nv < 0x7fffffffLL) {
+    const unsigned ui = (unsigned)i, nv = (unsigned)g.nv, m0 = (unsigned)g.mv[0], m1 = (unsigned)g.mv[1];
+    const unsigned uf = ui / nv, ur = ui - uf * nv, t = ur / m0;
+    f = uf;
+    r = ur;
+    x = (int)(ur - t * m0);
+    y = (int)(t % m1);
+    z = (int)(t / m1);
+  } else {
+    f = i / g.nv;
+    r = i - f * g.nv;
+    x = (int)(r % g.mv[0]);
+    y = (int)((r / g.mv[0]) % g.mv[1]);
+    z = (int)(r / ((long long)g.mv[0] * g.mv[1]));
+  }
+}
+
+// The regulariser at field f, node r = (x, y, z) (split_index).
 template <int D, bool CURV>
-__device__ __forceinline__ float reg_value(const Geo& g, const float* __restrict__ p, const float* __restrict__ scale,
-                                           float gamma, const float ih2[3], long long i) {
-  const long long f = i / g.nv;
-  const long long r = i - f * g.nv;
+__device__ __forceinline__ float reg_value_at(const Geo& g, const float* __restrict__ p,
+                                              const float* __restrict__ scale, float gamma, const float ih2[3],
+                                              long long f, long long r, int x, int y, int z) {
   const int j = (int)(f / D);
   const float* fld = p + f * g.nv;
   const int m[3] = {g.mv[0], g.mv[1], D == 3 ? g.mv[2] : 1};
-  const int x = (int)(r % m[0]), y = (int)((r / m[0]) % m[1]), z = (int)(r / ((long long)m[0] * m[1]));
   float a;
   if (!CURV) {
     a = lap_at<D>(fld, m, ih2, x, y, z);
@@ -227,8 +248,18 @@ __device__ __forceinline__ float reg_value(const Geo& g, const float* __restrict
     a = s;
   }
   float val = scale[j] * a;
-  if (gamma != 0.f) val = fmaf(gamma, fld[r], val);
+  const float cr = fld[r];           // loaded either way: no branch around a load
+  if (gamma != 0.f) val = fmaf(gamma, cr, val);
   return val;
+}
+
+template <int D, bool CURV>
+__device__ __forceinline__ float reg_value(const Geo& g, const float* __restrict__ p, const float* __restrict__ scale,
+                                           float gamma, const float ih2[3], long long i) {
+  long long f, r;
+  int x, y, z;
+  split_index(g, i, f, r, x, y, z);   // z = 0 in 2-D (a node lies below mv[0] mv[1])
+  return reg_value_at<D, CURV>(g, p, scale, gamma, ih2, f, r, x, y, z);
 }
 
 // Block-wide float64 sum in a fixed tree (every thread of the block calls

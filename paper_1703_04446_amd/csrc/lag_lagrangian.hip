@@ -2597,11 +2597,9 @@ template <int D, int K>
 __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fields, const float* __restrict__ part,
                                           const int* __restrict__ cs0, const int2* __restrict__ ce0,
                                           const int* __restrict__ cs1, const int2* __restrict__ ce1,
-                                          const int* __restrict__ cs2, const int2* __restrict__ ce2, long long i) {
-  const long long f = i / g.nv, r = i - f * g.nv;
-  const int X = (int)(r % g.mv[0]);
-  const int Y = (int)((r / g.mv[0]) % g.mv[1]);
-  const int Z = D == 3 ? (int)(r / ((long long)g.mv[0] * g.mv[1])) : 0;
+                                          const int* __restrict__ cs2, const int2* __restrict__ ce2, long long f,
+                                          int X, int Y, int Z) {
+  if (D != 3) Z = 0;
   const long long tsz = (long long)fields * B.tvol;
   const float* pf = part + f * B.tvol;
   float sum = 0.f;
@@ -2609,12 +2607,27 @@ __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fie
     const int sx = cs0[X], nx = cs0[X + 1] - sx;
     const int sy = cs1[Y], ny = cs1[Y + 1] - sy;
     const int sz = cs2[Z], nz = cs2[Z + 1] - sz;
+    // The first two entries of each list and their 2x2x2 tile values are
+    // loaded unconditionally, at indices that are always in range (a
+    // conditional load becomes a branch that waits for it alone): entries
+    // past a list's end read a valid slot and are replaced by (0, 0), whose
+    // tile value is read and left out of the sum.  Third and later entries
+    // (rarer) load under their conditions.
     int2 cx[K], cy[K], cz[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      cx[k] = k < nx ? ce0[sx + k] : make_int2(0, 0);
-      cy[k] = k < ny ? ce1[sy + k] : make_int2(0, 0);
-      cz[k] = k < nz ? ce2[sz + k] : make_int2(0, 0);
+      if (k < 2) {
+        const int2 ex = ce0[nx > 0 ? sx + min(k, nx - 1) : 0];
+        const int2 ey = ce1[ny > 0 ? sy + min(k, ny - 1) : 0];
+        const int2 ez = ce2[nz > 0 ? sz + min(k, nz - 1) : 0];
+        cx[k] = k < nx ? ex : make_int2(0, 0);
+        cy[k] = k < ny ? ey : make_int2(0, 0);
+        cz[k] = k < nz ? ez : make_int2(0, 0);
+      } else {
+        cx[k] = k < nx ? ce0[sx + k] : make_int2(0, 0);
+        cy[k] = k < ny ? ce1[sy + k] : make_int2(0, 0);
+        cz[k] = k < nz ? ce2[sz + k] : make_int2(0, 0);
+      }
     }
     float v[K][K][K];
 #pragma unroll
@@ -2623,20 +2636,23 @@ __device__ __forceinline__ float tile_sum(const Geo& g, const Bricks& B, int fie
       for (int ky = 0; ky < K; ++ky)
 #pragma unroll
         for (int kx = 0; kx < K; ++kx) {
-          v[kz][ky][kx] = 0.f;
-          if (kz < nz && ky < ny && kx < nx) {
-            const long long b = cx[kx].x + (long long)B.nb[0] * (cy[ky].x + B.nb[1] * cz[kz].x);
-            const int t = cx[kx].y + B.tdim[0] * (cy[ky].y + B.tdim[1] * cz[kz].y);
-            v[kz][ky][kx] = pf[b * tsz + t];
-          }
+          const long long b = cx[kx].x + (long long)B.nb[0] * (cy[ky].x + B.nb[1] * cz[kz].x);
+          const int t = cx[kx].y + B.tdim[0] * (cy[ky].y + B.tdim[1] * cz[kz].y);
+          if (kz < 2 && ky < 2 && kx < 2) v[kz][ky][kx] = pf[b * tsz + t];
+          else v[kz][ky][kx] = (kz < nz && ky < ny && kx < nx) ? pf[b * tsz + t] : 0.f;
         }
+    // the first term unconditionally and the others through selects, so no
+    // load is sunk into a branch of its own (adding +0 leaves the sum as is;
+    // a node without covering tiles takes 0 at the end)
+    sum = v[0][0][0];
 #pragma unroll
     for (int kz = 0; kz < K; ++kz)
 #pragma unroll
       for (int ky = 0; ky < K; ++ky)
 #pragma unroll
         for (int kx = 0; kx < K; ++kx)
-          if (kz < nz && ky < ny && kx < nx) sum += v[kz][ky][kx];
+          if (kz + ky + kx > 0) sum += (kz < nz && ky < ny && kx < nx) ? v[kz][ky][kx] : 0.f;
+    if (nx == 0 || ny == 0 || nz == 0) sum = 0.f;
   } else {
     for (int ez = cs2[Z]; ez < cs2[Z + 1]; ++ez) {
       const int2 cz = ce2[ez];
@@ -2671,7 +2687,15 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
   const bool valid = i < g.nv * fields;
   float val = 0.f;
   if (valid) {
-    const float sum = tile_sum<D, K>(g, B, fields, part, cs0, ce0, cs1, ce1, cs2, ce2, i);
+    // one index split and no branch between the tile sum's chain of
+    // cover-list and tile loads and the regulariser's loads, which the
+    // compiler then issues before it waits for the tile values
+    long long f, r;
+    int X, Y, Z;
+    split_index(g, i, f, r, X, Y, Z);
+    const float sum = tile_sum<D, K>(g, B, fields, part, cs0, ce0, cs1, ce1, cs2, ce2, f, X, Y, Z);
+    float rv = 0.f;
+    if constexpr (REG != 0) rv = reg_value_at<D, REG == 2>(g, rt.p, rt.scale, rt.gamma, rt.ih2, f, r, X, Y, Z);
     float t;
     if (fb) {
       t = sum + fb[i];
@@ -2688,8 +2712,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_reduce(Geo g, Bricks B, int fie
       }
     }
     if constexpr (REG != 0) {
-      val = reg_value<D, REG == 2>(g, rt.p, rt.scale, rt.gamma, rt.ih2, i);
-      val += t;
+      val = rv + t;
     } else {
       val = t;
     }
