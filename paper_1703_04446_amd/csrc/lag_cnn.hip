@@ -36,6 +36,8 @@
 #include <random>
 #include <vector>
 
+#include <type_traits>
+
 #include "lag_internal.hpp"
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
@@ -119,7 +121,7 @@ __device__ __forceinline__ int tap_off(int t, int hx, int hy) {
 // chunks z, z + gridDim.z, ... and, with gridDim.z > 1, writes its raw sums
 // to kpart[z][v][out_cs] for k_conv_finish.
 template <bool BWD, int NT>
-__global__ void __launch_bounds__(256) k_conv_mfma(const unsigned short* __restrict__ in, int in_cs, int in_co,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) k_conv_mfma(const unsigned short* __restrict__ in, int in_cs, int in_co,
                                                    int kch, int s, ConvTile T,
                                                    const unsigned short* __restrict__ w, int wn, int wk,
                                                    const float* __restrict__ bias, float* __restrict__ out,
@@ -153,61 +155,109 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const unsigned short* __restr
   const int kz = gridDim.z;
   for (int c = 16 * blockIdx.z; c < kch; c += 16 * kz) {
     __syncthreads();   // the previous chunk's reads are done
-    for (int q = threadIdx.x; q < 2 * H; q += blockDim.x) {
-      const int r = q >> 1, half = q & 1;
-      const int hx = r % HX, hy = (r / HX) % HY, hz = r / (HX * HY);
-      int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-      gx = gx < 0 ? gx + s : (gx >= s ? gx - s : gx);
-      gy = gy < 0 ? gy + s : (gy >= s ? gy - s : gy);
-      gz = gz < 0 ? gz + s : (gz >= s ? gz - s : gz);
-      const long long v = ((long long)gz * s + gy) * s + gx;
-      const uint4 val = *reinterpret_cast<const uint4*>(in + v * in_cs + in_co + c + 8 * half);
-      *reinterpret_cast<uint4*>(tile + r * kRow + 8 * half) = val;
+    // halo and weights, four rows per thread and pass: the four loads go
+    // out before the stores (a plain strided loop waits on one global trip
+    // per row); past the end a thread loads and stores the last row again,
+    // the same value that row's own thread writes
+    for (int q0 = threadIdx.x; q0 < 2 * H; q0 += 4 * blockDim.x) {
+      uint4 val[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = min(q0 + k * (int)blockDim.x, 2 * H - 1);
+        const int r = q >> 1, half = q & 1;
+        const int hx = r % HX, hy = (r / HX) % HY, hz = r / (HX * HY);
+        int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        gx = gx < 0 ? gx + s : (gx >= s ? gx - s : gx);
+        gy = gy < 0 ? gy + s : (gy >= s ? gy - s : gy);
+        gz = gz < 0 ? gz + s : (gz >= s ? gz - s : gz);
+        const long long v = ((long long)gz * s + gy) * s + gx;
+        val[k] = *reinterpret_cast<const uint4*>(in + v * in_cs + in_co + c + 8 * half);
+      }
+      __builtin_amdgcn_sched_barrier(0);   // else each load is sunk to its store and waited for alone
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {   // unconditional: a row past the end stores the last row's value again
+        const int q = min(q0 + k * (int)blockDim.x, 2 * H - 1);
+        *reinterpret_cast<uint4*>(tile + (q >> 1) * kRow + 8 * (q & 1)) = val[k];
+      }
     }
-    for (int q = threadIdx.x; q < kTaps * 16 * NT * 2; q += blockDim.x) {
-      const int row = q >> 1, half = q & 1;   // row = t * 16 NT + n
-      const int t = row / (16 * NT), n = row - t * 16 * NT;
-      const uint4 val = *reinterpret_cast<const uint4*>(w + ((long long)t * wn + n_base + n) * wk + c + 8 * half);
-      *reinterpret_cast<uint4*>(wt + row * 16 + 8 * half) = val;
+    for (int q0 = threadIdx.x; q0 < kTaps * 16 * NT * 2; q0 += 4 * blockDim.x) {
+      uint4 val[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = min(q0 + k * (int)blockDim.x, kTaps * 16 * NT * 2 - 1);
+        const int row = q >> 1, half = q & 1;   // row = t * 16 NT + n
+        const int t = row / (16 * NT), n = row - t * 16 * NT;
+        val[k] = *reinterpret_cast<const uint4*>(w + ((long long)t * wn + n_base + n) * wk + c + 8 * half);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = min(q0 + k * (int)blockDim.x, kTaps * 16 * NT * 2 - 1);
+        *reinterpret_cast<uint4*>(wt + (q >> 1) * 16 + 8 * (q & 1)) = val[k];
+      }
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 14; ++q) {
+    // operands of K step q + 1 are read from LDS while step q's MFMAs run
+    bf16x8 bv[2][NT], av[2][4];
+    auto load_step = [&](int q, bf16x8* b, bf16x8* a) {
       const int t = 2 * q + (grp >> 1);
       const int off = tap_off(BWD ? (t >= 27 ? 27 : 26 - t) : t, HX, HY);
-      bf16x8 bv[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
-        bv[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(wt + ((t * 16 * NT) + 16 * nt + m) * 16 + ci0));
+        b[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(wt + ((t * 16 * NT) + 16 * nt + m) * 16 + ci0));
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(tile + (hb[i] + off) * kRow + ci0));
+      for (int i = 0; i < 4; ++i) a[i] = as_bf16x8(*reinterpret_cast<const uint4*>(tile + (hb[i] + off) * kRow + ci0));
+    };
+    load_step(0, bv[0], av[0]);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[i][nt], 0, 0, 0);
-      }
+    for (int q = 0; q < 14; ++q) {
+      const int cur = q & 1;
+      if (q + 1 < 14) load_step(q + 1, bv[cur ^ 1], av[cur ^ 1]);
+      // left to itself the scheduler sinks each read to its MFMA and waits
+      // for it alone (one LDS trip per MFMA)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[cur][i], bv[cur][nt], acc[i][nt], 0, 0, 0);
     }
   }
+  // Epilogue: the case is decided once per thread (a branch per output
+  // made the compiler wait for every earlier store before the next one).
+  // MODE 0: raw split sums to kpart; 1: backward gx to out; 2: forward
+  // bias -> relu -> bf16 act, 3: and the pre-activation to out.
+  auto epilogue = [&](auto mode_c) {
+    constexpr int MODE = decltype(mode_c)::value;
+    float bn[NT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int nt = 0; nt < NT; ++nt) bn[nt] = MODE >= 2 ? bias[n_base + 16 * nt + m] : 0.f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int u = 64 * wave + 16 * i + 4 * grp + j;
-      const int x = x0 + (u & (TX - 1)), y = y0 + ((u >> T.lx) & (TY - 1)), z = z0 + (u >> (T.lx + T.ly));
-      const long long v = ((long long)z * s + y) * s + x;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int n = n_base + 16 * nt + m;
-        if (kz > 1) {
-          kpart[((long long)blockIdx.z * s * s * s + v) * out_cs + n] = acc[i][nt][j];
-        } else if constexpr (BWD) {
-          out[v * out_cs + n] = acc[i][nt][j];
-        } else {
-          const float val = acc[i][nt][j] + bias[n];
-          if (out) out[v * out_cs + n] = val;
-          act[v * act_cs + act_co + n] = f2bf(fmaxf(val, 0.f));
+      for (int j = 0; j < 4; ++j) {
+        const int u = 64 * wave + 16 * i + 4 * grp + j;
+        const int x = x0 + (u & (TX - 1)), y = y0 + ((u >> T.lx) & (TY - 1)), z = z0 + (u >> (T.lx + T.ly));
+        const long long v = ((long long)z * s + y) * s + x;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int n = n_base + 16 * nt + m;
+          if constexpr (MODE == 0) {
+            kpart[((long long)blockIdx.z * s * s * s + v) * out_cs + n] = acc[i][nt][j];
+          } else if constexpr (MODE == 1) {
+            out[v * out_cs + n] = acc[i][nt][j];
+          } else {
+            const float val = acc[i][nt][j] + bn[nt];
+            if constexpr (MODE == 3) out[v * out_cs + n] = val;
+            act[v * act_cs + act_co + n] = f2bf(fmaxf(val, 0.f));
+          }
         }
       }
-    }
+  };
+  if (kz > 1) epilogue(std::integral_constant<int, 0>{});
+  else if constexpr (BWD) epilogue(std::integral_constant<int, 1>{});
+  else if (out) epilogue(std::integral_constant<int, 3>{});
+  else epilogue(std::integral_constant<int, 2>{});
 }
 
 // Sum of the split contraction in order of z, then the epilogue: forward
