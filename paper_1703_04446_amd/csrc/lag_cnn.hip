@@ -370,6 +370,44 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const unsigned short* __rest
       transpose_4x8(r4, xT + ((8 * half) * HZ * HY + rr) * 16 + 4 * xr, HZ * HY * 16);
     }
     __syncthreads();
+    if (TX == 8) {
+      // tile side 8: every read of a K step (B, and the two row halves of
+      // each of the wave's tap rows) is issued before its MFMAs
+      for (int q = 0; q < NV / 32; ++q) {
+        const int u0 = 32 * q + 8 * grp;
+        bf16x8 bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          bv[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(gT + (16 * nt + m) * NV + u0));
+        const int y = (u0 >> 3) & (TY - 1), z = u0 >> (3 + T.ly);
+        uint4 lo[kMaxRows], hi[kMaxRows];
+#pragma unroll
+        for (int k = 0; k < kMaxRows; ++k) {
+          const int j = min(wave + nw * k, 8);   // rows past 8 read row 8 and are not used
+          const unsigned short* row = xT + ((m * HZ + z + j / 3) * HY + y + j % 3) * 16;
+          lo[k] = *reinterpret_cast<const uint4*>(row);
+          hi[k] = *reinterpret_cast<const uint4*>(row + 8);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // else each read is sunk to its MFMAs and waited for alone
+#pragma unroll
+        for (int k = 0; k < kMaxRows; ++k) {
+          if (wave + nw * k >= 9) continue;
+          const bf16x8 a0 = as_bf16x8(lo[k]);
+          const bf16x8 a1 = as_bf16x8(make_uint4(__builtin_amdgcn_alignbyte(lo[k].y, lo[k].x, 2),
+                                                 __builtin_amdgcn_alignbyte(lo[k].z, lo[k].y, 2),
+                                                 __builtin_amdgcn_alignbyte(lo[k].w, lo[k].z, 2),
+                                                 __builtin_amdgcn_alignbyte(hi[k].x, lo[k].w, 2)));
+          const bf16x8 a2 = as_bf16x8(make_uint4(lo[k].y, lo[k].z, lo[k].w, hi[k].x));
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            acc[k][0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv[nt], acc[k][0][nt], 0, 0, 0);
+            acc[k][1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv[nt], acc[k][1][nt], 0, 0, 0);
+            acc[k][2][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bv[nt], acc[k][2][nt], 0, 0, 0);
+          }
+        }
+      }
+      continue;                      // next tile
+    }
     for (int q = 0; q < NV / 32; ++q) {
       // lane group grp: voxels u = 32 q + 8 grp .. +8; B once per step
       const int u0 = 32 * q + 8 * grp;
@@ -725,11 +763,20 @@ __global__ void k_head_fwd(const unsigned short* __restrict__ d0, int c, int V, 
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   float o0 = bh[0], o1 = bh[1], o2 = bh[2];
-  for (int ch = 0; ch < c; ++ch) {
-    float a = bf2f(d0[(long long)v * c + ch]);
-    o0 = fmaf(a, wh[ch * 3 + 0], o0);
-    o1 = fmaf(a, wh[ch * 3 + 1], o1);
-    o2 = fmaf(a, wh[ch * 3 + 2], o2);
+  // the voxel's channels (a multiple of 16) as 16-byte loads, all issued
+  // before the sums, which take the channels in order
+  for (int c16 = 0; c16 < c; c16 += 16) {
+    const uint4 r0 = *reinterpret_cast<const uint4*>(d0 + (long long)v * c + c16);
+    const uint4 r1 = *reinterpret_cast<const uint4*>(d0 + (long long)v * c + c16 + 8);
+    const unsigned int rw[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int ch = c16 + e;
+      const float a = __uint_as_float((e & 1) ? (rw[e >> 1] & 0xffff0000u) : (rw[e >> 1] << 16));
+      o0 = fmaf(a, wh[ch * 3 + 0], o0);
+      o1 = fmaf(a, wh[ch * 3 + 1], o1);
+      o2 = fmaf(a, wh[ch * 3 + 2], o2);
+    }
   }
   vout[v] = scale * o0;
   vout[V + v] = scale * o1;
