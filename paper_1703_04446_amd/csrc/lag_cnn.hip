@@ -635,15 +635,31 @@ __global__ void __launch_bounds__(256) k_conv_in2(const float* __restrict__ T, c
   }
 }
 
+// Voxel and channel of the flat element i = v c + ch for a channel count c
+// that is a power of two (16, 32 or 64 here), and x, y, z of voxel v on a
+// grid of side s: 32-bit arithmetic (at most 256^3 x 64 < 2^31 elements;
+// 64-bit divisions expand into long branchy sequences).
+__device__ __forceinline__ void split_vc(long long i, int c, int& v, int& ch) {
+  const unsigned ui = (unsigned)i;
+  v = (int)(ui >> (__ffs(c) - 1));
+  ch = (int)(ui & (unsigned)(c - 1));
+}
+__device__ __forceinline__ void split_xyz(int v, int s, int& x, int& y, int& z) {
+  const unsigned uv = (unsigned)v, us = (unsigned)s, t = uv / us;
+  x = (int)(uv - t * us);
+  y = (int)(t % us);
+  z = (int)(t / us);
+}
+
 // pool: out (size s/2) = mean of the 2x2x2 children of `in` (size s)
 __global__ void k_pool(const unsigned short* __restrict__ in, int in_cs, int in_co, int c, int s,
                        unsigned short* __restrict__ out) {
   const int h = s / 2;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)h * h * h * c) return;
-  const int ch = (int)(i % c);
-  const int v = (int)(i / c);
-  const int x = v % h, y = (v / h) % h, z = v / (h * h);
+  int v, ch, x, y, z;
+  split_vc(i, c, v, ch);
+  split_xyz(v, h, x, y, z);
   float sum = 0.f;
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
@@ -660,9 +676,10 @@ __global__ void k_up(const unsigned short* __restrict__ in, int c, int s, unsign
   const int c8 = c / 8;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)s * s * s * c8) return;
-  const int ch = 8 * (int)(i % c8);
-  const int v = (int)(i / c8);
-  const int x = v % s, y = (v / s) % s, z = v / (s * s);
+  int v, ch, x, y, z;
+  split_vc(i, c8, v, ch);
+  ch *= 8;
+  split_xyz(v, s, x, y, z);
   const int h = s / 2;
   const int pv = ((z >> 1) * h + (y >> 1)) * h + (x >> 1);
   *reinterpret_cast<uint4*>(out + (long long)v * out_cs + ch) =
@@ -720,9 +737,9 @@ __global__ void k_pool_back(const float* __restrict__ gp, int c, int s, float* _
                             int gf_co) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)s * s * s * c) return;
-  const int ch = (int)(i % c);
-  const int v = (int)(i / c);
-  const int x = v % s, y = (v / s) % s, z = v / (s * s);
+  int v, ch, x, y, z;
+  split_vc(i, c, v, ch);
+  split_xyz(v, s, x, y, z);
   const int h = s / 2;
   const int pv = ((z >> 1) * h + (y >> 1)) * h + (x >> 1);
   gf[(long long)v * gf_cs + gf_co + ch] += 0.125f * gp[(long long)pv * c + ch];
@@ -733,9 +750,9 @@ __global__ void k_up_back(const float* __restrict__ g, int gcs, int c, int s, fl
   const int h = s / 2;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)h * h * h * c) return;
-  const int ch = (int)(i % c);
-  const int v = (int)(i / c);
-  const int x = v % h, y = (v / h) % h, z = v / (h * h);
+  int v, ch, x, y, z;
+  split_vc(i, c, v, ch);
+  split_xyz(v, h, x, y, z);
   float sum = 0.f;
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
