@@ -275,7 +275,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
   float2* b0 = sh;
   float2* b1 = sh + lpb * ls;
   float2* twl = sh + 2 * lpb * ls;  // twiddles, staged with the first load
-  for (int q = threadIdx.x; q < n; q += blockDim.x) twl[q] = L.tw[q];
+  // the thread's first twiddle is stored after the data loads below (both
+  // trips overlap; a thread past the end stores the last twiddle again)
+  const int tq = min((int)threadIdx.x, n - 1);
+  const float2 twv = L.tw[tq];
+  for (int q = threadIdx.x + blockDim.x; q < n; q += blockDim.x) twl[q] = L.tw[q];
   const int m0 = cx, m1 = g.mv[1], m2 = D == 3 ? g.mv[2] : 1;
   const long long fstride = (long long)m0 * m1 * m2;
   const int fields = g.nodes * D;
@@ -295,10 +299,23 @@ __global__ void __launch_bounds__(kBlock) k_fft_axis(Geo g, int axis, int lpb, F
   const int c1 = axis == 1 ? 0 : o;  // y of the lines (z pass)
   // load across lines (neighbouring x columns): contiguous runs of nlines
   const DivBy by_lines(nlines), by_n(n);
-  for (int e = threadIdx.x; e < nlines * n; e += blockDim.x) {
-    const int i = by_lines(e), l = e - i * nlines;
-    b0[l * ls + i] = in[base + l + (long long)i * estride];
+  // two elements per thread and pass, both loads issued before the stores
+  // (past the end the last element is loaded and stored again)
+  for (int e0 = threadIdx.x; e0 < nlines * n; e0 += 2 * blockDim.x) {
+    float2 v[2];
+    int at[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(e0 + u * (int)blockDim.x, nlines * n - 1);
+      const int i = by_lines(e), l = e - i * nlines;
+      v[u] = in[base + l + (long long)i * estride];
+      at[u] = l * ls + i;
+    }
+    __builtin_amdgcn_sched_barrier(0);   // else the second load is issued after the first store's wait
+#pragma unroll
+    for (int u = 0; u < 2; ++u) b0[at[u]] = v[u];
   }
+  twl[tq] = twv;
   __syncthreads();
   float2* res;
   if (MODE == 1) {
@@ -434,17 +451,32 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_fwd(Geo g, FftLine Lx, F
   float2* b1 = sh + cap;
   float2* twx = sh + 2 * cap;
   float2* twy = twx + nx;
-  for (int q = threadIdx.x; q < nx; q += blockDim.x) twx[q] = Lx.tw[q];
-  for (int q = threadIdx.x; q < ny; q += blockDim.x) twy[q] = Ly.tw[q];
+  // twiddles (twy follows twx): the thread's first one is loaded here and
+  // stored after the data loads below, so both trips overlap (a thread past
+  // the end stores the last twiddle again)
+  const int tq = min((int)threadIdx.x, nx + ny - 1);
+  const float2 twv = tq < nx ? Lx.tw[tq] : Ly.tw[tq - nx];
+  for (int q = threadIdx.x + blockDim.x; q < nx + ny; q += blockDim.x) twx[q] = q < nx ? Lx.tw[q] : Ly.tw[q - nx];
   const long long plane = blockIdx.x;
   const float* src = in + plane * nx * ny;
-  for (int e = threadIdx.x; e < pairs * nx; e += blockDim.x) {
-    const int l = by_nx(e), i = e - l * nx;
-    const int y = 2 * l;
-    const float a = src[y * nx + i];
-    const float b = y + 1 < ny ? src[(y + 1) * nx + i] : 0.f;
-    b0[l * lsx + i] = make_float2(a, b);
+  for (int e0 = threadIdx.x; e0 < pairs * nx; e0 += 2 * blockDim.x) {   // two per pass, loads first
+    float2 v[2];
+    int at[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(e0 + u * (int)blockDim.x, pairs * nx - 1);
+      const int l = by_nx(e), i = e - l * nx;
+      const int y = 2 * l;
+      const float a = src[y * nx + i];
+      const float b = src[min(y + 1, ny - 1) * nx + i];
+      v[u] = make_float2(a, y + 1 < ny ? b : 0.f);
+      at[u] = l * lsx + i;
+    }
+    __builtin_amdgcn_sched_barrier(0);   // else the second load is issued after the first store's wait
+#pragma unroll
+    for (int u = 0; u < 2; ++u) b0[at[u]] = v[u];
   }
+  twx[tq] = twv;
   __syncthreads();
   float2* rx = lds_fft<false>(Lx, twx, pairs, lsx, b0, b1);
   float2* t = rx == b0 ? b1 : b0;
@@ -479,14 +511,29 @@ __global__ void __launch_bounds__(kPlaneBlock) k_fft_xy_inv(Geo g, FftLine Lx, F
   float2* b1 = sh + cap;
   float2* twx = sh + 2 * cap;
   float2* twy = twx + nx;
-  for (int q = threadIdx.x; q < nx; q += blockDim.x) twx[q] = Lx.tw[q];
-  for (int q = threadIdx.x; q < ny; q += blockDim.x) twy[q] = Ly.tw[q];
+  // twiddles (twy follows twx): the thread's first one is loaded here and
+  // stored after the data loads below, so both trips overlap (a thread past
+  // the end stores the last twiddle again)
+  const int tq = min((int)threadIdx.x, nx + ny - 1);
+  const float2 twv = tq < nx ? Lx.tw[tq] : Ly.tw[tq - nx];
+  for (int q = threadIdx.x + blockDim.x; q < nx + ny; q += blockDim.x) twx[q] = q < nx ? Lx.tw[q] : Ly.tw[q - nx];
   const long long plane = blockIdx.x;
   const float2* src = in + plane * ny * cx;
-  for (int e = threadIdx.x; e < ny * cx; e += blockDim.x) {
-    const int y = by_cx(e), k = e - y * cx;
-    b0[k * lsy + y] = src[y * cx + k];
+  for (int e0 = threadIdx.x; e0 < ny * cx; e0 += 2 * blockDim.x) {   // two per pass, loads first
+    float2 v[2];
+    int at[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(e0 + u * (int)blockDim.x, ny * cx - 1);
+      const int y = by_cx(e), k = e - y * cx;
+      v[u] = src[y * cx + k];
+      at[u] = k * lsy + y;
+    }
+    __builtin_amdgcn_sched_barrier(0);   // else the second load is issued after the first store's wait
+#pragma unroll
+    for (int u = 0; u < 2; ++u) b0[at[u]] = v[u];
   }
+  twx[tq] = twv;
   __syncthreads();
   float2* ry = lds_fft<true>(Ly, twy, cx, lsy, b0, b1);
   float2* t = ry == b0 ? b1 : b0;
