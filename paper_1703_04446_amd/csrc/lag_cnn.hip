@@ -260,22 +260,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))
   else epilogue(std::integral_constant<int, 2>{});
 }
 
+constexpr int kMaxSplit = 8;   // contraction splits (conv_split: at most 128 input channels / 16)
+
 // Sum of the split contraction in order of z, then the epilogue: forward
 // (bias) -> bf16 relu activation (and the pre-activation if out != null);
 // backward -> gx.
-template <bool BWD>
-__global__ void k_conv_finish(const float* __restrict__ kpart, int kz, long long V, int nch,
+template <bool BWD, int KZ>
+__global__ void k_conv_finish(const float* __restrict__ kpart, long long V, int nch,
                               const float* __restrict__ bias, float* __restrict__ out, unsigned short* __restrict__ act,
                               int act_cs, int act_co) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V * nch) return;
+  // the KZ parts, all loaded before the sum
+  float p[KZ];
+#pragma unroll
+  for (int z = 0; z < KZ; ++z) p[z] = kpart[z * V * nch + i];
   float sum = 0.f;
-  for (int z = 0; z < kz; ++z) sum += kpart[z * V * nch + i];
+#pragma unroll
+  for (int z = 0; z < KZ; ++z) sum += p[z];
   if constexpr (BWD) {
     out[i] = sum;
   } else {
-    const int n = (int)(i % nch);
-    const long long v = i / nch;
+    // forward: nch is a layer's output width, 16, 32 or 64 (a power of
+    // two: no 64-bit division); i < 2^31
+    const int n = (int)((unsigned)i & (unsigned)(nch - 1));
+    const long long v = (long long)((unsigned)i >> (__ffs(nch) - 1));
     const float val = sum + bias[n];
     if (out) out[i] = val;
     act[v * act_cs + act_co + n] = f2bf(fmaxf(val, 0.f));
@@ -1028,7 +1037,7 @@ static int conv_nt(int s, int n16) {
 static int conv_split(int s, int nout, int kch) {
   const int blocks = conv_tiles(s) * (nout / (16 * conv_nt(s, nout / 16)));
   if (blocks >= 512) return 1;
-  return std::max(1, std::min(kch / 16, ceil_div(512, blocks)));
+  return std::max(1, std::min(std::min(kch / 16, kMaxSplit), ceil_div(512, blocks)));
 }
 
 extern "C" {
@@ -1247,8 +1256,20 @@ static int launch_conv(lag_cnn n, int s, int nout, const unsigned short* in, int
   LAG_LAUNCH_CHECK();
   if (kz > 1) {
     const long long V = (long long)s * s * s;
-    hipLaunchKernelGGL((k_conv_finish<BWD>), dim3(ceil_div(V * nout, 256)), dim3(256), 0, st, n->kpart, kz, V, nout,
-                       bias, out, act, act_cs, act_co);
+    const dim3 fg(ceil_div(V * nout, 256));
+#define LAG_FIN(KZ)                                                                                         \
+  hipLaunchKernelGGL((k_conv_finish<BWD, KZ>), fg, dim3(256), 0, st, n->kpart, V, nout, bias, out, act, act_cs, \
+                     act_co)
+    switch (kz) {
+      case 2: LAG_FIN(2); break;
+      case 3: LAG_FIN(3); break;
+      case 4: LAG_FIN(4); break;
+      case 5: LAG_FIN(5); break;
+      case 6: LAG_FIN(6); break;
+      case 7: LAG_FIN(7); break;
+      default: LAG_FIN(8); break;   // conv_split never exceeds kMaxSplit = 8
+    }
+#undef LAG_FIN
     LAG_LAUNCH_CHECK();
   }
   return LAG_OK;
