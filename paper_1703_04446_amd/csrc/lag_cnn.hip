@@ -735,7 +735,15 @@ __global__ void k_relu_back(const float* __restrict__ g, int gcs, int goff, cons
   if ((int)threadIdx.x < c) {
     const int grp = threadIdx.x >> 3, e = threadIdx.x & 7;
     float s = 0.f;
-    for (int k = grp; k < 256; k += c8) s += sh[k][e];
+    // rows k = grp, grp + c8, ... (256 / c8 of them, a multiple of 8) added
+    // in that order, eight LDS reads in flight at a time
+    for (int k0 = grp; k0 < 256; k0 += 8 * c8) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = sh[k0 + u * c8][e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += x[u];
+    }
     part[(long long)blockIdx.x * c + threadIdx.x] = s;
   }
 }
