@@ -980,11 +980,13 @@ static int pcg_impl(lag_plan P, Op H, const float* b, float* x, double tol, int3
   P->geo.halt = P->ctl;
   for (int it = 0; it < maxit; ++it) {
     prof_at.push_back(P->prof_n);
-    if ((rc = pcg_iteration(P, H, x, s))) break;
-    ++enq;
     const int slot = it & 1;
-    if (hipMemcpyAsync(P->ctl_host + 8 * slot, P->ctl, sizeof(int) * 6, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipEventRecord(P->ctl_ev[slot], s) != hipSuccess) {
+    P->ctl_mirror = P->ctl_host + 8 * slot;   // the check writes this iteration's control block there
+    rc = pcg_iteration(P, H, x, s);
+    P->ctl_mirror = nullptr;
+    if (rc) break;
+    ++enq;
+    if (hipEventRecord(P->ctl_ev[slot], s) != hipSuccess) {
       rc = set_hip_error(hipGetLastError());
       break;
     }

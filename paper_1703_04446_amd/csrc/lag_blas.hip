@@ -292,8 +292,22 @@ __global__ void k_pcg_ctl_init(int* ctl, const double* sc, int maxit) {
 // After an iteration: sc[3] = r.r from the `rr` partials (mirrored into the
 // control block for the host), sc[0] = sc[2] (the new r.z becomes current),
 // then the stopping test.
-__global__ void __launch_bounds__(kBlock) k_pcg_check(int* ctl, double* sc, const double* __restrict__ rr, int nrr) {
-  if (ctl[0] != 0) return;
+__global__ void __launch_bounds__(kBlock) k_pcg_check(int* ctl, double* sc, const double* __restrict__ rr, int nrr,
+                                                       int* mirror) {
+  // mirror != null: the control block's first six ints are also written to
+  // pinned host memory (visible once the kernel has completed), which
+  // spares a separate device-to-host copy per iteration
+  auto publish = [&]() {
+    if (mirror) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) mirror[k] = ctl[k];
+      __threadfence_system();
+    }
+  };
+  if (ctl[0] != 0) {
+    if (threadIdx.x == 0) publish();
+    return;
+  }
   __shared__ double sh[kBlock];
   const double t = sum_partials(rr, nrr, sh);
   if (threadIdx.x != 0) return;
@@ -303,11 +317,13 @@ __global__ void __launch_bounds__(kBlock) k_pcg_check(int* ctl, double* sc, cons
   const int it = ctl[1] + 1;
   if (sc[4] != 0.0) {     // this iteration broke down: it does not count
     ctl[0] = 2;
+    publish();
     return;
   }
   ctl[1] = it;
   if (t <= sc[6]) ctl[0] = 1;
   else if (it >= ctl[2]) ctl[0] = 3;
+  publish();
 }
 
 int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s) {
@@ -319,7 +335,8 @@ int launch_pcg_ctl_init(int* ctl, const double* sc, int maxit, hipStream_t s) {
 int launch_pcg_check(lag_plan P, hipStream_t s) {
   unsigned blocks;
   reduce_launch(P->n_unknowns, blocks);
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(kBlock), 0, s, P->ctl, P->scalars, P->red_partial2, (int)blocks);
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(kBlock), 0, s, P->ctl, P->scalars, P->red_partial2, (int)blocks,
+                     P->ctl_mirror);
   LAG_LAUNCH_CHECK();
   return LAG_OK;
 }

@@ -106,6 +106,7 @@ struct lag_plan_s {
   // cached graph executable with the arguments it was captured for
   int* ctl = nullptr;          // device int[8]: status, iterations, cap, -, r.r (double at [4])
   int* ctl_host = nullptr;     // pinned host int[2][8]
+  int* ctl_mirror = nullptr;   // set around an eager PCG iteration: k_pcg_check writes the control block there
   double* sc_host = nullptr;   // pinned host double[8]
   hipEvent_t ctl_ev[2] = {nullptr, nullptr};
   hipStream_t gstream = nullptr;
