@@ -202,6 +202,23 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restric
                                                     int nphp, double* __restrict__ rr, const int* __restrict__ halt) {
   if (halted(halt)) return;
   __shared__ double sh[kBlock];
+  const long long st = (long long)gridDim.x * blockDim.x;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // four elements' loads in flight (clamped), terms added in index order;
+  // the first four go out before the p.Hp partials are summed, so both
+  // trips overlap
+  float ra[4], pa[4], xa[4], ha[4];
+  auto load4 = [&](long long i0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long k = min(i0 + u * st, n - 1);
+      ra[u] = r[k];
+      pa[u] = p[k];
+      xa[u] = x[k];
+      ha[u] = Hp[k];
+    }
+  };
+  if (i < n) load4(i);
   const double pHp = sum_partials(php, nphp, sh);
   const bool ok = pHp > 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -210,18 +227,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(long long n, float* __restric
   }
   const float a = ok ? (float)(sc[0] / pHp) : 0.f;
   double s = 0.0;
-  const long long st = (long long)gridDim.x * blockDim.x;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i < n; i += 4 * st) {   // four elements' loads in flight (clamped), terms added in index order
-    float ra[4], pa[4], xa[4], ha[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const long long k = min(i + u * st, n - 1);
-      ra[u] = r[k];
-      pa[u] = p[k];
-      xa[u] = x[k];
-      ha[u] = Hp[k];
-    }
+  for (; i < n; i += 4 * st) {
+    if (i != (long long)blockIdx.x * blockDim.x + threadIdx.x) load4(i);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (i + u * st >= n) break;
@@ -250,24 +257,38 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p_pack(Geo g, float* __restrict_
                                                         typename VecT<D>::T* __restrict__ pk) {
   if (halted(halt)) return;
   __shared__ double sh[kBlock];
+  const long long nv = g.nv, tot = nv * g.nodes;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // the first node's p and z are loaded before the r.z partials are summed
+  // (both trips overlap)
+  float p0[D], z0[D];
+  if (t0 < tot) {
+    const long long j = t0 / nv, q = t0 - j * nv;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const long long i = (j * D + c) * nv + q;
+      p0[c] = p[i];
+      z0[c] = z[i];
+    }
+  }
   const double rznew = sum_partials(rz, nrz, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[2] = rznew;
   const float beta = (float)(rznew / sc[0]);
-  const long long nv = g.nv, tot = nv * g.nodes;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
-    const long long j = t / nv, q = t - j * nv;
+  for (long long t = t0; t < tot; t += (long long)gridDim.x * blockDim.x) {
+    long long j, q;
+    int x, y, zc;
+    split_index(g, t, j, q, x, y, zc);
+    if (D != 3) zc = 0;
     float v[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       const long long i = (j * D + c) * nv + q;
-      v[c] = fmaf(beta, p[i], z[i]);
+      v[c] = fmaf(beta, t == t0 ? p0[c] : p[i], t == t0 ? z0[c] : z[i]);
       p[i] = v[c];
     }
     typename VecT<D>::T val;
     if constexpr (D == 3) val = make_float4(v[0], v[1], v[2], 0.f);
     else val = make_float2(v[0], v[1]);
-    const int x = (int)(q % g.mv[0]), y = (int)((q / g.mv[0]) % g.mv[1]);
-    const int zc = D == 3 ? (int)(q / ((long long)g.mv[0] * g.mv[1])) : 0;
 #pragma unroll
     for (int o = 0; o < (1 << D); ++o) {
       if (((o & 1) && x != 0) || ((o & 2) && y != 0) || ((o & 4) && zc != 0)) continue;
