@@ -60,8 +60,8 @@ MEASURED_TRAFFIC = {
     "source": "paper_1703_04446_amd/csrc/lag_lagrangian.hip",
     "sha256": "8316310a9d76284831c20830f34ff8f544016cd0d2292f5a492ec05b48410f53",
     "workload": "3d128_transport",
-    "fetch_kib": 179111.0, "fetch_scale": 1.999748,
-    "write_kib": 14658.4, "write_scale": 1.0,
+    "fetch_kib": 179085.0, "fetch_scale": 1.999743,
+    "write_kib": 14658.3, "write_scale": 1.0,
 }
 
 
