@@ -435,7 +435,7 @@ static int plan_create_locked(const lag_problem* prob, const int32_t* brick_targ
       ALLOC(P->pg_cells, sizeof(int) * chunks * 64);
       ALLOC(P->pg_rows, sizeof(int) * chunks * 64);
       ALLOC(P->pg_npages, sizeof(int) * (size_t)B.nbricks);
-      ALLOC(P->pg_order, sizeof(int) * (size_t)B.nbricks);
+      ALLOC(P->pg_order, sizeof(int) * pg_order_len(B.nbricks));
       ALLOC(P->pg_redo, sizeof(int));
       HIPC(hipMemset(P->pg_redo, 0, sizeof(int)));
     }
@@ -741,7 +741,7 @@ static bool jacobian_grow(lag_plan P, int need) {
   if (pcap > 0 && (!P->pg_npages || !P->pg_order || !P->pg_redo)) {
     const size_t nb = sizeof(int) * (size_t)P->bricks.nbricks;
     if ((!P->pg_npages && hipMalloc(&P->pg_npages, nb) != hipSuccess) ||
-        (!P->pg_order && hipMalloc(&P->pg_order, nb) != hipSuccess) ||
+        (!P->pg_order && hipMalloc(&P->pg_order, sizeof(int) * pg_order_len(P->bricks.nbricks)) != hipSuccess) ||
         (!P->pg_redo && (hipMalloc(&P->pg_redo, sizeof(int)) != hipSuccess ||
                          hipMemset(P->pg_redo, 0, sizeof(int)) != hipSuccess))) {
       (void)hipGetLastError();

@@ -75,7 +75,7 @@ struct lag_plan_s {
   int* pg_cells = nullptr;
   int* pg_rows = nullptr;
   int* pg_npages = nullptr;
-  int* pg_order = nullptr;     // launch order of the bricks (k_brick_order)
+  int* pg_order = nullptr;     // [XCD][slot] launch order of the bricks, -1 past a range (k_brick_order)
   int* pg_redo = nullptr;      // count of bricks whose product pass was redone at the exact scale
   // per-brick partial velocity tiles and, per axis, the list of (brick,
   // tile offset) pairs covering each velocity index (fixed-order reduction)
@@ -189,6 +189,10 @@ size_t adjoint_lds_bytes(lag_plan P);
 int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u, hipStream_t s);
 // pages per brick of the paged copy for capacity kmax (0: layout not used)
 int jac_pages_per_brick(lag_plan P, int kmax);
+// Launch slots per XCD of the paged product (room for a brick range of up to
+// twice the even share; k_brick_order), and the length of the order array.
+__host__ __device__ inline int pg_xcd_slots(long long nbricks) { return (int)(2 * ((nbricks + kXcds - 1) / kXcds)); }
+__host__ __device__ inline size_t pg_order_len(long long nbricks) { return (size_t)kXcds * (size_t)pg_xcd_slots(nbricks); }
 int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const float* wseed, float scale, float* out,
                      hipStream_t s, const RegTail* rt);
 int tiles_setup(lag_plan P);       // partial-tile buffer + cover tables (plan creation)

@@ -2279,25 +2279,85 @@ __global__ void __launch_bounds__(1024) k_cover_filter(int D, int3 mv, int3 nb, 
   if (threadIdx.x == 0) os[m] = carry;
 }
 
-// Launch order of the bricks for the paged product: within each XCD's
-// contiguous range of logical blocks (xcd_block), bricks in decreasing
-// order of their page counts, ties by brick index.  The heaviest bricks then
-// start in the first generation of resident blocks and the lightest fill the
-// slots that free up, while every XCD keeps its compact set of bricks (and
-// its L2 working set).  One block; every brick's thread counts the bricks
-// of its range that go first (more pages, or as many and a lower index).
-__global__ void __launch_bounds__(1024) k_brick_order(const int* __restrict__ npages, int nbricks,
-                                                      int* __restrict__ order) {
-  const int per = (nbricks + kXcds - 1) / kXcds;
+// Launch order of the bricks for the paged product.  Each XCD takes a
+// contiguous range of bricks (a compact set, so its L2 holds its part of p
+// and of the tiles), the ranges cut where the running sum of page counts
+// crosses each eighth of the total (even ranges of bricks left the fullest
+// XCD about 8 % above the mean at 128^3), each at most `cap` bricks long;
+// within a range the bricks go in decreasing order of their page counts
+// (ties by brick index), so the heaviest start in the first generation of
+// resident blocks and the lightest fill the slots that free up.
+// order[x * cap + j] is the j-th brick of XCD x, -1 past its range.  With
+// balance == 0 (more bricks than the LDS prefix holds) the ranges are even.
+// One block; every brick's thread counts the bricks of its range that go
+// first.
+__global__ void __launch_bounds__(1024) k_brick_order(const int* __restrict__ npages, int nbricks, int cap,
+                                                      int balance, int* __restrict__ order) {
+  extern __shared__ int pre[];       // [nbricks + 1] page counts before each brick
+  __shared__ int sc[1024];
+  __shared__ int s_lo[kXcds + 1];
+  __shared__ int carry;
+  if (balance) {
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nbricks; c0 += blockDim.x) {   // inclusive scan in chunks of blockDim
+      const int b = c0 + threadIdx.x;
+      sc[threadIdx.x] = b < nbricks ? npages[b] : 0;
+      __syncthreads();
+      for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+        const int t = (int)threadIdx.x >= d ? sc[threadIdx.x - d] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += t;
+        __syncthreads();
+      }
+      if (b < nbricks) pre[b + 1] = carry + sc[threadIdx.x];
+      __syncthreads();
+      if (threadIdx.x == blockDim.x - 1) carry += sc[threadIdx.x];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) pre[0] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int even = (nbricks + kXcds - 1) / kXcds;
+    s_lo[0] = 0;
+    for (int x = 0; x < kXcds - 1; ++x) {
+      int bnd;
+      if (balance) {                 // first brick with at least (x + 1) / 8 of the pages before it
+        const long long target = (long long)pre[nbricks] * (x + 1) / kXcds;
+        int lo = 0, hi = nbricks;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (pre[mid] >= target) hi = mid;
+          else lo = mid + 1;
+        }
+        bnd = lo;
+      } else {
+        bnd = min(nbricks, (x + 1) * even);
+      }
+      // every range within cap bricks, and room for the rest
+      bnd = max(bnd, max(s_lo[x], nbricks - (kXcds - 1 - x) * cap));
+      bnd = min(bnd, min(s_lo[x] + cap, nbricks));
+      s_lo[x + 1] = bnd;
+    }
+    s_lo[kXcds] = nbricks;
+  }
+  __syncthreads();
   for (int b = threadIdx.x; b < nbricks; b += blockDim.x) {
-    const int lo = (b / per) * per, hi = min(nbricks, lo + per);
+    int x = 0;
+    while (x < kXcds - 1 && b >= s_lo[x + 1]) ++x;
+    const int lo = s_lo[x], hi = s_lo[x + 1];
     const int key = npages[b];
     int rank = 0;                    // bricks of the range that go first
     for (int c = lo; c < hi; ++c) {
       const int kc = npages[c];
       rank += kc > key || (kc == key && c < b);
     }
-    order[lo + rank] = b;
+    order[x * cap + rank] = b;
+  }
+  for (int q = threadIdx.x; q < kXcds * cap; q += blockDim.x) {
+    const int x = q / cap, j = q - x * cap;
+    if (j >= s_lo[x + 1] - s_lo[x]) order[q] = -1;
   }
 }
 
@@ -2342,9 +2402,10 @@ k_jac_apply_pg(Geo g, Bricks B, const float4* __restrict__ pv, const int* __rest
                const int* __restrict__ axbox) {
   if (halted(g.halt)) return;
   extern __shared__ float lds[];
-  const long long lb = xcd_block(B.nbricks);
+  const long long lb = xcd_block((long long)kXcds * pg_xcd_slots(B.nbricks));   // XCD x's slots x * cap + j
   if (lb < 0) return;
   const long long bid = order[lb];   // heaviest bricks of each XCD first
+  if (bid < 0) return;               // past this XCD's range
   int O[3], org[3];
   brick_origin<D>(g, B, bid, O, org);
   const int tot = D * B.tvol;
@@ -3065,7 +3126,9 @@ int launch_jac_assemble(lag_plan P, const void* vpack, const float* T, float* u,
                        P->cover_start[2], P->cover_ent[2], P->pgc_start[0], P->pgc_ent[0], P->pgc_start[1],
                        P->pgc_ent[1], P->pgc_start[2], P->pgc_ent[2]);
     LAG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_brick_order, dim3(1), dim3(1024), 0, s, P->pg_npages, B.nbricks, P->pg_order);
+    const int balance = B.nbricks < 16000;   // the page-count prefix fits 64 KB of LDS
+    hipLaunchKernelGGL(k_brick_order, dim3(1), dim3(1024), balance ? sizeof(int) * (B.nbricks + 1) : 0, s,
+                       P->pg_npages, (int)B.nbricks, pg_xcd_slots(B.nbricks), balance, P->pg_order);
     LAG_LAUNCH_CHECK();
   }
   return LAG_OK;
@@ -3086,6 +3149,7 @@ int launch_jac_apply(lag_plan P, const void* ppack, const float* wvox, const flo
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!wseed) prof_events(P, &e0, &e1);
   if (P->pg_cap > 0) {
+    grid = (unsigned)pg_order_len(B.nbricks);   // the order array's slots (k_brick_order)
     const size_t plds = sizeof(float) * ((size_t)P->geo.dim * B.tvol + 2 * (kPgBlock / 64) + kPgBlock);
 #define LAG_PG(DD, WS, WV, VT)                                                                                    \
   do {                                                                                                            \
