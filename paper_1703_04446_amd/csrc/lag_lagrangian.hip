@@ -2081,8 +2081,12 @@ __global__ void __launch_bounds__(kBlock) k_jac_pack(Bricks B, const float4* __r
   extern __shared__ int sh[];
   __shared__ int s_rows, s_pos;
   __shared__ int s_box[6];           // per axis: lowest and highest tile node touched
-  const long long bid = xcd_block(B.nbricks);
-  if (bid < 0) return;
+  // bricks dealt round-robin over the XCDs (brick b on XCD b mod 8): the
+  // copy streams every byte once, so no XCD needs a compact brick set, and
+  // interleaving evens out their page totals (contiguous ranges left the
+  // fullest XCD about 8 % above the mean at 128^3)
+  const long long bid = blockIdx.x;
+  if (bid >= B.nbricks) return;
   if (threadIdx.x < 6) s_box[threadIdx.x] = threadIdx.x < 3 ? 0x7fff : -1;
   const int rows = B.bdim[0] * B.bdim[1] * B.bdim[2];
   const long long base = bid * (long long)rows;
