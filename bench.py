@@ -58,10 +58,10 @@ PEAK_HBM_GBS = 8000.0
 # measured on: reported as null once that file changes.
 MEASURED_TRAFFIC = {
     "source": "paper_1703_04446_amd/csrc/lag_lagrangian.hip",
-    "sha256": "69b84efd079c685939c23475eba9d3b78ddb8d7f01cd0201d5b35e591c2a5b20",
+    "sha256": "3effd20c1a479b49ea0260c619005bcddb60d9fa66f47d86394d04900440c0a5",
     "workload": "3d128_transport",
-    "fetch_kib": 178944.9, "fetch_scale": 1.999741,
-    "write_kib": 14658.4, "write_scale": 1.0,
+    "fetch_kib": 178920.9, "fetch_scale": 1.999747,
+    "write_kib": 14658.5, "write_scale": 1.0,
 }
 
 
