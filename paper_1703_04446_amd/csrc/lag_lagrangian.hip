@@ -1642,8 +1642,11 @@ __global__ void __launch_bounds__(kBlock) k_jac_assemble(Geo g, Stages st, Brick
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int items = brick_items(B);
   const long long nitems = (long long)B.nbricks * items;
-  const long long blk = xcd_block((nitems + nw - 1) / nw);
-  if (blk < 0) return;
+  // blocks in launch order (dealt round-robin over the XCDs): every XCD gets
+  // the same mix of full and short bricks (the top slab of bricks holds
+  // fewer image rows)
+  const long long blk = blockIdx.x;
+  if (blk >= (nitems + nw - 1) / nw) return;
   const long long item = blk * nw + wave;
   if (item >= nitems) return;  // whole wave
   const long long bid = item / items;
